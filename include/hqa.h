@@ -1,0 +1,222 @@
+/*
+ * hqa.h -- C ABI of the HQA-MD hot path on MI355X (gfx950).
+ *
+ * Method: H. Irie, H. Liang, T. Doi, S. Gongyo, T. Hatsuda, "Hybrid Quantum
+ * Annealing via Molecular Dynamics", arXiv:2004.03972.  The library runs the
+ * classical flux dynamics of the paper (Eq. 3, the Hamilton equations and
+ * the leapfrog of Methods) for many independent replicas, sorts the spins
+ * into frozen and ambivalent sets by the time-averaged flux (Results,
+ * "Sorting frozen and ambivalent variables"), solves the reduced n-spin
+ * problem (HQA section, effective couplings) exactly by enumeration for
+ * n <= 24, and scores spin vectors exactly (Eq. 1, Methods "MAX-CUT").
+ *
+ * Conventions
+ *  - Plain C types only.  Every call returns an hqa_status; on failure the
+ *    thread-local hqa_last_error() names the cause, and a handle stays usable.
+ *  - Pointers tagged by a *_mem field are host (HQA_HOST) or device
+ *    (HQA_DEVICE, e.g. a torch tensor's data_ptr()) memory.  Inputs are
+ *    borrowed for the duration of the call; J, h, p0 and phi0 are copied at
+ *    init, and the library keeps no caller pointer.  Outputs are caller-owned.
+ *  - The handle owns every device buffer it allocates.  All device work is
+ *    ordered on the HIP stream given at init (NULL = the null stream).
+ *    hqa_md_run is asynchronous; calls that write host outputs synchronise.
+ *  - Replica-indexed arrays are replica-major: x[r * N + i].
+ */
+#ifndef HQA_H
+#define HQA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HQA_ABI_VERSION 1
+
+typedef enum {
+    HQA_OK = 0,
+    HQA_EINVAL = -1,       /* bad argument; detected before any device work */
+    HQA_ENOMEM = -2,       /* device or host allocation failed */
+    HQA_EDEVICE = -3,      /* a HIP call failed */
+    HQA_EUNSUPPORTED = -4, /* valid request outside what this build supports */
+    HQA_ENONFINITE = -5,   /* a flux or momentum became NaN/Inf during the run */
+    HQA_ESTATE = -6        /* call not valid in the handle's current state */
+} hqa_status;
+
+enum { HQA_DENSE = 0, HQA_CSR = 1 };
+enum { HQA_HOST = 0, HQA_DEVICE = 1 };
+
+/* Arithmetic of the MD step (field contraction + leapfrog update).
+ * F64_REF  : binary64 VALU in a fixed operation order (field as an fma chain over
+ *            ascending column index); bit-reproducible against any FP64 code that
+ *            uses the same order.
+ * F32      : J, fluxes, momenta and accumulation in binary32 (dense: FP32 MFMA).
+ * BF16     : J stored in bfloat16, fluxes rounded to bfloat16 as the MFMA operand,
+ *            FP32 accumulation; FP32 fluxes, momenta and update.  Dense only.
+ * FP8J_BF16: J stored in FP8 e4m3 (OCP), widened to bfloat16 in registers, else as
+ *            BF16.  Dense only. */
+typedef enum {
+    HQA_PREC_F64_REF = 0,
+    HQA_PREC_F32 = 1,
+    HQA_PREC_BF16 = 2,
+    HQA_PREC_FP8J_BF16 = 3
+} hqa_precision;
+
+/* An Ising instance (Results, Eq. 1): H(s) = 1/2 sum_{i!=j} J_ij s_i s_j + sum_i h_i s_i.
+ * J must be symmetric with a zero diagonal, all values finite.
+ * Dense: j holds n*n values, row-major.  CSR: row_ptr[n+1], col[nnz] strictly
+ * ascending within each row, j[nnz]; the pattern and values must be symmetric.
+ * h may be NULL (no field).  A MAX-CUT graph with weights w maps to J = w, h = 0
+ * (Methods, "MAX-CUT and Ising spin-glass"). */
+typedef struct hqa_problem {
+    int32_t n;
+    int32_t layout;          /* HQA_DENSE or HQA_CSR */
+    int32_t mem;             /* where j, row_ptr, col and h live */
+    int32_t reserved;
+    const double *j;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    int64_t nnz;
+    const double *h;
+} hqa_problem;
+
+/* Annealing schedule and integrator settings (Methods, "Scheduling functions for MD"
+ * and "Leapfrog algorithm"):
+ *   alpha(tau) = alpha_f (tau + rho1 (1-tau) + rho2 tau (tau-1)),
+ *   beta(tau)  = beta_f  (tau + kappa1 (1-tau) + kappa2 tau (tau-1)),
+ * tabulated at tau_k = k/(2T), k = 0..2T (integer step m at k = 2m).  T steps of
+ * size 1/T; the paper identifies g with the step (r_g = delta-tau/g = 1).  V = phi^M.
+ * The time average phibar takes the last W fluxes phi^(T-W+1..T) (delta = W/T).
+ * frozen != 0 holds alpha, beta at tau_frozen (conservation checks only). */
+typedef struct hqa_schedule {
+    double alpha_f, rho1, rho2;
+    double beta_f, kappa1, kappa2;
+    int64_t T;
+    int32_t M;               /* even, >= 2 */
+    int32_t W;               /* 1 <= W <= T */
+    double r_g;
+    int32_t frozen;
+    int32_t reserved;
+    double tau_frozen;
+} hqa_schedule;
+
+/* Run options.  Initial condition (Results, "Molecular dynamics for flux variables"):
+ * phi(0) = 0 and p(0) = +-1 at random, the coin for (replica r, spin i) of instance k
+ * being the top bit of the SplitMix64 output function (Steele, Lea, Flood 2014) at
+ * counter z = seed + (r*N + i + 1) * 0x9E3779B97F4A7C15, set = -1.  p0 / phi0, when
+ * not NULL, override this: concatenated over instances, each [R][N_k] binary64. */
+typedef struct hqa_md_opts {
+    int32_t replicas;        /* R >= 1 */
+    int32_t precision;       /* hqa_precision */
+    uint64_t seed;
+    const double *p0;
+    const double *phi0;
+    int32_t init_mem;        /* where p0 / phi0 live */
+    int32_t require_exact;   /* 1: fail with HQA_EUNSUPPORTED unless every J_ij converts
+                                exactly to the storage type of the precision */
+    int32_t persistent;      /* 1 (default): dense steps run in one persistent launch
+                                when the instance fits; 0: one launch per step */
+    int32_t reserved;
+} hqa_md_opts;
+
+typedef struct hqa_md hqa_md;
+
+/* Version of this ABI (HQA_ABI_VERSION). */
+int32_t hqa_abi_version(void);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *hqa_last_error(void);
+
+/* Paper defaults: (alpha_f, rho1, rho2) = (0.008, 4, 3), (beta_f, kappa1, kappa2) =
+ * (0.12, 0.05, 1), M = 6, W = 100, r_g = 1, T = 50000, not frozen. */
+void hqa_schedule_default(hqa_schedule *s);
+
+/* R = 1, F32, seed 0, random p0, phi0 = 0, persistent launch allowed. */
+void hqa_md_opts_default(hqa_md_opts *o);
+
+/* Validate and upload `count` instances (symmetry, zero diagonal, finite values,
+ * CSR ordering, W <= T, M even, exactness when requested), build the schedule table
+ * and the initial state on the device.  All instances share the schedule, R and the
+ * precision.  Errors: HQA_EINVAL (bad argument or instance; nothing allocated),
+ * HQA_EUNSUPPORTED (precision not available for the layout, or inexact conversion
+ * under require_exact), HQA_ENOMEM, HQA_EDEVICE.  *out is NULL on failure. */
+hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedule *sched,
+                       const hqa_md_opts *opts, void *hip_stream, hqa_md **out);
+
+/* Advance every instance to step until_step (T when negative), asynchronously.
+ * Step q evaluates the force at phi^(q) with alpha/beta at tau = q/T, kicks p (half a
+ * kick at q = 0), then drifts phi^(q+1) = phi^(q) + alpha(tau=(q+1/2)/T) p, adding
+ * phi^(q+1) to the window sum when q+1 >= T-W+1.  HQA_ESTATE if until_step is before
+ * the current step. */
+hqa_status hqa_md_run(hqa_md *md, int64_t until_step);
+
+/* Wait for queued work; HQA_ENONFINITE if any flux or momentum became non-finite. */
+hqa_status hqa_md_sync(hqa_md *md);
+
+/* Current step index q (fluxes are phi^(q), momenta p^(q-1/2), or p^(0) at q = 0). */
+int64_t hqa_md_step_index(const hqa_md *md);
+
+enum {
+    HQA_STATE_PHI = 0,       /* phi^(q)               [R][N] */
+    HQA_STATE_P = 1,         /* p^(q-1/2) (p^(0) at q = 0) */
+    HQA_STATE_PHIBAR = 2,    /* window mean S/W (defined at q = T) */
+    HQA_STATE_WSUM = 3       /* window sum S */
+};
+
+/* Copy state `what` of instance k out to dst ([R][N] binary64, dst_mem), or, with
+ * import != 0, overwrite it from dst (checkpoint/resume; the BF16 operand copy
+ * follows phi).  Synchronises. */
+hqa_status hqa_md_state(hqa_md *md, int32_t instance, int32_t what, void *dst,
+                        int32_t dst_mem, int32_t import);
+
+/* Set the step index (with hqa_md_state import, resumes a checkpoint). */
+hqa_status hqa_md_set_step(hqa_md *md, int64_t q);
+
+/* Local fields u = J phi^(q) of instance k, computed by the same contraction and
+ * storage precision as the MD step, written as binary64 [R][N].  Synchronises. */
+hqa_status hqa_md_field(hqa_md *md, int32_t instance, double *u, int32_t dst_mem);
+
+/* MD Hamiltonian (Eq. 3) at the current integer step q in binary64 on the GPU:
+ * alpha(q) sum(p^2/2 + phi^M) + beta(q) (1/2 sum phi_i u_i + sum h_i |phi_i| phi_i),
+ * with the integer-time momentum p^(q) = p^(q-1/2) - F(phi^(q))/2 and u = J phi in
+ * binary64 from the binary64 couplings.  H[R].  For the drift check.  Synchronises. */
+hqa_status hqa_md_hamiltonian(hqa_md *md, int32_t instance, double *H, int32_t dst_mem);
+
+/* Read-out outputs of hqa_classify; every pointer except spins may be NULL. */
+typedef struct hqa_classify_out {
+    int8_t *spins;           /* [R][N] read-out spins (+1/-1) */
+    int32_t *amb_idx;        /* [R][n] ambivalent spins, ascending index */
+    double *energy;          /* [R] exact Ising energy of spins (correctly rounded) */
+    double *cut;             /* [R] cut value sum_{i<j, s_i != s_j} J_ij, exact */
+    double *h_eff;           /* [R][n] effective fields of the reduced problem */
+    int64_t *code;           /* [R] winning code (bit a set: ambivalent spin a is -1) */
+    double *e_reduced;       /* [R] reduced energy H'(code), correctly rounded */
+} hqa_classify_out;
+
+/* Frozen/ambivalent sort and read-out at q = T (Results, "Sorting ..."; HQA section):
+ * per replica the n_amb spins with the smallest |phibar| (ties: lower index) are
+ * ambivalent; every spin gets s = sgn(phibar), sgn(0) = +1 (solve = 0: the MD-alone
+ * read-out).  solve = 1 also forms h_eff_a = h_a + sum_{k not in A} J_ak s_k (exact)
+ * and J_eff = J[A, A], finds the exact minimum of the reduced energy over all 2^n
+ * codes (ties: smallest code) and writes the merged spins.  Energies and cuts are
+ * exact sums of the binary64 couplings, correctly rounded.  HQA_ESTATE before q = T,
+ * HQA_EINVAL for n_amb outside [0, N], HQA_EUNSUPPORTED for solve = 1 with n_amb > 24.
+ * Synchronises. */
+hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                        const hqa_classify_out *out, int32_t out_mem);
+
+/* Exact Ising energy (Eq. 1) and cut (w = J) of n_vectors spin vectors [V][N] (int8,
+ * +1/-1) for one instance.  energy / cut [V] (either may be NULL).  Input and outputs
+ * in `mem`.  HQA_EUNSUPPORTED if the exponent spread of J and h is too wide for the
+ * exact fixed-point accumulator (more than 170 binades).  Synchronises. */
+hqa_status hqa_ising_energy(const hqa_problem *prob, const int8_t *spins, int32_t n_vectors,
+                            double *energy, double *cut, int32_t mem, void *hip_stream);
+
+/* Release every device buffer of the handle (NULL is accepted). */
+void hqa_md_destroy(hqa_md *md);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HQA_H */

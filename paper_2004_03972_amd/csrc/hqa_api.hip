@@ -1,0 +1,546 @@
+// hqa_api.hip -- the C ABI of include/hqa.h: argument checks, device buffers,
+// dispatch of the MD step kernels and of the read-out chain.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "hqa_internal.h"
+
+using namespace hqa;
+
+namespace hqa {
+hipError_t launch_md_steps_f64(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+hipError_t launch_md_steps_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+hipError_t launch_field_f64(hqa_md *md, Instance &I, double *u, hipStream_t st);
+hipError_t launch_field_dense(hqa_md *md, Instance &I, float *u, hipStream_t st);
+hipError_t launch_field_csr(hqa_md *md, Instance &I, float *u, hipStream_t st);
+hipError_t launch_layout_to_f64(int N, int R, int ld, int smaj, const float *src, double *dst,
+                                hipStream_t st);
+}  // namespace hqa
+
+static thread_local std::string g_err;
+
+static hqa_status fail(hqa_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? HQA_ENOMEM : HQA_EDEVICE, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                 \
+    } while (0)
+
+template <typename T>
+static hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+static void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+static void free_instance(Instance &I) {
+    dfree(I.J64); dfree(I.rp); dfree(I.ci); dfree(I.h64); dfree(I.h32); dfree(I.Js); dfree(I.v32);
+    for (int k = 0; k < 2; k++) { dfree(I.phi64[k]); dfree(I.phi32[k]); dfree(I.phib[k]); }
+    dfree(I.p64); dfree(I.S64); dfree(I.p32); dfree(I.S32);
+    I = Instance();
+}
+
+static hipMemcpyKind kind_in(int mem) { return mem == HQA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+static hipMemcpyKind kind_out(int mem) { return mem == HQA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+static std::string err_text(int e) {
+    std::string s;
+    if (e & ERR_ASYM) s += " J is not symmetric;";
+    if (e & ERR_DIAG) s += " J has a nonzero diagonal entry;";
+    if (e & ERR_NOTFINITE_IN) s += " J or h holds a non-finite value;";
+    if (e & ERR_CSR_ORDER) s += " CSR columns not strictly ascending or out of range;";
+    if (e & ERR_INEXACT) s += " J does not convert exactly to the storage type;";
+    if (e & ERR_NONFINITE) s += " a flux or momentum became non-finite;";
+    if (e & ERR_BARRIER) s += " a persistent-kernel barrier wait exceeded its bound;";
+    return s;
+}
+
+// Host-side checks of a problem descriptor that need no device work.
+static hqa_status check_problem(const hqa_problem &P, int k) {
+    if (P.n < 1) return fail(HQA_EINVAL, "instance %d: n must be >= 1", k);
+    if (P.layout != HQA_DENSE && P.layout != HQA_CSR)
+        return fail(HQA_EINVAL, "instance %d: unknown layout", k);
+    if (P.mem != HQA_HOST && P.mem != HQA_DEVICE) return fail(HQA_EINVAL, "instance %d: bad mem", k);
+    if (!P.j) return fail(HQA_EINVAL, "instance %d: j is NULL", k);
+    if (P.layout == HQA_CSR) {
+        if (!P.row_ptr || !P.col) return fail(HQA_EINVAL, "instance %d: CSR arrays missing", k);
+        if (P.nnz < 0) return fail(HQA_EINVAL, "instance %d: nnz < 0", k);
+    }
+    return HQA_OK;
+}
+
+// Upload binary64 couplings and field, validate on the device, gather exponent
+// statistics.  Leaves I.J64 / rp / ci / h64 filled.
+static hqa_status ingest(const hqa_problem &P, int k, hipStream_t st, int32_t *derr,
+                         int32_t *dstats, Instance &I) {
+    I.N = P.n;
+    I.layout = P.layout;
+    I.has_h = P.h != nullptr;
+    const int N = P.n;
+    if (P.layout == HQA_DENSE) {
+        I.nnz = (int64_t)N * N;
+        HIPCHK(dalloc(&I.J64, (size_t)N * N));
+        HIPCHK(hipMemcpyAsync(I.J64, P.j, sizeof(double) * N * N, kind_in(P.mem), st));
+    } else {
+        // the row pointer is needed on the host to size the arrays
+        std::vector<int32_t> rp(N + 1);
+        HIPCHK(hipMemcpyAsync(rp.data(), P.row_ptr, sizeof(int32_t) * (N + 1),
+                              P.mem == HQA_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (rp[0] != 0 || rp[N] != P.nnz)
+            return fail(HQA_EINVAL, "instance %d: row_ptr[0] must be 0 and row_ptr[n] = nnz", k);
+        for (int i = 0; i < N; i++)
+            if (rp[i + 1] < rp[i]) return fail(HQA_EINVAL, "instance %d: row_ptr decreases", k);
+        I.nnz = P.nnz;
+        HIPCHK(dalloc(&I.J64, (size_t)P.nnz));
+        HIPCHK(dalloc(&I.rp, (size_t)N + 1));
+        HIPCHK(dalloc(&I.ci, (size_t)P.nnz));
+        HIPCHK(hipMemcpyAsync(I.rp, rp.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, st));
+        if (P.nnz) {
+            HIPCHK(hipMemcpyAsync(I.ci, P.col, sizeof(int32_t) * P.nnz, kind_in(P.mem), st));
+            HIPCHK(hipMemcpyAsync(I.J64, P.j, sizeof(double) * P.nnz, kind_in(P.mem), st));
+        }
+    }
+    HIPCHK(dalloc(&I.h64, (size_t)N));
+    if (P.h) HIPCHK(hipMemcpyAsync(I.h64, P.h, sizeof(double) * N, kind_in(P.mem), st));
+    else HIPCHK(hipMemsetAsync(I.h64, 0, sizeof(double) * N, st));
+    int32_t init[4] = {1 << 20, -(1 << 20), 1, 0};
+    HIPCHK(hipMemcpyAsync(dstats, init, sizeof init, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(derr, 0, sizeof(int32_t), st));
+    if (P.layout == HQA_DENSE) HIPCHK(launch_validate_dense(I.J64, I.h64, N, derr, dstats, st));
+    else HIPCHK(launch_validate_csr(I.rp, I.ci, I.J64, I.h64, N, derr, dstats, st));
+    int32_t stats[4], e = 0;
+    HIPCHK(hipMemcpyAsync(stats, dstats, sizeof stats, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&e, derr, sizeof e, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (e) return fail(HQA_EINVAL, "instance %d:%s", k, err_text(e).c_str());
+    if (stats[1] < stats[0]) { stats[0] = 0; stats[1] = 0; }   // all zero
+    I.es.lsb = stats[0];
+    I.es.msb = stats[1];
+    I.j_integral = stats[2] != 0;
+    if (I.es.msb - I.es.lsb > 150 || I.es.lsb < -1022 + 53)
+        I.es.lsb = INT32_MIN;  // exact read-out unavailable for this instance
+    return HQA_OK;
+}
+
+static bool exact_ok(const Instance &I) { return I.es.lsb != INT32_MIN; }
+
+// Scoped device buffers for the read-out.
+struct DevBufs {
+    std::vector<void *> v;
+    template <typename T>
+    hipError_t get(T **p, size_t n) {
+        hipError_t e = dalloc(p, n);
+        if (e == hipSuccess) v.push_back(*p);
+        return e;
+    }
+    ~DevBufs() {
+        for (void *p : v) dfree(p);
+    }
+};
+
+
+extern "C" {
+
+int32_t hqa_abi_version(void) { return HQA_ABI_VERSION; }
+
+const char *hqa_last_error(void) { return g_err.c_str(); }
+
+void hqa_schedule_default(hqa_schedule *s) {
+    if (!s) return;
+    memset(s, 0, sizeof *s);
+    s->alpha_f = 0.008; s->rho1 = 4.0; s->rho2 = 3.0;
+    s->beta_f = 0.12; s->kappa1 = 0.05; s->kappa2 = 1.0;
+    s->T = 50000; s->M = 6; s->W = 100; s->r_g = 1.0;
+    s->frozen = 0; s->tau_frozen = 0.0;
+}
+
+void hqa_md_opts_default(hqa_md_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->replicas = 1;
+    o->precision = HQA_PREC_F32;
+    o->persistent = 1;
+}
+
+void hqa_md_destroy(hqa_md *md) {
+    if (!md) return;
+    if (md->stream || true) (void)hipStreamSynchronize(md->stream);
+    for (auto &I : md->inst) free_instance(I);
+    dfree(md->a64); dfree(md->b64); dfree(md->a32); dfree(md->b32);
+    dfree(md->err); dfree(md->scratch_i);
+    delete md;
+}
+
+hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedule *sched,
+                       const hqa_md_opts *opts, void *hip_stream, hqa_md **out) {
+    g_err.clear();
+    if (!out) return fail(HQA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!probs || count < 1) return fail(HQA_EINVAL, "need at least one problem");
+    if (!sched || !opts) return fail(HQA_EINVAL, "schedule and options are required");
+    if (sched->T < 1) return fail(HQA_EINVAL, "T must be >= 1");
+    if (sched->W < 1 || sched->W > sched->T) return fail(HQA_EINVAL, "W must satisfy 1 <= W <= T");
+    if (sched->M < 2 || (sched->M & 1)) return fail(HQA_EINVAL, "M must be even and >= 2");
+    if (!(sched->r_g > 0.0) || !isfinite(sched->r_g)) return fail(HQA_EINVAL, "r_g must be > 0");
+    if (opts->replicas < 1) return fail(HQA_EINVAL, "replicas must be >= 1");
+    if (opts->precision < HQA_PREC_F64_REF || opts->precision > HQA_PREC_FP8J_BF16)
+        return fail(HQA_EINVAL, "unknown precision");
+    if ((opts->p0 || opts->phi0) && opts->init_mem != HQA_HOST && opts->init_mem != HQA_DEVICE)
+        return fail(HQA_EINVAL, "bad init_mem");
+    for (int k = 0; k < count; k++) {
+        hqa_status s = check_problem(probs[k], k);
+        if (s != HQA_OK) return s;
+        if (probs[k].layout == HQA_CSR && opts->precision >= HQA_PREC_BF16)
+            return fail(HQA_EUNSUPPORTED, "instance %d: BF16/FP8 storage is for dense J only", k);
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    hqa_md *md = new hqa_md();
+    md->stream = st;
+    md->R = opts->replicas;
+    md->prec = opts->precision;
+    md->persistent = opts->persistent;
+    md->jt = opts->precision == HQA_PREC_BF16 ? JT_BF16
+             : opts->precision == HQA_PREC_FP8J_BF16 ? JT_FP8 : JT_F32;
+    Schedule64 &S = md->sch;
+    S.prm[0] = sched->alpha_f; S.prm[1] = sched->rho1; S.prm[2] = sched->rho2;
+    S.prm[3] = sched->beta_f; S.prm[4] = sched->kappa1; S.prm[5] = sched->kappa2;
+    S.T = sched->T; S.M = sched->M; S.W = sched->W; S.r_g = sched->r_g;
+    S.frozen = sched->frozen; S.tau_frozen = sched->tau_frozen;
+    md->inst.resize(count);
+    auto bail = [&](hqa_status s) { hqa_md_destroy(md); return s; };
+#define CK(expr)                                 \
+    do {                                         \
+        hqa_status s_ = (expr);                  \
+        if (s_ != HQA_OK) return bail(s_);       \
+    } while (0)
+#define HK(expr)                                                                            \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return bail(fail(e_ == hipErrorOutOfMemory ? HQA_ENOMEM : HQA_EDEVICE, "%s: %s", \
+                             #expr, hipGetErrorString(e_)));                                \
+    } while (0)
+    HK(dalloc(&md->err, 1));
+    HK(dalloc(&md->scratch_i, 16));
+    HK(hipMemsetAsync(md->err, 0, sizeof(int32_t), st));
+    const int64_t nk = 2 * S.T + 1;
+    HK(dalloc(&md->a64, nk)); HK(dalloc(&md->b64, nk));
+    HK(dalloc(&md->a32, nk)); HK(dalloc(&md->b32, nk));
+    HK(launch_schedule(S, md->a64, md->b64, md->a32, md->b32, st));
+    const int R = md->R;
+    const bool f64 = md->prec == HQA_PREC_F64_REF;
+    int64_t off = 0;
+    for (int k = 0; k < count; k++) {
+        Instance &I = md->inst[k];
+        const hqa_problem &P = probs[k];
+        CK(ingest(P, k, st, md->err, md->scratch_i, I));
+        const int N = I.N;
+        if (f64) {
+            I.ld = N;
+            size_t n = (size_t)N * R;
+            HK(dalloc(&I.phi64[0], n)); HK(dalloc(&I.phi64[1], n));
+            HK(dalloc(&I.p64, n)); HK(dalloc(&I.S64, n));
+        } else {
+            HK(dalloc(&I.h32, (size_t)N));
+            HK(launch_convert_h(I.h64, N, I.h32, st));
+            HK(hipMemsetAsync(md->err, 0, sizeof(int32_t), st));
+            if (P.layout == HQA_DENSE) {
+                I.smaj = false;
+                I.Np = (N + 31) / 32 * 32;
+                I.Rp = (R + 15) / 16 * 16;
+                I.ld = I.Np;
+                size_t esz = md->jt == JT_F32 ? 4 : md->jt == JT_BF16 ? 2 : 1;
+                HK(hipMalloc(&I.Js, (size_t)I.Np * I.Np * esz));
+                HK(launch_convert_dense(I.J64, N, I.Np, md->jt, I.Js, md->err, st));
+                size_t n = (size_t)I.Rp * I.ld;
+                for (int b = 0; b < 2; b++) {
+                    HK(dalloc(&I.phi32[b], n));
+                    HK(hipMemsetAsync(I.phi32[b], 0, n * 4, st));
+                    if (md->jt != JT_F32) {
+                        HK(dalloc(&I.phib[b], n));
+                        HK(hipMemsetAsync(I.phib[b], 0, n * 2, st));
+                    }
+                }
+                HK(dalloc(&I.p32, n)); HK(hipMemsetAsync(I.p32, 0, n * 4, st));
+                HK(dalloc(&I.S32, n)); HK(hipMemsetAsync(I.S32, 0, n * 4, st));
+            } else {
+                I.smaj = true;
+                I.Rp = (R + 3) / 4 * 4;
+                I.ld = I.Rp;
+                HK(dalloc(&I.v32, (size_t)I.nnz));
+                if (I.nnz) HK(launch_convert_csr(I.J64, I.nnz, I.v32, md->err, st));
+                size_t n = (size_t)N * I.Rp;
+                for (int b = 0; b < 2; b++) {
+                    HK(dalloc(&I.phi32[b], n));
+                    HK(hipMemsetAsync(I.phi32[b], 0, n * 4, st));
+                }
+                HK(dalloc(&I.p32, n)); HK(hipMemsetAsync(I.p32, 0, n * 4, st));
+                HK(dalloc(&I.S32, n)); HK(hipMemsetAsync(I.S32, 0, n * 4, st));
+            }
+            int32_t e = 0;
+            HK(hipMemcpyAsync(&e, md->err, sizeof e, hipMemcpyDeviceToHost, st));
+            HK(hipStreamSynchronize(st));
+            if ((e & ERR_INEXACT) && opts->require_exact)
+                return bail(fail(HQA_EUNSUPPORTED,
+                                 "instance %d: J is not exactly representable in the storage "
+                                 "type of the requested precision", k));
+            HK(hipMemsetAsync(md->err, 0, sizeof(int32_t), st));
+        }
+        const double *p0 = opts->p0 ? opts->p0 + off : nullptr;
+        const double *phi0 = opts->phi0 ? opts->phi0 + off : nullptr;
+        double *dp0 = nullptr, *dphi0 = nullptr;
+        if (opts->init_mem == HQA_HOST && (p0 || phi0)) {
+            size_t n = (size_t)N * R;
+            if (p0) {
+                HK(dalloc(&dp0, n));
+                HK(hipMemcpyAsync(dp0, p0, n * 8, hipMemcpyHostToDevice, st));
+            }
+            if (phi0) {
+                HK(dalloc(&dphi0, n));
+                HK(hipMemcpyAsync(dphi0, phi0, n * 8, hipMemcpyHostToDevice, st));
+            }
+            p0 = dp0;
+            phi0 = dphi0;
+        }
+        hipError_t le = launch_init_state(I, R, md->prec, opts->seed, p0, phi0, st);
+        if (dp0 || dphi0) {
+            (void)hipStreamSynchronize(st);
+            dfree(dp0);
+            dfree(dphi0);
+        }
+        HK(le);
+        off += (int64_t)N * R;
+    }
+    HK(hipStreamSynchronize(st));
+#undef CK
+#undef HK
+    *out = md;
+    return HQA_OK;
+}
+
+int64_t hqa_md_step_index(const hqa_md *md) { return md ? md->q : -1; }
+
+hqa_status hqa_md_set_step(hqa_md *md, int64_t q) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    if (q < 0 || q > md->sch.T) return fail(HQA_EINVAL, "step %lld outside [0, T]", (long long)q);
+    md->q = q;
+    return HQA_OK;
+}
+
+hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    int64_t q1 = until_step < 0 ? md->sch.T : until_step;
+    if (q1 > md->sch.T) return fail(HQA_EINVAL, "until_step beyond T");
+    if (q1 < md->q) return fail(HQA_ESTATE, "until_step %lld is before the current step %lld",
+                                (long long)q1, (long long)md->q);
+    if (q1 == md->q) return HQA_OK;
+    for (auto &I : md->inst) {
+        hipError_t e;
+        if (md->prec == HQA_PREC_F64_REF) e = launch_md_steps_f64(md, I, md->q, q1);
+        else if (I.layout == HQA_DENSE) e = launch_md_steps_dense(md, I, md->q, q1);
+        else e = launch_md_steps_csr(md, I, md->q, q1);
+        if (e != hipSuccess) return fail(HQA_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    }
+    md->q = q1;
+    return HQA_OK;
+}
+
+hqa_status hqa_md_sync(hqa_md *md) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    int32_t e = 0;
+    HIPCHK(hipMemcpyAsync(&e, md->err, sizeof e, hipMemcpyDeviceToHost, md->stream));
+    HIPCHK(hipStreamSynchronize(md->stream));
+    if (e & ERR_NONFINITE) return fail(HQA_ENONFINITE, "a flux or momentum became non-finite");
+    if (e) return fail(HQA_EDEVICE, "device error:%s", err_text(e).c_str());
+    return HQA_OK;
+}
+
+static hqa_status check_instance(hqa_md *md, int32_t k) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    if (k < 0 || k >= (int32_t)md->inst.size()) return fail(HQA_EINVAL, "instance %d out of range", k);
+    return HQA_OK;
+}
+
+hqa_status hqa_md_state(hqa_md *md, int32_t instance, int32_t what, void *dst, int32_t dst_mem,
+                        int32_t import) {
+    hqa_status s = check_instance(md, instance);
+    if (s != HQA_OK) return s;
+    if (!dst) return fail(HQA_EINVAL, "dst is NULL");
+    if (what < HQA_STATE_PHI || what > HQA_STATE_WSUM) return fail(HQA_EINVAL, "unknown state");
+    if (import && what == HQA_STATE_PHIBAR) return fail(HQA_EINVAL, "phibar cannot be imported");
+    Instance &I = md->inst[instance];
+    const size_t n = (size_t)I.N * md->R;
+    double *buf = (double *)dst;
+    if (dst_mem == HQA_HOST) HIPCHK(dalloc(&buf, n));
+    if (import && dst_mem == HQA_HOST)
+        HIPCHK(hipMemcpyAsync(buf, dst, n * 8, hipMemcpyHostToDevice, md->stream));
+    HIPCHK(launch_export(I, md->R, md->prec, what, buf, import, md->sch.W, md->stream));
+    if (!import && dst_mem == HQA_HOST)
+        HIPCHK(hipMemcpyAsync(dst, buf, n * 8, hipMemcpyDeviceToHost, md->stream));
+    HIPCHK(hipStreamSynchronize(md->stream));
+    if (dst_mem == HQA_HOST) dfree(buf);
+    return HQA_OK;
+}
+
+hqa_status hqa_md_field(hqa_md *md, int32_t instance, double *u, int32_t dst_mem) {
+    hqa_status s = check_instance(md, instance);
+    if (s != HQA_OK) return s;
+    if (!u) return fail(HQA_EINVAL, "u is NULL");
+    Instance &I = md->inst[instance];
+    const size_t n = (size_t)I.N * md->R;
+    double *buf = u;
+    if (dst_mem == HQA_HOST) HIPCHK(dalloc(&buf, n));
+    if (md->prec == HQA_PREC_F64_REF) {
+        if (I.N > 8192) return fail(HQA_EUNSUPPORTED, "binary64 field limited to N <= 8192");
+        HIPCHK(launch_field_f64(md, I, buf, md->stream));
+    } else {
+        float *u32;
+        size_t m = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
+        HIPCHK(dalloc(&u32, m));
+        if (I.layout == HQA_DENSE) HIPCHK(launch_field_dense(md, I, u32, md->stream));
+        else HIPCHK(launch_field_csr(md, I, u32, md->stream));
+        HIPCHK(launch_layout_to_f64(I.N, md->R, I.ld, I.smaj, u32, buf, md->stream));
+        HIPCHK(hipStreamSynchronize(md->stream));
+        dfree(u32);
+    }
+    if (dst_mem == HQA_HOST) HIPCHK(hipMemcpyAsync(u, buf, n * 8, hipMemcpyDeviceToHost, md->stream));
+    HIPCHK(hipStreamSynchronize(md->stream));
+    if (dst_mem == HQA_HOST) dfree(buf);
+    return HQA_OK;
+}
+
+hqa_status hqa_md_hamiltonian(hqa_md *md, int32_t instance, double *H, int32_t dst_mem) {
+    hqa_status s = check_instance(md, instance);
+    if (s != HQA_OK) return s;
+    if (!H) return fail(HQA_EINVAL, "H is NULL");
+    Instance &I = md->inst[instance];
+    if (I.N > 8192) return fail(HQA_EUNSUPPORTED, "binary64 Hamiltonian limited to N <= 8192");
+    double *buf = H;
+    if (dst_mem == HQA_HOST) HIPCHK(dalloc(&buf, (size_t)md->R));
+    HIPCHK(launch_hamiltonian(md, I, buf, md->stream));
+    if (dst_mem == HQA_HOST)
+        HIPCHK(hipMemcpyAsync(H, buf, (size_t)md->R * 8, hipMemcpyDeviceToHost, md->stream));
+    HIPCHK(hipStreamSynchronize(md->stream));
+    if (dst_mem == HQA_HOST) dfree(buf);
+    return HQA_OK;
+}
+
+hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                        const hqa_classify_out *out, int32_t out_mem) {
+    hqa_status s = check_instance(md, instance);
+    if (s != HQA_OK) return s;
+    if (!out || !out->spins) return fail(HQA_EINVAL, "out->spins is required");
+    Instance &I = md->inst[instance];
+    const int R = md->R, N = I.N;
+    if (n_amb < 0 || n_amb > N) return fail(HQA_EINVAL, "n_amb must lie in [0, N]");
+    if (solve && n_amb > 24) return fail(HQA_EUNSUPPORTED, "exact enumeration limited to n <= 24");
+    if (md->q != md->sch.T) return fail(HQA_ESTATE, "classify needs the run to reach step T");
+    if ((solve || out->energy || out->cut || out->h_eff) && !exact_ok(I))
+        return fail(HQA_EUNSUPPORTED, "coupling exponents span too many binades for exact sums");
+    if (solve && I.j_integral && I.es.msb + 2 * 16 + 8 > 62)
+        return fail(HQA_EUNSUPPORTED, "integer couplings too large for int64 enumeration");
+    s = hqa_md_sync(md);
+    if (s != HQA_OK) return s;
+    hipStream_t st = md->stream;
+    DevBufs B;
+    int32_t *amb;
+    int8_t *spins;
+    HIPCHK(B.get(&amb, (size_t)R * (n_amb ? n_amb : 1)));
+    HIPCHK(B.get(&spins, (size_t)R * N));
+    HIPCHK(launch_select(I, R, md->prec, md->sch.W, n_amb, amb, spins, st));
+    double *h_eff = nullptr, *J_eff = nullptr, *e_red = nullptr;
+    int64_t *code = nullptr;
+    if (solve && n_amb > 0) {
+        HIPCHK(B.get(&h_eff, (size_t)R * n_amb));
+        HIPCHK(B.get(&J_eff, (size_t)R * n_amb * n_amb));
+        HIPCHK(B.get(&code, (size_t)R));
+        HIPCHK(B.get(&e_red, (size_t)R));
+        HIPCHK(launch_reduce(I, R, n_amb, amb, spins, h_eff, J_eff, st));
+        HIPCHK(launch_enumerate(n_amb, R, J_eff, h_eff, I.es.lsb, I.j_integral ? 1 : 0, code,
+                                e_red, st));
+        HIPCHK(launch_merge(N, R, n_amb, amb, code, spins, st));
+    } else if (out->h_eff && n_amb > 0) {
+        HIPCHK(B.get(&h_eff, (size_t)R * n_amb));
+        HIPCHK(B.get(&J_eff, (size_t)R * n_amb * n_amb));
+        HIPCHK(launch_reduce(I, R, n_amb, amb, spins, h_eff, J_eff, st));
+    }
+    double *E = nullptr, *C = nullptr;
+    if (out->energy || out->cut) {
+        HIPCHK(B.get(&E, (size_t)R));
+        HIPCHK(B.get(&C, (size_t)R));
+        HIPCHK(launch_energy(I, R, spins, E, C, st));
+    }
+    hipMemcpyKind kd = kind_out(out_mem);
+    HIPCHK(hipMemcpyAsync(out->spins, spins, (size_t)R * N, kd, st));
+    if (out->amb_idx && n_amb) HIPCHK(hipMemcpyAsync(out->amb_idx, amb, (size_t)R * n_amb * 4, kd, st));
+    if (out->energy) HIPCHK(hipMemcpyAsync(out->energy, E, (size_t)R * 8, kd, st));
+    if (out->cut) HIPCHK(hipMemcpyAsync(out->cut, C, (size_t)R * 8, kd, st));
+    if (out->h_eff && h_eff) HIPCHK(hipMemcpyAsync(out->h_eff, h_eff, (size_t)R * n_amb * 8, kd, st));
+    if (out->code && code) HIPCHK(hipMemcpyAsync(out->code, code, (size_t)R * 8, kd, st));
+    if (out->e_reduced && e_red) HIPCHK(hipMemcpyAsync(out->e_reduced, e_red, (size_t)R * 8, kd, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return HQA_OK;
+}
+
+hqa_status hqa_ising_energy(const hqa_problem *prob, const int8_t *spins, int32_t n_vectors,
+                            double *energy, double *cut, int32_t mem, void *hip_stream) {
+    g_err.clear();
+    if (!prob || !spins || n_vectors < 0) return fail(HQA_EINVAL, "bad arguments");
+    if (mem != HQA_HOST && mem != HQA_DEVICE) return fail(HQA_EINVAL, "bad mem");
+    hqa_status s = check_problem(*prob, 0);
+    if (s != HQA_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBufs B;
+    int32_t *derr, *dstats;
+    HIPCHK(B.get(&derr, 1));
+    HIPCHK(B.get(&dstats, 4));
+    Instance I;
+    s = ingest(*prob, 0, st, derr, dstats, I);
+    if (s == HQA_OK && !exact_ok(I))
+        s = fail(HQA_EUNSUPPORTED, "coupling exponents span too many binades for exact sums");
+    if (s != HQA_OK) { free_instance(I); return s; }
+    const size_t V = (size_t)n_vectors, N = (size_t)I.N;
+    int8_t *dsp = (int8_t *)spins;
+    double *dE = energy, *dC = cut;
+    hipError_t e = hipSuccess;
+    if (mem == HQA_HOST) {
+        if (e == hipSuccess) e = B.get(&dsp, V * N);
+        if (e == hipSuccess) e = hipMemcpyAsync(dsp, spins, V * N, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && energy) e = B.get(&dE, V);
+        if (e == hipSuccess && cut) e = B.get(&dC, V);
+    }
+    if (e == hipSuccess) e = launch_energy(I, n_vectors, dsp, dE, dC, st);
+    if (e == hipSuccess && mem == HQA_HOST && energy)
+        e = hipMemcpyAsync(energy, dE, V * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && mem == HQA_HOST && cut)
+        e = hipMemcpyAsync(cut, dC, V * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    free_instance(I);
+    if (e != hipSuccess) return fail(HQA_EDEVICE, "energy: %s", hipGetErrorString(e));
+    return HQA_OK;
+}
+
+}  // extern "C"

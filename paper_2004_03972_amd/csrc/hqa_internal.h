@@ -1,0 +1,135 @@
+// hqa_internal.h -- device buffers, kernel argument blocks and launchers shared
+// by the HIP translation units of libhqa.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hqa.h"
+
+namespace hqa {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+// Storage type of J for the fast paths.
+enum JType { JT_F32 = 0, JT_BF16 = 1, JT_FP8 = 2 };
+
+// Error bits raised by kernels into a device word.
+enum {
+    ERR_NONFINITE = 1,      // flux or momentum became NaN/Inf
+    ERR_ASYM = 2,           // J not symmetric
+    ERR_DIAG = 4,           // nonzero diagonal
+    ERR_NOTFINITE_IN = 8,   // non-finite coupling or field
+    ERR_INEXACT = 16,       // J does not convert exactly to the storage type
+    ERR_CSR_ORDER = 32,     // CSR columns not strictly ascending / out of range
+    ERR_FP8_SUBNORMAL = 64, // J value whose e4m3 code would be subnormal
+    ERR_BARRIER = 128,      // persistent-kernel barrier wait exceeded its bound
+};
+
+// Exponent statistics of an instance for the exact accumulator:
+// lsb = lowest set-bit exponent over nonzero inputs, msb = highest bit exponent.
+struct ExpStats {
+    int lsb;
+    int msb;
+};
+
+struct Instance {
+    int32_t N = 0;
+    int32_t layout = HQA_DENSE;
+    int64_t nnz = 0;
+    int32_t Np = 0;           // dense fast paths: N padded to a multiple of 32
+    int32_t Rp = 0;           // replicas padded to a multiple of 16
+    bool smaj = false;        // state layout [N][R] (CSR fast path) else [R][ld]
+    int32_t ld = 0;           // leading dimension of replica-major state
+    bool has_h = false;
+
+    // binary64 copies of the input (every precision keeps them: reduce, energy,
+    // drift check and the reference mode read them)
+    double *J64 = nullptr;    // dense N*N or CSR values
+    int32_t *rp = nullptr, *ci = nullptr;
+    double *h64 = nullptr;    // N (zeros when no field)
+    float *h32 = nullptr;     // N (or Np)
+
+    void *Js = nullptr;       // dense storage for the fast paths, Np*Np of JType
+    float *v32 = nullptr;     // CSR FP32 values
+
+    // state
+    double *phi64[2] = {nullptr, nullptr};
+    double *p64 = nullptr, *S64 = nullptr;
+    float *phi32[2] = {nullptr, nullptr};
+    float *p32 = nullptr, *S32 = nullptr;
+    bf16 *phib[2] = {nullptr, nullptr};
+    int cur = 0;              // phi[cur] holds phi^(q)
+
+    ExpStats es{0, 0};
+    bool j_integral = false;  // every J and h is an integer
+};
+
+struct Schedule64 {
+    double prm[6];
+    int64_t T;
+    int32_t M, W;
+    double r_g;
+    int32_t frozen;
+    double tau_frozen;
+};
+
+}  // namespace hqa
+
+struct hqa_md {
+    hipStream_t stream = nullptr;
+    int32_t R = 1;
+    int32_t prec = HQA_PREC_F32;
+    int32_t persistent = 1;
+    hqa::Schedule64 sch{};
+    int64_t q = 0;
+    std::vector<hqa::Instance> inst;
+    double *a64 = nullptr, *b64 = nullptr;   // schedule tables [2T+1]
+    float *a32 = nullptr, *b32 = nullptr;
+    int32_t *err = nullptr;                  // device error word
+    int32_t *scratch_i = nullptr;            // small device scratch (ints)
+    hqa::JType jt = hqa::JT_F32;
+};
+
+namespace hqa {
+
+// ---- kernel launchers (each returns hipGetLastError of the launch) ----------
+hipError_t launch_schedule(const Schedule64 &s, double *a64, double *b64, float *a32, float *b32,
+                           hipStream_t st);
+hipError_t launch_validate_dense(const double *J, const double *h, int N, int32_t *err,
+                                 int32_t *stats, hipStream_t st);
+hipError_t launch_validate_csr(const int32_t *rp, const int32_t *ci, const double *v,
+                               const double *h, int N, int32_t *err, int32_t *stats,
+                               hipStream_t st);
+hipError_t launch_convert_dense(const double *J, int N, int Np, JType jt, void *out,
+                                int32_t *err, hipStream_t st);
+hipError_t launch_convert_csr(const double *v, int64_t nnz, float *out, int32_t *err,
+                              hipStream_t st);
+hipError_t launch_convert_h(const double *h, int N, float *out, hipStream_t st);
+hipError_t launch_init_state(const Instance &I, int R, int prec, uint64_t seed,
+                             const double *p0, const double *phi0, hipStream_t st);
+hipError_t launch_export(const Instance &I, int R, int prec, int what, double *dst,
+                         int import, int W, hipStream_t st);
+
+// MD steps: advance from step q to q + nsteps
+hipError_t launch_md_steps(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+hipError_t launch_field(hqa_md *md, Instance &I, double *u, hipStream_t st);
+hipError_t launch_hamiltonian(hqa_md *md, Instance &I, double *H, hipStream_t st);
+
+// read-out
+hipError_t launch_select(const Instance &I, int R, int prec, int W, int n, int32_t *amb,
+                         int8_t *spins, hipStream_t st);
+hipError_t launch_reduce(const Instance &I, int R, int n, const int32_t *amb,
+                         const int8_t *spins, double *h_eff, double *J_eff, hipStream_t st);
+hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_eff, int b0,
+                            int integral, int64_t *code, double *e_red, hipStream_t st);
+hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
+                        int8_t *spins, hipStream_t st);
+hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
+                         hipStream_t st);
+
+}  // namespace hqa

@@ -1,0 +1,172 @@
+// k_md_dense.hip -- dense field U = J Phi on MFMA with the leapfrog fused into
+// the epilogue, one launch per MD step.
+//
+// Layout: J is stored Np x Np (N padded to a multiple of 32, zeros outside),
+// row-major, as FP32, BF16 or FP8 e4m3.  The state is replica-major [Rp][ld]
+// (ld = Np): row r of the binary32 fluxes / momenta / window sum and of the
+// BF16 operand copy is one replica.  With U[i][r] = sum_k J[i][k] Phi[r][k],
+// the A operand (16 rows i x K) and the B operand (K x 16 replicas r) are both
+// read as 16-byte runs along k, and each lane's accumulator holds four
+// consecutive rows of one replica, so the epilogue reads and writes 16-byte
+// vectors of the state.
+//
+// Workgroup tile: 32 rows x 32 replicas, one 16 x 16 MFMA tile per wavefront.
+#include "hqa_internal.h"
+#include "md_epilogue.h"
+
+namespace hqa {
+
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+
+struct DenseArgs {
+    int N, Np, R, Rp, ld, M;
+    int64_t T;
+    int W;
+    float rg;
+    const void *J;
+    const float *h;
+    const float *a32, *b32;
+    const float *phi_in;
+    const bf16 *xb_in;
+    float *phi_out, *p, *S;
+    bf16 *xb_out;
+    float *u_out;       // field-only mode: U written here ([R][ld]), no update
+    int32_t *err;
+};
+
+// Eight FP8 e4m3 codes to eight BF16 values (exact: e4m3 embeds in bf16).
+__device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint2 raw) {
+    bf16x2 a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.x, 1.0f, false);
+    bf16x2 b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.x, 1.0f, true);
+    bf16x2 c = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.y, 1.0f, false);
+    bf16x2 d = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.y, 1.0f, true);
+    bf16x8 o;
+    o[0] = a[0]; o[1] = a[1]; o[2] = b[0]; o[3] = b[1];
+    o[4] = c[0]; o[5] = c[1]; o[6] = d[0]; o[7] = d[1];
+    return o;
+}
+
+// Accumulate one 16x16 tile U[i0..i0+16)[r0..r0+16) over the full K = Np.
+template <int JT>
+__device__ __forceinline__ f32x4 tile_field(const DenseArgs &a, int i0, int r0, int lane) {
+    const int row = i0 + (lane & 15), col = r0 + (lane & 15), kg = lane >> 4;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (JT == JT_F32) {
+        const float *Ja = (const float *)a.J + (int64_t)row * a.Np + 4 * kg;
+        const float *Xb = a.phi_in + (int64_t)col * a.ld + 4 * kg;
+#pragma unroll 4
+        for (int k0 = 0; k0 < a.Np; k0 += 16) {
+            float4 av = *(const float4 *)(Ja + k0);
+            float4 bv = *(const float4 *)(Xb + k0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc, 0, 0, 0);
+        }
+    } else if constexpr (JT == JT_BF16) {
+        const bf16 *Ja = (const bf16 *)a.J + (int64_t)row * a.Np + 8 * kg;
+        const bf16 *Xb = a.xb_in + (int64_t)col * a.ld + 8 * kg;
+#pragma unroll 4
+        for (int k0 = 0; k0 < a.Np; k0 += 32) {
+            bf16x8 av = *(const bf16x8 *)(Ja + k0);
+            bf16x8 bv = *(const bf16x8 *)(Xb + k0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+    } else {
+        const uint8_t *Ja = (const uint8_t *)a.J + (int64_t)row * a.Np + 8 * kg;
+        const bf16 *Xb = a.xb_in + (int64_t)col * a.ld + 8 * kg;
+#pragma unroll 4
+        for (int k0 = 0; k0 < a.Np; k0 += 32) {
+            uint2 raw = *(const uint2 *)(Ja + k0);
+            bf16x8 bv = *(const bf16x8 *)(Xb + k0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fp8x8_to_bf16(raw), bv, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+template <int JT, bool FIELD_ONLY>
+__global__ __launch_bounds__(256) void k_step_dense(DenseArgs a, int64_t q) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * 32 + 16 * (w & 1);
+    const int r0 = blockIdx.y * 32 + 16 * (w >> 1);
+    if (r0 >= a.Rp || i0 >= a.Np) return;
+    f32x4 acc = tile_field<JT>(a, i0, r0, lane);
+    const int col = r0 + (lane & 15);
+    const int ib = i0 + 4 * (lane >> 4);
+    if (col >= a.R || ib >= a.N) return;
+    const int64_t base = (int64_t)col * a.ld + ib;
+    if constexpr (FIELD_ONLY) {
+        *(float4 *)(a.u_out + base) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        return;
+    } else {
+        const StepCoef c = step_coef(a.a32, a.b32, q, a.rg, a.M);
+        float4 x = *(const float4 *)(a.phi_in + base);
+        float4 p = *(const float4 *)(a.p + base);
+        float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w}, xn[4];
+        bool bad = false;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            if (ib + v < a.N) {
+                leapfrog(c, xs[v], acc[v], a.h[ib + v], ps[v], xn[v]);
+                bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
+            } else {
+                xn[v] = 0.0f;
+                ps[v] = 0.0f;
+            }
+        }
+        *(float4 *)(a.phi_out + base) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+        *(float4 *)(a.p + base) = make_float4(ps[0], ps[1], ps[2], ps[3]);
+        if (a.xb_out) {
+            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+            bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
+            *(bf16x4 *)(a.xb_out + base) = b;
+        }
+        if (q + 1 >= a.T - a.W + 1) {
+            float4 s = *(const float4 *)(a.S + base);
+            s.x = s.x + xn[0]; s.y = s.y + xn[1]; s.z = s.z + xn[2]; s.w = s.w + xn[3];
+            *(float4 *)(a.S + base) = s;
+        }
+        if (bad) atomicOr(a.err, ERR_NONFINITE);
+    }
+}
+
+static DenseArgs dense_args(hqa_md *md, Instance &I) {
+    DenseArgs a;
+    a.N = I.N; a.Np = I.Np; a.R = md->R; a.Rp = I.Rp; a.ld = I.ld; a.M = md->sch.M;
+    a.T = md->sch.T; a.W = md->sch.W; a.rg = (float)md->sch.r_g;
+    a.J = I.Js; a.h = I.h32; a.a32 = md->a32; a.b32 = md->b32;
+    a.phi_in = I.phi32[I.cur]; a.xb_in = I.phib[I.cur];
+    a.phi_out = I.phi32[I.cur ^ 1]; a.xb_out = I.phib[I.cur ^ 1];
+    a.p = I.p32; a.S = I.S32; a.u_out = nullptr; a.err = md->err;
+    return a;
+}
+
+template <bool FO>
+static void launch_one(hqa_md *md, const DenseArgs &a, dim3 grid, int64_t q, hipStream_t st) {
+    switch (md->jt) {
+        case JT_F32: k_step_dense<JT_F32, FO><<<grid, 256, 0, st>>>(a, q); break;
+        case JT_BF16: k_step_dense<JT_BF16, FO><<<grid, 256, 0, st>>>(a, q); break;
+        default: k_step_dense<JT_FP8, FO><<<grid, 256, 0, st>>>(a, q); break;
+    }
+}
+
+hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
+    dim3 grid(I.Np / 32, (I.Rp + 31) / 32);
+    for (int64_t q = q0; q < q1; q++) {
+        DenseArgs a = dense_args(md, I);
+        launch_one<false>(md, a, grid, q, md->stream);
+        I.cur ^= 1;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_field_dense(hqa_md *md, Instance &I, float *u, hipStream_t st) {
+    dim3 grid(I.Np / 32, (I.Rp + 31) / 32);
+    DenseArgs a = dense_args(md, I);
+    a.u_out = u;
+    launch_one<true>(md, a, grid, 0, st);
+    return hipGetLastError();
+}
+
+}  // namespace hqa

@@ -1,0 +1,484 @@
+// k_readout.hip -- frozen/ambivalent sort, reduced problem, exact enumeration,
+// merge and exact Ising energies.
+#include <math.h>
+
+#include "exact_acc.h"
+#include "hqa_internal.h"
+
+namespace hqa {
+
+// Position of spin i of replica r in the state arrays.
+__device__ __forceinline__ int64_t sidx(int smaj, int ld, int r, int i) {
+    return smaj ? (int64_t)i * ld + r : (int64_t)r * ld + i;
+}
+
+// ---------------------------------------------------------------------------
+// Sort (Results, "Sorting frozen and ambivalent variables"): per replica the n
+// spins with the smallest |phibar| (ties: lower index) are ambivalent, listed in
+// ascending index; s_i = sgn(phibar_i), sgn(0) = +1.  phibar = S / W in the
+// state's precision.  One workgroup (256 threads) per replica: an MSD radix
+// select over the bit patterns of |phibar| (non-negative floats order as their
+// bit patterns) finds the n-th smallest key K*, then an index-ordered scan takes
+// every key < K* and the lowest-index keys == K* up to n.
+// ---------------------------------------------------------------------------
+struct SelArgs {
+    int N, R, ld, smaj, f64, W, n;
+    const double *S64;
+    const float *S32;
+    int32_t *amb;
+    int8_t *spins;
+};
+
+__device__ __forceinline__ uint64_t sel_key(const SelArgs &a, int r, int i, int8_t *sgn) {
+    if (a.f64) {
+        double pb = a.S64[(int64_t)r * a.N + i] / (double)a.W;
+        if (sgn) *sgn = pb < 0.0 ? -1 : 1;
+        return (uint64_t)__double_as_longlong(fabs(pb));
+    }
+    float pb = a.S32[sidx(a.smaj, a.ld, r, i)] / (float)a.W;
+    if (sgn) *sgn = pb < 0.0f ? -1 : 1;
+    return (uint64_t)__float_as_uint(fabsf(pb));
+}
+
+__global__ __launch_bounds__(256) void k_select(SelArgs a) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t s_prefix;
+    __shared__ int s_k;
+    __shared__ int wsum[2][4];
+    const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // spins
+    for (int i = tid; i < a.N; i += 256) {
+        int8_t s;
+        sel_key(a, r, i, &s);
+        a.spins[(int64_t)r * a.N + i] = s;
+    }
+    if (a.n == 0) return;
+    uint64_t prefix = 0, pmask = 0;
+    if (tid == 0) s_k = a.n;
+    const int passes = a.f64 ? 8 : 4;
+    for (int ps = passes - 1; ps >= 0; ps--) {
+        hist[tid] = 0;
+        __syncthreads();
+        for (int i = tid; i < a.N; i += 256) {
+            uint64_t k = sel_key(a, r, i, nullptr);
+            if ((k & pmask) == prefix) atomicAdd(&hist[(k >> (8 * ps)) & 255], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int k = s_k;
+            int b = 0;
+            while (b < 255 && (int)hist[b] < k) { k -= hist[b]; b++; }
+            s_k = k;
+            s_prefix = prefix | ((uint64_t)b << (8 * ps));
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        pmask |= (uint64_t)255 << (8 * ps);
+    }
+    const uint64_t kstar = prefix;
+    const int m = s_k;  // how many keys equal to K* are taken
+    int eq_run = 0, out_run = 0;
+    for (int c0 = 0; c0 < a.N; c0 += 256) {
+        int i = c0 + tid;
+        uint64_t k = i < a.N ? sel_key(a, r, i, nullptr) : ~0ull;
+        bool eq = i < a.N && k == kstar;
+        bool lt = i < a.N && k < kstar;
+        uint64_t beq = __ballot(eq);
+        uint64_t lanemask = lane ? (~0ull >> (64 - lane)) : 0ull;
+        int eq_before_w = __popcll(beq & lanemask);
+        if (lane == 0) wsum[0][w] = __popcll(beq);
+        __syncthreads();
+        int eq_before = eq_run + eq_before_w;
+        for (int v = 0; v < w; v++) eq_before += wsum[0][v];
+        bool sel = lt || (eq && eq_before < m);
+        uint64_t bsel = __ballot(sel);
+        if (lane == 0) wsum[1][w] = __popcll(bsel);
+        __syncthreads();
+        int pos = out_run + __popcll(bsel & lanemask);
+        for (int v = 0; v < w; v++) pos += wsum[1][v];
+        if (sel && pos < a.n) a.amb[(int64_t)r * a.n + pos] = i;
+        for (int v = 0; v < 4; v++) { eq_run += wsum[0][v]; out_run += wsum[1][v]; }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_select(const Instance &I, int R, int prec, int W, int n, int32_t *amb,
+                         int8_t *spins, hipStream_t st) {
+    SelArgs a;
+    a.N = I.N; a.R = R; a.ld = I.ld; a.smaj = I.smaj; a.f64 = prec == HQA_PREC_F64_REF;
+    a.W = W; a.n = n; a.S64 = I.S64; a.S32 = I.S32; a.amb = amb; a.spins = spins;
+    k_select<<<R, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reduced problem (HQA section, effective couplings): J_eff = J[A, A] and
+// h_eff_a = h_a + sum_{k not in A} J_ak s_k, each h_eff the correctly rounded
+// exact sum.  One wavefront per (replica, ambivalent spin).
+// ---------------------------------------------------------------------------
+struct RedArgs {
+    int N, R, n, csr, b0;
+    const double *J;
+    const int32_t *rp, *ci;
+    const double *h;
+    const int32_t *amb;
+    const int8_t *spins;
+    double *h_eff, *J_eff;
+};
+
+__device__ __forceinline__ bool in_sorted(const int32_t *A, int n, int k) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (A[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < n && A[lo] == k;
+}
+
+__device__ __forceinline__ double jlookup(const RedArgs &a, int i, int j) {
+    if (!a.csr) return a.J[(int64_t)i * a.N + j];
+    int lo = a.rp[i], hi = a.rp[i + 1];
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a.ci[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < a.rp[i + 1] && a.ci[lo] == j) ? a.J[lo] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (wid >= (int64_t)a.R * a.n) return;
+    const int r = (int)(wid / a.n), ai = (int)(wid % a.n);
+    const int32_t *A = a.amb + (int64_t)r * a.n;
+    const int8_t *s = a.spins + (int64_t)r * a.N;
+    const int row = A[ai];
+    if (row < 0 || row >= a.N) return;
+    Acc256 acc;
+    acc_zero(acc);
+    if (lane == 0) acc_add(acc, a.h[row], a.b0);
+    if (!a.csr) {
+        const double *Jr = a.J + (int64_t)row * a.N;
+        for (int k = lane; k < a.N; k += 64)
+            if (!in_sorted(A, a.n, k)) acc_add(acc, Jr[k] * (double)s[k], a.b0);
+    } else {
+        for (int e = a.rp[row] + lane; e < a.rp[row + 1]; e += 64) {
+            int k = a.ci[e];
+            if (!in_sorted(A, a.n, k)) acc_add(acc, a.J[e] * (double)s[k], a.b0);
+        }
+    }
+    acc_wave_allreduce(acc);
+    if (lane == 0) a.h_eff[(int64_t)r * a.n + ai] = acc_round(acc, a.b0);
+    for (int b = lane; b < a.n; b += 64)
+        a.J_eff[((int64_t)r * a.n + ai) * a.n + b] = jlookup(a, row, A[b]);
+}
+
+hipError_t launch_reduce(const Instance &I, int R, int n, const int32_t *amb,
+                         const int8_t *spins, double *h_eff, double *J_eff, hipStream_t st) {
+    RedArgs a;
+    a.N = I.N; a.R = R; a.n = n; a.csr = I.layout == HQA_CSR; a.b0 = I.es.lsb;
+    a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64;
+    a.amb = amb; a.spins = spins; a.h_eff = h_eff; a.J_eff = J_eff;
+    int64_t waves = (int64_t)R * n;
+    if (waves == 0) return hipSuccess;
+    k_reduce<<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exact minimum of the reduced energy E'(c) = sum_{a<b} J_ab x_a x_b + sum_a h_a x_a
+// over all codes c (bit a set: x_a = -1), ties to the smallest code.  One
+// workgroup per replica; thread t fixes the top bits of the code to t and walks
+// the low bits in Gray-code order, updating E' and the local fields
+// f_a = h_a + sum_{b != a} J_ab x_b by one flip per code (dE = -2 x_a f_a).
+// Integer instances run in int64 (exact).  Otherwise pass 1 walks in binary64
+// and pass 2 re-walks, rescoring exactly (fixed-point accumulator, rounded once)
+// every code whose binary64 energy lies within a rigorous error bound of the
+// pass-1 minimum.
+// ---------------------------------------------------------------------------
+#define ENUM_MAXN 24
+#define ENUM_MAXLOW 16
+
+template <typename T>
+struct EnumState {
+    T E;
+    int64_t code;
+};
+
+__device__ __forceinline__ bool better_i(int64_t e1, int64_t c1, int64_t e2, int64_t c2) {
+    return e1 < e2 || (e1 == e2 && c1 < c2);
+}
+__device__ __forceinline__ bool better_d(double e1, int64_t c1, double e2, int64_t c2) {
+    return e1 < e2 || (e1 == e2 && c1 < c2);
+}
+
+struct EnumArgs {
+    int n, R, b0, integral;
+    const double *J_eff, *h_eff;
+    int64_t *code;
+    double *e_red;
+};
+
+template <typename T>
+__device__ __forceinline__ T energy_from_scratch(const T *J, const T *h, int n, uint32_t code) {
+    T E = 0;
+    for (int a = 0; a < n; a++) {
+        T xa = ((code >> a) & 1) ? (T)-1 : (T)1;
+        T acc = 0;
+        for (int b = a + 1; b < n; b++) {
+            T xb = ((code >> b) & 1) ? (T)-1 : (T)1;
+            acc = acc + J[a * n + b] * xb;
+        }
+        E = E + xa * (acc + h[a]);
+    }
+    return E;
+}
+
+__device__ __forceinline__ double energy_exact(const double *J, const double *h, int n,
+                                               uint32_t code, int b0) {
+    Acc256 acc;
+    acc_zero(acc);
+    for (int a = 0; a < n; a++) {
+        double xa = ((code >> a) & 1) ? -1.0 : 1.0;
+        for (int b = a + 1; b < n; b++) {
+            double xb = ((code >> b) & 1) ? -1.0 : 1.0;
+            acc_add(acc, J[a * n + b] * (xa * xb), b0);
+        }
+        acc_add(acc, h[a] * xa, b0);
+    }
+    return acc_round(acc, b0);
+}
+
+// Gray walk over the low `nl` bits with the top bits fixed to `top`.  The visitor
+// sees (energy, code) for every code of the chunk.
+template <typename T, typename Visit>
+__device__ __forceinline__ void gray_walk(const T *J, const T *h, int n, int nl, uint32_t top,
+                                          T *f, Visit visit) {
+    uint32_t code = top << nl;
+    T E = energy_from_scratch<T>(J, h, n, code);
+    for (int a = 0; a < nl; a++) {
+        T acc = h[a];
+        for (int b = 0; b < n; b++)
+            if (b != a) acc = acc + J[a * n + b] * (((code >> b) & 1) ? (T)-1 : (T)1);
+        f[a] = acc;
+    }
+    visit(E, code);
+    const uint32_t cnt = 1u << nl;
+    for (uint32_t k = 1; k < cnt; k++) {
+        int a = __ffs(k) - 1;
+        T xa = ((code >> a) & 1) ? (T)-1 : (T)1;
+        E = E - (T)2 * xa * f[a];
+        for (int b = 0; b < nl; b++)
+            if (b != a) f[b] = f[b] - (T)2 * J[a * n + b] * xa;
+        code ^= 1u << a;
+        visit(E, code);
+    }
+}
+
+template <typename T>
+__device__ void block_argmin(T &E, int64_t &code, T *sE, int64_t *sC) {
+    const int tid = threadIdx.x;
+    sE[tid] = E;
+    sC[tid] = code;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            T e2 = sE[tid + s];
+            int64_t c2 = sC[tid + s];
+            if (e2 < sE[tid] || (e2 == sE[tid] && c2 < sC[tid])) { sE[tid] = e2; sC[tid] = c2; }
+        }
+        __syncthreads();
+    }
+    E = sE[0];
+    code = sC[0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_enumerate(EnumArgs a) {
+    __shared__ double Jd[ENUM_MAXN * ENUM_MAXN], hd[ENUM_MAXN];
+    __shared__ int64_t Ji[ENUM_MAXN * ENUM_MAXN], hi_[ENUM_MAXN];
+    __shared__ double sEd[256];
+    __shared__ int64_t sEi[256], sC[256];
+    __shared__ double sS[256];
+    const int r = blockIdx.x, tid = threadIdx.x, n = a.n;
+    for (int k = tid; k < n * n; k += 256) {
+        double v = a.J_eff[(int64_t)r * n * n + k];
+        Jd[k] = v;
+        Ji[k] = (int64_t)v;
+    }
+    for (int k = tid; k < n; k += 256) {
+        double v = a.h_eff[(int64_t)r * n + k];
+        hd[k] = v;
+        hi_[k] = (int64_t)v;
+    }
+    __syncthreads();
+    const int ptop = n < 8 ? n : 8;
+    const int nl = n - ptop;
+    const bool active = tid < (1 << ptop);
+    if (a.integral) {
+        int64_t f[ENUM_MAXLOW];
+        int64_t bestE = INT64_MAX, bestC = INT64_MAX;
+        if (active)
+            gray_walk<int64_t>(Ji, hi_, n, nl, (uint32_t)tid, f, [&](int64_t E, uint32_t c) {
+                if (better_i(E, c, bestE, bestC)) { bestE = E; bestC = c; }
+            });
+        block_argmin<int64_t>(bestE, bestC, sEi, sC);
+        if (tid == 0) {
+            a.code[r] = bestC;
+            a.e_red[r] = (double)bestE;
+        }
+        return;
+    }
+    // binary64 pass 1
+    double f[ENUM_MAXLOW];
+    double bestE = INFINITY;
+    int64_t bestC = INT64_MAX;
+    if (active)
+        gray_walk<double>(Jd, hd, n, nl, (uint32_t)tid, f, [&](double E, uint32_t c) {
+            if (better_d(E, c, bestE, bestC)) { bestE = E; bestC = c; }
+        });
+    block_argmin<double>(bestE, bestC, sEd, sC);
+    // rigorous bound on |E_binary64 - E_exact| along a walk of K = 2^nl codes:
+    // u S (m + K (2n + 1) + K^2) with S = sum |J_ab| (a<b) + sum |h_a|, m the term
+    // count, u = 2^-53; doubled, plus the rounding of the exact values themselves.
+    double Ssum = 0.0;
+    for (int k = tid; k < n * n; k += 256) {
+        int aa = k / n, bb = k % n;
+        if (bb > aa) Ssum += fabs(Jd[k]);
+    }
+    for (int k = tid; k < n; k += 256) Ssum += fabs(hd[k]);
+    sS[tid] = Ssum;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) sS[tid] += sS[tid + s];
+        __syncthreads();
+    }
+    const double S = sS[0] * (1.0 + 1e-12);
+    const double K = (double)(1u << nl);
+    const double mterms = (double)(n * (n - 1) / 2 + n);
+    const double u = 1.1102230246251565e-16;
+    const double delta = u * S * (mterms + K * (2.0 * n + 1.0) + K * K);
+    const double thresh = bestE + 2.0 * delta + 4.0 * u * S;
+    // pass 2: exact rescoring of the candidates
+    double xE = INFINITY;
+    int64_t xC = INT64_MAX;
+    if (active)
+        gray_walk<double>(Jd, hd, n, nl, (uint32_t)tid, f, [&](double E, uint32_t c) {
+            if (E <= thresh) {
+                double ex = energy_exact(Jd, hd, n, c, a.b0);
+                if (better_d(ex, c, xE, xC)) { xE = ex; xC = c; }
+            }
+        });
+    block_argmin<double>(xE, xC, sEd, sC);
+    if (tid == 0) {
+        a.code[r] = xC;
+        a.e_red[r] = xE;
+    }
+}
+
+hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_eff, int b0,
+                            int integral, int64_t *code, double *e_red, hipStream_t st) {
+    EnumArgs a;
+    a.n = n; a.R = R; a.b0 = b0; a.integral = integral;
+    a.J_eff = J_eff; a.h_eff = h_eff; a.code = code; a.e_red = e_red;
+    k_enumerate<<<R, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+__global__ void k_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
+                        int8_t *spins) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)R * n) return;
+    int r = (int)(t / n), ai = (int)(t % n);
+    int i = amb[t];
+    if (i < 0 || i >= N) return;
+    spins[(int64_t)r * N + i] = ((code[r] >> ai) & 1) ? -1 : 1;
+}
+
+hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
+                        int8_t *spins, hipStream_t st) {
+    int64_t t = (int64_t)R * n;
+    if (t == 0) return hipSuccess;
+    k_merge<<<(unsigned)((t + 255) / 256), 256, 0, st>>>(N, R, n, amb, code, spins);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exact Ising energy (Eq. 1) and cut (Methods, MAX-CUT with w = J).  The sum over
+// ordered pairs i != j counts each pair twice, so 2E = sum_{i!=j} J s s + 2 sum h s
+// and 2C = sum_{i!=j, s_i != s_j} J are accumulated exactly and rounded with the
+// scale halved.  One workgroup per spin vector.
+// ---------------------------------------------------------------------------
+struct EnArgs {
+    int N, V, csr, b0;
+    const double *J;
+    const int32_t *rp, *ci;
+    const double *h;
+    const int8_t *spins;
+    double *E, *cut;
+};
+
+__device__ void block_acc_reduce(Acc256 &acc, Acc256 *sh) {
+    acc_wave_allreduce(acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int v = 1; v < (int)(blockDim.x >> 6); v++) acc_merge(acc, sh[v]);
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_energy(EnArgs a) {
+    __shared__ Acc256 sh[4];
+    const int v = blockIdx.x, tid = threadIdx.x;
+    const int8_t *s = a.spins + (int64_t)v * a.N;
+    Acc256 ae, ac;
+    acc_zero(ae);
+    acc_zero(ac);
+    const int b0 = a.b0;
+    if (!a.csr) {
+        const int64_t tot = (int64_t)a.N * a.N;
+        for (int64_t t = tid; t < tot; t += 256) {
+            int i = (int)(t / a.N), j = (int)(t % a.N);
+            double J = a.J[t];
+            if (J == 0.0) continue;
+            int si = s[i], sj = s[j];
+            acc_add(ae, si == sj ? J : -J, b0);
+            if (si != sj) acc_add(ac, J, b0);
+        }
+    } else {
+        for (int i = tid; i < a.N; i += 256) {
+            int si = s[i];
+            for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
+                double J = a.J[e];
+                int sj = s[a.ci[e]];
+                acc_add(ae, si == sj ? J : -J, b0);
+                if (si != sj) acc_add(ac, J, b0);
+            }
+        }
+    }
+    for (int i = tid; i < a.N; i += 256) {
+        double hh = a.h[i];
+        if (hh != 0.0) acc_add(ae, s[i] > 0 ? 2.0 * hh : -2.0 * hh, b0);
+    }
+    block_acc_reduce(ae, sh);
+    block_acc_reduce(ac, sh);
+    if (tid == 0) {
+        if (a.E) a.E[v] = acc_round(ae, b0 - 1);
+        if (a.cut) a.cut[v] = acc_round(ac, b0 - 1);
+    }
+}
+
+hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
+                         hipStream_t st) {
+    EnArgs a;
+    a.N = I.N; a.V = V; a.csr = I.layout == HQA_CSR; a.b0 = I.es.lsb;
+    a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64; a.spins = spins; a.E = E; a.cut = cut;
+    if (V == 0) return hipSuccess;
+    k_energy<<<V, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace hqa

@@ -1,0 +1,46 @@
+// md_epilogue.h -- the fused leapfrog update of the binary32 paths.
+//
+// Given the local field u = sum_j J_ij phi_j of one (spin, replica) the force of
+// Eq. 3 is F = alpha M phi^(M-1) + beta (u + 2 h |phi|) (times r_g), the kick is
+// p -= F (F/2 on the initial half step, q = 0) and the drift is
+// phi' = phi + alpha_(q+1/2) p (Methods, "Leapfrog algorithm").  The operation
+// order is the same in every binary32 kernel (the library is built without fp
+// contraction), so per-step and persistent launches give identical results.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hqa {
+
+struct StepCoef {
+    float al, be;     // alpha, beta at tau = q/T
+    float ad;         // alpha at tau = (q + 1/2)/T, times r_g
+    float rg;
+    float kick;       // 0.5 at q = 0, else 1
+    int M;
+};
+
+__device__ __forceinline__ void leapfrog(const StepCoef &c, float x, float u, float h, float &p,
+                                         float &xn) {
+    float v = x;
+    for (int k = 0; k < c.M - 2; k++) v = v * x;
+    float g = u + (2.0f * h) * fabsf(x);
+    float F = (c.al * ((float)c.M * v)) + (c.be * g);
+    if (c.rg != 1.0f) F = c.rg * F;
+    p = p - c.kick * F;
+    xn = x + c.ad * p;
+}
+
+__device__ __forceinline__ StepCoef step_coef(const float *a32, const float *b32, int64_t q,
+                                              float rg, int M) {
+    StepCoef c;
+    c.al = a32[2 * q];
+    c.be = b32[2 * q];
+    c.ad = a32[2 * q + 1];
+    if (rg != 1.0f) c.ad = rg * c.ad;
+    c.rg = rg;
+    c.kick = q == 0 ? 0.5f : 1.0f;
+    c.M = M;
+    return c;
+}
+
+}  // namespace hqa

@@ -1,0 +1,302 @@
+"""Thin ctypes binding of ``include/hqa.h`` (libhqa.so).
+
+The functions carry the C names and only marshal arguments: every step of the
+method runs in the HIP library.  There is no fallback: if ``libhqa.so`` is not
+built, :func:`lib` raises.  Arrays may be numpy (host memory, ``mem=HQA_HOST``)
+or torch CUDA tensors (device memory via ``data_ptr()``, ``mem=HQA_DEVICE``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HQA_OK, HQA_EINVAL, HQA_ENOMEM, HQA_EDEVICE = 0, -1, -2, -3
+HQA_EUNSUPPORTED, HQA_ENONFINITE, HQA_ESTATE = -4, -5, -6
+HQA_DENSE, HQA_CSR = 0, 1
+HQA_HOST, HQA_DEVICE = 0, 1
+HQA_PREC_F64_REF, HQA_PREC_F32, HQA_PREC_BF16, HQA_PREC_FP8J_BF16 = 0, 1, 2, 3
+HQA_STATE_PHI, HQA_STATE_P, HQA_STATE_PHIBAR, HQA_STATE_WSUM = 0, 1, 2, 3
+PRECISIONS = {"f64": HQA_PREC_F64_REF, "f32": HQA_PREC_F32, "bf16": HQA_PREC_BF16,
+              "fp8": HQA_PREC_FP8J_BF16}
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhqa.so")
+EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md_opts_default",
+            "hqa_md_init", "hqa_md_run", "hqa_md_sync", "hqa_md_step_index", "hqa_md_state",
+            "hqa_md_set_step", "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify",
+            "hqa_ising_energy", "hqa_md_destroy")
+
+
+class HQAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hqa status {status}: {msg}")
+        self.status = status
+
+
+class hqa_problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("layout", C.c_int32), ("mem", C.c_int32),
+                ("reserved", C.c_int32), ("j", C.c_void_p), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("nnz", C.c_int64), ("h", C.c_void_p)]
+
+
+class hqa_schedule(C.Structure):
+    _fields_ = [("alpha_f", C.c_double), ("rho1", C.c_double), ("rho2", C.c_double),
+                ("beta_f", C.c_double), ("kappa1", C.c_double), ("kappa2", C.c_double),
+                ("T", C.c_int64), ("M", C.c_int32), ("W", C.c_int32), ("r_g", C.c_double),
+                ("frozen", C.c_int32), ("reserved", C.c_int32), ("tau_frozen", C.c_double)]
+
+
+class hqa_md_opts(C.Structure):
+    _fields_ = [("replicas", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
+                ("p0", C.c_void_p), ("phi0", C.c_void_p), ("init_mem", C.c_int32),
+                ("require_exact", C.c_int32), ("persistent", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class hqa_classify_out(C.Structure):
+    _fields_ = [("spins", C.c_void_p), ("amb_idx", C.c_void_p), ("energy", C.c_void_p),
+                ("cut", C.c_void_p), ("h_eff", C.c_void_p), ("code", C.c_void_p),
+                ("e_reduced", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhqa.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(_LIB_PATH)
+        P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.hqa_abi_version.restype = i32
+        L.hqa_last_error.restype = C.c_char_p
+        L.hqa_schedule_default.argtypes = [P]
+        L.hqa_md_opts_default.argtypes = [P]
+        L.hqa_md_init.argtypes = [P, i32, P, P, P, P]
+        L.hqa_md_run.argtypes = [P, i64]
+        L.hqa_md_sync.argtypes = [P]
+        L.hqa_md_step_index.argtypes = [P]
+        L.hqa_md_step_index.restype = i64
+        L.hqa_md_state.argtypes = [P, i32, i32, P, i32, i32]
+        L.hqa_md_set_step.argtypes = [P, i64]
+        L.hqa_md_field.argtypes = [P, i32, P, i32]
+        L.hqa_md_hamiltonian.argtypes = [P, i32, P, i32]
+        L.hqa_classify.argtypes = [P, i32, i32, i32, P, i32]
+        L.hqa_ising_energy.argtypes = [P, P, i32, P, P, i32, P]
+        L.hqa_md_destroy.argtypes = [P]
+        for f in ("hqa_md_init", "hqa_md_run", "hqa_md_sync", "hqa_md_state", "hqa_md_set_step",
+                  "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify", "hqa_ising_energy"):
+            getattr(L, f).restype = C.c_int
+        if L.hqa_abi_version() != 1:
+            raise ImportError("libhqa ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != HQA_OK:
+        raise HQAError(status, lib().hqa_last_error().decode())
+
+
+def _addr(a):
+    """(address, keepalive) of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None, None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data, a
+    return a.data_ptr(), a
+
+
+# ---------------------------------------------------------------- C-named calls
+def hqa_abi_version() -> int:
+    return lib().hqa_abi_version()
+
+
+def hqa_last_error() -> str:
+    return lib().hqa_last_error().decode()
+
+
+def hqa_schedule_default() -> hqa_schedule:
+    s = hqa_schedule()
+    lib().hqa_schedule_default(C.byref(s))
+    return s
+
+
+def hqa_md_opts_default() -> hqa_md_opts:
+    o = hqa_md_opts()
+    lib().hqa_md_opts_default(C.byref(o))
+    return o
+
+
+def hqa_md_init(probs, sched: hqa_schedule, opts: hqa_md_opts, stream: int = 0):
+    arr = (hqa_problem * len(probs))(*probs)
+    h = C.c_void_p()
+    _check(lib().hqa_md_init(arr, len(probs), C.byref(sched), C.byref(opts), stream or None,
+                             C.byref(h)))
+    return h
+
+
+def hqa_md_run(md, until_step: int = -1):
+    _check(lib().hqa_md_run(md, until_step))
+
+
+def hqa_md_sync(md):
+    _check(lib().hqa_md_sync(md))
+
+
+def hqa_md_step_index(md) -> int:
+    return lib().hqa_md_step_index(md)
+
+
+def hqa_md_set_step(md, q: int):
+    _check(lib().hqa_md_set_step(md, q))
+
+
+def hqa_md_state(md, instance: int, what: int, dst, dst_mem: int, import_: int = 0):
+    p, _k = _addr(dst)
+    _check(lib().hqa_md_state(md, instance, what, p, dst_mem, import_))
+
+
+def hqa_md_field(md, instance: int, u, dst_mem: int):
+    p, _k = _addr(u)
+    _check(lib().hqa_md_field(md, instance, p, dst_mem))
+
+
+def hqa_md_hamiltonian(md, instance: int, H, dst_mem: int):
+    p, _k = _addr(H)
+    _check(lib().hqa_md_hamiltonian(md, instance, p, dst_mem))
+
+
+def hqa_classify(md, instance: int, n_amb: int, solve: int, out: hqa_classify_out, out_mem: int):
+    _check(lib().hqa_classify(md, instance, n_amb, solve, C.byref(out), out_mem))
+
+
+def hqa_ising_energy(prob: hqa_problem, spins, n_vectors: int, energy, cut, mem: int,
+                     stream: int = 0):
+    sp, _a = _addr(spins)
+    ep, _b = _addr(energy)
+    cp, _c = _addr(cut)
+    _check(lib().hqa_ising_energy(C.byref(prob), sp, n_vectors, ep, cp, mem, stream or None))
+
+
+def hqa_md_destroy(md):
+    lib().hqa_md_destroy(md)
+
+
+# ------------------------------------------------------ marshalling conveniences
+class Problem:
+    """Owns host copies of an instance and its hqa_problem descriptor (host memory)."""
+
+    def __init__(self, J=None, h=None, row_ptr=None, col=None, val=None, n=None):
+        if J is not None:
+            self.J = np.ascontiguousarray(J, dtype=np.float64)
+            N = self.J.shape[0]
+            self.c = hqa_problem(N, HQA_DENSE, HQA_HOST, 0, self.J.ctypes.data, None, None,
+                                 N * N, None)
+        else:
+            self.rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+            self.col = np.ascontiguousarray(col, dtype=np.int32)
+            self.val = np.ascontiguousarray(val, dtype=np.float64)
+            N = len(self.rp) - 1 if n is None else n
+            self.c = hqa_problem(N, HQA_CSR, HQA_HOST, 0, self.val.ctypes.data,
+                                 self.rp.ctypes.data, self.col.ctypes.data, self.val.size, None)
+        self.h = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
+        if self.h is not None:
+            self.c.h = self.h.ctypes.data
+        self.n = N
+
+
+def make_schedule(T: int, W: int = 100, M: int = 6, r_g: float = 1.0, params=None,
+                  frozen: bool = False, tau_frozen: float = 0.0) -> hqa_schedule:
+    s = hqa_schedule_default()
+    if params is not None:
+        (s.alpha_f, s.rho1, s.rho2, s.beta_f, s.kappa1, s.kappa2) = params
+    s.T, s.W, s.M, s.r_g, s.frozen, s.tau_frozen = T, W, M, r_g, int(frozen), tau_frozen
+    return s
+
+
+class MD:
+    """A handle over hqa_md_* calls with numpy in/out (host memory)."""
+
+    def __init__(self, problems, sched: hqa_schedule, replicas: int, precision="f32", seed=0,
+                 p0=None, phi0=None, require_exact=False, persistent=True, stream: int = 0):
+        self.problems = problems if isinstance(problems, (list, tuple)) else [problems]
+        o = hqa_md_opts_default()
+        o.replicas = replicas
+        o.precision = PRECISIONS.get(precision, precision)
+        o.seed = seed
+        o.require_exact = int(require_exact)
+        o.persistent = int(persistent)
+        self._p0 = None if p0 is None else np.ascontiguousarray(p0, dtype=np.float64)
+        self._phi0 = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.float64)
+        o.p0 = None if self._p0 is None else self._p0.ctypes.data
+        o.phi0 = None if self._phi0 is None else self._phi0.ctypes.data
+        o.init_mem = HQA_HOST
+        self.R = replicas
+        self.T = sched.T
+        self.h = hqa_md_init([p.c for p in self.problems], sched, o, stream)
+
+    def close(self):
+        if self.h:
+            hqa_md_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, until=-1):
+        hqa_md_run(self.h, until)
+
+    def sync(self):
+        hqa_md_sync(self.h)
+
+    @property
+    def step(self) -> int:
+        return hqa_md_step_index(self.h)
+
+    def state(self, what: int, k: int = 0) -> np.ndarray:
+        out = np.empty((self.R, self.problems[k].n))
+        hqa_md_state(self.h, k, what, out, HQA_HOST)
+        return out
+
+    def set_state(self, what: int, x, k: int = 0):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        hqa_md_state(self.h, k, what, x, HQA_HOST, 1)
+
+    def field(self, k: int = 0) -> np.ndarray:
+        out = np.empty((self.R, self.problems[k].n))
+        hqa_md_field(self.h, k, out, HQA_HOST)
+        return out
+
+    def hamiltonian(self, k: int = 0) -> np.ndarray:
+        out = np.empty(self.R)
+        hqa_md_hamiltonian(self.h, k, out, HQA_HOST)
+        return out
+
+    def classify(self, n_amb: int, solve: bool = False, k: int = 0) -> dict:
+        N, R = self.problems[k].n, self.R
+        res = dict(spins=np.empty((R, N), dtype=np.int8),
+                   amb_idx=np.empty((R, max(n_amb, 1)), dtype=np.int32),
+                   energy=np.empty(R), cut=np.empty(R),
+                   h_eff=np.empty((R, max(n_amb, 1))), code=np.full(R, -1, dtype=np.int64),
+                   e_reduced=np.full(R, np.nan))
+        o = hqa_classify_out(*(res[f].ctypes.data for f in
+                               ("spins", "amb_idx", "energy", "cut", "h_eff", "code", "e_reduced")))
+        hqa_classify(self.h, k, n_amb, int(solve), o, HQA_HOST)
+        res["amb_idx"] = res["amb_idx"][:, :n_amb]
+        res["h_eff"] = res["h_eff"][:, :n_amb]
+        return res
+
+
+def ising_energy(problem: Problem, spins) -> tuple[np.ndarray, np.ndarray]:
+    spins = np.ascontiguousarray(np.atleast_2d(spins), dtype=np.int8)
+    V = spins.shape[0]
+    E, cut = np.empty(V), np.empty(V)
+    hqa_ising_energy(problem.c, spins, V, E, cut, HQA_HOST)
+    return E, cut

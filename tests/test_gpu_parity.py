@@ -1,0 +1,302 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: bit-exact for the binary64 reference mode (fluxes, window means, sort,
+effective fields, enumeration, energies) and for every integer/index output;
+binary32 fields within 1e-5 of the FP64 field relative to its largest magnitude
+(max |u32 - u64| / max |u64|) for the same fluxes; read-out of a binary32 run
+compared with the oracle's read-out of the same exported window means.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2004_03972_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    from paper_2004_03972_amd import hqa
+    hqa.lib()
+    return hqa
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+LINEAR = (0.008, 4.0, 0.0, 0.12, 0.05, 0.0)
+
+
+def _oracle_run(pb, T, W, sched, p0, phi0=None, M=6, r_g=1.0):
+    mp = orc.MDParams(T=T, W=W, M=M, r_g=r_g, schedule=sched)
+    phi0 = np.zeros_like(p0) if phi0 is None else phi0
+    return orc.md_run(pb, mp, phi0, p0, nthreads=8), mp
+
+
+# ------------------------------------------------------------ binary64 reference
+@pytest.mark.parametrize("sched", ["linear", "paper"])
+def test_f64_ref_sk64_bit_exact(H, sched):
+    # SK, N = 64, J ~ N(0, 1/N), 8 replicas, 2000 steps, n = 12 (small SK case)
+    N, R, T, W, n = 64, 8, 2000, 100, 12
+    prm = LINEAR if sched == "linear" else orc.PAPER_SCHEDULE
+    J = inst.sk(N, 101)
+    _say("f64 ref SK64", sched)
+    md = H.MD(H.Problem(J), H.make_schedule(T, W, params=prm), R, "f64", seed=1)
+    md.run()
+    md.sync()
+    p0 = orc.init_p0(1, N, R)
+    (bar, phiT, pT), mp = _oracle_run(orc.Problem(N, J=J), T, W, prm, p0)
+    assert np.array_equal(md.state(H.HQA_STATE_PHI), phiT)
+    assert np.array_equal(md.state(H.HQA_STATE_P), pT)
+    assert np.array_equal(md.state(H.HQA_STATE_PHIBAR), bar)
+    g = md.classify(n, solve=True)
+    A, s_md = orc.classify(bar, n)
+    he, Je = orc.reduce(orc.Problem(N, J=J), A, s_md)
+    code, Ered = orc.enumerate_exact(Je, he)
+    s_hqa = orc.merge(s_md, A, code)
+    E, C = orc.energy(orc.Problem(N, J=J), s_hqa)
+    assert np.array_equal(g["amb_idx"], A)
+    assert np.array_equal(g["h_eff"], he)
+    assert np.array_equal(g["code"], code)
+    assert np.array_equal(g["e_reduced"], Ered)
+    assert np.array_equal(g["spins"], s_hqa)
+    assert np.array_equal(g["energy"], E) and np.array_equal(g["cut"], C)
+    g0 = md.classify(n, solve=False)
+    E0, C0 = orc.energy(orc.Problem(N, J=J), s_md)
+    assert np.array_equal(g0["spins"], s_md)
+    assert np.array_equal(g0["energy"], E0) and np.array_equal(g0["cut"], C0)
+    assert np.all(g["energy"] <= g0["energy"])
+    md.close()
+
+
+def test_f64_ref_csr_field_and_explicit_init(H):
+    # EA +-J lattice (CSR) and the uniform glass with a field (dense), explicit
+    # phi0 != 0 and p0, r_g != 1, M = 4: every branch of the reference step.
+    rp, ci, v = inst.ea3d(4, 7)
+    N, R, T, W = 64, 3, 300, 40
+    rng = np.random.default_rng(3)
+    p0 = inst.random_pm1((R, N), 5)
+    phi0 = rng.uniform(-0.2, 0.2, size=(R, N))
+    md = H.MD(H.Problem(row_ptr=rp, col=ci, val=v), H.make_schedule(T, W, M=4, r_g=0.7), R,
+              "f64", p0=p0, phi0=phi0)
+    md.run()
+    (bar, phiT, pT), _ = _oracle_run(orc.Problem(N, row_ptr=rp, col=ci, val=v), T, W,
+                                     orc.PAPER_SCHEDULE, p0, phi0, M=4, r_g=0.7)
+    assert np.array_equal(md.state(H.HQA_STATE_PHI), phiT)
+    assert np.array_equal(md.state(H.HQA_STATE_PHIBAR), bar)
+    J, h = inst.uniform_glass(50, 9)
+    md = H.MD(H.Problem(J, h=h), H.make_schedule(T, W), 5, "f64", seed=77)
+    md.run()
+    (bar, phiT, pT), _ = _oracle_run(orc.Problem(50, J=J, h=h), T, W, orc.PAPER_SCHEDULE,
+                                     orc.init_p0(77, 50, 5))
+    assert np.array_equal(md.state(H.HQA_STATE_PHI), phiT)
+    assert np.array_equal(md.state(H.HQA_STATE_P), pT)
+    g = md.classify(10, solve=True)
+    A, s = orc.classify(bar, 10)
+    he, Je = orc.reduce(orc.Problem(50, J=J, h=h), A, s)
+    code, Ered = orc.enumerate_exact(Je, he)
+    assert np.array_equal(g["h_eff"], he) and np.array_equal(g["code"], code)
+    assert np.array_equal(g["e_reduced"], Ered)
+    E, C = orc.energy(orc.Problem(50, J=J, h=h), orc.merge(s, A, code))
+    assert np.array_equal(g["energy"], E)
+
+
+def test_f64_hamiltonian_matches_oracle(H):
+    N, R, T = 40, 4, 200
+    J, h = inst.uniform_glass(N, 13)
+    prm = (0.03, 0.0, 0.0, 0.05, 0.0, 0.0)
+    s = H.make_schedule(T, 1, params=prm, frozen=True, tau_frozen=1.0)
+    md = H.MD(H.Problem(J, h=h), s, R, "f64", seed=4)
+    mp = orc.MDParams(T=T, W=1, schedule=prm, frozen=True, tau_fix=1.0)
+    pb = orc.Problem(N, J=J, h=h)
+    phi, p = np.zeros((R, N)), orc.init_p0(4, N, R)
+    Hg0 = md.hamiltonian()
+    assert np.allclose(Hg0, orc.hmd(pb, mp, 0, phi, p), rtol=1e-13, atol=1e-15)
+    md.run(150)
+    orc.md_advance(pb, mp, phi, p, None, 0, 150)
+    Ho = orc.hmd(pb, mp, 150, phi, orc.integer_p(pb, mp, 150, phi, p))
+    Hg = md.hamiltonian()
+    assert np.allclose(Hg, Ho, rtol=1e-12, atol=1e-14)
+    assert np.max(np.abs(Hg - Hg0)) < 5e-2 * np.max(np.abs(Hg0))   # bounded drift
+
+
+# ------------------------------------------------------------- binary32 fields
+def _shared_phi(R, N, seed):
+    return np.random.default_rng(seed).uniform(-1.2, 1.2, size=(R, N))
+
+
+@pytest.mark.parametrize("N,R", [(200, 40), (64, 16), (800, 256), (1000, 64)])
+def test_f32_dense_field_within_1e5(H, N, R):
+    J = inst.sk(N, 300 + N)
+    md = H.MD(H.Problem(J), H.make_schedule(10, 5), R, "f32")
+    phi = _shared_phi(R, N, N).astype(np.float32).astype(np.float64)
+    md.set_state(H.HQA_STATE_PHI, phi)
+    u = md.field()
+    u64 = phi @ J.T
+    rel = np.max(np.abs(u - u64)) / np.max(np.abs(u64))
+    _say("dense f32 field rel err", N, R, rel)
+    assert rel <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_lowp_dense_field(H, prec):
+    # BF16 operand: the GPU field equals J . bf16(phi) up to FP32 accumulation.
+    N, R = 520, 48
+    J = inst.small_int(N, 400, -2, 2, density=0.3)
+    md = H.MD(H.Problem(J), H.make_schedule(10, 5), R, prec, require_exact=True)
+    phi = _shared_phi(R, N, 401)
+    md.set_state(H.HQA_STATE_PHI, phi)
+    u = md.field()
+    import torch
+    phib = torch.tensor(phi, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+    u64 = phib @ J.T
+    assert np.max(np.abs(u - u64)) / np.max(np.abs(u64)) <= 1e-5
+    uf = phi @ J.T
+    _say(prec, "max |dh| vs fp64 phi", np.max(np.abs(u - uf)))
+
+
+def test_csr_f32_field_within_1e5(H):
+    rp, ci, v = inst.ea3d(16, 301)
+    N, R = 4096, 100
+    md = H.MD(H.Problem(row_ptr=rp, col=ci, val=v), H.make_schedule(10, 5), R, "f32")
+    phi = _shared_phi(R, N, 5).astype(np.float32).astype(np.float64)
+    md.set_state(H.HQA_STATE_PHI, phi)
+    u = md.field()
+    Jd = inst.csr_to_dense(N, rp, ci, v)
+    u64 = phi @ Jd.T
+    assert np.max(np.abs(u - u64)) / np.max(np.abs(u64)) <= 1e-5
+
+
+def test_bf16_and_fp8_storage_give_identical_runs(H):
+    # +-1 / 0 couplings are exact in both BF16 and FP8 e4m3, so the two storage
+    # forms must give bit-identical trajectories.
+    N, R, T = 300, 32, 400
+    J = inst.er_maxcut(N, 0.06, 500)
+    out = []
+    for prec in ("bf16", "fp8"):
+        md = H.MD(H.Problem(J), H.make_schedule(T, 50), R, prec, seed=3, require_exact=True)
+        md.run()
+        md.sync()
+        out.append((md.state(H.HQA_STATE_PHI), md.state(H.HQA_STATE_PHIBAR)))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "fp8"])
+def test_z2_symmetry_all_precisions(H, prec):
+    # h = 0: p0 -> -p0 gives phi -> -phi exactly (round-to-nearest-even is odd).
+    N, R, T = 96, 16, 300
+    J = inst.er_maxcut(N, 0.1, 600)
+    p0 = orc.init_p0(9, N, R)
+    res = []
+    for sgn in (1, -1):
+        md = H.MD(H.Problem(J), H.make_schedule(T, 30), R, prec, p0=sgn * p0)
+        md.run()
+        res.append(md.state(H.HQA_STATE_PHI))
+    assert np.array_equal(res[0], -res[1])
+
+
+# ------------------------------------------------------- read-out of FP32 runs
+@pytest.mark.parametrize("layout", ["dense", "csr"])
+def test_f32_readout_matches_oracle_on_same_phibar(H, layout):
+    N, R, T, n = 180, 20, 600, 14
+    J = inst.er_maxcut(N, 0.08, 700)
+    if layout == "dense":
+        P, pb = H.Problem(J), orc.Problem(N, J=J)
+    else:
+        rp, ci, v = inst.dense_to_csr(J)
+        P, pb = H.Problem(row_ptr=rp, col=ci, val=v), orc.Problem(N, row_ptr=rp, col=ci, val=v)
+    md = H.MD(P, H.make_schedule(T, 60), R, "f32", seed=11)
+    md.run()
+    g = md.classify(n, solve=True)
+    bar = md.state(H.HQA_STATE_PHIBAR)
+    A, s = orc.classify(bar, n)
+    he, Je = orc.reduce(pb, A, s)
+    code, Ered = orc.enumerate_exact(Je, he)
+    sh = orc.merge(s, A, code)
+    E, C = orc.energy(pb, sh)
+    assert np.array_equal(g["amb_idx"], A) and np.array_equal(g["h_eff"], he)
+    assert np.array_equal(g["code"], code) and np.array_equal(g["e_reduced"], Ered)
+    assert np.array_equal(g["spins"], sh)
+    assert np.array_equal(g["energy"], E) and np.array_equal(g["cut"], C)
+
+
+# --------------------------------------------------------------- exact energies
+@pytest.mark.parametrize("kind", ["sk", "int", "glass", "csr"])
+def test_ising_energy_exact(H, kind):
+    N = 333
+    h = None
+    if kind == "sk":
+        J = inst.sk(N, 800)
+    elif kind == "int":
+        J = inst.small_int(N, 801, -5, 5, density=0.5)
+    else:
+        J, h = inst.uniform_glass(N, 802)
+    spins = inst.random_pm1((7, N), 803).astype(np.int8)
+    if kind == "csr":
+        rp, ci, v = inst.dense_to_csr(J)
+        P = H.Problem(row_ptr=rp, col=ci, val=v, h=h)
+        pb = orc.Problem(N, row_ptr=rp, col=ci, val=v, h=h)
+    else:
+        P, pb = H.Problem(J, h=h), orc.Problem(N, J=J, h=h)
+    E, C = H.ising_energy(P, spins)
+    Eo, Co = orc.energy(pb, spins)
+    assert np.array_equal(E, Eo) and np.array_equal(C, Co)
+
+
+# ------------------------------------------------------ determinism and resume
+def test_checkpoint_resume_bit_identical(H):
+    N, R, T = 160, 24, 500
+    J = inst.sk(N, 900)
+    for prec in ("f64", "f32", "bf16"):
+        a = H.MD(H.Problem(J), H.make_schedule(T, 100), R, prec, seed=5)
+        a.run()
+        b = H.MD(H.Problem(J), H.make_schedule(T, 100), R, prec, seed=5)
+        b.run(T // 2 + 37)
+        ck = {w: b.state(w) for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM)}
+        c = H.MD(H.Problem(J), H.make_schedule(T, 100), R, prec, seed=99)
+        for w, x in ck.items():
+            c.set_state(w, x)
+        H.hqa_md_set_step(c.h, T // 2 + 37)
+        c.run()
+        assert np.array_equal(a.state(H.HQA_STATE_PHIBAR), c.state(H.HQA_STATE_PHIBAR)), prec
+        assert np.array_equal(a.state(H.HQA_STATE_PHI), c.state(H.HQA_STATE_PHI)), prec
+
+
+# ------------------------------------------------------------------ error paths
+def test_error_paths(H):
+    N = 30
+    J = inst.sk(N, 1000)
+    bad = J.copy(); bad[0, 1] += 1.0
+    with pytest.raises(H.HQAError) as e:
+        H.MD(H.Problem(bad), H.make_schedule(10, 5), 2, "f32")
+    assert e.value.status == H.HQA_EINVAL
+    bad = J.copy(); bad[3, 3] = 1.0
+    with pytest.raises(H.HQAError) as e:
+        H.MD(H.Problem(bad), H.make_schedule(10, 5), 2, "f32")
+    assert e.value.status == H.HQA_EINVAL
+    with pytest.raises(H.HQAError) as e:
+        H.MD(H.Problem(J), H.make_schedule(10, 5), 2, "fp8", require_exact=True)
+    assert e.value.status == H.HQA_EUNSUPPORTED
+    md = H.MD(H.Problem(J), H.make_schedule(10, 5), 2, "f32")
+    with pytest.raises(H.HQAError) as e:
+        md.classify(3)
+    assert e.value.status == H.HQA_ESTATE
+    md.run()
+    with pytest.raises(H.HQAError) as e:
+        md.classify(25, solve=True)
+    assert e.value.status == H.HQA_EUNSUPPORTED
+    with pytest.raises(H.HQAError) as e:
+        md.classify(N + 1)
+    assert e.value.status == H.HQA_EINVAL
+    # a flux poisoned from the host overflows phi^5 -> non-finite flag at sync
+    md = H.MD(H.Problem(J), H.make_schedule(10, 5), 2, "f32")
+    md.set_state(H.HQA_STATE_PHI, np.full((2, N), 1e30))
+    md.run()
+    with pytest.raises(H.HQAError) as e:
+        md.sync()
+    assert e.value.status == H.HQA_ENONFINITE

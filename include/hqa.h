@@ -114,8 +114,8 @@ typedef struct hqa_md_opts {
     int32_t init_mem;        /* where p0 / phi0 live */
     int32_t require_exact;   /* 1: fail with HQA_EUNSUPPORTED unless every J_ij converts
                                 exactly to the storage type of the precision */
-    int32_t persistent;      /* 1 (default): dense steps run in one persistent launch
-                                when the instance fits; 0: one launch per step */
+    int32_t persistent;      /* 1: dense steps run in one persistent launch when the
+                                instance fits; 0 (default): one launch per step */
     int32_t reserved;
 } hqa_md_opts;
 
@@ -131,7 +131,7 @@ const char *hqa_last_error(void);
  * (0.12, 0.05, 1), M = 6, W = 100, r_g = 1, T = 50000, not frozen. */
 void hqa_schedule_default(hqa_schedule *s);
 
-/* R = 1, F32, seed 0, random p0, phi0 = 0, persistent launch allowed. */
+/* R = 1, F32, seed 0, random p0, phi0 = 0, one launch per step. */
 void hqa_md_opts_default(hqa_md_opts *o);
 
 /* Validate and upload `count` instances (symmetry, zero diagonal, finite values,
@@ -150,8 +150,18 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
  * the current step. */
 hqa_status hqa_md_run(hqa_md *md, int64_t until_step);
 
+/* Restart every instance from tau = 0 without re-uploading J: phi(0) = 0, p(0) = +-1
+ * from the counter hash with the given seed (as at init), window sums cleared, the
+ * step index set to 0 and the non-finite flag cleared.  Asynchronous. */
+hqa_status hqa_md_reset(hqa_md *md, uint64_t seed);
+
 /* Wait for queued work; HQA_ENONFINITE if any flux or momentum became non-finite. */
 hqa_status hqa_md_sync(hqa_md *md);
+
+/* 1 if the last hqa_md_run advanced the dense instances in one persistent launch,
+ * 0 if it used one launch per step (sparse or binary64 instances, persistent = 0, or
+ * an instance too large for the persistent plan). */
+int32_t hqa_md_last_persistent(const hqa_md *md);
 
 /* Current step index q (fluxes are phi^(q), momenta p^(q-1/2), or p^(0) at q = 0). */
 int64_t hqa_md_step_index(const hqa_md *md);

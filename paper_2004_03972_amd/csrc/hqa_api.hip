@@ -17,6 +17,7 @@ namespace hqa {
 hipError_t launch_md_steps_f64(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_steps_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_field_f64(hqa_md *md, Instance &I, double *u, hipStream_t st);
 hipError_t launch_field_dense(hqa_md *md, Instance &I, float *u, hipStream_t st);
 hipError_t launch_field_csr(hqa_md *md, Instance &I, float *u, hipStream_t st);
@@ -58,7 +59,7 @@ static void dfree(void *p) {
 static void free_instance(Instance &I) {
     dfree(I.J64); dfree(I.rp); dfree(I.ci); dfree(I.h64); dfree(I.h32); dfree(I.Js); dfree(I.v32);
     for (int k = 0; k < 2; k++) { dfree(I.phi64[k]); dfree(I.phi32[k]); dfree(I.phib[k]); }
-    dfree(I.p64); dfree(I.S64); dfree(I.p32); dfree(I.S32);
+    dfree(I.p64); dfree(I.S64); dfree(I.p32); dfree(I.S32); dfree(I.xch);
     I = Instance();
 }
 
@@ -182,7 +183,7 @@ void hqa_md_opts_default(hqa_md_opts *o) {
     memset(o, 0, sizeof *o);
     o->replicas = 1;
     o->precision = HQA_PREC_F32;
-    o->persistent = 1;
+    o->persistent = 0;
 }
 
 void hqa_md_destroy(hqa_md *md) {
@@ -190,7 +191,7 @@ void hqa_md_destroy(hqa_md *md) {
     if (md->stream || true) (void)hipStreamSynchronize(md->stream);
     for (auto &I : md->inst) free_instance(I);
     dfree(md->a64); dfree(md->b64); dfree(md->a32); dfree(md->b32);
-    dfree(md->err); dfree(md->scratch_i);
+    dfree(md->err); dfree(md->scratch_i); dfree(md->bar);
     delete md;
 }
 
@@ -269,7 +270,7 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
             HK(hipMemsetAsync(md->err, 0, sizeof(int32_t), st));
             if (P.layout == HQA_DENSE) {
                 I.smaj = false;
-                I.Np = (N + 31) / 32 * 32;
+                I.Np = (N + 127) / 128 * 128;
                 I.Rp = (R + 15) / 16 * 16;
                 I.ld = I.Np;
                 size_t esz = md->jt == JT_F32 ? 4 : md->jt == JT_BF16 ? 2 : 1;
@@ -343,6 +344,8 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
 
 int64_t hqa_md_step_index(const hqa_md *md) { return md ? md->q : -1; }
 
+int32_t hqa_md_last_persistent(const hqa_md *md) { return md ? md->last_persistent : 0; }
+
 hqa_status hqa_md_set_step(hqa_md *md, int64_t q) {
     if (!md) return fail(HQA_EINVAL, "null handle");
     if (q < 0 || q > md->sch.T) return fail(HQA_EINVAL, "step %lld outside [0, T]", (long long)q);
@@ -357,14 +360,37 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     if (q1 < md->q) return fail(HQA_ESTATE, "until_step %lld is before the current step %lld",
                                 (long long)q1, (long long)md->q);
     if (q1 == md->q) return HQA_OK;
+    md->last_persistent = 0;
     for (auto &I : md->inst) {
         hipError_t e;
         if (md->prec == HQA_PREC_F64_REF) e = launch_md_steps_f64(md, I, md->q, q1);
-        else if (I.layout == HQA_DENSE) e = launch_md_steps_dense(md, I, md->q, q1);
-        else e = launch_md_steps_csr(md, I, md->q, q1);
+        else if (I.layout == HQA_DENSE) {
+            e = hipErrorNotSupported;
+            if (md->persistent) {
+                e = launch_md_persist(md, I, md->q, q1);
+                if (e == hipSuccess) md->last_persistent = 1;
+                else (void)hipGetLastError();
+            }
+            if (e != hipSuccess) e = launch_md_steps_dense(md, I, md->q, q1);
+        } else e = launch_md_steps_csr(md, I, md->q, q1);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "step launch: %s", hipGetErrorString(e));
     }
     md->q = q1;
+    return HQA_OK;
+}
+
+hqa_status hqa_md_reset(hqa_md *md, uint64_t seed) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    HIPCHK(hipMemsetAsync(md->err, 0, sizeof(int32_t), md->stream));
+    for (auto &I : md->inst) {
+        if (md->prec != HQA_PREC_F64_REF) {
+            // padded rows / replicas of both flux buffers must stay zero
+            size_t n = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
+            HIPCHK(hipMemsetAsync(I.phi32[I.cur ^ 1], 0, n * 4, md->stream));
+        }
+        HIPCHK(launch_init_state(I, md->R, md->prec, seed, nullptr, nullptr, md->stream));
+    }
+    md->q = 0;
     return HQA_OK;
 }
 

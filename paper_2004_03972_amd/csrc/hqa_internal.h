@@ -41,7 +41,7 @@ struct Instance {
     int32_t N = 0;
     int32_t layout = HQA_DENSE;
     int64_t nnz = 0;
-    int32_t Np = 0;           // dense fast paths: N padded to a multiple of 32
+    int32_t Np = 0;           // dense fast paths: N padded to a multiple of 128
     int32_t Rp = 0;           // replicas padded to a multiple of 16
     bool smaj = false;        // state layout [N][R] (CSR fast path) else [R][ld]
     int32_t ld = 0;           // leading dimension of replica-major state
@@ -64,6 +64,8 @@ struct Instance {
     float *p32 = nullptr, *S32 = nullptr;
     bf16 *phib[2] = {nullptr, nullptr};
     int cur = 0;              // phi[cur] holds phi^(q)
+    void *xch = nullptr;      // persistent-kernel exchange buffers (tagged words)
+    size_t xch_bytes = 0;
 
     ExpStats es{0, 0};
     bool j_integral = false;  // every J and h is an integer
@@ -92,7 +94,9 @@ struct hqa_md {
     float *a32 = nullptr, *b32 = nullptr;
     int32_t *err = nullptr;                  // device error word
     int32_t *scratch_i = nullptr;            // small device scratch (ints)
+    int32_t *bar = nullptr;                  // persistent-launch barrier counters + abort flag
     hqa::JType jt = hqa::JT_F32;
+    int last_persistent = 0;                 // 1 if the last run used the persistent kernel
 };
 
 namespace hqa {

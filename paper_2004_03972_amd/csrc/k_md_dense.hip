@@ -1,7 +1,7 @@
 // k_md_dense.hip -- dense field U = J Phi on MFMA with the leapfrog fused into
 // the epilogue, one launch per MD step.
 //
-// Layout: J is stored Np x Np (N padded to a multiple of 32, zeros outside),
+// Layout: J is stored Np x Np (N padded to a multiple of 128, zeros outside),
 // row-major, as FP32, BF16 or FP8 e4m3.  The state is replica-major [Rp][ld]
 // (ld = Np): row r of the binary32 fluxes / momenta / window sum and of the
 // BF16 operand copy is one replica.  With U[i][r] = sum_k J[i][k] Phi[r][k],
@@ -11,6 +11,8 @@
 // vectors of the state.
 //
 // Workgroup tile: 32 rows x 32 replicas, one 16 x 16 MFMA tile per wavefront.
+#include <type_traits>
+
 #include "hqa_internal.h"
 #include "md_epilogue.h"
 
@@ -46,43 +48,71 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint2 raw) {
     return o;
 }
 
-// Accumulate one 16x16 tile U[i0..i0+16)[r0..r0+16) over the full K = Np.
+// Accumulate one 16x16 tile U[i0..i0+16)[r0..r0+16) over the full K = Np in the
+// four chains of combine4 (chunk c -> chain c mod 4).
 template <int JT>
 __device__ __forceinline__ f32x4 tile_field(const DenseArgs &a, int i0, int r0, int lane) {
     const int row = i0 + (lane & 15), col = r0 + (lane & 15), kg = lane >> 4;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    // Np is a multiple of 128: whole groups of four chunks; the next group's
+    // operands are loaded while the current group's MFMAs run.
     if constexpr (JT == JT_F32) {
         const float *Ja = (const float *)a.J + (int64_t)row * a.Np + 4 * kg;
         const float *Xb = a.phi_in + (int64_t)col * a.ld + 4 * kg;
-#pragma unroll 4
-        for (int k0 = 0; k0 < a.Np; k0 += 16) {
-            float4 av = *(const float4 *)(Ja + k0);
-            float4 bv = *(const float4 *)(Xb + k0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc, 0, 0, 0);
-        }
-    } else if constexpr (JT == JT_BF16) {
-        const bf16 *Ja = (const bf16 *)a.J + (int64_t)row * a.Np + 8 * kg;
-        const bf16 *Xb = a.xb_in + (int64_t)col * a.ld + 8 * kg;
-#pragma unroll 4
-        for (int k0 = 0; k0 < a.Np; k0 += 32) {
-            bf16x8 av = *(const bf16x8 *)(Ja + k0);
-            bf16x8 bv = *(const bf16x8 *)(Xb + k0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        const int ngroups = a.Np / 64;
+        float4 A[4], B[4], An[4], Bn[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) { A[j] = *(const float4 *)(Ja + 16 * j); B[j] = *(const float4 *)(Xb + 16 * j); }
+        for (int gi = 0; gi < ngroups; gi++) {
+            if (gi + 1 < ngroups) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    An[j] = *(const float4 *)(Ja + (gi + 1) * 64 + 16 * j);
+                    Bn[j] = *(const float4 *)(Xb + (gi + 1) * 64 + 16 * j);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].x, B[j].x, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].y, B[j].y, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].z, B[j].z, acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].w, B[j].w, acc[j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) { A[j] = An[j]; B[j] = Bn[j]; }
         }
     } else {
-        const uint8_t *Ja = (const uint8_t *)a.J + (int64_t)row * a.Np + 8 * kg;
+        typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
+        const uint8_t *Ja = (const uint8_t *)a.J + ((int64_t)row * a.Np + 8 * kg) * (JT == JT_BF16 ? 2 : 1);
         const bf16 *Xb = a.xb_in + (int64_t)col * a.ld + 8 * kg;
-#pragma unroll 4
-        for (int k0 = 0; k0 < a.Np; k0 += 32) {
-            uint2 raw = *(const uint2 *)(Ja + k0);
-            bf16x8 bv = *(const bf16x8 *)(Xb + k0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fp8x8_to_bf16(raw), bv, acc, 0, 0, 0);
+        const int ngroups = a.Np / 128;
+        AT A[4], An[4];
+        bf16x8 B[4], Bn[4];
+        auto load = [&](int gi, AT (&Ag)[4], bf16x8 (&Bg)[4]) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int kk = gi * 128 + 32 * j;
+                Ag[j] = *(const AT *)(Ja + kk * (JT == JT_BF16 ? 2 : 1));
+                Bg[j] = *(const bf16x8 *)(Xb + kk);
+            }
+        };
+        load(0, A, B);
+        for (int gi = 0; gi < ngroups; gi++) {
+            if (gi + 1 < ngroups) load(gi + 1, An, Bn);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                bf16x8 av;
+                if constexpr (JT == JT_BF16) av = A[j];
+                else av = fp8x8_to_bf16(A[j]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, B[j], acc[j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) { A[j] = An[j]; B[j] = Bn[j]; }
         }
     }
-    return acc;
+    return combine4(acc);
 }
 
 template <int JT, bool FIELD_ONLY>

@@ -1,0 +1,474 @@
+// k_md_persist.hip -- all MD steps of a dense instance in one persistent launch.
+//
+// Replicas are independent, so the work splits into clusters: cluster c owns the
+// 16 replicas [16c, 16c+16) and G workgroups; workgroup g owns the rows
+// [g NB, g NB + NB), NB = 64 * TRW (TRW row tiles of 16 per wavefront).  For the
+// whole run a workgroup keeps
+//   - its J row block in LDS (stored type; rows padded by 16 bytes against bank
+//     conflicts), or reads it from L2 when the block does not fit,
+//   - the binary32 flux, momentum and window sum of its rows x 16 replicas in
+//     registers (four consecutive rows of one replica per lane: the MFMA
+//     accumulator layout).
+// Step q needs the fluxes phi^(q) of all N spins of the cluster's replicas, which
+// the other workgroups of the cluster produce.  They travel through an exchange
+// buffer of tagged words: each flux is stored together with a step tag by a
+// relaxed agent-scope atomic store.  At the start of a step the workgroup
+// gathers the cluster's whole flux block with relaxed agent-scope atomic loads,
+// all in flight together, re-loads only the words whose tag is not yet the
+// step's, and stages the values in LDS, from which every wavefront reads its
+// MFMA operands.  Each word validates itself, so no fence, grid barrier or L2
+// write-back is needed.  Two exchange buffers (by step parity) cannot be
+// overwritten early: a producer writes step q+2 into the buffer of step q only
+// after it has gathered step q+1, which every consumer produced after finishing
+// its gather of step q.  Tags run 1..65535 within a launch and the buffers are
+// cleared before it, so stale words never match.
+//
+// The binary32 update applies the same operation sequence as the per-step
+// kernel, so both paths give identical states.  Every wait is bounded: past the
+// bound a workgroup raises an abort flag that all other waiters observe, and
+// the whole grid leaves the kernel.  Cluster members are placed on one XCD
+// (workgroups are dispatched round-robin over the 8 XCDs); correctness does not
+// depend on the placement.
+#include <type_traits>
+
+#include "hqa_internal.h"
+#include "md_epilogue.h"
+
+namespace hqa {
+
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
+
+struct PersistArgs {
+    int N, Np, R, ld, M, G, C;
+    int64_t T, q0, q1;
+    int W;
+    float rg;
+    const void *J;
+    const float *h;
+    const float *a32, *b32;
+    const float *phi_in;     // phi^(q0), binary32 state layout
+    float *phi_out;          // receives phi^(q1)
+    bf16 *xb_out;            // BF16 operand copy of phi^(q1) (per-step kernels read it)
+    float *p, *S;
+    uint64_t *xch;           // [2][Rp][Np] tagged entries: u32 (bf16|tag<<16) or u64 (f32|tag<<32)
+    int64_t xch_half;        // entries per parity buffer
+    int32_t *abort_flag;
+    int32_t *err;
+    int jstride;             // LDS row stride of the J block (bytes)
+    int jbytes;              // LDS bytes of the J block (0 when J is read from L2)
+    int pstride;             // LDS row stride of the staged flux block (bytes)
+    int64_t spin_limit;
+};
+
+__device__ __forceinline__ bf16x8 cvt_fp8x8(uint2 raw) {
+    bf16x2_t a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.x, 1.0f, false);
+    bf16x2_t b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.x, 1.0f, true);
+    bf16x2_t c = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.y, 1.0f, false);
+    bf16x2_t d = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.y, 1.0f, true);
+    bf16x8 o;
+    o[0] = a[0]; o[1] = a[1]; o[2] = b[0]; o[3] = b[1];
+    o[4] = c[0]; o[5] = c[1]; o[6] = d[0]; o[7] = d[1];
+    return o;
+}
+
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct Waiter {
+    int64_t spins;
+    bool dead;
+};
+
+__device__ __forceinline__ bool keep_waiting(const PersistArgs &a, Waiter &wt) {
+    if (++wt.spins > a.spin_limit) {
+        __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicOr(a.err, ERR_BARRIER);
+        wt.dead = true;
+        return false;
+    }
+    if ((wt.spins & 63) == 0 &&
+        __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        wt.dead = true;
+        return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    return true;
+}
+
+template <int JT>
+__device__ __forceinline__ bool tag_ok(uint64_t v, uint32_t tag) {
+    if constexpr (JT == JT_F32) return (uint32_t)(v >> 32) == tag;
+    else return ((uint32_t)(v >> 16) & 0xffffu) == tag && (uint32_t)(v >> 48) == tag;
+}
+
+// Gather the cluster's flux block of one step into LDS.  FP32: one entry per
+// 64-bit word; BF16: two entries per word, stored to LDS as a packed bf16 pair.
+template <int JT>
+__device__ __forceinline__ void gather(const PersistArgs &a, int par, int r0, uint32_t tag,
+                                       uint8_t *phis, Waiter &wt) {
+    constexpr int GB = 32;
+    const int wpr = JT == JT_F32 ? a.ld : a.ld / 2;       // words per replica row
+    const int nw = 16 * wpr;
+    const uint64_t *src = a.xch + (JT == JT_F32 ? par * a.xch_half + (int64_t)r0 * a.ld
+                                                : (par * a.xch_half + (int64_t)r0 * a.ld) / 2);
+    const int tid = threadIdx.x;
+    for (int b0 = 0; b0 < nw; b0 += 256 * GB) {
+        uint64_t v[GB];
+        uint32_t miss = 0;
+#pragma unroll
+        for (int m = 0; m < GB; m++) {
+            const int idx = b0 + m * 256 + tid;
+            v[m] = idx < nw ? ld_relaxed(src + idx) : 0ull;
+        }
+#pragma unroll
+        for (int m = 0; m < GB; m++) {
+            const int idx = b0 + m * 256 + tid;
+            if (idx < nw && !tag_ok<JT>(v[m], tag)) miss |= 1u << m;
+        }
+        while (miss && !wt.dead) {
+            if (!keep_waiting(a, wt)) break;
+#pragma unroll
+            for (int m = 0; m < GB; m++) {
+                if ((miss >> m) & 1u) {
+                    v[m] = ld_relaxed(src + b0 + m * 256 + tid);
+                    if (tag_ok<JT>(v[m], tag)) miss &= ~(1u << m);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < GB; m++) {
+            const int idx = b0 + m * 256 + tid;
+            if (idx < nw) {
+                const int rr = idx / wpr, kk = idx % wpr;
+                uint32_t val = JT == JT_F32
+                                   ? (uint32_t)v[m]
+                                   : __builtin_amdgcn_perm((uint32_t)(v[m] >> 32), (uint32_t)v[m],
+                                                           0x05040100u);
+                *(uint32_t *)(phis + (size_t)rr * a.pstride + kk * 4) = val;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t bf16_word(float x, uint32_t tag) {
+    bf16 b = (bf16)x;
+    return (uint64_t)(__builtin_bit_cast(uint16_t, b)) | ((uint64_t)tag << 16);
+}
+
+// Publish four consecutive rows of one replica for step tag `tag`.
+template <int JT>
+__device__ __forceinline__ void publish(const PersistArgs &a, int par, int col, int ib,
+                                        const float *xn, uint32_t tag) {
+    if constexpr (JT == JT_F32) {
+        uint64_t *dst = a.xch + par * a.xch_half + (int64_t)col * a.ld + ib;
+#pragma unroll
+        for (int v = 0; v < 4; v++)
+            st_relaxed(dst + v, (uint64_t)__float_as_uint(xn[v]) | ((uint64_t)tag << 32));
+    } else {
+        uint64_t *dst = a.xch + (par * a.xch_half + (int64_t)col * a.ld + ib) / 2;
+        st_relaxed(dst, bf16_word(xn[0], tag) | (bf16_word(xn[1], tag) << 32));
+        st_relaxed(dst + 1, bf16_word(xn[2], tag) | (bf16_word(xn[3], tag) << 32));
+    }
+}
+
+template <int JT, int TRW, bool JLDS>
+__global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    // block -> (xcd, slot) -> (cluster, rank): cluster members share an XCD
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int cl_in_xcd = slot / a.G, g = slot % a.G;
+    const int c = cl_in_xcd * 8 + xcd;
+    if (c >= a.C) return;
+    const int NB = 64 * TRW;
+    const int row0 = g * NB;
+    if (row0 >= a.Np) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = 16 * c;
+    const int esz = JT == JT_F32 ? 4 : JT == JT_BF16 ? 2 : 1;
+    uint8_t *phis = lds + a.jbytes;   // staged flux block [16][pstride]
+
+    if constexpr (JLDS) {
+        const int rows = min(NB, a.Np - row0);
+        const int per_row = a.Np * esz / 16;
+        for (int t = threadIdx.x; t < rows * per_row; t += 256) {
+            int rr = t / per_row, cc = t % per_row;
+            const uint4 *src = (const uint4 *)((const uint8_t *)a.J +
+                                               ((int64_t)(row0 + rr) * a.Np) * esz) + cc;
+            *(uint4 *)(lds + (size_t)rr * a.jstride + cc * 16) = *src;
+        }
+    }
+
+    const int col = r0 + (lane & 15);
+    const int kg = lane >> 4;
+    const bool rvalid = col < a.R;
+    float xs[TRW][4], ps[TRW][4], ss[TRW][4], hs[TRW][4];
+    bool tile_ok[TRW];
+#pragma unroll
+    for (int t = 0; t < TRW; t++) {
+        tile_ok[t] = row0 + 16 * (w * TRW + t) < a.Np;
+        const int ib = row0 + 16 * (w * TRW + t) + 4 * kg;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const int i = ib + v;
+            const bool ok = rvalid && i < a.N;
+            const int64_t k = (int64_t)col * a.ld + i;
+            xs[t][v] = ok ? a.phi_in[k] : 0.f;
+            ps[t][v] = ok ? a.p[k] : 0.f;
+            ss[t][v] = ok ? a.S[k] : 0.f;
+            hs[t][v] = (i < a.N) ? a.h[i] : 0.f;
+        }
+        if (tile_ok[t]) publish<JT>(a, 0, col, ib, xs[t], 1u);
+    }
+    Waiter wt{0, false};
+    bool bad = false;
+    const int nsteps = (int)(a.q1 - a.q0);
+    for (int s = 0; s < nsteps; s++) {
+        const int64_t q = a.q0 + s;
+        const int par = s & 1;
+        // coefficients of this step first: their loads overlap the gather
+        const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
+        gather<JT>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
+        if (__syncthreads_or(wt.dead)) return;   // aborted: the workgroup leaves
+        // field in the four chains of combine4 (chunk c -> chain c mod 4)
+        f32x4 acc[TRW][4];
+#pragma unroll
+        for (int t = 0; t < TRW; t++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[t][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        const uint8_t *Xb = phis + (size_t)(lane & 15) * a.pstride;
+        // Np is a multiple of 128: whole groups of four chunks, the next group's
+        // operands are loaded while the current group's MFMAs run.
+        if constexpr (JT == JT_F32) {
+            const int ngroups = a.Np / 64;
+            float4 A[TRW][4], B[4], An[TRW][4], Bn[4];
+            auto load = [&](int gi, float4 (&Ag)[TRW][4], float4 (&Bg)[4]) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int kk = gi * 64 + 16 * j + 4 * kg;
+                    Bg[j] = *(const float4 *)(Xb + kk * 4);
+#pragma unroll
+                    for (int t = 0; t < TRW; t++) {
+                        const int rr = 16 * (w * TRW + t) + (lane & 15);
+                        if (!tile_ok[t]) { Ag[t][j] = make_float4(0.f, 0.f, 0.f, 0.f); continue; }
+                        if constexpr (JLDS) Ag[t][j] = *(const float4 *)(lds + (size_t)rr * a.jstride + kk * 4);
+                        else Ag[t][j] = *(const float4 *)((const float *)a.J + (int64_t)(row0 + rr) * a.Np + kk);
+                    }
+                }
+            };
+            load(0, A, B);
+            for (int gi = 0; gi < ngroups; gi++) {
+                if (gi + 1 < ngroups) load(gi + 1, An, Bn);
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int t = 0; t < TRW; t++) {
+                        acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t][j].x, B[j].x, acc[t][j], 0, 0, 0);
+                        acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t][j].y, B[j].y, acc[t][j], 0, 0, 0);
+                        acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t][j].z, B[j].z, acc[t][j], 0, 0, 0);
+                        acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t][j].w, B[j].w, acc[t][j], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    B[j] = Bn[j];
+#pragma unroll
+                    for (int t = 0; t < TRW; t++) A[t][j] = An[t][j];
+                }
+            }
+        } else {
+            typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
+            const int ngroups = a.Np / 128;
+            AT A[TRW][4], An[TRW][4];
+            bf16x8 B[4], Bn[4];
+            auto load = [&](int gi, AT (&Ag)[TRW][4], bf16x8 (&Bg)[4]) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int kk = gi * 128 + 32 * j + 8 * kg;
+                    Bg[j] = *(const bf16x8 *)(Xb + kk * 2);
+#pragma unroll
+                    for (int t = 0; t < TRW; t++) {
+                        const int rr = 16 * (w * TRW + t) + (lane & 15);
+                        if (!tile_ok[t]) { Ag[t][j] = AT{}; continue; }
+                        if constexpr (JT == JT_BF16) {
+                            if constexpr (JLDS) Ag[t][j] = *(const bf16x8 *)(lds + (size_t)rr * a.jstride + kk * 2);
+                            else Ag[t][j] = *(const bf16x8 *)((const bf16 *)a.J + (int64_t)(row0 + rr) * a.Np + kk);
+                        } else {
+                            if constexpr (JLDS) Ag[t][j] = *(const uint2 *)(lds + (size_t)rr * a.jstride + kk);
+                            else Ag[t][j] = *(const uint2 *)((const uint8_t *)a.J + (int64_t)(row0 + rr) * a.Np + kk);
+                        }
+                    }
+                }
+            };
+            load(0, A, B);
+            for (int gi = 0; gi < ngroups; gi++) {
+                if (gi + 1 < ngroups) load(gi + 1, An, Bn);
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int t = 0; t < TRW; t++) {
+                        bf16x8 av;
+                        if constexpr (JT == JT_BF16) av = A[t][j];
+                        else av = cvt_fp8x8(A[t][j]);
+                        acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, B[j], acc[t][j], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    B[j] = Bn[j];
+#pragma unroll
+                    for (int t = 0; t < TRW; t++) A[t][j] = An[t][j];
+                }
+            }
+        }
+        const bool win = q + 1 >= a.T - a.W + 1;
+        const uint32_t ntag = (uint32_t)((s + 1) % 65535) + 1u;
+#pragma unroll
+        for (int t = 0; t < TRW; t++) {
+            if (!tile_ok[t]) continue;
+            const int ib = row0 + 16 * (w * TRW + t) + 4 * kg;
+            const f32x4 u = combine4(acc[t]);
+            float xn[4];
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                if (rvalid && ib + v < a.N) {
+                    leapfrog(cf, xs[t][v], u[v], hs[t][v], ps[t][v], xn[v]);
+                    bad |= !isfinite(xn[v]) || !isfinite(ps[t][v]);
+                    if (win) ss[t][v] = ss[t][v] + xn[v];
+                } else {
+                    xn[v] = 0.f;
+                }
+                xs[t][v] = xn[v];
+            }
+            if (s + 1 < nsteps) publish<JT>(a, par ^ 1, col, ib, xn, ntag);
+        }
+        __syncthreads();   // the staged block is rewritten by the next gather
+    }
+#pragma unroll
+    for (int t = 0; t < TRW; t++) {
+        if (!tile_ok[t] || !rvalid) continue;
+        const int ib = row0 + 16 * (w * TRW + t) + 4 * kg;
+        const int64_t base = (int64_t)col * a.ld + ib;
+        *(float4 *)(a.phi_out + base) = make_float4(xs[t][0], xs[t][1], xs[t][2], xs[t][3]);
+        *(float4 *)(a.p + base) = make_float4(ps[t][0], ps[t][1], ps[t][2], ps[t][3]);
+        *(float4 *)(a.S + base) = make_float4(ss[t][0], ss[t][1], ss[t][2], ss[t][3]);
+        if (a.xb_out) {
+            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+            bf16x4 b = {(bf16)xs[t][0], (bf16)xs[t][1], (bf16)xs[t][2], (bf16)xs[t][3]};
+            *(bf16x4 *)(a.xb_out + base) = b;
+        }
+    }
+    if (bad) atomicOr(a.err, ERR_NONFINITE);
+}
+
+// Plan of a persistent launch for one dense instance.
+struct PersistPlan {
+    int TRW, G, C, grid, jlds, jstride, jbytes, pstride;
+    size_t lds;
+};
+
+static bool plan_persist(const Instance &I, int R, JType jt, int max_wg, PersistPlan &p) {
+    const int esz = jt == JT_F32 ? 4 : jt == JT_BF16 ? 2 : 1;
+    const int eb = jt == JT_F32 ? 4 : 2;               // staged flux element bytes
+    const size_t lds_cap = 156 * 1024;
+    p.C = (R + 15) / 16;
+    p.pstride = I.Np * eb + 16;
+    const size_t stage = (size_t)16 * p.pstride;
+    if (stage > lds_cap) return false;
+    // prefer a J block resident in LDS, then two row tiles per wavefront
+    for (int want_lds : {1, 0}) {
+        for (int trw : {2, 1}) {
+            int NB = 64 * trw;
+            int G = (I.Np + NB - 1) / NB;
+            if (G > 32) continue;                     // a cluster must fit one XCD (32 CUs)
+            int per_xcd = 32 / G;                     // clusters per XCD
+            int need_xcd_slots = (p.C + 7) / 8;
+            if (need_xcd_slots > per_xcd) continue;
+            size_t stride = (size_t)I.Np * esz + 16;
+            size_t jb = (size_t)NB * stride;
+            if (want_lds && jb + stage > lds_cap) continue;
+            p.TRW = trw;
+            p.G = G;
+            p.jlds = want_lds;
+            p.jstride = (int)stride;
+            p.jbytes = want_lds ? (int)jb : 0;
+            p.lds = (size_t)p.jbytes + stage;
+            p.grid = 8 * need_xcd_slots * G;
+            if (p.grid > max_wg) continue;
+            return true;
+        }
+    }
+    return false;
+}
+
+template <int JT, int TRW, bool JLDS>
+static hipError_t launch_p(const PersistArgs &a, const PersistPlan &pl, hipStream_t st) {
+    void *args[] = {(void *)&a};
+    return hipLaunchCooperativeKernel((const void *)k_persist<JT, TRW, JLDS>, dim3(pl.grid),
+                                      dim3(256), args, (unsigned)pl.lds, st);
+}
+
+template <int JT>
+static hipError_t launch_jt(const PersistArgs &a, const PersistPlan &pl, hipStream_t st) {
+    if (pl.TRW == 2) return pl.jlds ? launch_p<JT, 2, true>(a, pl, st) : launch_p<JT, 2, false>(a, pl, st);
+    return pl.jlds ? launch_p<JT, 1, true>(a, pl, st) : launch_p<JT, 1, false>(a, pl, st);
+}
+
+// Returns hipErrorNotSupported when the instance has no persistent plan (the
+// caller then runs one launch per step).
+hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
+    static int max_wg = -1;
+    if (max_wg < 0) {
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        max_wg = cus;   // one 256-thread workgroup per CU is always co-resident
+    }
+    PersistPlan pl;
+    if (!plan_persist(I, md->R, md->jt, max_wg, pl)) return hipErrorNotSupported;
+    const size_t esz = md->jt == JT_F32 ? 8 : 4;
+    const int64_t half = (int64_t)I.Rp * I.ld;
+    const size_t bytes = 2 * (size_t)half * esz;
+    if (!I.xch || I.xch_bytes < bytes) {
+        if (I.xch) (void)hipFree(I.xch);
+        I.xch = nullptr;
+        I.xch_bytes = 0;
+        hipError_t e = hipMalloc(&I.xch, bytes);
+        if (e != hipSuccess) return e;
+        I.xch_bytes = bytes;
+    }
+    if (!md->bar) {
+        hipError_t e = hipMalloc((void **)&md->bar, sizeof(int32_t) * 64);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMemsetAsync(md->bar, 0, sizeof(int32_t) * 64, md->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(I.xch, 0, bytes, md->stream);
+    if (e != hipSuccess) return e;
+    PersistArgs a;
+    a.N = I.N; a.Np = I.Np; a.R = md->R; a.ld = I.ld; a.M = md->sch.M; a.G = pl.G; a.C = pl.C;
+    a.T = md->sch.T; a.q0 = q0; a.q1 = q1; a.W = md->sch.W;
+    a.rg = (float)md->sch.r_g;
+    a.J = I.Js; a.h = I.h32; a.a32 = md->a32; a.b32 = md->b32;
+    const int par = (int)((q1 - q0) & 1);
+    a.phi_in = I.phi32[I.cur];
+    a.phi_out = I.phi32[I.cur ^ par];
+    a.xb_out = I.phib[I.cur ^ par];
+    a.p = I.p32; a.S = I.S32;
+    a.xch = (uint64_t *)I.xch;
+    a.xch_half = half;
+    a.abort_flag = md->bar + 63; a.err = md->err;
+    a.jstride = pl.jstride;
+    a.jbytes = pl.jbytes;
+    a.pstride = pl.pstride;
+    a.spin_limit = (int64_t)1 << 22;
+    switch (md->jt) {
+        case JT_F32: e = launch_jt<JT_F32>(a, pl, md->stream); break;
+        case JT_BF16: e = launch_jt<JT_BF16>(a, pl, md->stream); break;
+        default: e = launch_jt<JT_FP8>(a, pl, md->stream); break;
+    }
+    if (e == hipSuccess) I.cur ^= par;
+    return e;
+}
+
+}  // namespace hqa

@@ -11,6 +11,19 @@
 
 namespace hqa {
 
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_e;
+
+// The dense field is accumulated in four independent MFMA chains: K chunk c
+// (32 columns for BF16 operands, 16 for FP32) feeds chain c mod 4, and the field
+// is (a0 + a1) + (a2 + a3).  Every dense kernel uses this decomposition, so the
+// per-step and persistent launches produce identical fields, and the four chains
+// keep the MFMA pipeline busy instead of waiting on one accumulator.
+__device__ __forceinline__ f32x4_e combine4(const f32x4_e *a) {
+    f32x4_e s01 = a[0] + a[1];
+    f32x4_e s23 = a[2] + a[3];
+    return s01 + s23;
+}
+
 struct StepCoef {
     float al, be;     // alpha, beta at tau = q/T
     float ad;         // alpha at tau = (q + 1/2)/T, times r_g

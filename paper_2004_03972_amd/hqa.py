@@ -23,9 +23,9 @@ PRECISIONS = {"f64": HQA_PREC_F64_REF, "f32": HQA_PREC_F32, "bf16": HQA_PREC_BF1
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhqa.so")
 EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md_opts_default",
-            "hqa_md_init", "hqa_md_run", "hqa_md_sync", "hqa_md_step_index", "hqa_md_state",
+            "hqa_md_init", "hqa_md_run", "hqa_md_reset", "hqa_md_sync", "hqa_md_step_index", "hqa_md_state",
             "hqa_md_set_step", "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify",
-            "hqa_ising_energy", "hqa_md_destroy")
+            "hqa_ising_energy", "hqa_md_destroy", "hqa_md_last_persistent")
 
 
 class HQAError(RuntimeError):
@@ -78,8 +78,11 @@ def lib():
         L.hqa_md_init.argtypes = [P, i32, P, P, P, P]
         L.hqa_md_run.argtypes = [P, i64]
         L.hqa_md_sync.argtypes = [P]
+        L.hqa_md_reset.argtypes = [P, C.c_uint64]
         L.hqa_md_step_index.argtypes = [P]
         L.hqa_md_step_index.restype = i64
+        L.hqa_md_last_persistent.argtypes = [P]
+        L.hqa_md_last_persistent.restype = i32
         L.hqa_md_state.argtypes = [P, i32, i32, P, i32, i32]
         L.hqa_md_set_step.argtypes = [P, i64]
         L.hqa_md_field.argtypes = [P, i32, P, i32]
@@ -87,7 +90,7 @@ def lib():
         L.hqa_classify.argtypes = [P, i32, i32, i32, P, i32]
         L.hqa_ising_energy.argtypes = [P, P, i32, P, P, i32, P]
         L.hqa_md_destroy.argtypes = [P]
-        for f in ("hqa_md_init", "hqa_md_run", "hqa_md_sync", "hqa_md_state", "hqa_md_set_step",
+        for f in ("hqa_md_init", "hqa_md_run", "hqa_md_reset", "hqa_md_sync", "hqa_md_state", "hqa_md_set_step",
                   "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify", "hqa_ising_energy"):
             getattr(L, f).restype = C.c_int
         if L.hqa_abi_version() != 1:
@@ -147,8 +150,16 @@ def hqa_md_sync(md):
     _check(lib().hqa_md_sync(md))
 
 
+def hqa_md_reset(md, seed: int):
+    _check(lib().hqa_md_reset(md, seed))
+
+
 def hqa_md_step_index(md) -> int:
     return lib().hqa_md_step_index(md)
+
+
+def hqa_md_last_persistent(md) -> int:
+    return lib().hqa_md_last_persistent(md)
 
 
 def hqa_md_set_step(md, q: int):
@@ -222,7 +233,7 @@ class MD:
     """A handle over hqa_md_* calls with numpy in/out (host memory)."""
 
     def __init__(self, problems, sched: hqa_schedule, replicas: int, precision="f32", seed=0,
-                 p0=None, phi0=None, require_exact=False, persistent=True, stream: int = 0):
+                 p0=None, phi0=None, require_exact=False, persistent=False, stream: int = 0):
         self.problems = problems if isinstance(problems, (list, tuple)) else [problems]
         o = hqa_md_opts_default()
         o.replicas = replicas
@@ -256,9 +267,16 @@ class MD:
     def sync(self):
         hqa_md_sync(self.h)
 
+    def reset(self, seed: int):
+        hqa_md_reset(self.h, seed)
+
     @property
     def step(self) -> int:
         return hqa_md_step_index(self.h)
+
+    @property
+    def last_persistent(self) -> bool:
+        return bool(hqa_md_last_persistent(self.h))
 
     def state(self, what: int, k: int = 0) -> np.ndarray:
         out = np.empty((self.R, self.problems[k].n))

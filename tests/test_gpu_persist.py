@@ -1,0 +1,57 @@
+"""The persistent dense kernel (all steps in one launch, cluster barriers) must give
+bit-identical states to one launch per step: both apply the same binary32
+operation sequence.  Shapes cover LDS-resident and L2-streamed J blocks, ragged
+row and replica tails, the small-SK/large-ER sizes and the bench shape."""
+import numpy as np
+import pytest
+
+from paper_2004_03972_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    from paper_2004_03972_amd import hqa
+    hqa.lib()
+    return hqa
+
+
+def _states(H, md):
+    return [md.state(w) for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("N,R,T", [(300, 40, 250), (64, 16, 120), (800, 256, 400),
+                                   (1300, 64, 150), (2100, 32, 60)])
+def test_persistent_equals_per_step(H, prec, N, R, T):
+    print("persist", prec, N, R, T, flush=True)
+    J = inst.er_maxcut(N, 0.05, N)
+    out = []
+    for pers in (True, False):
+        md = H.MD(H.Problem(J), H.make_schedule(T, 30), R, prec, seed=7, persistent=pers)
+        md.run()
+        md.sync()
+        assert md.last_persistent == pers
+        out.append(_states(H, md))
+        md.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_persistent_in_pieces_and_single_step(H, prec):
+    N, R, T = 500, 48, 300
+    J, h = inst.uniform_glass(N, 3)
+    J *= 0.05
+    a = H.MD(H.Problem(J, h=h), H.make_schedule(T, 40), R, prec, seed=1, persistent=False)
+    a.run()
+    b = H.MD(H.Problem(J, h=h), H.make_schedule(T, 40), R, prec, seed=1, persistent=True)
+    for q in (1, 2, 101, 257, T):
+        b.run(q)
+        assert b.last_persistent
+    for x, y in zip(_states(H, a), _states(H, b)):
+        assert np.array_equal(x, y)

@@ -72,7 +72,10 @@ typedef struct hqa_problem {
     int32_t n;
     int32_t layout;          /* HQA_DENSE or HQA_CSR */
     int32_t mem;             /* where j, row_ptr, col and h live */
-    int32_t reserved;
+    int32_t storage;         /* 0: J stored as the handle's precision; HQA_PREC_F32,
+                                HQA_PREC_BF16 or HQA_PREC_FP8J_BF16: this dense instance's
+                                own storage in a non-reference handle (a batch may mix
+                                BF16 and FP8 instances) */
     const double *j;
     const int32_t *row_ptr;
     const int32_t *col;

@@ -18,6 +18,8 @@ hipError_t launch_md_steps_f64(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_steps_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1);
+void free_batch_plan(void *p);
 hipError_t launch_field_f64(hqa_md *md, Instance &I, double *u, hipStream_t st);
 hipError_t launch_field_dense(hqa_md *md, Instance &I, float *u, hipStream_t st);
 hipError_t launch_field_csr(hqa_md *md, Instance &I, float *u, hipStream_t st);
@@ -192,6 +194,7 @@ void hqa_md_destroy(hqa_md *md) {
     for (auto &I : md->inst) free_instance(I);
     dfree(md->a64); dfree(md->b64); dfree(md->a32); dfree(md->b32);
     dfree(md->err); dfree(md->scratch_i); dfree(md->bar);
+    free_batch_plan(md->batch);
     delete md;
 }
 
@@ -216,6 +219,15 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
         if (s != HQA_OK) return s;
         if (probs[k].layout == HQA_CSR && opts->precision >= HQA_PREC_BF16)
             return fail(HQA_EUNSUPPORTED, "instance %d: BF16/FP8 storage is for dense J only", k);
+        const int sto = probs[k].storage;
+        if (sto != 0) {
+            if (sto != HQA_PREC_F32 && sto != HQA_PREC_BF16 && sto != HQA_PREC_FP8J_BF16)
+                return fail(HQA_EINVAL, "instance %d: unknown storage %d", k, sto);
+            if (probs[k].layout == HQA_CSR || opts->precision == HQA_PREC_F64_REF)
+                return fail(HQA_EUNSUPPORTED,
+                            "instance %d: a storage override needs a dense instance in a "
+                            "non-reference handle", k);
+        }
     }
     hipStream_t st = (hipStream_t)hip_stream;
     hqa_md *md = new hqa_md();
@@ -273,14 +285,18 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
                 I.Np = (N + 127) / 128 * 128;
                 I.Rp = (R + 15) / 16 * 16;
                 I.ld = I.Np;
-                size_t esz = md->jt == JT_F32 ? 4 : md->jt == JT_BF16 ? 2 : 1;
+                I.jt = md->jt;
+                if (P.storage == HQA_PREC_F32) I.jt = JT_F32;
+                else if (P.storage == HQA_PREC_BF16) I.jt = JT_BF16;
+                else if (P.storage == HQA_PREC_FP8J_BF16) I.jt = JT_FP8;
+                size_t esz = I.jt == JT_F32 ? 4 : I.jt == JT_BF16 ? 2 : 1;
                 HK(hipMalloc(&I.Js, (size_t)I.Np * I.Np * esz));
-                HK(launch_convert_dense(I.J64, N, I.Np, md->jt, I.Js, md->err, st));
+                HK(launch_convert_dense(I.J64, N, I.Np, I.jt, I.Js, md->err, st));
                 size_t n = (size_t)I.Rp * I.ld;
                 for (int b = 0; b < 2; b++) {
                     HK(dalloc(&I.phi32[b], n));
                     HK(hipMemsetAsync(I.phi32[b], 0, n * 4, st));
-                    if (md->jt != JT_F32) {
+                    if (I.jt != JT_F32) {
                         HK(dalloc(&I.phib[b], n));
                         HK(hipMemsetAsync(I.phib[b], 0, n * 2, st));
                     }
@@ -361,9 +377,17 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
                                 (long long)q1, (long long)md->q);
     if (q1 == md->q) return HQA_OK;
     md->last_persistent = 0;
+    int ndense = 0;
+    for (auto &I : md->inst) ndense += I.layout == HQA_DENSE;
+    const bool batched = md->prec != HQA_PREC_F64_REF && ndense > 1 && !md->persistent;
+    if (batched) {
+        hipError_t e = launch_md_steps_batch(md, md->q, q1);
+        if (e != hipSuccess) return fail(HQA_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
+    }
     for (auto &I : md->inst) {
         hipError_t e;
         if (md->prec == HQA_PREC_F64_REF) e = launch_md_steps_f64(md, I, md->q, q1);
+        else if (I.layout == HQA_DENSE && batched) e = hipSuccess;
         else if (I.layout == HQA_DENSE) {
             e = hipErrorNotSupported;
             if (md->persistent) {

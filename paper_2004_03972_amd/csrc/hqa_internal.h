@@ -54,6 +54,7 @@ struct Instance {
     double *h64 = nullptr;    // N (zeros when no field)
     float *h32 = nullptr;     // N (or Np)
 
+    JType jt = JT_F32;        // storage type of Js
     void *Js = nullptr;       // dense storage for the fast paths, Np*Np of JType
     float *v32 = nullptr;     // CSR FP32 values
 
@@ -97,6 +98,7 @@ struct hqa_md {
     int32_t *bar = nullptr;                  // persistent-launch barrier counters + abort flag
     hqa::JType jt = hqa::JT_F32;
     int last_persistent = 0;                 // 1 if the last run used the persistent kernel
+    void *batch = nullptr;                   // device tile tables of a multi-instance batch
 };
 
 namespace hqa {

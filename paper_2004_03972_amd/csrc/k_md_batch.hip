@@ -1,0 +1,272 @@
+// k_md_batch.hip -- one MD step of many dense instances in one launch.
+//
+// A batch of uneven instances (sizes N_k, one shared schedule and replica count)
+// advances step by step; each step is one launch per storage type over a tile
+// table.  A tile is (instance, 32 rows, 64 replicas): wavefront w takes rows
+// i0 + 16 (w & 1) and the two replica tiles r0 + 32 (w >> 1) + {0, 16}, so every
+// J fragment it loads feeds two MFMA tiles and, with 64 replicas, each J row
+// block is read once per step.  The tile table is ordered longest-first (LPT by
+// padded size), so the largest instances start first and the short tiles fill
+// the tail of the step.  The field uses the chunk-to-chain decomposition of the
+// other dense kernels, and the update the same binary32 sequence, so a batched
+// instance evolves bit-identically to the same instance run alone.
+#include <type_traits>
+
+#include "hqa_internal.h"
+#include "md_epilogue.h"
+
+namespace hqa {
+
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_b;
+
+__device__ __forceinline__ bf16x8 cvt_fp8x8_b(uint2 raw) {
+    bf16x2_b a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.x, 1.0f, false);
+    bf16x2_b b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.x, 1.0f, true);
+    bf16x2_b c = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.y, 1.0f, false);
+    bf16x2_b d = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(raw.y, 1.0f, true);
+    bf16x8 o;
+    o[0] = a[0]; o[1] = a[1]; o[2] = b[0]; o[3] = b[1];
+    o[4] = c[0]; o[5] = c[1]; o[6] = d[0]; o[7] = d[1];
+    return o;
+}
+
+struct BatchInst {
+    int N, Np, ld, pad;
+    const void *J;
+    const float *h;
+    float *phi[2];
+    bf16 *xb[2];
+    float *p, *S;
+};
+
+struct BatchTile {
+    int inst, i0, r0, pad;
+};
+
+struct BatchArgs {
+    const BatchInst *inst;
+    const BatchTile *tiles;
+    int ntiles, R, M, W, cur;
+    int64_t T;
+    float rg;
+    const float *a32, *b32;
+    int32_t *err;
+};
+
+template <int JT>
+__global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
+    const BatchTile tl = a.tiles[blockIdx.x];
+    const BatchInst I = a.inst[tl.inst];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kg = lane >> 4;
+    const int i0 = tl.i0 + 16 * (w & 1);
+    const int rb = tl.r0 + 32 * (w >> 1);         // first of the wavefront's two replica tiles
+    if (i0 >= I.Np || rb >= a.R) return;
+    const int row = i0 + (lane & 15);
+    const float *phi_in = I.phi[a.cur];
+    const bf16 *xb_in = I.xb[a.cur];
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[c][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    // replica columns of the two tiles (clamped to valid rows of the state array;
+    // columns >= R only feed accumulators that are never stored)
+    int colr[2];
+#pragma unroll
+    for (int c = 0; c < 2; c++) colr[c] = min(rb + 16 * c + (lane & 15), a.R - 1);
+    if constexpr (JT == JT_F32) {
+        const float *Ja = (const float *)I.J + (int64_t)row * I.Np + 4 * kg;
+        const int ngroups = I.Np / 64;
+        for (int gi = 0; gi < ngroups; gi++) {
+            float4 A[4], B[2][4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int kk = gi * 64 + 16 * j;
+                A[j] = *(const float4 *)(Ja + kk);
+#pragma unroll
+                for (int c = 0; c < 2; c++)
+                    B[c][j] = *(const float4 *)(phi_in + (int64_t)colr[c] * I.ld + kk + 4 * kg);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].x, B[c][j].x, acc[c][j], 0, 0, 0);
+                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].y, B[c][j].y, acc[c][j], 0, 0, 0);
+                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].z, B[c][j].z, acc[c][j], 0, 0, 0);
+                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].w, B[c][j].w, acc[c][j], 0, 0, 0);
+                }
+        }
+    } else {
+        typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
+        const uint8_t *Ja = (const uint8_t *)I.J + ((int64_t)row * I.Np + 8 * kg) * (JT == JT_BF16 ? 2 : 1);
+        const int ngroups = I.Np / 128;
+        AT A[4], An[4];
+        bf16x8 B[2][4], Bn[2][4];
+        auto load = [&](int gi, AT (&Ag)[4], bf16x8 (&Bg)[2][4]) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int kk = gi * 128 + 32 * j;
+                Ag[j] = *(const AT *)(Ja + kk * (JT == JT_BF16 ? 2 : 1));
+#pragma unroll
+                for (int c = 0; c < 2; c++)
+                    Bg[c][j] = *(const bf16x8 *)(xb_in + (int64_t)colr[c] * I.ld + kk + 8 * kg);
+            }
+        };
+        load(0, A, B);
+        for (int gi = 0; gi < ngroups; gi++) {
+            if (gi + 1 < ngroups) load(gi + 1, An, Bn);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                bf16x8 av;
+                if constexpr (JT == JT_BF16) av = A[j];
+                else av = cvt_fp8x8_b(A[j]);
+#pragma unroll
+                for (int c = 0; c < 2; c++)
+                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, B[c][j], acc[c][j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                A[j] = An[j];
+#pragma unroll
+                for (int c = 0; c < 2; c++) B[c][j] = Bn[c][j];
+            }
+        }
+    }
+    const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
+    const int ib = i0 + 4 * kg;
+    const bool win = q + 1 >= a.T - a.W + 1;
+    bool bad = false;
+    float *phi_out = I.phi[a.cur ^ 1];
+    bf16 *xb_out = I.xb[a.cur ^ 1];
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        const int col = rb + 16 * c + (lane & 15);
+        if (col >= a.R || ib >= I.N) continue;
+        const f32x4 u = combine4(acc[c]);
+        const int64_t base = (int64_t)col * I.ld + ib;
+        float4 x = *(const float4 *)(phi_in + base);
+        float4 p = *(const float4 *)(I.p + base);
+        float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w}, xn[4];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            if (ib + v < I.N) {
+                leapfrog(cf, xs[v], u[v], I.h[ib + v], ps[v], xn[v]);
+                bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
+            } else {
+                xn[v] = 0.0f;
+                ps[v] = 0.0f;
+            }
+        }
+        *(float4 *)(phi_out + base) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+        *(float4 *)(I.p + base) = make_float4(ps[0], ps[1], ps[2], ps[3]);
+        if (xb_out) {
+            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+            bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
+            *(bf16x4 *)(xb_out + base) = b;
+        }
+        if (win) {
+            float4 s = *(const float4 *)(I.S + base);
+            s.x = s.x + xn[0]; s.y = s.y + xn[1]; s.z = s.z + xn[2]; s.w = s.w + xn[3];
+            *(float4 *)(I.S + base) = s;
+        }
+    }
+    if (bad) atomicOr(a.err, ERR_NONFINITE);
+}
+
+// Device tables of a batch, built once per handle: instance descriptors and one
+// LPT-ordered tile list per storage type.
+struct BatchPlan {
+    BatchInst *dinst = nullptr;
+    BatchTile *dtiles[3] = {nullptr, nullptr, nullptr};
+    int ntiles[3] = {0, 0, 0};
+};
+
+void free_batch_plan(void *p) {
+    BatchPlan *bp = (BatchPlan *)p;
+    if (!bp) return;
+    if (bp->dinst) (void)hipFree(bp->dinst);
+    for (int t = 0; t < 3; t++)
+        if (bp->dtiles[t]) (void)hipFree(bp->dtiles[t]);
+    delete bp;
+}
+
+static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
+    BatchPlan *bp = new BatchPlan();
+    std::vector<BatchInst> hi;
+    std::vector<int> dense;
+    for (size_t k = 0; k < md->inst.size(); k++) {
+        Instance &I = md->inst[k];
+        BatchInst b;
+        b.N = I.N; b.Np = I.Np; b.ld = I.ld; b.pad = 0;
+        b.J = I.Js; b.h = I.h32;
+        b.phi[0] = I.phi32[0]; b.phi[1] = I.phi32[1];
+        b.xb[0] = I.phib[0]; b.xb[1] = I.phib[1];
+        b.p = I.p32; b.S = I.S32;
+        hi.push_back(b);
+        if (I.layout == HQA_DENSE) dense.push_back((int)k);
+    }
+    // longest processing time first: larger padded size first, then instance index
+    std::stable_sort(dense.begin(), dense.end(), [&](int x, int y) {
+        return md->inst[x].Np > md->inst[y].Np;
+    });
+    std::vector<BatchTile> ht[3];
+    for (int k : dense) {
+        const Instance &I = md->inst[k];
+        for (int i0 = 0; i0 < I.Np; i0 += 32)
+            for (int r0 = 0; r0 < md->R; r0 += 64) ht[I.jt].push_back({k, i0, r0, 0});
+    }
+    hipError_t e = hipMalloc((void **)&bp->dinst, sizeof(BatchInst) * hi.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(bp->dinst, hi.data(), sizeof(BatchInst) * hi.size(), hipMemcpyHostToDevice);
+    for (int t = 0; t < 3 && e == hipSuccess; t++) {
+        bp->ntiles[t] = (int)ht[t].size();
+        if (!bp->ntiles[t]) continue;
+        e = hipMalloc((void **)&bp->dtiles[t], sizeof(BatchTile) * ht[t].size());
+        if (e == hipSuccess)
+            e = hipMemcpy(bp->dtiles[t], ht[t].data(), sizeof(BatchTile) * ht[t].size(),
+                          hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        free_batch_plan(bp);
+        return e;
+    }
+    out = bp;
+    return hipSuccess;
+}
+
+// Advance every dense instance of the handle from q0 to q1, one launch per step
+// and storage type.  Instances advance in lockstep, so one parity serves all.
+hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1) {
+    if (!md->batch) {
+        BatchPlan *bp = nullptr;
+        hipError_t e = build_plan(md, bp);
+        if (e != hipSuccess) return e;
+        md->batch = bp;
+    }
+    BatchPlan *bp = (BatchPlan *)md->batch;
+    int cur = -1;
+    for (auto &I : md->inst)
+        if (I.layout == HQA_DENSE) { cur = I.cur; break; }
+    if (cur < 0) return hipSuccess;
+    BatchArgs a;
+    a.inst = bp->dinst; a.R = md->R; a.M = md->sch.M; a.W = md->sch.W; a.T = md->sch.T;
+    a.rg = (float)md->sch.r_g; a.a32 = md->a32; a.b32 = md->b32; a.err = md->err;
+    for (int64_t q = q0; q < q1; q++) {
+        a.cur = cur;
+        for (int t = 0; t < 3; t++) {
+            if (!bp->ntiles[t]) continue;
+            a.tiles = bp->dtiles[t];
+            a.ntiles = bp->ntiles[t];
+            if (t == JT_F32) k_step_batch<JT_F32><<<a.ntiles, 256, 0, md->stream>>>(a, q);
+            else if (t == JT_BF16) k_step_batch<JT_BF16><<<a.ntiles, 256, 0, md->stream>>>(a, q);
+            else k_step_batch<JT_FP8><<<a.ntiles, 256, 0, md->stream>>>(a, q);
+        }
+        cur ^= 1;
+    }
+    for (auto &I : md->inst)
+        if (I.layout == HQA_DENSE) I.cur = cur;
+    return hipGetLastError();
+}
+
+}  // namespace hqa

@@ -33,6 +33,7 @@ struct DenseArgs {
     float *phi_out, *p, *S;
     bf16 *xb_out;
     float *u_out;       // field-only mode: U written here ([R][ld]), no update
+    int jt;             // storage type of J (host-side dispatch)
     int32_t *err;
 };
 
@@ -168,13 +169,13 @@ static DenseArgs dense_args(hqa_md *md, Instance &I) {
     a.J = I.Js; a.h = I.h32; a.a32 = md->a32; a.b32 = md->b32;
     a.phi_in = I.phi32[I.cur]; a.xb_in = I.phib[I.cur];
     a.phi_out = I.phi32[I.cur ^ 1]; a.xb_out = I.phib[I.cur ^ 1];
-    a.p = I.p32; a.S = I.S32; a.u_out = nullptr; a.err = md->err;
+    a.p = I.p32; a.S = I.S32; a.u_out = nullptr; a.err = md->err; a.jt = I.jt;
     return a;
 }
 
 template <bool FO>
 static void launch_one(hqa_md *md, const DenseArgs &a, dim3 grid, int64_t q, hipStream_t st) {
-    switch (md->jt) {
+    switch (a.jt) {
         case JT_F32: k_step_dense<JT_F32, FO><<<grid, 256, 0, st>>>(a, q); break;
         case JT_BF16: k_step_dense<JT_BF16, FO><<<grid, 256, 0, st>>>(a, q); break;
         default: k_step_dense<JT_FP8, FO><<<grid, 256, 0, st>>>(a, q); break;

@@ -426,8 +426,8 @@ hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
         max_wg = cus;   // one 256-thread workgroup per CU is always co-resident
     }
     PersistPlan pl;
-    if (!plan_persist(I, md->R, md->jt, max_wg, pl)) return hipErrorNotSupported;
-    const size_t esz = md->jt == JT_F32 ? 8 : 4;
+    if (!plan_persist(I, md->R, I.jt, max_wg, pl)) return hipErrorNotSupported;
+    const size_t esz = I.jt == JT_F32 ? 8 : 4;
     const int64_t half = (int64_t)I.Rp * I.ld;
     const size_t bytes = 2 * (size_t)half * esz;
     if (!I.xch || I.xch_bytes < bytes) {
@@ -462,7 +462,7 @@ hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
     a.jbytes = pl.jbytes;
     a.pstride = pl.pstride;
     a.spin_limit = (int64_t)1 << 22;
-    switch (md->jt) {
+    switch (I.jt) {
         case JT_F32: e = launch_jt<JT_F32>(a, pl, md->stream); break;
         case JT_BF16: e = launch_jt<JT_BF16>(a, pl, md->stream); break;
         default: e = launch_jt<JT_FP8>(a, pl, md->stream); break;

@@ -36,7 +36,7 @@ class HQAError(RuntimeError):
 
 class hqa_problem(C.Structure):
     _fields_ = [("n", C.c_int32), ("layout", C.c_int32), ("mem", C.c_int32),
-                ("reserved", C.c_int32), ("j", C.c_void_p), ("row_ptr", C.c_void_p),
+                ("storage", C.c_int32), ("j", C.c_void_p), ("row_ptr", C.c_void_p),
                 ("col", C.c_void_p), ("nnz", C.c_int64), ("h", C.c_void_p)]
 
 
@@ -201,11 +201,12 @@ def hqa_md_destroy(md):
 class Problem:
     """Owns host copies of an instance and its hqa_problem descriptor (host memory)."""
 
-    def __init__(self, J=None, h=None, row_ptr=None, col=None, val=None, n=None):
+    def __init__(self, J=None, h=None, row_ptr=None, col=None, val=None, n=None, storage=0):
+        storage = PRECISIONS.get(storage, storage) if storage else 0
         if J is not None:
             self.J = np.ascontiguousarray(J, dtype=np.float64)
             N = self.J.shape[0]
-            self.c = hqa_problem(N, HQA_DENSE, HQA_HOST, 0, self.J.ctypes.data, None, None,
+            self.c = hqa_problem(N, HQA_DENSE, HQA_HOST, storage, self.J.ctypes.data, None, None,
                                  N * N, None)
         else:
             self.rp = np.ascontiguousarray(row_ptr, dtype=np.int32)

@@ -1,0 +1,113 @@
+"""Batched uneven instances (one launch per step over an LPT tile table).
+
+- a batched instance evolves bit-identically to the same instance run alone,
+  with SK (BF16, inexact) and ER (FP8 e4m3, exact) instances mixed in one batch;
+- fields of every instance of a batch on a shared flux: FP8/BF16 storage equals
+  J . bf16(phi) (with J rounded to its storage) within 1e-5 relative;
+- a short FP32 batched run tracks the FP64 oracle (same step semantics).
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2004_03972_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    from paper_2004_03972_amd import hqa
+    hqa.lib()
+    return hqa
+
+
+def bf16_nearest(x):
+    """Nearest bfloat16 (ties to even) of binary64 values, chosen between the two
+    bfloat16 neighbours by exact binary64 distance (no double rounding)."""
+    x = np.asarray(x, dtype=np.float64)
+    f = x.astype(np.float32).view(np.uint32)
+    lo = (f & np.uint32(0xFFFF0000))
+    hi = lo + np.uint32(0x10000)
+    clo = lo.view(np.float32).astype(np.float64)
+    chi = hi.view(np.float32).astype(np.float64)
+    dlo, dhi = np.abs(x - clo), np.abs(x - chi)
+    even_lo = ((lo >> 16) & 1) == 0
+    pick_lo = (dlo < dhi) | ((dlo == dhi) & even_lo)
+    return np.where(pick_lo, clo, chi)
+
+
+def _mixed_batch(H, sizes_sk, sizes_er, seed0):
+    probs, Js = [], []
+    for k, N in enumerate(sizes_sk):
+        J = inst.sk(N, seed0 + k)
+        probs.append(H.Problem(J, storage="bf16"))
+        Js.append(("sk", J))
+    for k, N in enumerate(sizes_er):
+        J = inst.er_maxcut(N, 0.05, seed0 + 100 + k)
+        probs.append(H.Problem(J, storage="fp8"))
+        Js.append(("er", J))
+    return probs, Js
+
+
+@pytest.mark.parametrize("R", [64, 40])
+def test_batch_equals_individual_runs(H, R):
+    probs, Js = _mixed_batch(H, [100, 333, 517], [700, 1200], 10)
+    T = 160
+    b = H.MD(probs, H.make_schedule(T, 30), R, "bf16", seed=3)
+    b.run()
+    b.sync()
+    for k, p in enumerate(probs):
+        a = H.MD(p, H.make_schedule(T, 30), R, "bf16", seed=3)
+        a.run()
+        for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM):
+            assert np.array_equal(a.state(w), b.state(w, k)), (k, w)
+        a.close()
+
+
+def test_batch_fields_all_instances(H):
+    import torch
+    rng = np.random.default_rng(77)
+    sizes_sk = list(rng.integers(100, 700, size=6))
+    sizes_er = list(rng.integers(300, 1500, size=6))
+    probs, Js = _mixed_batch(H, sizes_sk, sizes_er, 40)
+    R = 64
+    b = H.MD(probs, H.make_schedule(10, 5), R, "bf16")
+    worst = 0.0
+    for k, (kind, J) in enumerate(Js):
+        N = J.shape[0]
+        phi = rng.uniform(-1.2, 1.2, size=(R, N))
+        b.set_state(H.HQA_STATE_PHI, phi, k)
+        u = b.field(k)
+        # the flux operand is rounded from its binary32 copy, J from binary64
+        phib = bf16_nearest(phi.astype(np.float32).astype(np.float64))
+        Jst = bf16_nearest(J)
+        u64 = phib @ Jst.T
+        rel = np.max(np.abs(u - u64)) / np.max(np.abs(u64))
+        worst = max(worst, rel)
+        dh = np.max(np.abs(u - phi @ J.T))
+        print(kind, N, "rel vs J.bf16(phi)", rel, "max |dh| vs FP64", dh, flush=True)
+    assert worst <= 1e-5
+
+
+def test_batch_f32_tracks_oracle(H):
+    sizes = [64, 150, 233, 97]
+    probs, Js = [], []
+    for k, N in enumerate(sizes):
+        J, h = inst.uniform_glass(N, 500 + k)
+        J *= 0.1
+        probs.append(H.Problem(J, h=h))
+        Js.append((J, h))
+    R, T, W = 8, 120, 20
+    b = H.MD(probs, H.make_schedule(T, W), R, "f32", seed=9)
+    b.run()
+    for k, (J, h) in enumerate(Js):
+        N = J.shape[0]
+        mp = orc.MDParams(T=T, W=W)
+        bar, phiT, _ = orc.md_run(orc.Problem(N, J=J, h=h), mp, np.zeros((R, N)),
+                                  orc.init_p0(9, N, R))
+        assert np.max(np.abs(b.state(H.HQA_STATE_PHI, k) - phiT)) < 1e-4
+        assert np.max(np.abs(b.state(H.HQA_STATE_PHIBAR, k) - bar)) < 1e-4

@@ -21,7 +21,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, "hqa_oracle.c")]
+_SRC = [os.path.join(_HERE, "hqa_oracle.c"), os.path.join(_HERE, "hqa_oracle_es.c")]
+NFEAT, NPARAM = 12, 5187
 
 # Schedule constants of the paper (Methods, "Scheduling functions for MD"):
 # (alpha_f, rho1, rho2) = (0.008, 4, 3), (beta_f, kappa1, kappa2) = (0.12, 0.05, 1).
@@ -80,6 +81,11 @@ def _declare(L):
         "or_enumerate": (C.c_int, [i32, i32, P, P, P, P]),
         "or_merge": (V, [i32, i32, i32, P, P, P]),
         "or_energy": (C.c_int, [P, i32, P, P, P]),
+        "or_es_features": (C.c_int, [P, P, i32, P, P, i64, i64, P, P, P]),
+        "or_gelu": (d, [d]),
+        "or_mlp_forward": (V, [P, i64, P, P]),
+        "or_mlp_loss_grad": (d, [P, i64, P, P, P, P]),
+        "or_adam_step": (V, [P, P, P, P, i64, i64, d, d, d, d]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -268,3 +274,45 @@ def hqa(pb: Problem, mp: MDParams, p0, n: int, phi0=None, nthreads: int = 1):
     return dict(phibar=phibar, phiT=phiT, pT=pT, amb_idx=A, spins_md=s_md, h_eff=he,
                 J_eff=Je, code=code, E_reduced=Ered, spins_hqa=s_hqa, E_md=E_md, cut_md=C_md,
                 E_hqa=E_hqa, cut_hqa=C_hqa)
+
+
+# ----------------------------------------------------------- learned early stop
+def es_features(pb: Problem, mp: MDParams, phi0, p0, K0: int, K1: int):
+    """Features [R, N, 12] at step K1 from statistics over steps [K0, K1); also
+    returns phi^(K1) and p^(K1-1/2)."""
+    phi0, p0 = _f64(phi0), _f64(p0)
+    R, N = phi0.shape
+    feat = np.empty((R, N, NFEAT))
+    phi, p = np.empty_like(phi0), np.empty_like(phi0)
+    st = lib().or_es_features(pb.c, mp.c, R, _ptr(phi0), _ptr(p0), K0, K1, _ptr(feat),
+                              _ptr(phi), _ptr(p))
+    if st != 0:
+        raise ValueError(f"or_es_features status {st}")
+    return feat, phi, p
+
+
+def gelu(z: float) -> float:
+    return lib().or_gelu(z)
+
+
+def mlp_forward(params, x):
+    params, x = _f64(params), _f64(np.atleast_2d(x))
+    prob = np.empty((x.shape[0], 3))
+    lib().or_mlp_forward(_ptr(params), x.shape[0], _ptr(x), _ptr(prob))
+    return prob
+
+
+def mlp_loss_grad(params, x, y, class_w):
+    params, x, cw = _f64(params), _f64(np.atleast_2d(x)), _f64(class_w)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    g = np.empty(NPARAM)
+    loss = lib().or_mlp_loss_grad(_ptr(params), x.shape[0], _ptr(x), _ptr(y), _ptr(cw), _ptr(g))
+    return loss, g
+
+
+def adam_step(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam update of (params, m, v) at step count t >= 1."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(grad)
+    lib().or_adam_step(_ptr(params), _ptr(g), _ptr(m), _ptr(v), params.size, t, lr, b1, b2, eps)

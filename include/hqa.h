@@ -228,6 +228,77 @@ hqa_status hqa_ising_energy(const hqa_problem *prob, const int8_t *spins, int32_
 /* Release every device buffer of the handle (NULL is accepted). */
 void hqa_md_destroy(hqa_md *md);
 
+/* ---------------------------------------------------------------------------
+ * Learned early stop.  The paper has no learned component; this is the
+ * library's extension: a small per-spin classifier, trained on trajectories of
+ * the method itself, predicts from the first steps which spins end frozen
+ * (and with which sign) and which end ambivalent, so that a run can stop early
+ * and hand the predicted ambivalent spins to the exact solver.
+ *
+ * Statistics: for every step q in a window [k0, k1) the step epilogue adds, per
+ * spin i and replica, with x = phi^(q), x' = phi^(q+1), u = (J phi^(q))_i,
+ * p = p^(q+1/2), nu = u / ||J_i||_2 and sgn(0) = +1:
+ *   x', x'^2, |x'|, [x' > 0], [sgn x' != sgn x], nu, nu^2, -sgn(x) nu, p^2.
+ * Features at the current step q (K = min(q, k1) - k0 window steps), per replica
+ * with sigma = rms_i phi^(q)_i and P = mean_i (sum p^2 / K):
+ *   0 mean x'/sigma, 1 std x'/sigma, 2 mean |x'|/sigma, 3 phi^(q)/sigma,
+ *   4 |2 mean[x'>0] - 1|, 5 sign-change rate, 6 mean nu/sigma, 7 std nu/sigma,
+ *   8 mean(-sgn x nu)/sigma, 9 mean p^2 / P, 10 ||J_i||_1 / mean_k ||J_k||_1, 11 q/T.
+ * Classifier: 12-64-64-3 perceptron with GELU x(1 + erf(x/sqrt 2))/2 and softmax
+ * over {0: frozen +, 1: frozen -, 2: ambivalent}; HQA_ES_NPARAM binary32
+ * parameters W1[64][12], b1[64], W2[64][64], b2[64], W3[3][64], b3[3] (row-major
+ * [out][in]).  Training minimises the class-weighted cross entropy
+ * sum_s w_{y_s} (-log prob_s[y_s]) / sum_s w_{y_s} with Adam (Kingma & Ba 2015;
+ * b1 = 0.9, b2 = 0.999, eps = 1e-8).
+ * ------------------------------------------------------------------------- */
+#define HQA_ES_NFEAT 12
+#define HQA_ES_NPARAM 5187
+
+/* Collect the statistics over steps [k0, k1) of the following runs (cleared now).
+ * Those steps run on the per-step kernels.  HQA_EUNSUPPORTED for the binary64
+ * reference precision; HQA_EINVAL unless 0 <= k0 < k1 <= T. */
+hqa_status hqa_md_stats_window(hqa_md *md, int64_t k0, int64_t k1);
+
+/* Features [R][N][12] (binary32) of instance k at the current step.  HQA_ESTATE if
+ * no window step has run.  Synchronises. */
+hqa_status hqa_md_features(hqa_md *md, int32_t instance, float *feat, int32_t dst_mem);
+
+/* Read-out from predicted class probabilities prob [R][N][3] instead of phibar
+ * (any step): s = +1 if P(frozen +) >= P(frozen -) else -1; the n_amb spins with
+ * the largest P(ambivalent) (ties: lower index; compared as 1 - P in binary32) are
+ * ambivalent; solve, outputs and errors as hqa_classify. */
+hqa_status hqa_classify_probs(hqa_md *md, int32_t instance, const float *prob, int32_t prob_mem,
+                              int32_t n_amb, int32_t solve, const hqa_classify_out *out,
+                              int32_t out_mem);
+
+typedef struct hqa_es hqa_es;
+
+/* New classifier: weights uniform in +-1/sqrt(fan_in) from the counter hash of the
+ * seed, biases 0, Adam moments 0.  All work on the given stream. */
+hqa_status hqa_es_create(uint64_t seed, void *hip_stream, hqa_es **out);
+
+/* Copy the HQA_ES_NPARAM parameters out, or in with import != 0 (which also resets
+ * the Adam state).  Synchronises. */
+hqa_status hqa_es_params(hqa_es *es, float *params, int32_t mem, int32_t import);
+
+/* Gradient (HQA_ES_NPARAM) and loss of the weighted cross entropy on n samples
+ * x [n][12], labels y [n] in {0,1,2}, class weights cw [3]; grad or loss may be
+ * NULL.  Inputs and outputs in `mem`.  Synchronises. */
+hqa_status hqa_es_grad(hqa_es *es, const float *x, const int32_t *y, int64_t n, const float *cw,
+                       float *grad, float *loss, int32_t mem);
+
+/* One Adam step on the minibatch (gradient as hqa_es_grad, learning rate lr);
+ * loss (may be NULL) receives the minibatch loss before the step. */
+hqa_status hqa_es_train_step(hqa_es *es, const float *x, const int32_t *y, int64_t n,
+                             const float *cw, float lr, float *loss, int32_t mem);
+
+/* Class probabilities prob [n][3] of x [n][12]; bf16_infer != 0 rounds weights and
+ * layer inputs to bfloat16 (binary32 accumulation).  Synchronises. */
+hqa_status hqa_es_predict(hqa_es *es, const float *x, int64_t n, float *prob, int32_t bf16_infer,
+                          int32_t mem);
+
+void hqa_es_destroy(hqa_es *es);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,7 @@ static void free_instance(Instance &I) {
     dfree(I.J64); dfree(I.rp); dfree(I.ci); dfree(I.h64); dfree(I.h32); dfree(I.Js); dfree(I.v32);
     for (int k = 0; k < 2; k++) { dfree(I.phi64[k]); dfree(I.phi32[k]); dfree(I.phib[k]); }
     dfree(I.p64); dfree(I.S64); dfree(I.p32); dfree(I.S32); dfree(I.xch);
+    dfree(I.st); dfree(I.n1); dfree(I.inv_n2);
     I = Instance();
 }
 
@@ -379,7 +380,11 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     md->last_persistent = 0;
     int ndense = 0;
     for (auto &I : md->inst) ndense += I.layout == HQA_DENSE;
-    const bool batched = md->prec != HQA_PREC_F64_REF && ndense > 1 && !md->persistent;
+    // steps inside an early-stop statistics window run on the per-step kernels,
+    // whose epilogues accumulate the statistics
+    const bool stats_live = md->stats_k1 > md->q && md->stats_k0 < q1;
+    const bool batched = md->prec != HQA_PREC_F64_REF && ndense > 1 && !md->persistent &&
+                         !stats_live;
     if (batched) {
         hipError_t e = launch_md_steps_batch(md, md->q, q1);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
@@ -390,7 +395,7 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
         else if (I.layout == HQA_DENSE && batched) e = hipSuccess;
         else if (I.layout == HQA_DENSE) {
             e = hipErrorNotSupported;
-            if (md->persistent) {
+            if (md->persistent && !stats_live) {
                 e = launch_md_persist(md, I, md->q, q1);
                 if (e == hipSuccess) md->last_persistent = 1;
                 else (void)hipGetLastError();
@@ -498,8 +503,11 @@ hqa_status hqa_md_hamiltonian(hqa_md *md, int32_t instance, double *H, int32_t d
     return HQA_OK;
 }
 
-hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
-                        const hqa_classify_out *out, int32_t out_mem) {
+// Read-out shared by hqa_classify (sort by |phibar|) and hqa_classify_probs (predicted
+// labels): selection, optional reduced problem and exact solve, merge, energies.
+static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                                const hqa_classify_out *out, int32_t out_mem, const float *prob,
+                                int32_t prob_mem) {
     hqa_status s = check_instance(md, instance);
     if (s != HQA_OK) return s;
     if (!out || !out->spins) return fail(HQA_EINVAL, "out->spins is required");
@@ -507,7 +515,8 @@ hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t sol
     const int R = md->R, N = I.N;
     if (n_amb < 0 || n_amb > N) return fail(HQA_EINVAL, "n_amb must lie in [0, N]");
     if (solve && n_amb > 24) return fail(HQA_EUNSUPPORTED, "exact enumeration limited to n <= 24");
-    if (md->q != md->sch.T) return fail(HQA_ESTATE, "classify needs the run to reach step T");
+    if (!prob && md->q != md->sch.T)
+        return fail(HQA_ESTATE, "classify needs the run to reach step T");
     if ((solve || out->energy || out->cut || out->h_eff) && !exact_ok(I))
         return fail(HQA_EUNSUPPORTED, "coupling exponents span too many binades for exact sums");
     if (solve && I.j_integral && I.es.msb + 2 * 16 + 8 > 62)
@@ -520,7 +529,20 @@ hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t sol
     int8_t *spins;
     HIPCHK(B.get(&amb, (size_t)R * (n_amb ? n_amb : 1)));
     HIPCHK(B.get(&spins, (size_t)R * N));
-    HIPCHK(launch_select(I, R, md->prec, md->sch.W, n_amb, amb, spins, st));
+    if (!prob) {
+        HIPCHK(launch_select(I, R, md->prec, md->sch.W, n_amb, amb, spins, st));
+    } else {
+        const float *dprob = prob;
+        float *tmp = nullptr, *keys = nullptr;
+        if (prob_mem == HQA_HOST) {
+            HIPCHK(B.get(&tmp, (size_t)R * N * 3));
+            HIPCHK(hipMemcpyAsync(tmp, prob, sizeof(float) * R * N * 3, hipMemcpyHostToDevice, st));
+            dprob = tmp;
+        }
+        HIPCHK(B.get(&keys, (size_t)R * N));
+        HIPCHK(launch_probs_to_keys((int64_t)R * N, dprob, spins, keys, st));
+        HIPCHK(launch_select_keys(N, R, keys, n_amb, amb, spins, st));
+    }
     double *h_eff = nullptr, *J_eff = nullptr, *e_red = nullptr;
     int64_t *code = nullptr;
     if (solve && n_amb > 0) {
@@ -552,6 +574,191 @@ hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t sol
     if (out->code && code) HIPCHK(hipMemcpyAsync(out->code, code, (size_t)R * 8, kd, st));
     if (out->e_reduced && e_red) HIPCHK(hipMemcpyAsync(out->e_reduced, e_red, (size_t)R * 8, kd, st));
     HIPCHK(hipStreamSynchronize(st));
+    return HQA_OK;
+}
+
+hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                        const hqa_classify_out *out, int32_t out_mem) {
+    return classify_impl(md, instance, n_amb, solve, out, out_mem, nullptr, HQA_HOST);
+}
+
+hqa_status hqa_classify_probs(hqa_md *md, int32_t instance, const float *prob, int32_t prob_mem,
+                              int32_t n_amb, int32_t solve, const hqa_classify_out *out,
+                              int32_t out_mem) {
+    if (!prob) return fail(HQA_EINVAL, "prob is NULL");
+    if (prob_mem != HQA_HOST && prob_mem != HQA_DEVICE) return fail(HQA_EINVAL, "bad prob_mem");
+    return classify_impl(md, instance, n_amb, solve, out, out_mem, prob, prob_mem);
+}
+
+hqa_status hqa_md_stats_window(hqa_md *md, int64_t k0, int64_t k1) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    if (md->prec == HQA_PREC_F64_REF)
+        return fail(HQA_EUNSUPPORTED, "early-stop statistics run on the binary32 paths");
+    if (k0 < 0 || k1 <= k0 || k1 > md->sch.T) return fail(HQA_EINVAL, "need 0 <= k0 < k1 <= T");
+    for (auto &I : md->inst) {
+        const size_t n = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
+        if (!I.st) {
+            HIPCHK(dalloc(&I.st, 9 * n));
+            HIPCHK(dalloc(&I.n1, (size_t)I.N));
+            HIPCHK(dalloc(&I.inv_n2, (size_t)I.N));
+            HIPCHK(launch_row_norms(I, I.n1, I.inv_n2, md->stream));
+            std::vector<float> h(I.N);
+            HIPCHK(hipMemcpyAsync(h.data(), I.n1, sizeof(float) * I.N, hipMemcpyDeviceToHost,
+                                  md->stream));
+            HIPCHK(hipStreamSynchronize(md->stream));
+            double s = 0.0;
+            for (float v : h) s += v;
+            I.mean_n1 = (float)(s / I.N);
+        }
+        HIPCHK(hipMemsetAsync(I.st, 0, sizeof(float) * 9 * n, md->stream));
+    }
+    md->stats_k0 = k0;
+    md->stats_k1 = k1;
+    return HQA_OK;
+}
+
+hqa_status hqa_md_features(hqa_md *md, int32_t instance, float *feat, int32_t dst_mem) {
+    hqa_status s = check_instance(md, instance);
+    if (s != HQA_OK) return s;
+    if (!feat) return fail(HQA_EINVAL, "feat is NULL");
+    Instance &I = md->inst[instance];
+    if (!I.st) return fail(HQA_ESTATE, "no statistics window set");
+    const int64_t K = std::min(md->q, md->stats_k1) - md->stats_k0;
+    if (K < 1) return fail(HQA_ESTATE, "no step of the statistics window has run");
+    const size_t n = (size_t)md->R * I.N * 12;
+    float *buf = feat;
+    if (dst_mem == HQA_HOST) HIPCHK(dalloc(&buf, n));
+    HIPCHK(launch_features(I, md->R, K, (float)((double)md->q / (double)md->sch.T), I.mean_n1,
+                           buf, md->stream));
+    if (dst_mem == HQA_HOST)
+        HIPCHK(hipMemcpyAsync(feat, buf, n * 4, hipMemcpyDeviceToHost, md->stream));
+    HIPCHK(hipStreamSynchronize(md->stream));
+    if (dst_mem == HQA_HOST) dfree(buf);
+    return HQA_OK;
+}
+
+// ------------------------------------------------------------- MLP model
+struct hqa_es {
+    hipStream_t stream = nullptr;
+    float *P = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *acc = nullptr;
+    int64_t t = 0;
+};
+
+void hqa_es_destroy(hqa_es *es) {
+    if (!es) return;
+    (void)hipStreamSynchronize(es->stream);
+    dfree(es->P); dfree(es->m); dfree(es->v); dfree(es->g); dfree(es->acc);
+    delete es;
+}
+
+hqa_status hqa_es_create(uint64_t seed, void *hip_stream, hqa_es **out) {
+    g_err.clear();
+    if (!out) return fail(HQA_EINVAL, "out is NULL");
+    *out = nullptr;
+    hqa_es *es = new hqa_es();
+    es->stream = (hipStream_t)hip_stream;
+    hipError_t e = dalloc(&es->P, HQA_ES_NPARAM);
+    if (e == hipSuccess) e = dalloc(&es->m, HQA_ES_NPARAM);
+    if (e == hipSuccess) e = dalloc(&es->v, HQA_ES_NPARAM);
+    if (e == hipSuccess) e = dalloc(&es->g, HQA_ES_NPARAM);
+    if (e == hipSuccess) e = dalloc(&es->acc, 4);
+    if (e == hipSuccess) e = hipMemsetAsync(es->m, 0, sizeof(float) * HQA_ES_NPARAM, es->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(es->v, 0, sizeof(float) * HQA_ES_NPARAM, es->stream);
+    if (e == hipSuccess) e = launch_mlp_init(es->P, seed, es->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(es->stream);
+    if (e != hipSuccess) {
+        hqa_es_destroy(es);
+        return fail(e == hipErrorOutOfMemory ? HQA_ENOMEM : HQA_EDEVICE, "es create: %s",
+                    hipGetErrorString(e));
+    }
+    *out = es;
+    return HQA_OK;
+}
+
+hqa_status hqa_es_params(hqa_es *es, float *params, int32_t mem, int32_t import) {
+    if (!es || !params) return fail(HQA_EINVAL, "bad arguments");
+    const size_t nb = sizeof(float) * HQA_ES_NPARAM;
+    if (import) {
+        HIPCHK(hipMemcpyAsync(es->P, params, nb, kind_in(mem), es->stream));
+        HIPCHK(hipMemsetAsync(es->m, 0, nb, es->stream));
+        HIPCHK(hipMemsetAsync(es->v, 0, nb, es->stream));
+        es->t = 0;
+    } else {
+        HIPCHK(hipMemcpyAsync(params, es->P, nb, kind_out(mem), es->stream));
+    }
+    HIPCHK(hipStreamSynchronize(es->stream));
+    return HQA_OK;
+}
+
+// Device copies of host minibatch inputs.
+static hqa_status es_inputs(hqa_es *es, DevBufs &B, const float *x, const int32_t *y,
+                            const float *cw, int64_t n, int32_t mem, const float **dx,
+                            const int32_t **dy, const float **dcw) {
+    *dx = x; *dy = y; *dcw = cw;
+    if (mem == HQA_DEVICE) return HQA_OK;
+    float *tx = nullptr, *tcw = nullptr;
+    int32_t *ty = nullptr;
+    HIPCHK(B.get(&tx, (size_t)n * 12));
+    HIPCHK(hipMemcpyAsync(tx, x, sizeof(float) * n * 12, hipMemcpyHostToDevice, es->stream));
+    *dx = tx;
+    if (y) {
+        HIPCHK(B.get(&ty, (size_t)n));
+        HIPCHK(hipMemcpyAsync(ty, y, sizeof(int32_t) * n, hipMemcpyHostToDevice, es->stream));
+        *dy = ty;
+    }
+    if (cw) {
+        HIPCHK(B.get(&tcw, 3));
+        HIPCHK(hipMemcpyAsync(tcw, cw, sizeof(float) * 3, hipMemcpyHostToDevice, es->stream));
+        *dcw = tcw;
+    }
+    return HQA_OK;
+}
+
+hqa_status hqa_es_grad(hqa_es *es, const float *x, const int32_t *y, int64_t n, const float *cw,
+                       float *grad, float *loss, int32_t mem) {
+    if (!es || !x || !y || !cw || n < 1) return fail(HQA_EINVAL, "bad arguments");
+    DevBufs B;
+    const float *dx, *dcw;
+    const int32_t *dy;
+    hqa_status s = es_inputs(es, B, x, y, cw, n, mem, &dx, &dy, &dcw);
+    if (s != HQA_OK) return s;
+    HIPCHK(launch_mlp_grad(es->P, n, dx, dy, dcw, es->g, es->acc, es->stream));
+    if (grad) HIPCHK(hipMemcpyAsync(grad, es->g, sizeof(float) * HQA_ES_NPARAM, kind_out(mem), es->stream));
+    if (loss) HIPCHK(hipMemcpyAsync(loss, es->acc + 2, sizeof(float), kind_out(mem), es->stream));
+    HIPCHK(hipStreamSynchronize(es->stream));
+    return HQA_OK;
+}
+
+hqa_status hqa_es_train_step(hqa_es *es, const float *x, const int32_t *y, int64_t n,
+                             const float *cw, float lr, float *loss, int32_t mem) {
+    if (!es || !x || !y || !cw || n < 1 || !(lr > 0.f)) return fail(HQA_EINVAL, "bad arguments");
+    DevBufs B;
+    const float *dx, *dcw;
+    const int32_t *dy;
+    hqa_status s = es_inputs(es, B, x, y, cw, n, mem, &dx, &dy, &dcw);
+    if (s != HQA_OK) return s;
+    HIPCHK(launch_mlp_grad(es->P, n, dx, dy, dcw, es->g, es->acc, es->stream));
+    es->t += 1;
+    HIPCHK(launch_adam(es->P, es->g, es->m, es->v, es->t, lr, es->stream));
+    if (loss) HIPCHK(hipMemcpyAsync(loss, es->acc + 2, sizeof(float), kind_out(mem), es->stream));
+    if (mem == HQA_HOST || loss) HIPCHK(hipStreamSynchronize(es->stream));
+    return HQA_OK;
+}
+
+hqa_status hqa_es_predict(hqa_es *es, const float *x, int64_t n, float *prob, int32_t bf16_infer,
+                          int32_t mem) {
+    if (!es || !x || !prob || n < 0) return fail(HQA_EINVAL, "bad arguments");
+    DevBufs B;
+    const float *dx, *dcw;
+    const int32_t *dy;
+    hqa_status s = es_inputs(es, B, x, nullptr, nullptr, n, mem, &dx, &dy, &dcw);
+    if (s != HQA_OK) return s;
+    float *dp = prob;
+    if (mem == HQA_HOST) HIPCHK(B.get(&dp, (size_t)n * 3));
+    HIPCHK(launch_mlp_predict(es->P, n, dx, dp, bf16_infer ? 1 : 0, es->stream));
+    if (mem == HQA_HOST)
+        HIPCHK(hipMemcpyAsync(prob, dp, sizeof(float) * n * 3, hipMemcpyDeviceToHost, es->stream));
+    HIPCHK(hipStreamSynchronize(es->stream));
     return HQA_OK;
 }
 

@@ -67,6 +67,10 @@ struct Instance {
     int cur = 0;              // phi[cur] holds phi^(q)
     void *xch = nullptr;      // persistent-kernel exchange buffers (tagged words)
     size_t xch_bytes = 0;
+    // learned early stop: nine statistics arrays (state layout), row norms
+    float *st = nullptr;
+    float *n1 = nullptr, *inv_n2 = nullptr;
+    float mean_n1 = 0.f;
 
     ExpStats es{0, 0};
     bool j_integral = false;  // every J and h is an integer
@@ -99,6 +103,7 @@ struct hqa_md {
     hqa::JType jt = hqa::JT_F32;
     int last_persistent = 0;                 // 1 if the last run used the persistent kernel
     void *batch = nullptr;                   // device tile tables of a multi-instance batch
+    int64_t stats_k0 = 0, stats_k1 = 0;      // early-stop statistics window [k0, k1)
 };
 
 namespace hqa {
@@ -137,5 +142,21 @@ hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *
                         int8_t *spins, hipStream_t st);
 hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
                          hipStream_t st);
+hipError_t launch_select_keys(int N, int R, const float *keys, int n, int32_t *amb,
+                              int8_t *spins, hipStream_t st);
+
+// learned early stop
+hipError_t launch_row_norms(const Instance &I, float *n1, float *inv_n2, hipStream_t st);
+hipError_t launch_features(const Instance &I, int R, int64_t K, float tau, float mean_n1,
+                           float *feat, hipStream_t st);
+hipError_t launch_mlp_init(float *P, uint64_t seed, hipStream_t st);
+hipError_t launch_mlp_predict(const float *P, int64_t B, const float *x, float *prob, int bf,
+                              hipStream_t st);
+hipError_t launch_mlp_grad(const float *P, int64_t B, const float *x, const int32_t *y,
+                           const float *cw, float *grad, float *acc, hipStream_t st);
+hipError_t launch_adam(float *P, const float *g, float *m, float *v, int64_t t, float lr,
+                       hipStream_t st);
+hipError_t launch_probs_to_keys(int64_t n, const float *prob, int8_t *spins, float *key,
+                                hipStream_t st);
 
 }  // namespace hqa

@@ -26,6 +26,9 @@ struct CsrArgs {
     float *phi_out, *p, *S;
     float *u_out;
     int32_t *err;
+    float *st;             // early-stop statistics (9 x state size) or null
+    int64_t sst;           // stride between the nine statistics arrays
+    const float *inv_n2;   // 1 / ||J_i||_2
 };
 
 template <bool FIELD_ONLY>
@@ -60,6 +63,13 @@ __global__ __launch_bounds__(256) void k_step_csr(CsrArgs a, int64_t q) {
         leapfrog(c, x.y, u.y, hi, p.y, xn.y);
         leapfrog(c, x.z, u.z, hi, p.z, xn.z);
         leapfrog(c, x.w, u.w, hi, p.w, xn.w);
+        if (a.st) {
+            const float in2 = a.inv_n2[i];
+            es_accumulate(a.st, a.sst, base + 0, x.x, xn.x, u.x, p.x, in2);
+            es_accumulate(a.st, a.sst, base + 1, x.y, xn.y, u.y, p.y, in2);
+            es_accumulate(a.st, a.sst, base + 2, x.z, xn.z, u.z, p.z, in2);
+            es_accumulate(a.st, a.sst, base + 3, x.w, xn.w, u.w, p.w, in2);
+        }
         *(float4 *)(a.phi_out + base) = xn;
         *(float4 *)(a.p + base) = p;
         if (q + 1 >= a.T - a.W + 1) {
@@ -80,6 +90,7 @@ static CsrArgs csr_args(hqa_md *md, Instance &I) {
     a.rp = I.rp; a.ci = I.ci; a.v = I.v32; a.h = I.h32; a.a32 = md->a32; a.b32 = md->b32;
     a.phi_in = I.phi32[I.cur]; a.phi_out = I.phi32[I.cur ^ 1];
     a.p = I.p32; a.S = I.S32; a.u_out = nullptr; a.err = md->err;
+    a.st = nullptr; a.sst = (int64_t)I.N * I.ld; a.inv_n2 = I.inv_n2;
     return a;
 }
 
@@ -88,6 +99,7 @@ hipError_t launch_md_steps_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1) 
     unsigned blocks = (unsigned)((n + 255) / 256);
     for (int64_t q = q0; q < q1; q++) {
         CsrArgs a = csr_args(md, I);
+        if (I.st && q >= md->stats_k0 && q < md->stats_k1) a.st = I.st;
         k_step_csr<false><<<blocks, 256, 0, md->stream>>>(a, q);
         I.cur ^= 1;
     }

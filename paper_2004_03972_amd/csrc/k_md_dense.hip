@@ -34,6 +34,9 @@ struct DenseArgs {
     bf16 *xb_out;
     float *u_out;       // field-only mode: U written here ([R][ld]), no update
     int jt;             // storage type of J (host-side dispatch)
+    float *st;          // early-stop statistics (9 x state size) or null
+    int64_t sst;
+    const float *inv_n2;
     int32_t *err;
 };
 
@@ -140,6 +143,8 @@ __global__ __launch_bounds__(256) void k_step_dense(DenseArgs a, int64_t q) {
         for (int v = 0; v < 4; v++) {
             if (ib + v < a.N) {
                 leapfrog(c, xs[v], acc[v], a.h[ib + v], ps[v], xn[v]);
+                if (a.st) es_accumulate(a.st, a.sst, base + v, xs[v], xn[v], acc[v], ps[v],
+                                        a.inv_n2[ib + v]);
                 bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
             } else {
                 xn[v] = 0.0f;
@@ -170,6 +175,7 @@ static DenseArgs dense_args(hqa_md *md, Instance &I) {
     a.phi_in = I.phi32[I.cur]; a.xb_in = I.phib[I.cur];
     a.phi_out = I.phi32[I.cur ^ 1]; a.xb_out = I.phib[I.cur ^ 1];
     a.p = I.p32; a.S = I.S32; a.u_out = nullptr; a.err = md->err; a.jt = I.jt;
+    a.st = nullptr; a.sst = (int64_t)I.Rp * I.ld; a.inv_n2 = I.inv_n2;
     return a;
 }
 
@@ -186,6 +192,7 @@ hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1
     dim3 grid(I.Np / 32, (I.Rp + 31) / 32);
     for (int64_t q = q0; q < q1; q++) {
         DenseArgs a = dense_args(md, I);
+        if (I.st && q >= md->stats_k0 && q < md->stats_k1) a.st = I.st;
         launch_one<false>(md, a, grid, q, md->stream);
         I.cur ^= 1;
     }

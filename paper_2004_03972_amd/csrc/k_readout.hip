@@ -27,9 +27,11 @@ struct SelArgs {
     const float *S32;
     int32_t *amb;
     int8_t *spins;
+    const float *keys;   // if set: keys [R][N] (non-negative) and spins already written
 };
 
 __device__ __forceinline__ uint64_t sel_key(const SelArgs &a, int r, int i, int8_t *sgn) {
+    if (a.keys) return (uint64_t)__float_as_uint(a.keys[(int64_t)r * a.N + i]);
     if (a.f64) {
         double pb = a.S64[(int64_t)r * a.N + i] / (double)a.W;
         if (sgn) *sgn = pb < 0.0 ? -1 : 1;
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(256) void k_select(SelArgs a) {
     __shared__ int wsum[2][4];
     const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // spins
-    for (int i = tid; i < a.N; i += 256) {
+    for (int i = tid; i < a.N && !a.keys; i += 256) {
         int8_t s;
         sel_key(a, r, i, &s);
         a.spins[(int64_t)r * a.N + i] = s;
@@ -107,6 +109,17 @@ hipError_t launch_select(const Instance &I, int R, int prec, int W, int n, int32
     SelArgs a;
     a.N = I.N; a.R = R; a.ld = I.ld; a.smaj = I.smaj; a.f64 = prec == HQA_PREC_F64_REF;
     a.W = W; a.n = n; a.S64 = I.S64; a.S32 = I.S32; a.amb = amb; a.spins = spins;
+    a.keys = nullptr;
+    k_select<<<R, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// Selection on explicit keys (ascending, ties to the lower index); spins untouched.
+hipError_t launch_select_keys(int N, int R, const float *keys, int n, int32_t *amb,
+                              int8_t *spins, hipStream_t st) {
+    SelArgs a;
+    a.N = N; a.R = R; a.ld = N; a.smaj = 0; a.f64 = 0; a.W = 1; a.n = n;
+    a.S64 = nullptr; a.S32 = nullptr; a.amb = amb; a.spins = spins; a.keys = keys;
     k_select<<<R, 256, 0, st>>>(a);
     return hipGetLastError();
 }

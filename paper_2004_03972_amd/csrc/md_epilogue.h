@@ -43,6 +43,25 @@ __device__ __forceinline__ void leapfrog(const StepCoef &c, float x, float u, fl
     xn = x + c.ad * p;
 }
 
+// Statistics of the learned early stop for one (spin, replica) and one step:
+// old flux xo = phi^(q), new flux xn = phi^(q+1), field u at phi^(q), momentum
+// p = p^(q+1/2), nu = u / ||J_i||_2 (inv_n2 = 1/||J_i||_2, 0 for an empty row).
+// Nine running sums, stored as st[j * stride + k]; sgn(0) = +1.
+__device__ __forceinline__ void es_accumulate(float *st, int64_t stride, int64_t k, float xo,
+                                              float xn, float u, float p, float inv_n2) {
+    const float nu = u * inv_n2;
+    const float so = xo < 0.0f ? -1.0f : 1.0f;
+    st[0 * stride + k] += xn;
+    st[1 * stride + k] += xn * xn;
+    st[2 * stride + k] += fabsf(xn);
+    st[3 * stride + k] += xn > 0.0f ? 1.0f : 0.0f;
+    st[4 * stride + k] += ((xn < 0.0f) != (xo < 0.0f)) ? 1.0f : 0.0f;
+    st[5 * stride + k] += nu;
+    st[6 * stride + k] += nu * nu;
+    st[7 * stride + k] += -so * nu;
+    st[8 * stride + k] += p * p;
+}
+
 __device__ __forceinline__ StepCoef step_coef(const float *a32, const float *b32, int64_t q,
                                               float rg, int M) {
     StepCoef c;

@@ -25,7 +25,11 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhqa.so"
 EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md_opts_default",
             "hqa_md_init", "hqa_md_run", "hqa_md_reset", "hqa_md_sync", "hqa_md_step_index", "hqa_md_state",
             "hqa_md_set_step", "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify",
-            "hqa_ising_energy", "hqa_md_destroy", "hqa_md_last_persistent")
+            "hqa_ising_energy", "hqa_md_destroy", "hqa_md_last_persistent",
+            "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
+            "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
+            "hqa_es_destroy")
+HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
 
 
 class HQAError(RuntimeError):
@@ -90,8 +94,19 @@ def lib():
         L.hqa_classify.argtypes = [P, i32, i32, i32, P, i32]
         L.hqa_ising_energy.argtypes = [P, P, i32, P, P, i32, P]
         L.hqa_md_destroy.argtypes = [P]
+        L.hqa_md_stats_window.argtypes = [P, i64, i64]
+        L.hqa_md_features.argtypes = [P, i32, P, i32]
+        L.hqa_classify_probs.argtypes = [P, i32, P, i32, i32, i32, P, i32]
+        L.hqa_es_create.argtypes = [C.c_uint64, P, P]
+        L.hqa_es_params.argtypes = [P, P, i32, i32]
+        L.hqa_es_grad.argtypes = [P, P, P, i64, P, P, P, i32]
+        L.hqa_es_train_step.argtypes = [P, P, P, i64, P, C.c_float, P, i32]
+        L.hqa_es_predict.argtypes = [P, P, i64, P, i32, i32]
+        L.hqa_es_destroy.argtypes = [P]
         for f in ("hqa_md_init", "hqa_md_run", "hqa_md_reset", "hqa_md_sync", "hqa_md_state", "hqa_md_set_step",
-                  "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify", "hqa_ising_energy"):
+                  "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify", "hqa_ising_energy",
+                  "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
+                  "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict"):
             getattr(L, f).restype = C.c_int
         if L.hqa_abi_version() != 1:
             raise ImportError("libhqa ABI version mismatch")
@@ -197,6 +212,107 @@ def hqa_md_destroy(md):
     lib().hqa_md_destroy(md)
 
 
+def hqa_md_stats_window(md, k0: int, k1: int):
+    _check(lib().hqa_md_stats_window(md, k0, k1))
+
+
+def hqa_md_features(md, instance: int, feat, dst_mem: int):
+    p, _k = _addr(feat)
+    _check(lib().hqa_md_features(md, instance, p, dst_mem))
+
+
+def hqa_classify_probs(md, instance: int, prob, prob_mem: int, n_amb: int, solve: int,
+                       out: hqa_classify_out, out_mem: int):
+    pp, _k = _addr(prob)
+    _check(lib().hqa_classify_probs(md, instance, pp, prob_mem, n_amb, solve, C.byref(out),
+                                    out_mem))
+
+
+def hqa_es_create(seed: int, stream: int = 0):
+    h = C.c_void_p()
+    _check(lib().hqa_es_create(seed, stream or None, C.byref(h)))
+    return h
+
+
+def hqa_es_params(es, params, mem: int, import_: int = 0):
+    p, _k = _addr(params)
+    _check(lib().hqa_es_params(es, p, mem, import_))
+
+
+def hqa_es_grad(es, x, y, n: int, cw, grad, loss, mem: int):
+    a = [_addr(v) for v in (x, y, cw, grad, loss)]
+    _check(lib().hqa_es_grad(es, a[0][0], a[1][0], n, a[2][0], a[3][0], a[4][0], mem))
+
+
+def hqa_es_train_step(es, x, y, n: int, cw, lr: float, loss, mem: int):
+    a = [_addr(v) for v in (x, y, cw, loss)]
+    _check(lib().hqa_es_train_step(es, a[0][0], a[1][0], n, a[2][0], lr, a[3][0], mem))
+
+
+def hqa_es_predict(es, x, n: int, prob, bf16_infer: int, mem: int):
+    a = [_addr(v) for v in (x, prob)]
+    _check(lib().hqa_es_predict(es, a[0][0], n, a[1][0], bf16_infer, mem))
+
+
+def hqa_es_destroy(es):
+    lib().hqa_es_destroy(es)
+
+
+class ES:
+    """The early-stop classifier with numpy in/out (host memory)."""
+
+    def __init__(self, seed: int = 0, stream: int = 0):
+        self.h = hqa_es_create(seed, stream)
+
+    def close(self):
+        if self.h:
+            hqa_es_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self) -> np.ndarray:
+        out = np.empty(HQA_ES_NPARAM, dtype=np.float32)
+        hqa_es_params(self.h, out, HQA_HOST)
+        return out
+
+    @params.setter
+    def params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        hqa_es_params(self.h, p, HQA_HOST, 1)
+
+    @staticmethod
+    def _xy(x, y=None, cw=None):
+        x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, HQA_ES_NFEAT)
+        y = None if y is None else np.ascontiguousarray(y, dtype=np.int32)
+        cw = None if cw is None else np.ascontiguousarray(cw, dtype=np.float32)
+        return x, y, cw
+
+    def grad(self, x, y, cw):
+        x, y, cw = self._xy(x, y, cw)
+        g = np.empty(HQA_ES_NPARAM, dtype=np.float32)
+        loss = np.empty(1, dtype=np.float32)
+        hqa_es_grad(self.h, x, y, x.shape[0], cw, g, loss, HQA_HOST)
+        return float(loss[0]), g
+
+    def train_step(self, x, y, cw, lr: float) -> float:
+        x, y, cw = self._xy(x, y, cw)
+        loss = np.empty(1, dtype=np.float32)
+        hqa_es_train_step(self.h, x, y, x.shape[0], cw, lr, loss, HQA_HOST)
+        return float(loss[0])
+
+    def predict(self, x, bf16: bool = False) -> np.ndarray:
+        x, _, _ = self._xy(x)
+        prob = np.empty((x.shape[0], 3), dtype=np.float32)
+        hqa_es_predict(self.h, x, x.shape[0], prob, int(bf16), HQA_HOST)
+        return prob
+
+
 # ------------------------------------------------------ marshalling conveniences
 class Problem:
     """Owns host copies of an instance and its hqa_problem descriptor (host memory)."""
@@ -298,7 +414,15 @@ class MD:
         hqa_md_hamiltonian(self.h, k, out, HQA_HOST)
         return out
 
-    def classify(self, n_amb: int, solve: bool = False, k: int = 0) -> dict:
+    def stats_window(self, k0: int, k1: int):
+        hqa_md_stats_window(self.h, k0, k1)
+
+    def features(self, k: int = 0) -> np.ndarray:
+        out = np.empty((self.R, self.problems[k].n, HQA_ES_NFEAT), dtype=np.float32)
+        hqa_md_features(self.h, k, out, HQA_HOST)
+        return out
+
+    def classify(self, n_amb: int, solve: bool = False, k: int = 0, prob=None) -> dict:
         N, R = self.problems[k].n, self.R
         res = dict(spins=np.empty((R, N), dtype=np.int8),
                    amb_idx=np.empty((R, max(n_amb, 1)), dtype=np.int32),
@@ -307,7 +431,11 @@ class MD:
                    e_reduced=np.full(R, np.nan))
         o = hqa_classify_out(*(res[f].ctypes.data for f in
                                ("spins", "amb_idx", "energy", "cut", "h_eff", "code", "e_reduced")))
-        hqa_classify(self.h, k, n_amb, int(solve), o, HQA_HOST)
+        if prob is None:
+            hqa_classify(self.h, k, n_amb, int(solve), o, HQA_HOST)
+        else:
+            prob = np.ascontiguousarray(prob, dtype=np.float32)
+            hqa_classify_probs(self.h, k, prob, HQA_HOST, n_amb, int(solve), o, HQA_HOST)
         res["amb_idx"] = res["amb_idx"][:, :n_amb]
         res["h_eff"] = res["h_eff"][:, :n_amb]
         return res

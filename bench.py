@@ -1,16 +1,22 @@
 """HQA-MD throughput on one MI355X: MD spin-updates/s, plain FP32 vs the chosen form.
 
-Workload: MAX-CUT on an Erdos-Renyi graph G(800, 0.06) with unit weights mapped to
-J = +w, 256 replicas, 5000 MD steps (paper schedule, M = 6, W = 100), n = 20
-ambivalent spins solved exactly.  One bench step is one pass of the whole hot
-path on the resident instance: reset of the initial state, T MD steps (field +
-fused leapfrog), the frozen/ambivalent sort, the reduced problem, exact
+Default workload: MAX-CUT on an Erdos-Renyi graph G(800, 0.06) with unit weights
+mapped to J = +w, 256 replicas, 5000 MD steps (paper schedule, M = 6, W = 100),
+n = 20 ambivalent spins solved exactly.  One bench step is one pass of the whole
+hot path on the resident instance: reset of the initial state, T MD steps (field
++ fused leapfrog), the frozen/ambivalent sort, the reduced problem, the exact
 enumeration, merge and exact energies/cuts.  value = N * R * T * steps / time of
-the chosen form (FP8 e4m3 J widened to BF16, BF16 flux operand, FP32 accumulate).
-The same steps run in plain FP32 (FP32 J and fluxes on FP32 MFMA) with the same
-initial momenta; the chosen form's best cut must be within 0.1% of FP32's.
+the chosen form.  Candidate forms: J in FP8 e4m3 (widened to BF16) or BF16, BF16
+flux operand, FP32 accumulation and state; the faster is reported, the other
+beside it.  The same steps run in plain FP32 with the same initial momenta; the
+chosen form's best cut must be within 0.1% of FP32's.
 
-  python bench.py [--steps K] [--warmup W] [--no-cpu] [--prec fp8|bf16|f32]
+Other workloads (measurement lines for the design notes, not the bench line):
+  --workload ea3d      3D +-J lattice 16^3, CSR FP32, R = 1024, T = 10000
+  --workload batch512  512 uneven instances (SK BF16 / ER FP8), R = 64, T = 5000
+  --workload copy      a plain device copy of known size (HBM counter calibration)
+
+  python bench.py [--steps K] [--warmup W] [--no-cpu] [--workload ...]
 """
 from __future__ import annotations
 
@@ -27,45 +33,52 @@ sys.path.insert(0, ROOT)
 
 N, P_EDGE, R, T, W, N_AMB = 800, 0.06, 256, 5000, 100, 20
 INSTANCE_SEED, RUN_SEED = 201, 2
-PEAK = {"bf16": 2.5e15, "fp8": 2.5e15, "f32": 157.3e12}   # dense MFMA FLOP/s (fp8 J runs bf16 MFMA)
+PEAK_MFMA = {"bf16": 2.5e15, "fp8": 2.5e15, "f32": 157.3e12}   # dense FLOP/s of the MFMA used
 HBM_PEAK = 8.0e12
+METRIC = "MD spin-updates/s (N×replicas×steps) at matched best cut; plain FP32 vs chosen"
 
 
 def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
 def run_form(hqa, torch, prob, prec, steps, warmup):
+    """Timed bench steps of one precision; returns times and read-out quality."""
     stream = torch.cuda.current_stream()
     md = hqa.MD(prob, hqa.make_schedule(T, W), R, prec, seed=RUN_SEED, require_exact=True,
                 stream=stream.cuda_stream)
-    best_cut, best_cut_md, md_ms = [], [], []
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for k in range(warmup):
         md.reset(RUN_SEED + 1000 + k)
         md.run()
         md.classify(N_AMB, solve=True)
     torch.cuda.synchronize()
-    ev[0].record(stream)
+    best_cut, best_md, md_ms, split = [], [], [], None
+    t0, t1 = _events(torch)
+    t0.record(stream)
     for k in range(steps):
         md.reset(RUN_SEED + k)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1 = _events(torch)
         e0.record(stream)
         md.run()
         e1.record(stream)
         g = md.classify(N_AMB, solve=True)          # synchronises
         md_ms.append(e0.elapsed_time(e1))
         best_cut.append(float(g["cut"].max()))
-        g0 = md.classify(N_AMB, solve=False) if k == 0 else None
-        if g0 is not None:
-            best_cut_md.append(float(g0["cut"].max()))
-            frozen_amb = dict(n_frozen=N - N_AMB, n_ambivalent=N_AMB)
-    ev[1].record(stream)
+    t1.record(stream)
     torch.cuda.synchronize()
-    total_ms = ev[0].elapsed_time(ev[1])
+    total_ms = t0.elapsed_time(t1)
+    # MD-alone read-out of the last step (outside the timed region)
+    g0 = md.classify(N_AMB, solve=False)
+    best_md.append(float(g0["cut"].max()))
+    split = {"n_frozen": N - N_AMB, "n_ambivalent": N_AMB,
+             "mean_abs_phibar_frozen": None}
     md.close()
-    return dict(total_ms=total_ms, md_ms=md_ms, best_cut=best_cut, best_cut_md=best_cut_md,
-                split=frozen_amb)
+    return dict(total_ms=total_ms, md_ms=md_ms, best_cut=best_cut, best_cut_md_alone=best_md,
+                split=split)
 
 
 def cpu_baseline():
@@ -83,8 +96,131 @@ def cpu_baseline():
     dt = time.perf_counter() - t0
     return {"value": N * Rs * T / dt, "unit": "spin-updates/s", "cores": min(threads, Rs),
             "kind": "oracle",
-            "sample": f"MD only: {Rs} replicas x {T} steps of the ER N={N} instance, FP64, "
-                      f"{dt:.1f} s"}
+            "sample": f"MD only: {Rs} of the {R} replicas x all {T} steps of the ER N={N} "
+                      f"instance, FP64 oracle, {dt:.1f} s"}
+
+
+def bench_er800(args, hqa, torch):
+    from paper_2004_03972_amd import instances as inst
+    J = inst.er_maxcut(N, P_EDGE, INSTANCE_SEED)
+    prob = hqa.Problem(J)
+    forms = {}
+    for prec in args.forms:
+        _log(f"bench: ER N={N} p={P_EDGE} R={R} T={T}; form {prec}")
+        forms[prec] = run_form(hqa, torch, prob, prec, args.steps, args.warmup)
+        _log(f"  {prec}: {forms[prec]['total_ms']:.1f} ms for {args.steps} steps")
+    upd = N * R * T
+    val = {p: upd * args.steps / (f["total_ms"] / 1e3) for p, f in forms.items()}
+    lowp = [p for p in forms if p != "f32"]
+    chosen = max(lowp, key=lambda p: val[p]) if lowp else "f32"
+    c = forms[chosen]
+    md_ms = float(np.mean(c["md_ms"]))
+    flop_per_launch = 2.0 * N * N * R           # field contraction of one MD step
+    launch_s = md_ms / 1e3 / T                  # one launch per MD step
+    achieved = flop_per_launch / launch_s
+    peak = PEAK_MFMA[chosen]
+    out = {
+        "metric": METRIC, "value": val[chosen], "unit": "spin-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": c["total_ms"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if chosen != "f32" else "f32", "data": "synthetic",
+        "config": {"workload": f"ER MAX-CUT G({N},{P_EDGE}) unit weights, J=+w, R={R} replicas, "
+                               f"T={T} MD steps, W={W}, n={N_AMB} exact; J storage {chosen}",
+                   "N": N, "replicas": R, "md_steps": T, "n_amb": N_AMB,
+                   "j_storage": chosen, "parallelism": "none (1 GPU)"},
+        "md_only_spin_updates_per_s": upd / (md_ms / 1e3),
+        "best_cut": {"chosen_hqa": c["best_cut"], "chosen_md_alone_last": c["best_cut_md_alone"]},
+        "split": c["split"],
+        "forms": {p: {"value": val[p], "ms_per_step": f["total_ms"] / args.steps,
+                      "md_ms": float(np.mean(f["md_ms"])), "best_cut_hqa": f["best_cut"]}
+                  for p, f in forms.items()},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": f"k_step_dense<{'JT_FP8' if chosen == 'fp8' else 'JT_BF16'}>",
+                     "flop_per_launch": flop_per_launch, "launch_us": launch_s * 1e6},
+    }
+    if "f32" in forms and chosen != "f32":
+        ratio = [a / b for a, b in zip(c["best_cut"], forms["f32"]["best_cut"])]
+        out["fp32"] = {"value": val["f32"], "best_cut_hqa": forms["f32"]["best_cut"]}
+        out["speedup_vs_fp32"] = val[chosen] / val["f32"]
+        out["matched_cut"] = {"min_ratio": min(ratio), "bar": 0.999, "ok": min(ratio) >= 0.999}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    return out
+
+
+def bench_ea3d(args, hqa, torch):
+    """3D +-J lattice 16^3, CSR FP32, 1024 replicas, 10000 steps (measurement line)."""
+    from paper_2004_03972_amd import instances as inst
+    L, Rr, Tt = 16, 1024, 10000
+    rp, ci, v = inst.ea3d(L, 301)
+    Nn = L ** 3
+    st = torch.cuda.current_stream()
+    md = hqa.MD(hqa.Problem(row_ptr=rp, col=ci, val=v), hqa.make_schedule(Tt, 100), Rr, "f32",
+                seed=3, stream=st.cuda_stream)
+    md.run(); md.sync()
+    times = []
+    for k in range(args.steps):
+        md.reset(3 + k)
+        e0, e1 = _events(torch)
+        e0.record(st); md.run(); e1.record(st)
+        g = md.classify(20, solve=True)
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.mean(times))
+    upd = Nn * Rr * Tt
+    bytes_alg = 16.0 * upd + 8.0 * v.size * Tt + 8.0 * Nn * Rr * 100   # state + J + window
+    return {"metric": "MD spin-updates/s", "workload": "EA 3D +-J 16^3 CSR FP32, R=1024, T=10000",
+            "value": upd / (ms / 1e3), "unit": "spin-updates/s", "md_ms": ms,
+            "roofline": {"bound": "hbm", "achieved": bytes_alg / (ms / 1e3) / 1e9,
+                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": bytes_alg / (ms / 1e3) / HBM_PEAK, "traffic": None,
+                         "kernel": "k_step_csr", "bytes_per_update": bytes_alg / upd},
+            "best_energy": float(g["energy"].min())}
+
+
+def bench_batch512(args, hqa, torch):
+    """512 uneven instances: SK N~U{100..2000} BF16, ER N~U{500..5000} p~U[0.01,0.1] FP8."""
+    from paper_2004_03972_amd import instances as inst
+    rng = np.random.default_rng(4)
+    K = args.instances
+    Rr, Tt = 64, args.md_steps or 5000
+    probs, flops, upd = [], 0.0, 0.0
+    for k in range(K):
+        if k < K // 2:
+            Nk = int(rng.integers(100, 2001))
+            probs.append(hqa.Problem(inst.sk(Nk, 4000 + k), storage="bf16"))
+        else:
+            Nk = int(rng.integers(500, 5001))
+            probs.append(hqa.Problem(inst.er_maxcut(Nk, rng.uniform(0.01, 0.1), 4000 + k),
+                                     storage="fp8"))
+        flops += 2.0 * Nk * Nk * Rr
+        upd += Nk * Rr
+        if k % 64 == 63:
+            _log(f"  generated {k + 1} instances")
+    st = torch.cuda.current_stream()
+    md = hqa.MD(probs, hqa.make_schedule(Tt, 100), Rr, "bf16", seed=4, stream=st.cuda_stream)
+    md.run(min(Tt, 10)); md.sync()
+    md.reset(4)
+    e0, e1 = _events(torch)
+    e0.record(st); md.run(); e1.record(st); md.sync()
+    ms = e0.elapsed_time(e1)
+    return {"metric": "MD spin-updates/s", "workload": f"{K} uneven instances, R={Rr}, T={Tt}",
+            "value": upd * Tt / (ms / 1e3), "unit": "spin-updates/s", "md_ms": ms,
+            "roofline": {"bound": "mfma", "achieved": flops * Tt / (ms / 1e3) / 1e12,
+                         "peak": 2.5e3, "unit": "TFLOP/s",
+                         "frac": flops * Tt / (ms / 1e3) / 2.5e15, "kernel": "k_step_batch"}}
+
+
+def bench_copy(args, hqa, torch):
+    """A plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB): HBM counter calibration."""
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"workload": "copy 1 GiB float32", "bytes_read": 4 * n, "bytes_written": 4 * n}
 
 
 def main():
@@ -92,64 +228,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="fp8", choices=["fp8", "bf16", "f32"])
+    ap.add_argument("--workload", default="er800", choices=["er800", "ea3d", "batch512", "copy"])
+    ap.add_argument("--forms", default="fp8,bf16,f32")
+    ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--md-steps", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true")
     args = ap.parse_args()
+    args.forms = [f for f in args.forms.split(",") if f]
     if args.gpus != 1:
-        print("this build runs on one GPU only: the method's replicas shard trivially, but no "
-              "multi-GPU path is built; run with --gpus 1", file=sys.stderr)
+        print("this build runs on one GPU: replicas and instances would shard across GPUs "
+              "without communication, but no multi-GPU path is built; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2004_03972_amd import hqa, instances as inst
+    from paper_2004_03972_amd import hqa
     hqa.lib()
     torch.cuda.set_device(0)
-    J = inst.er_maxcut(N, P_EDGE, INSTANCE_SEED)
-    prob = hqa.Problem(J)
-    _log(f"bench: ER N={N} p={P_EDGE} R={R} T={T}; chosen={args.prec}")
-    chosen = run_form(hqa, torch, prob, args.prec, args.steps, args.warmup)
-    _log("chosen done", chosen["total_ms"], "ms")
-    ref = None
-    if not args.no_fp32 and args.prec != "f32":
-        ref = run_form(hqa, torch, prob, "f32", args.steps, args.warmup)
-        _log("fp32 done", ref["total_ms"], "ms")
-    upd = N * R * T
-    value = upd * args.steps / (chosen["total_ms"] / 1e3)
-    md_ms = float(np.mean(chosen["md_ms"]))
-    flop_per_launch = 2.0 * N * N * R                  # field contraction of one MD step
-    launch_s = md_ms / 1e3 / T                         # one launch per MD step
-    achieved = flop_per_launch / launch_s
-    peak = PEAK[args.prec]
-    out = {
-        "metric": "MD spin-updates/s (N×replicas×steps) at matched best cut; "
-                  "plain FP32 vs chosen",
-        "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": chosen["total_ms"] / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16" if args.prec != "f32" else "f32", "data": "synthetic",
-        "config": {"workload": f"ER MAX-CUT G({N},{P_EDGE}) w=+1 -> J=+w, R={R}, T={T}, "
-                               f"W={W}, n={N_AMB} exact; J {args.prec}",
-                   "N": N, "replicas": R, "md_steps": T, "n_amb": N_AMB,
-                   "precision": args.prec, "parallelism": "none (1 GPU)"},
-        "md_only_spin_updates_per_s": upd / (md_ms / 1e3),
-        "best_cut": {"chosen_hqa": chosen["best_cut"], "chosen_md_alone": chosen["best_cut_md"]},
-        "split": chosen["split"],
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_step_dense (field + leapfrog)",
-                     "flop_per_launch": flop_per_launch, "launch_ms": launch_s * 1e3},
-    }
-    if ref is not None:
-        rv = upd * args.steps / (ref["total_ms"] / 1e3)
-        ratio = [c / f for c, f in zip(chosen["best_cut"], ref["best_cut"])]
-        out["fp32"] = {"value": rv, "ms_per_step": ref["total_ms"] / args.steps,
-                       "md_only_spin_updates_per_s": upd / (np.mean(ref["md_ms"]) / 1e3),
-                       "best_cut_hqa": ref["best_cut"]}
-        out["speedup_vs_fp32"] = value / rv
-        out["matched_cut"] = {"min_ratio": min(ratio), "bar": 0.999, "ok": min(ratio) >= 0.999}
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out), flush=True)
+    fn = {"er800": bench_er800, "ea3d": bench_ea3d, "batch512": bench_batch512,
+          "copy": bench_copy}[args.workload]
+    print(json.dumps(fn(args, hqa, torch)), flush=True)
 
 
 if __name__ == "__main__":

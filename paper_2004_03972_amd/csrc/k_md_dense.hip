@@ -10,7 +10,16 @@
 // consecutive rows of one replica, so the epilogue reads and writes 16-byte
 // vectors of the state.
 //
-// Workgroup tile: 32 rows x 32 replicas, one 16 x 16 MFMA tile per wavefront.
+// Workgroup: a block of 2 x TN output tiles (32 rows x 16 TN replicas, TN = 4
+// when the padded replica count allows), K split over the four wavefronts by
+// accumulation chain.  The dense field is accumulated in four chains (K chunk c
+// of 32 columns for BF16 operands, 16 for FP32, feeds chain c mod 4; see
+// combine4), and wavefront w computes chain w of every tile of the block:
+// chunks w, w+4, w+8, ... in ascending order, four chunks' loads in flight
+// together, each loaded fragment feeding several MFMAs.  The partial tiles meet
+// in LDS; the combine (a0 + a1) + (a2 + a3) and the leapfrog are shared out over
+// the wavefronts.  The result is bit-identical to the batched and persistent
+// kernels, which accumulate the same chains.
 #include <type_traits>
 
 #include "hqa_internal.h"
@@ -52,118 +61,150 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint2 raw) {
     return o;
 }
 
-// Accumulate one 16x16 tile U[i0..i0+16)[r0..r0+16) over the full K = Np in the
-// four chains of combine4 (chunk c -> chain c mod 4).
-template <int JT>
-__device__ __forceinline__ f32x4 tile_field(const DenseArgs &a, int i0, int r0, int lane) {
-    const int row = i0 + (lane & 15), col = r0 + (lane & 15), kg = lane >> 4;
-    f32x4 acc[4];
+// Chain w of a block of TM x TN output tiles (rows i0 + 16 tm, replicas r0 + 16 tn):
+// per chunk the wavefront loads TM A fragments and TN B fragments and issues
+// TM * TN MFMAs, so each fragment is reused across the block.
+template <int JT, int TM, int TN>
+__device__ __forceinline__ void chain_block(const DenseArgs &a, int i0, int r0, int lane, int w,
+                                            f32x4 (&acc)[TM][TN]) {
+    constexpr int CB = 4;
+    const int kg = lane >> 4;
 #pragma unroll
-    for (int j = 0; j < 4; j++) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    // Np is a multiple of 128: whole groups of four chunks; the next group's
-    // operands are loaded while the current group's MFMAs run.
+    for (int tm = 0; tm < TM; tm++)
+#pragma unroll
+        for (int tn = 0; tn < TN; tn++) acc[tm][tn] = (f32x4){0.f, 0.f, 0.f, 0.f};
     if constexpr (JT == JT_F32) {
-        const float *Ja = (const float *)a.J + (int64_t)row * a.Np + 4 * kg;
-        const float *Xb = a.phi_in + (int64_t)col * a.ld + 4 * kg;
-        const int ngroups = a.Np / 64;
-        float4 A[4], B[4], An[4], Bn[4];
+        const int nch = a.Np / 64;
+        for (int m0 = 0; m0 < nch; m0 += CB) {
+            float4 A[CB][TM], B[CB][TN];
 #pragma unroll
-        for (int j = 0; j < 4; j++) { A[j] = *(const float4 *)(Ja + 16 * j); B[j] = *(const float4 *)(Xb + 16 * j); }
-        for (int gi = 0; gi < ngroups; gi++) {
-            if (gi + 1 < ngroups) {
+            for (int m = 0; m < CB; m++) {
+                if (m0 + m >= nch) continue;
+                const int kk = 16 * (w + 4 * (m0 + m)) + 4 * kg;
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    An[j] = *(const float4 *)(Ja + (gi + 1) * 64 + 16 * j);
-                    Bn[j] = *(const float4 *)(Xb + (gi + 1) * 64 + 16 * j);
-                }
+                for (int tm = 0; tm < TM; tm++)
+                    A[m][tm] = *(const float4 *)((const float *)a.J +
+                                                 (int64_t)(i0 + 16 * tm + (lane & 15)) * a.Np + kk);
+#pragma unroll
+                for (int tn = 0; tn < TN; tn++)
+                    B[m][tn] = *(const float4 *)(a.phi_in +
+                                                 (int64_t)(r0 + 16 * tn + (lane & 15)) * a.ld + kk);
             }
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].x, B[j].x, acc[j], 0, 0, 0);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].y, B[j].y, acc[j], 0, 0, 0);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].z, B[j].z, acc[j], 0, 0, 0);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].w, B[j].w, acc[j], 0, 0, 0);
-            }
+            for (int m = 0; m < CB; m++) {
+                if (m0 + m >= nch) continue;
 #pragma unroll
-            for (int j = 0; j < 4; j++) { A[j] = An[j]; B[j] = Bn[j]; }
+                for (int tm = 0; tm < TM; tm++)
+#pragma unroll
+                    for (int tn = 0; tn < TN; tn++) {
+                        f32x4 &c = acc[tm][tn];
+                        c = __builtin_amdgcn_mfma_f32_16x16x4f32(A[m][tm].x, B[m][tn].x, c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x4f32(A[m][tm].y, B[m][tn].y, c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x4f32(A[m][tm].z, B[m][tn].z, c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x4f32(A[m][tm].w, B[m][tn].w, c, 0, 0, 0);
+                    }
+            }
         }
     } else {
         typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
-        const uint8_t *Ja = (const uint8_t *)a.J + ((int64_t)row * a.Np + 8 * kg) * (JT == JT_BF16 ? 2 : 1);
-        const bf16 *Xb = a.xb_in + (int64_t)col * a.ld + 8 * kg;
-        const int ngroups = a.Np / 128;
-        AT A[4], An[4];
-        bf16x8 B[4], Bn[4];
-        auto load = [&](int gi, AT (&Ag)[4], bf16x8 (&Bg)[4]) {
+        constexpr int esz = JT == JT_BF16 ? 2 : 1;
+        const int nch = a.Np / 128;
+        for (int m0 = 0; m0 < nch; m0 += CB) {
+            AT A[CB][TM];
+            bf16x8 B[CB][TN];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int kk = gi * 128 + 32 * j;
-                Ag[j] = *(const AT *)(Ja + kk * (JT == JT_BF16 ? 2 : 1));
-                Bg[j] = *(const bf16x8 *)(Xb + kk);
-            }
-        };
-        load(0, A, B);
-        for (int gi = 0; gi < ngroups; gi++) {
-            if (gi + 1 < ngroups) load(gi + 1, An, Bn);
+            for (int m = 0; m < CB; m++) {
+                if (m0 + m >= nch) continue;
+                const int kk = 32 * (w + 4 * (m0 + m)) + 8 * kg;
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                bf16x8 av;
-                if constexpr (JT == JT_BF16) av = A[j];
-                else av = fp8x8_to_bf16(A[j]);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, B[j], acc[j], 0, 0, 0);
+                for (int tm = 0; tm < TM; tm++)
+                    A[m][tm] = *(const AT *)((const uint8_t *)a.J +
+                                             ((int64_t)(i0 + 16 * tm + (lane & 15)) * a.Np + kk) * esz);
+#pragma unroll
+                for (int tn = 0; tn < TN; tn++)
+                    B[m][tn] = *(const bf16x8 *)(a.xb_in + (int64_t)(r0 + 16 * tn + (lane & 15)) * a.ld + kk);
             }
 #pragma unroll
-            for (int j = 0; j < 4; j++) { A[j] = An[j]; B[j] = Bn[j]; }
+            for (int m = 0; m < CB; m++) {
+                if (m0 + m >= nch) continue;
+#pragma unroll
+                for (int tm = 0; tm < TM; tm++) {
+                    bf16x8 av;
+                    if constexpr (JT == JT_BF16) av = A[m][tm];
+                    else av = fp8x8_to_bf16(A[m][tm]);
+#pragma unroll
+                    for (int tn = 0; tn < TN; tn++)
+                        acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, B[m][tn], acc[tm][tn], 0, 0, 0);
+                }
+            }
         }
     }
-    return combine4(acc);
 }
 
-template <int JT, bool FIELD_ONLY>
-__global__ __launch_bounds__(256) void k_step_dense(DenseArgs a, int64_t q) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i0 = blockIdx.x * 32 + 16 * (w & 1);
-    const int r0 = blockIdx.y * 32 + 16 * (w >> 1);
-    if (r0 >= a.Rp || i0 >= a.Np) return;
-    f32x4 acc = tile_field<JT>(a, i0, r0, lane);
-    const int col = r0 + (lane & 15);
-    const int ib = i0 + 4 * (lane >> 4);
-    if (col >= a.R || ib >= a.N) return;
+// Leapfrog of four consecutive rows (ib..ib+3) of replica col with field u.
+__device__ __forceinline__ void dense_update(const DenseArgs &a, int64_t q, int col, int ib,
+                                             const f32x4 &u) {
     const int64_t base = (int64_t)col * a.ld + ib;
-    if constexpr (FIELD_ONLY) {
-        *(float4 *)(a.u_out + base) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        return;
-    } else {
-        const StepCoef c = step_coef(a.a32, a.b32, q, a.rg, a.M);
-        float4 x = *(const float4 *)(a.phi_in + base);
-        float4 p = *(const float4 *)(a.p + base);
-        float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w}, xn[4];
-        bool bad = false;
+    const StepCoef c = step_coef(a.a32, a.b32, q, a.rg, a.M);
+    float4 x = *(const float4 *)(a.phi_in + base);
+    float4 p = *(const float4 *)(a.p + base);
+    float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w}, xn[4];
+    bool bad = false;
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            if (ib + v < a.N) {
-                leapfrog(c, xs[v], acc[v], a.h[ib + v], ps[v], xn[v]);
-                if (a.st) es_accumulate(a.st, a.sst, base + v, xs[v], xn[v], acc[v], ps[v],
-                                        a.inv_n2[ib + v]);
-                bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
-            } else {
-                xn[v] = 0.0f;
-                ps[v] = 0.0f;
-            }
+    for (int v = 0; v < 4; v++) {
+        if (ib + v < a.N) {
+            leapfrog(c, xs[v], u[v], a.h[ib + v], ps[v], xn[v]);
+            if (a.st) es_accumulate(a.st, a.sst, base + v, xs[v], xn[v], u[v], ps[v],
+                                    a.inv_n2[ib + v]);
+            bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
+        } else {
+            xn[v] = 0.0f;
+            ps[v] = 0.0f;
         }
-        *(float4 *)(a.phi_out + base) = make_float4(xn[0], xn[1], xn[2], xn[3]);
-        *(float4 *)(a.p + base) = make_float4(ps[0], ps[1], ps[2], ps[3]);
-        if (a.xb_out) {
-            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-            bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
-            *(bf16x4 *)(a.xb_out + base) = b;
+    }
+    *(float4 *)(a.phi_out + base) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+    *(float4 *)(a.p + base) = make_float4(ps[0], ps[1], ps[2], ps[3]);
+    if (a.xb_out) {
+        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+        bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
+        *(bf16x4 *)(a.xb_out + base) = b;
+    }
+    if (q + 1 >= a.T - a.W + 1) {
+        float4 s = *(const float4 *)(a.S + base);
+        s.x = s.x + xn[0]; s.y = s.y + xn[1]; s.z = s.z + xn[2]; s.w = s.w + xn[3];
+        *(float4 *)(a.S + base) = s;
+    }
+    if (bad) atomicOr(a.err, ERR_NONFINITE);
+}
+
+// Block of TM x TN output tiles (32 rows x 16 TN replicas for TM = 2): each
+// wavefront accumulates one chain of every tile; the partial tiles meet in LDS
+// and wavefront w combines and updates tiles w, w + 4, ... in chain order.
+template <int JT, int TM, int TN, bool FIELD_ONLY>
+__global__ __launch_bounds__(256) void k_step_block(DenseArgs a, int64_t q) {
+    __shared__ f32x4 part[4][TM * TN][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * 16 * TM, r0 = blockIdx.y * 16 * TN;
+    f32x4 acc[TM][TN];
+    chain_block<JT, TM, TN>(a, i0, r0, lane, w, acc);
+#pragma unroll
+    for (int tm = 0; tm < TM; tm++)
+#pragma unroll
+        for (int tn = 0; tn < TN; tn++) part[w][tm * TN + tn][lane] = acc[tm][tn];
+    __syncthreads();
+    for (int t = w; t < TM * TN; t += 4) {
+        const int tm = t / TN, tn = t % TN;
+        const int col = r0 + 16 * tn + (lane & 15);
+        const int ib = i0 + 16 * tm + 4 * (lane >> 4);
+        if (col >= a.R || ib >= a.N) continue;
+        const f32x4 parts[4] = {part[0][t][lane], part[1][t][lane], part[2][t][lane],
+                                part[3][t][lane]};
+        const f32x4 u = combine4(parts);
+        if constexpr (FIELD_ONLY) {
+            *(float4 *)(a.u_out + (int64_t)col * a.ld + ib) = make_float4(u[0], u[1], u[2], u[3]);
+        } else {
+            dense_update(a, q, col, ib, u);
         }
-        if (q + 1 >= a.T - a.W + 1) {
-            float4 s = *(const float4 *)(a.S + base);
-            s.x = s.x + xn[0]; s.y = s.y + xn[1]; s.z = s.z + xn[2]; s.w = s.w + xn[3];
-            *(float4 *)(a.S + base) = s;
-        }
-        if (bad) atomicOr(a.err, ERR_NONFINITE);
     }
 }
 
@@ -179,31 +220,41 @@ static DenseArgs dense_args(hqa_md *md, Instance &I) {
     return a;
 }
 
+// Replica tiles per block: 4 (64 replicas) when they divide Rp, else 2, else 1.
+static int block_tn(int Rp) { return Rp % 64 == 0 ? 4 : Rp % 32 == 0 ? 2 : 1; }
+
+template <int JT, bool FO>
+static void launch_jt(const DenseArgs &a, int tn, int64_t q, hipStream_t st) {
+    dim3 grid(a.Np / 32, a.Rp / (16 * tn));
+    if (tn == 4) k_step_block<JT, 2, 4, FO><<<grid, 256, 0, st>>>(a, q);
+    else if (tn == 2) k_step_block<JT, 2, 2, FO><<<grid, 256, 0, st>>>(a, q);
+    else k_step_block<JT, 2, 1, FO><<<grid, 256, 0, st>>>(a, q);
+}
+
 template <bool FO>
-static void launch_one(hqa_md *md, const DenseArgs &a, dim3 grid, int64_t q, hipStream_t st) {
+static void launch_one(const DenseArgs &a, int64_t q, hipStream_t st) {
+    const int tn = block_tn(a.Rp);
     switch (a.jt) {
-        case JT_F32: k_step_dense<JT_F32, FO><<<grid, 256, 0, st>>>(a, q); break;
-        case JT_BF16: k_step_dense<JT_BF16, FO><<<grid, 256, 0, st>>>(a, q); break;
-        default: k_step_dense<JT_FP8, FO><<<grid, 256, 0, st>>>(a, q); break;
+        case JT_F32: launch_jt<JT_F32, FO>(a, tn, q, st); break;
+        case JT_BF16: launch_jt<JT_BF16, FO>(a, tn, q, st); break;
+        default: launch_jt<JT_FP8, FO>(a, tn, q, st); break;
     }
 }
 
 hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
-    dim3 grid(I.Np / 32, (I.Rp + 31) / 32);
     for (int64_t q = q0; q < q1; q++) {
         DenseArgs a = dense_args(md, I);
         if (I.st && q >= md->stats_k0 && q < md->stats_k1) a.st = I.st;
-        launch_one<false>(md, a, grid, q, md->stream);
+        launch_one<false>(a, q, md->stream);
         I.cur ^= 1;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_field_dense(hqa_md *md, Instance &I, float *u, hipStream_t st) {
-    dim3 grid(I.Np / 32, (I.Rp + 31) / 32);
     DenseArgs a = dense_args(md, I);
     a.u_out = u;
-    launch_one<true>(md, a, grid, 0, st);
+    launch_one<true>(a, 0, st);
     return hipGetLastError();
 }
 

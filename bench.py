@@ -6,9 +6,9 @@ n = 20 ambivalent spins solved exactly.  One bench step is one pass of the whole
 hot path on the resident instance: reset of the initial state, T MD steps (field
 + fused leapfrog), the frozen/ambivalent sort, the reduced problem, the exact
 enumeration, merge and exact energies/cuts.  value = N * R * T * steps / time of
-the chosen form.  Candidate forms: J in FP8 e4m3 (widened to BF16) or BF16, BF16
-flux operand, FP32 accumulation and state; the faster is reported, the other
-beside it.  The same steps run in plain FP32 with the same initial momenta; the
+the chosen form: J stored exactly in FP8 e4m3 and widened to BF16 in registers,
+BF16 flux operand, FP32 accumulation and state (BF16 storage of J is reported
+beside it).  The same steps run in plain FP32 with the same initial momenta; the
 chosen form's best cut must be within 0.1% of FP32's.
 
 Other workloads (measurement lines for the design notes, not the bench line):
@@ -36,6 +36,32 @@ INSTANCE_SEED, RUN_SEED = 201, 2
 PEAK_MFMA = {"bf16": 2.5e15, "fp8": 2.5e15, "f32": 157.3e12}   # dense FLOP/s of the MFMA used
 HBM_PEAK = 8.0e12
 METRIC = "MD spin-updates/s (N×replicas×steps) at matched best cut; plain FP32 vs chosen"
+
+
+JT_NAME = {"f32": 0, "bf16": 1, "fp8": 2}
+
+
+def measured_traffic(name, sources="dense"):
+    """HBM bytes per launch from a committed PMC summary (FETCH_SIZE and WRITE_SIZE in KiB
+    per dispatch, each scaled by the factor a plain copy of known size gives), or None when
+    the summary is missing or the kernel's sources changed since the counters were taken."""
+    from paper_2004_03972_amd import profsum
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#", "$")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        srcs = profsum.DENSE_SOURCES if sources == "dense" else profsum.CSR_SOURCES
+        if kv.get("source_sha256") != profsum.source_hash(srcs):
+            return None
+        return (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_factor"])
+                + float(kv["write_kib_per_dispatch"]) * float(kv["write_factor"])) * 1024.0
+    except (KeyError, ValueError):
+        return None
 
 
 def _log(*a):
@@ -111,8 +137,10 @@ def bench_er800(args, hqa, torch):
         _log(f"  {prec}: {forms[prec]['total_ms']:.1f} ms for {args.steps} steps")
     upd = N * R * T
     val = {p: upd * args.steps / (f["total_ms"] / 1e3) for p, f in forms.items()}
-    lowp = [p for p in forms if p != "f32"]
-    chosen = max(lowp, key=lambda p: val[p]) if lowp else "f32"
+    # the chosen form: exact FP8 e4m3 storage of the unit weights (BF16 MFMA operands);
+    # BF16 storage is reported beside it
+    lowp = [p for p in ("fp8", "bf16") if p in forms]
+    chosen = lowp[0] if lowp else "f32"
     c = forms[chosen]
     md_ms = float(np.mean(c["md_ms"]))
     flop_per_launch = 2.0 * N * N * R           # field contraction of one MD step
@@ -136,8 +164,9 @@ def bench_er800(args, hqa, torch):
                       "md_ms": float(np.mean(f["md_ms"])), "best_cut_hqa": f["best_cut"]}
                   for p, f in forms.items()},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": f"k_step_dense<{'JT_FP8' if chosen == 'fp8' else 'JT_BF16'}>",
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(f"k_step_block_{chosen}_er800_pmc.txt"),
+                     "kernel": f"k_step_block<{JT_NAME[chosen]}, 2, 4, false>",
                      "flop_per_launch": flop_per_launch, "launch_us": launch_s * 1e6},
     }
     if "f32" in forms and chosen != "f32":
@@ -174,7 +203,8 @@ def bench_ea3d(args, hqa, torch):
             "value": upd / (ms / 1e3), "unit": "spin-updates/s", "md_ms": ms,
             "roofline": {"bound": "hbm", "achieved": bytes_alg / (ms / 1e3) / 1e9,
                          "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                         "frac": bytes_alg / (ms / 1e3) / HBM_PEAK, "traffic": None,
+                         "frac": bytes_alg / (ms / 1e3) / HBM_PEAK,
+                         "traffic": measured_traffic("k_step_csr_ea3d_pmc.txt", "csr"),
                          "kernel": "k_step_csr", "bytes_per_update": bytes_alg / upd},
             "best_energy": float(g["energy"].min())}
 

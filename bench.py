@@ -55,7 +55,8 @@ def measured_traffic(name, sources="dense"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        srcs = profsum.DENSE_SOURCES if sources == "dense" else profsum.CSR_SOURCES
+        srcs = {"dense": profsum.DENSE_SOURCES, "csr": profsum.CSR_SOURCES,
+                "resident": profsum.RESIDENT_SOURCES}[sources]
         if kv.get("source_sha256") != profsum.source_hash(srcs):
             return None
         return (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_factor"])
@@ -77,6 +78,8 @@ def run_form(hqa, torch, prob, prec, steps, warmup):
     stream = torch.cuda.current_stream()
     md = hqa.MD(prob, hqa.make_schedule(T, W), R, prec, seed=RUN_SEED, require_exact=True,
                 stream=stream.cuda_stream)
+    md.tune(20)                                    # plan and tile shape, untimed
+    plan = md.tuned_plan()
     for k in range(warmup):
         md.reset(RUN_SEED + 1000 + k)
         md.run()
@@ -104,7 +107,7 @@ def run_form(hqa, torch, prob, prec, steps, warmup):
              "mean_abs_phibar_frozen": None}
     md.close()
     return dict(total_ms=total_ms, md_ms=md_ms, best_cut=best_cut, best_cut_md_alone=best_md,
-                split=split)
+                split=split, plan=plan)
 
 
 def cpu_baseline():
@@ -143,8 +146,15 @@ def bench_er800(args, hqa, torch):
     chosen = lowp[0] if lowp else "f32"
     c = forms[chosen]
     md_ms = float(np.mean(c["md_ms"]))
-    flop_per_launch = 2.0 * N * N * R           # field contraction of one MD step
-    launch_s = md_ms / 1e3 / T                  # one launch per MD step
+    plan, tm, tn = c["plan"]
+    if plan == "resident":                      # two launches: before and inside the window
+        kernel = f"k_md_resident<{JT_NAME[chosen]}, {2 if chosen == 'fp8' else 1}, false>"
+        launches, srcs = 2, "resident"
+    else:                                       # one launch per MD step
+        kernel = f"k_step_block<{JT_NAME[chosen]}, {tm or 2}, {tn or 4}, false>"
+        launches, srcs = T, "dense"
+    flop_per_launch = 2.0 * N * N * R * T / launches   # field contraction (2 N^2 R per step)
+    launch_s = md_ms / 1e3 / launches
     achieved = flop_per_launch / launch_s
     peak = PEAK_MFMA[chosen]
     out = {
@@ -161,12 +171,14 @@ def bench_er800(args, hqa, torch):
         "best_cut": {"chosen_hqa": c["best_cut"], "chosen_md_alone_last": c["best_cut_md_alone"]},
         "split": c["split"],
         "forms": {p: {"value": val[p], "ms_per_step": f["total_ms"] / args.steps,
-                      "md_ms": float(np.mean(f["md_ms"])), "best_cut_hqa": f["best_cut"]}
+                      "md_ms": float(np.mean(f["md_ms"])), "best_cut_hqa": f["best_cut"],
+                      "plan": f["plan"]}
                   for p, f in forms.items()},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(f"k_step_block_{chosen}_er800_pmc.txt"),
-                     "kernel": f"k_step_block<{JT_NAME[chosen]}, 2, 4, false>",
+                     "traffic": measured_traffic(f"{kernel.split('<')[0]}_{chosen}_er800_pmc.txt",
+                                                 srcs),
+                     "kernel": kernel, "plan": plan,
                      "flop_per_launch": flop_per_launch, "launch_us": launch_s * 1e6},
     }
     if "f32" in forms and chosen != "f32":

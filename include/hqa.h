@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 1
+#define HQA_ABI_VERSION 2
 
 typedef enum {
     HQA_OK = 0,
@@ -117,10 +117,33 @@ typedef struct hqa_md_opts {
     int32_t init_mem;        /* where p0 / phi0 live */
     int32_t require_exact;   /* 1: fail with HQA_EUNSUPPORTED unless every J_ij converts
                                 exactly to the storage type of the precision */
-    int32_t persistent;      /* 1: dense steps run in one persistent launch when the
-                                instance fits; 0 (default): one launch per step */
+    int32_t plan;            /* hqa_plan for the dense binary32 instances (below);
+                                every plan gives bit-identical trajectories */
     int32_t reserved;
 } hqa_md_opts;
+
+/* Execution plans of the dense binary32 step.  All of them compute the same
+ * binary32 operations in the same order (K chunk c of 32 columns feeds MFMA
+ * accumulation chain c mod 4, field (a0 + a1) + (a2 + a3), then the fused
+ * leapfrog), so they differ only in speed.
+ *   HQA_PLAN_AUTO      the tuned plan of the instance if hqa_md_tune has run, else
+ *                      STEP (BATCH for several dense instances).
+ *   HQA_PLAN_STEP      one launch per MD step (any size).
+ *   HQA_PLAN_CLUSTER   all steps in one cooperative launch; workgroups of a cluster
+ *                      own row blocks and exchange fluxes through L2 every step.
+ *   HQA_PLAN_RESIDENT  all steps in one launch; one workgroup per 16 replicas keeps
+ *                      their whole state in LDS and streams J from L2 (BF16/FP8 J,
+ *                      N up to 800 on a device with 160 KB of LDS per workgroup).
+ *   HQA_PLAN_BATCH     (reported only) several dense instances in one launch per step.
+ * A plan that does not apply to an instance (too large, FP32 J, statistics window
+ * live) falls back to STEP for that run; hqa_md_last_plan reports what ran. */
+enum {
+    HQA_PLAN_AUTO = 0,
+    HQA_PLAN_STEP = 1,
+    HQA_PLAN_CLUSTER = 2,
+    HQA_PLAN_RESIDENT = 3,
+    HQA_PLAN_BATCH = 4
+};
 
 typedef struct hqa_md hqa_md;
 
@@ -134,7 +157,7 @@ const char *hqa_last_error(void);
  * (0.12, 0.05, 1), M = 6, W = 100, r_g = 1, T = 50000, not frozen. */
 void hqa_schedule_default(hqa_schedule *s);
 
-/* R = 1, F32, seed 0, random p0, phi0 = 0, one launch per step. */
+/* R = 1, F32, seed 0, random p0, phi0 = 0, plan HQA_PLAN_AUTO. */
 void hqa_md_opts_default(hqa_md_opts *o);
 
 /* Validate and upload `count` instances (symmetry, zero diagonal, finite values,
@@ -161,10 +184,28 @@ hqa_status hqa_md_reset(hqa_md *md, uint64_t seed);
 /* Wait for queued work; HQA_ENONFINITE if any flux or momentum became non-finite. */
 hqa_status hqa_md_sync(hqa_md *md);
 
-/* 1 if the last hqa_md_run advanced the dense instances in one persistent launch,
- * 0 if it used one launch per step (sparse or binary64 instances, persistent = 0, or
- * an instance too large for the persistent plan). */
-int32_t hqa_md_last_persistent(const hqa_md *md);
+/* The plan the last hqa_md_run used for the dense binary32 instances (HQA_PLAN_STEP,
+ * _CLUSTER, _RESIDENT or _BATCH; the last instance's when they differ), 0 if it
+ * advanced none (sparse or binary64 instances only). */
+int32_t hqa_md_last_plan(const hqa_md *md);
+
+/* Autotuner: for every dense binary32 instance, time each applicable plan and tile
+ * shape (per-step blocks of 16 or 32 rows x 16, 32 or 64 replicas; cluster; resident) over `steps`
+ * MD steps from the current state with HIP events on the handle's stream, restore
+ * the state, and keep the fastest for HQA_PLAN_AUTO.  Because the plans are
+ * bit-identical the choice never changes results.  Synchronises.  HQA_EINVAL for
+ * steps < 1; HQA_ESTATE if fewer than `steps` steps remain before T. */
+hqa_status hqa_md_tune(hqa_md *md, int32_t steps);
+
+/* The tuned plan of dense instance k (0 if not tuned, -1 for a bad argument); *tm and
+ * *tn, if not NULL, receive the per-step block shape in row and replica tiles of 16
+ * (0 = default). */
+int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn);
+
+/* Pin dense instance k to the per-step plan with blocks of tm row tiles (1 or 2) by
+ * tn replica tiles (1, 2 or 4; 16 tn must divide the replica count padded to a
+ * multiple of 16), as if the tuner had chosen it.  HQA_EINVAL otherwise. */
+hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn);
 
 /* Current step index q (fluxes are phi^(q), momenta p^(q-1/2), or p^(0) at q = 0). */
 int64_t hqa_md_step_index(const hqa_md *md);

@@ -61,7 +61,7 @@ static void dfree(void *p) {
 static void free_instance(Instance &I) {
     dfree(I.J64); dfree(I.rp); dfree(I.ci); dfree(I.h64); dfree(I.h32); dfree(I.Js); dfree(I.v32);
     for (int k = 0; k < 2; k++) { dfree(I.phi64[k]); dfree(I.phi32[k]); dfree(I.phib[k]); }
-    dfree(I.p64); dfree(I.S64); dfree(I.p32); dfree(I.S32); dfree(I.xch);
+    dfree(I.p64); dfree(I.S64); dfree(I.p32); dfree(I.S32); dfree(I.xch); dfree(I.Jt);
     dfree(I.st); dfree(I.n1); dfree(I.inv_n2);
     I = Instance();
 }
@@ -186,7 +186,7 @@ void hqa_md_opts_default(hqa_md_opts *o) {
     memset(o, 0, sizeof *o);
     o->replicas = 1;
     o->precision = HQA_PREC_F32;
-    o->persistent = 0;
+    o->plan = HQA_PLAN_AUTO;
 }
 
 void hqa_md_destroy(hqa_md *md) {
@@ -215,6 +215,8 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
         return fail(HQA_EINVAL, "unknown precision");
     if ((opts->p0 || opts->phi0) && opts->init_mem != HQA_HOST && opts->init_mem != HQA_DEVICE)
         return fail(HQA_EINVAL, "bad init_mem");
+    if (opts->plan < HQA_PLAN_AUTO || opts->plan > HQA_PLAN_RESIDENT)
+        return fail(HQA_EINVAL, "unknown plan %d", opts->plan);
     for (int k = 0; k < count; k++) {
         hqa_status s = check_problem(probs[k], k);
         if (s != HQA_OK) return s;
@@ -235,7 +237,14 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
     md->stream = st;
     md->R = opts->replicas;
     md->prec = opts->precision;
-    md->persistent = opts->persistent;
+    md->plan = opts->plan;
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            lds > 0)
+            md->max_lds = lds;
+    }
     md->jt = opts->precision == HQA_PREC_BF16 ? JT_BF16
              : opts->precision == HQA_PREC_FP8J_BF16 ? JT_FP8 : JT_F32;
     Schedule64 &S = md->sch;
@@ -361,13 +370,38 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
 
 int64_t hqa_md_step_index(const hqa_md *md) { return md ? md->q : -1; }
 
-int32_t hqa_md_last_persistent(const hqa_md *md) { return md ? md->last_persistent : 0; }
+int32_t hqa_md_last_plan(const hqa_md *md) { return md ? md->last_plan : 0; }
 
 hqa_status hqa_md_set_step(hqa_md *md, int64_t q) {
     if (!md) return fail(HQA_EINVAL, "null handle");
     if (q < 0 || q > md->sch.T) return fail(HQA_EINVAL, "step %lld outside [0, T]", (long long)q);
     md->q = q;
     return HQA_OK;
+}
+
+// Steps [q0, q1) of one dense binary32 instance under `plan`; a plan that does not
+// apply (or whose launch is refused) falls back to one launch per step.
+static hipError_t run_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1, bool stats_live,
+                            int plan, int *used) {
+    if (plan == HQA_PLAN_AUTO) plan = I.tuned_plan ? I.tuned_plan : HQA_PLAN_STEP;
+    if (!stats_live && plan == HQA_PLAN_RESIDENT && resident_fits(I, md->max_lds)) {
+        hipError_t e = launch_md_resident(md, I, q0, q1);
+        if (e == hipSuccess) {
+            *used = HQA_PLAN_RESIDENT;
+            return e;
+        }
+        (void)hipGetLastError();
+    }
+    if (!stats_live && plan == HQA_PLAN_CLUSTER) {
+        hipError_t e = launch_md_persist(md, I, q0, q1);
+        if (e == hipSuccess) {
+            *used = HQA_PLAN_CLUSTER;
+            return e;
+        }
+        (void)hipGetLastError();
+    }
+    *used = HQA_PLAN_STEP;
+    return launch_md_steps_dense(md, I, q0, q1);
 }
 
 hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
@@ -377,31 +411,25 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     if (q1 < md->q) return fail(HQA_ESTATE, "until_step %lld is before the current step %lld",
                                 (long long)q1, (long long)md->q);
     if (q1 == md->q) return HQA_OK;
-    md->last_persistent = 0;
+    md->last_plan = 0;
     int ndense = 0;
     for (auto &I : md->inst) ndense += I.layout == HQA_DENSE;
     // steps inside an early-stop statistics window run on the per-step kernels,
     // whose epilogues accumulate the statistics
     const bool stats_live = md->stats_k1 > md->q && md->stats_k0 < q1;
-    const bool batched = md->prec != HQA_PREC_F64_REF && ndense > 1 && !md->persistent &&
-                         !stats_live;
+    const bool batched = md->prec != HQA_PREC_F64_REF && ndense > 1 &&
+                         md->plan == HQA_PLAN_AUTO && !stats_live;
     if (batched) {
         hipError_t e = launch_md_steps_batch(md, md->q, q1);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
+        md->last_plan = HQA_PLAN_BATCH;
     }
     for (auto &I : md->inst) {
         hipError_t e;
         if (md->prec == HQA_PREC_F64_REF) e = launch_md_steps_f64(md, I, md->q, q1);
         else if (I.layout == HQA_DENSE && batched) e = hipSuccess;
-        else if (I.layout == HQA_DENSE) {
-            e = hipErrorNotSupported;
-            if (md->persistent && !stats_live) {
-                e = launch_md_persist(md, I, md->q, q1);
-                if (e == hipSuccess) md->last_persistent = 1;
-                else (void)hipGetLastError();
-            }
-            if (e != hipSuccess) e = launch_md_steps_dense(md, I, md->q, q1);
-        } else e = launch_md_steps_csr(md, I, md->q, q1);
+        else if (I.layout == HQA_DENSE) e = run_dense(md, I, md->q, q1, stats_live, md->plan, &md->last_plan);
+        else e = launch_md_steps_csr(md, I, md->q, q1);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "step launch: %s", hipGetErrorString(e));
     }
     md->q = q1;
@@ -421,6 +449,144 @@ hqa_status hqa_md_reset(hqa_md *md, uint64_t seed) {
     }
     md->q = 0;
     return HQA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of the dense binary32 step.  Every candidate computes the same
+// binary32 operations in the same order, so the tuner may pick by time alone:
+// it snapshots the state, times `steps` steps of each candidate from it with
+// HIP events, restores it after each, and keeps the fastest for HQA_PLAN_AUTO.
+// ---------------------------------------------------------------------------
+struct TuneCand {
+    int plan, tm, tn;
+};
+
+hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    if (steps < 1) return fail(HQA_EINVAL, "steps must be >= 1");
+    if (md->q + steps > md->sch.T) return fail(HQA_ESTATE, "fewer than %d steps remain before T", steps);
+    if (md->prec == HQA_PREC_F64_REF) return HQA_OK;
+    HIPCHK(hipStreamSynchronize(md->stream));
+    const int64_t k0 = md->stats_k0, k1 = md->stats_k1;
+    md->stats_k0 = md->stats_k1 = 0;   // candidates accumulate no statistics
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hqa_status rs = HQA_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rs = fail(HQA_EDEVICE, "event creation failed");
+    for (auto &I : md->inst) {
+        if (rs != HQA_OK) break;
+        if (I.layout != HQA_DENSE) continue;
+        const size_t n = (size_t)I.Rp * I.ld;
+        float *sx = nullptr, *sp = nullptr, *sS = nullptr;
+        bf16 *sb = nullptr;
+        if (dalloc(&sx, n) != hipSuccess || dalloc(&sp, n) != hipSuccess ||
+            dalloc(&sS, n) != hipSuccess || dalloc(&sb, n) != hipSuccess) {
+            dfree(sx); dfree(sp); dfree(sS); dfree(sb);
+            rs = fail(HQA_ENOMEM, "tuner snapshot");
+            break;
+        }
+        const int cur0 = I.cur;
+        auto copy = [&](bool save) -> hipError_t {
+            hipError_t e = hipSuccess;
+            auto cp = [&](void *a, void *b, size_t bytes) {
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(save ? b : a, save ? a : b, bytes, hipMemcpyDeviceToDevice,
+                                       md->stream);
+            };
+            cp(I.phi32[cur0], sx, n * 4);
+            cp(I.p32, sp, n * 4);
+            cp(I.S32, sS, n * 4);
+            if (I.phib[cur0]) cp(I.phib[cur0], sb, n * 2);   // BF16 operand copy, if kept
+            I.cur = cur0;
+            return e;
+        };
+        std::vector<TuneCand> cands;
+        for (int tm : {2, 1})
+            for (int tn : {4, 2, 1})
+                if (I.Rp % (16 * tn) == 0) cands.push_back({HQA_PLAN_STEP, tm, tn});
+        cands.push_back({HQA_PLAN_CLUSTER, 0, 0});
+        if (resident_fits(I, md->max_lds)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0});
+        float best = 1e30f;
+        TuneCand pick{HQA_PLAN_STEP, 0, 0};
+        const int tn0 = I.step_tn, tm0 = I.step_tm;
+        const char *stage = "snapshot";
+        hipError_t he = copy(true);
+        TuneCand failed{0, 0, 0};
+        for (const TuneCand &c : cands) {
+            if (he != hipSuccess) break;
+            failed = c;
+            I.step_tn = c.tn;
+            I.step_tm = c.tm;
+            float ms = 0.f;
+            for (int pass = 0; pass < 2 && he == hipSuccess; pass++) {   // pass 0 warms up
+                int used = 0;
+                stage = "event record";
+                he = hipEventRecord(e0, md->stream);
+                if (he == hipSuccess) {
+                    stage = "run";
+                    he = run_dense(md, I, md->q, md->q + steps, false, c.plan, &used);
+                }
+                if (he == hipSuccess) {
+                    stage = "event record";
+                    he = hipEventRecord(e1, md->stream);
+                }
+                if (he == hipSuccess) {
+                    stage = "event synchronize";
+                    he = hipEventSynchronize(e1);
+                }
+                if (he == hipSuccess) {
+                    stage = "elapsed time";
+                    he = hipEventElapsedTime(&ms, e0, e1);
+                }
+                if (he == hipSuccess) {
+                    stage = "restore";
+                    he = copy(false);
+                }
+                if (he == hipSuccess && used != c.plan) ms = 1e30f;   // not applicable
+            }
+            if (he == hipSuccess && ms < best) {
+                best = ms;
+                pick = c;
+            }
+        }
+        I.step_tn = tn0;
+        I.step_tm = tm0;
+        if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
+        dfree(sx); dfree(sp); dfree(sS); dfree(sb);
+        if (he != hipSuccess) {
+            rs = fail(HQA_EDEVICE, "tuning (plan %d, tiles %d x %d, %s): %s", failed.plan, failed.tm,
+                      failed.tn, stage, hipGetErrorString(he));
+            break;
+        }
+        I.tuned_plan = pick.plan;
+        I.step_tn = pick.tn;
+        I.step_tm = pick.tm;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    md->stats_k0 = k0;
+    md->stats_k1 = k1;
+    return rs;
+}
+
+hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    if (k < 0 || k >= (int32_t)md->inst.size()) return fail(HQA_EINVAL, "instance %d out of range", k);
+    Instance &I = md->inst[k];
+    if (I.layout != HQA_DENSE) return fail(HQA_EINVAL, "instance %d is not dense", k);
+    if ((tm != 1 && tm != 2) || (tn != 1 && tn != 2 && tn != 4) || I.Rp % (16 * tn) != 0)
+        return fail(HQA_EINVAL, "block of %d x %d tiles does not fit (padded replicas %d)", tm, tn, I.Rp);
+    I.step_tm = tm;
+    I.step_tn = tn;
+    I.tuned_plan = HQA_PLAN_STEP;
+    return HQA_OK;
+}
+
+int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn) {
+    if (!md || k < 0 || k >= (int32_t)md->inst.size()) return -1;
+    if (tm) *tm = md->inst[k].step_tm;
+    if (tn) *tn = md->inst[k].step_tn;
+    return md->inst[k].tuned_plan;
 }
 
 hqa_status hqa_md_sync(hqa_md *md) {

@@ -56,6 +56,7 @@ struct Instance {
 
     JType jt = JT_F32;        // storage type of Js
     void *Js = nullptr;       // dense storage for the fast paths, Np*Np of JType
+    void *Jt = nullptr;       // MFMA-tiled copy of Js for the resident plan (built on first use)
     float *v32 = nullptr;     // CSR FP32 values
 
     // state
@@ -74,6 +75,10 @@ struct Instance {
 
     ExpStats es{0, 0};
     bool j_integral = false;  // every J and h is an integer
+    // dense binary32 plan chosen by the tuner (0: not tuned) and its per-step tile width
+    int32_t tuned_plan = 0;
+    int32_t step_tn = 0;      // replica tiles of 16 per per-step block (0: widest that divides Rp)
+    int32_t step_tm = 0;      // row tiles of 16 per per-step block (0: 2)
 };
 
 struct Schedule64 {
@@ -91,7 +96,8 @@ struct hqa_md {
     hipStream_t stream = nullptr;
     int32_t R = 1;
     int32_t prec = HQA_PREC_F32;
-    int32_t persistent = 1;
+    int32_t plan = HQA_PLAN_AUTO;            // requested plan of the dense binary32 step
+    int32_t max_lds = 65536;                 // LDS bytes per workgroup on the device
     hqa::Schedule64 sch{};
     int64_t q = 0;
     std::vector<hqa::Instance> inst;
@@ -101,7 +107,7 @@ struct hqa_md {
     int32_t *scratch_i = nullptr;            // small device scratch (ints)
     int32_t *bar = nullptr;                  // persistent-launch barrier counters + abort flag
     hqa::JType jt = hqa::JT_F32;
-    int last_persistent = 0;                 // 1 if the last run used the persistent kernel
+    int last_plan = 0;                       // plan the last run used (HQA_PLAN_*)
     void *batch = nullptr;                   // device tile tables of a multi-instance batch
     int64_t stats_k0 = 0, stats_k1 = 0;      // early-stop statistics window [k0, k1)
 };
@@ -128,6 +134,9 @@ hipError_t launch_export(const Instance &I, int R, int prec, int what, double *d
 
 // MD steps: advance from step q to q + nsteps
 hipError_t launch_md_steps(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+size_t resident_lds_bytes(int N);
+bool resident_fits(const Instance &I, int max_lds);
+hipError_t launch_md_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_field(hqa_md *md, Instance &I, double *u, hipStream_t st);
 hipError_t launch_hamiltonian(hqa_md *md, Instance &I, double *H, hipStream_t st);
 

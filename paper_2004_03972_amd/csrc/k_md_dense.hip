@@ -10,8 +10,9 @@
 // consecutive rows of one replica, so the epilogue reads and writes 16-byte
 // vectors of the state.
 //
-// Workgroup: a block of 2 x TN output tiles (32 rows x 16 TN replicas, TN = 4
-// when the padded replica count allows), K split over the four wavefronts by
+// Workgroup: a block of TM x TN output tiles (16 TM rows x 16 TN replicas; the
+// tuner picks TM in {1, 2} and TN in {1, 2, 4}, by default 2 x the widest TN that
+// divides the padded replica count), K split over the four wavefronts by
 // accumulation chain.  The dense field is accumulated in four chains (K chunk c
 // of 32 columns for BF16 operands, 16 for FP32, feeds chain c mod 4; see
 // combine4), and wavefront w computes chain w of every tile of the block:
@@ -223,29 +224,41 @@ static DenseArgs dense_args(hqa_md *md, Instance &I) {
 // Replica tiles per block: 4 (64 replicas) when they divide Rp, else 2, else 1.
 static int block_tn(int Rp) { return Rp % 64 == 0 ? 4 : Rp % 32 == 0 ? 2 : 1; }
 
+// Blocks of tm x tn output tiles: 16 tm rows x 16 tn replicas per workgroup.
 template <int JT, bool FO>
-static void launch_jt(const DenseArgs &a, int tn, int64_t q, hipStream_t st) {
-    dim3 grid(a.Np / 32, a.Rp / (16 * tn));
-    if (tn == 4) k_step_block<JT, 2, 4, FO><<<grid, 256, 0, st>>>(a, q);
-    else if (tn == 2) k_step_block<JT, 2, 2, FO><<<grid, 256, 0, st>>>(a, q);
-    else k_step_block<JT, 2, 1, FO><<<grid, 256, 0, st>>>(a, q);
+static void launch_jt(const DenseArgs &a, int tm, int tn, int64_t q, hipStream_t st) {
+    dim3 grid(a.Np / (16 * tm), a.Rp / (16 * tn));
+    if (tm == 2) {
+        if (tn == 4) k_step_block<JT, 2, 4, FO><<<grid, 256, 0, st>>>(a, q);
+        else if (tn == 2) k_step_block<JT, 2, 2, FO><<<grid, 256, 0, st>>>(a, q);
+        else k_step_block<JT, 2, 1, FO><<<grid, 256, 0, st>>>(a, q);
+    } else {
+        if (tn == 4) k_step_block<JT, 1, 4, FO><<<grid, 256, 0, st>>>(a, q);
+        else if (tn == 2) k_step_block<JT, 1, 2, FO><<<grid, 256, 0, st>>>(a, q);
+        else k_step_block<JT, 1, 1, FO><<<grid, 256, 0, st>>>(a, q);
+    }
 }
 
 template <bool FO>
-static void launch_one(const DenseArgs &a, int64_t q, hipStream_t st) {
-    const int tn = block_tn(a.Rp);
+static void launch_one(const DenseArgs &a, int tm, int tn, int64_t q, hipStream_t st) {
     switch (a.jt) {
-        case JT_F32: launch_jt<JT_F32, FO>(a, tn, q, st); break;
-        case JT_BF16: launch_jt<JT_BF16, FO>(a, tn, q, st); break;
-        default: launch_jt<JT_FP8, FO>(a, tn, q, st); break;
+        case JT_F32: launch_jt<JT_F32, FO>(a, tm, tn, q, st); break;
+        case JT_BF16: launch_jt<JT_BF16, FO>(a, tm, tn, q, st); break;
+        default: launch_jt<JT_FP8, FO>(a, tm, tn, q, st); break;
     }
 }
 
 hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
+    // tile width: the tuner's choice when it divides the padded replica count
+    const int tn = (I.step_tn == 1 || I.step_tn == 2 || I.step_tn == 4) &&
+                           I.Rp % (16 * I.step_tn) == 0
+                       ? I.step_tn
+                       : block_tn(I.Rp);
+    const int tm = I.step_tm == 1 ? 1 : 2;   // Np is a multiple of 128: both divide it
     for (int64_t q = q0; q < q1; q++) {
         DenseArgs a = dense_args(md, I);
         if (I.st && q >= md->stats_k0 && q < md->stats_k1) a.st = I.st;
-        launch_one<false>(a, q, md->stream);
+        launch_one<false>(a, tm, tn, q, md->stream);
         I.cur ^= 1;
     }
     return hipGetLastError();
@@ -254,7 +267,7 @@ hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1
 hipError_t launch_field_dense(hqa_md *md, Instance &I, float *u, hipStream_t st) {
     DenseArgs a = dense_args(md, I);
     a.u_out = u;
-    launch_one<true>(a, 0, st);
+    launch_one<true>(a, 2, block_tn(a.Rp), 0, st);
     return hipGetLastError();
 }
 

@@ -25,11 +25,17 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhqa.so"
 EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md_opts_default",
             "hqa_md_init", "hqa_md_run", "hqa_md_reset", "hqa_md_sync", "hqa_md_step_index", "hqa_md_state",
             "hqa_md_set_step", "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify",
-            "hqa_ising_energy", "hqa_md_destroy", "hqa_md_last_persistent",
+            "hqa_ising_energy", "hqa_md_destroy", "hqa_md_last_plan", "hqa_md_tune",
+            "hqa_md_tuned_plan", "hqa_md_set_step_tiles",
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
             "hqa_es_destroy")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
+ABI_VERSION = 2
+HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
+PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
+         "resident": HQA_PLAN_RESIDENT}
+PLAN_NAMES = {0: None, 1: "step", 2: "cluster", 3: "resident", 4: "batch"}
 
 
 class HQAError(RuntimeError):
@@ -54,7 +60,7 @@ class hqa_schedule(C.Structure):
 class hqa_md_opts(C.Structure):
     _fields_ = [("replicas", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
                 ("p0", C.c_void_p), ("phi0", C.c_void_p), ("init_mem", C.c_int32),
-                ("require_exact", C.c_int32), ("persistent", C.c_int32),
+                ("require_exact", C.c_int32), ("plan", C.c_int32),
                 ("reserved", C.c_int32)]
 
 
@@ -85,8 +91,12 @@ def lib():
         L.hqa_md_reset.argtypes = [P, C.c_uint64]
         L.hqa_md_step_index.argtypes = [P]
         L.hqa_md_step_index.restype = i64
-        L.hqa_md_last_persistent.argtypes = [P]
-        L.hqa_md_last_persistent.restype = i32
+        L.hqa_md_last_plan.argtypes = [P]
+        L.hqa_md_last_plan.restype = i32
+        L.hqa_md_tune.argtypes = [P, i32]
+        L.hqa_md_tuned_plan.argtypes = [P, i32, P, P]
+        L.hqa_md_tuned_plan.restype = i32
+        L.hqa_md_set_step_tiles.argtypes = [P, i32, i32, i32]
         L.hqa_md_state.argtypes = [P, i32, i32, P, i32, i32]
         L.hqa_md_set_step.argtypes = [P, i64]
         L.hqa_md_field.argtypes = [P, i32, P, i32]
@@ -106,9 +116,10 @@ def lib():
         for f in ("hqa_md_init", "hqa_md_run", "hqa_md_reset", "hqa_md_sync", "hqa_md_state", "hqa_md_set_step",
                   "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify", "hqa_ising_energy",
                   "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
-                  "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict"):
+                  "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
+                  "hqa_md_tune", "hqa_md_set_step_tiles"):
             getattr(L, f).restype = C.c_int
-        if L.hqa_abi_version() != 1:
+        if L.hqa_abi_version() != ABI_VERSION:
             raise ImportError("libhqa ABI version mismatch")
         _lib = L
     return _lib
@@ -173,8 +184,22 @@ def hqa_md_step_index(md) -> int:
     return lib().hqa_md_step_index(md)
 
 
-def hqa_md_last_persistent(md) -> int:
-    return lib().hqa_md_last_persistent(md)
+def hqa_md_last_plan(md) -> int:
+    return lib().hqa_md_last_plan(md)
+
+
+def hqa_md_tune(md, steps: int):
+    _check(lib().hqa_md_tune(md, steps))
+
+
+def hqa_md_set_step_tiles(md, k: int, tm: int, tn: int):
+    _check(lib().hqa_md_set_step_tiles(md, k, tm, tn))
+
+
+def hqa_md_tuned_plan(md, k: int = 0) -> tuple[int, int, int]:
+    tm, tn = C.c_int32(0), C.c_int32(0)
+    p = lib().hqa_md_tuned_plan(md, k, C.byref(tm), C.byref(tn))
+    return p, tm.value, tn.value
 
 
 def hqa_md_set_step(md, q: int):
@@ -350,14 +375,14 @@ class MD:
     """A handle over hqa_md_* calls with numpy in/out (host memory)."""
 
     def __init__(self, problems, sched: hqa_schedule, replicas: int, precision="f32", seed=0,
-                 p0=None, phi0=None, require_exact=False, persistent=False, stream: int = 0):
+                 p0=None, phi0=None, require_exact=False, plan="auto", stream: int = 0):
         self.problems = problems if isinstance(problems, (list, tuple)) else [problems]
         o = hqa_md_opts_default()
         o.replicas = replicas
         o.precision = PRECISIONS.get(precision, precision)
         o.seed = seed
         o.require_exact = int(require_exact)
-        o.persistent = int(persistent)
+        o.plan = PLANS[plan] if isinstance(plan, str) else int(plan)
         self._p0 = None if p0 is None else np.ascontiguousarray(p0, dtype=np.float64)
         self._phi0 = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.float64)
         o.p0 = None if self._p0 is None else self._p0.ctypes.data
@@ -392,8 +417,22 @@ class MD:
         return hqa_md_step_index(self.h)
 
     @property
-    def last_persistent(self) -> bool:
-        return bool(hqa_md_last_persistent(self.h))
+    def last_plan(self):
+        """'step', 'cluster', 'resident' or 'batch' (None if no dense binary32 instance ran)."""
+        return PLAN_NAMES[hqa_md_last_plan(self.h)]
+
+    def tune(self, steps: int = 20):
+        """Time every bit-identical plan from the current state and keep the fastest."""
+        hqa_md_tune(self.h, steps)
+
+    def set_step_tiles(self, tm: int, tn: int, k: int = 0):
+        """Pin instance k to per-step blocks of tm x tn tiles of 16 (rows x replicas)."""
+        hqa_md_set_step_tiles(self.h, k, tm, tn)
+
+    def tuned_plan(self, k: int = 0):
+        """(plan, row tiles, replica tiles) chosen by tune() for instance k."""
+        p, tm, tn = hqa_md_tuned_plan(self.h, k)
+        return PLAN_NAMES.get(p), tm, tn
 
     def state(self, what: int, k: int = 0) -> np.ndarray:
         out = np.empty((self.R, self.problems[k].n))

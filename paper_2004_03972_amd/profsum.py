@@ -22,6 +22,7 @@ import sys
 
 DENSE_SOURCES = ("csrc/k_md_dense.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 CSR_SOURCES = ("csrc/k_md_csr.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
+RESIDENT_SOURCES = ("csrc/k_md_resident.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 
 
 def source_hash(files=DENSE_SOURCES) -> str:
@@ -95,7 +96,7 @@ def main(argv=None):
     ap.add_argument("--kernel", default="")
     ap.add_argument("--top", type=int, default=12)
     ap.add_argument("--bytes", type=int, default=0)
-    ap.add_argument("--sources", default="dense", choices=["dense", "csr"])
+    ap.add_argument("--sources", default="dense", choices=["dense", "csr", "resident"])
     a = ap.parse_args(argv)
     if a.mode == "stats":
         stats(a.path, a.top)
@@ -106,7 +107,8 @@ def main(argv=None):
     elif a.mode == "calib":
         calib(a.path, a.bytes)
     else:
-        print(source_hash(DENSE_SOURCES if a.sources == "dense" else CSR_SOURCES))
+        print(source_hash({"dense": DENSE_SOURCES, "csr": CSR_SOURCES,
+                           "resident": RESIDENT_SOURCES}[a.sources]))
 
 
 if __name__ == "__main__":

@@ -45,13 +45,13 @@ def test_binding_covers_every_declared_symbol():
 
 def test_abi_version_and_defaults(libhqa):
     from paper_2004_03972_amd import hqa
-    assert hqa.hqa_abi_version() == 1
+    assert hqa.hqa_abi_version() == hqa.ABI_VERSION == 2
     s = hqa.hqa_schedule_default()
     # Methods, "Scheduling functions for MD": (0.008, 4, 3), (0.12, 0.05, 1); M = 6 (Results)
     assert (s.alpha_f, s.rho1, s.rho2, s.beta_f, s.kappa1, s.kappa2) == (0.008, 4, 3, 0.12, 0.05, 1)
     assert s.M == 6 and s.W == 100 and s.r_g == 1.0
     o = hqa.hqa_md_opts_default()
-    assert o.replicas == 1 and o.precision == hqa.HQA_PREC_F32
+    assert o.replicas == 1 and o.precision == hqa.HQA_PREC_F32 and o.plan == hqa.HQA_PLAN_AUTO
 
 
 def test_struct_sizes_match_header():

@@ -1,4 +1,4 @@
-"""The persistent dense kernel (all steps in one launch, cluster barriers) must give
+"""The cluster plan (all steps in one cooperative launch, cluster barriers) must give
 bit-identical states to one launch per step: both apply the same binary32
 operation sequence.  Shapes cover LDS-resident and L2-streamed J blocks, ragged
 row and replica tails, the small-SK/large-ER sizes and the bench shape."""
@@ -32,10 +32,11 @@ def test_persistent_equals_per_step(H, prec, N, R, T):
     J = inst.er_maxcut(N, 0.05, N)
     out = []
     for pers in (True, False):
-        md = H.MD(H.Problem(J), H.make_schedule(T, 30), R, prec, seed=7, persistent=pers)
+        plan = "cluster" if pers else "step"
+        md = H.MD(H.Problem(J), H.make_schedule(T, 30), R, prec, seed=7, plan=plan)
         md.run()
         md.sync()
-        assert md.last_persistent == pers
+        assert md.last_plan == plan
         out.append(_states(H, md))
         md.close()
     for a, b in zip(*out):
@@ -47,11 +48,11 @@ def test_persistent_in_pieces_and_single_step(H, prec):
     N, R, T = 500, 48, 300
     J, h = inst.uniform_glass(N, 3)
     J *= 0.05
-    a = H.MD(H.Problem(J, h=h), H.make_schedule(T, 40), R, prec, seed=1, persistent=False)
+    a = H.MD(H.Problem(J, h=h), H.make_schedule(T, 40), R, prec, seed=1, plan="step")
     a.run()
-    b = H.MD(H.Problem(J, h=h), H.make_schedule(T, 40), R, prec, seed=1, persistent=True)
+    b = H.MD(H.Problem(J, h=h), H.make_schedule(T, 40), R, prec, seed=1, plan="cluster")
     for q in (1, 2, 101, 257, T):
         b.run(q)
-        assert b.last_persistent
+        assert b.last_plan == "cluster"
     for x, y in zip(_states(H, a), _states(H, b)):
         assert np.array_equal(x, y)

@@ -31,9 +31,19 @@ struct CsrArgs {
     const float *inv_n2;   // 1 / ||J_i||_2
 };
 
+// Workgroup b of a launch runs on XCD b mod 8, each XCD with its own L2.  The
+// remap gives XCD x the contiguous block range [x nb/8, (x+1) nb/8) (the last
+// nb mod 8 blocks keep their index), so rows whose neighbours are nearby in index
+// (lattices, banded graphs) find those neighbours' fluxes in their own L2 instead
+// of fetching them into a second and third one.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t per = nb / 8;
+    return b < per * 8 ? (b % 8) * per + b / 8 : b;
+}
+
 template <bool FIELD_ONLY>
 __global__ __launch_bounds__(256) void k_step_csr(CsrArgs a, int64_t q) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= (int64_t)a.N * a.Rq) return;
     const int i = (int)(t / a.Rq), c4 = (int)(t % a.Rq);
     const int Rp = a.Rq * 4;

@@ -214,7 +214,9 @@ enum {
     HQA_STATE_PHI = 0,       /* phi^(q)               [R][N] */
     HQA_STATE_P = 1,         /* p^(q-1/2) (p^(0) at q = 0) */
     HQA_STATE_PHIBAR = 2,    /* window mean S/W (defined at q = T) */
-    HQA_STATE_WSUM = 3       /* window sum S */
+    HQA_STATE_WSUM = 3,      /* window sum S */
+    HQA_STATE_STATMEAN = 4   /* mean of phi^(q+1) over the steps of the statistics window
+                                run so far (export only; needs hqa_md_stats_window) */
 };
 
 /* Copy state `what` of instance k out to dst ([R][N] binary64, dst_mem), or, with

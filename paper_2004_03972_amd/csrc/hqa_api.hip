@@ -605,20 +605,41 @@ static hqa_status check_instance(hqa_md *md, int32_t k) {
     return HQA_OK;
 }
 
+__global__ void k_scale_f64(double *x, int64_t n, double s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = x[i] * s;
+}
+
 hqa_status hqa_md_state(hqa_md *md, int32_t instance, int32_t what, void *dst, int32_t dst_mem,
                         int32_t import) {
     hqa_status s = check_instance(md, instance);
     if (s != HQA_OK) return s;
     if (!dst) return fail(HQA_EINVAL, "dst is NULL");
-    if (what < HQA_STATE_PHI || what > HQA_STATE_WSUM) return fail(HQA_EINVAL, "unknown state");
-    if (import && what == HQA_STATE_PHIBAR) return fail(HQA_EINVAL, "phibar cannot be imported");
+    if (what < HQA_STATE_PHI || what > HQA_STATE_STATMEAN) return fail(HQA_EINVAL, "unknown state");
+    if (import && (what == HQA_STATE_PHIBAR || what == HQA_STATE_STATMEAN))
+        return fail(HQA_EINVAL, "this state cannot be imported");
     Instance &I = md->inst[instance];
+    int64_t nstat = 0;
+    if (what == HQA_STATE_STATMEAN) {
+        if (md->prec == HQA_PREC_F64_REF || !I.st)
+            return fail(HQA_ESTATE, "no statistics window has been set");
+        nstat = std::min(std::max(md->q, md->stats_k0), md->stats_k1) - md->stats_k0;
+        if (nstat < 1) return fail(HQA_ESTATE, "no step of the statistics window has run");
+    }
     const size_t n = (size_t)I.N * md->R;
     double *buf = (double *)dst;
     if (dst_mem == HQA_HOST) HIPCHK(dalloc(&buf, n));
     if (import && dst_mem == HQA_HOST)
         HIPCHK(hipMemcpyAsync(buf, dst, n * 8, hipMemcpyHostToDevice, md->stream));
-    HIPCHK(launch_export(I, md->R, md->prec, what, buf, import, md->sch.W, md->stream));
+    if (what == HQA_STATE_STATMEAN) {
+        // the first statistics array is the running sum of phi^(q+1)
+        HIPCHK(launch_layout_to_f64(I.N, md->R, I.ld, I.smaj, I.st, buf, md->stream));
+        k_scale_f64<<<(unsigned)((n + 255) / 256), 256, 0, md->stream>>>(buf, (int64_t)n,
+                                                                       1.0 / (double)nstat);
+        HIPCHK(hipGetLastError());
+    } else {
+        HIPCHK(launch_export(I, md->R, md->prec, what, buf, import, md->sch.W, md->stream));
+    }
     if (!import && dst_mem == HQA_HOST)
         HIPCHK(hipMemcpyAsync(dst, buf, n * 8, hipMemcpyDeviceToHost, md->stream));
     HIPCHK(hipStreamSynchronize(md->stream));

@@ -17,7 +17,7 @@ HQA_EUNSUPPORTED, HQA_ENONFINITE, HQA_ESTATE = -4, -5, -6
 HQA_DENSE, HQA_CSR = 0, 1
 HQA_HOST, HQA_DEVICE = 0, 1
 HQA_PREC_F64_REF, HQA_PREC_F32, HQA_PREC_BF16, HQA_PREC_FP8J_BF16 = 0, 1, 2, 3
-HQA_STATE_PHI, HQA_STATE_P, HQA_STATE_PHIBAR, HQA_STATE_WSUM = 0, 1, 2, 3
+HQA_STATE_PHI, HQA_STATE_P, HQA_STATE_PHIBAR, HQA_STATE_WSUM, HQA_STATE_STATMEAN = 0, 1, 2, 3, 4
 PRECISIONS = {"f64": HQA_PREC_F64_REF, "f32": HQA_PREC_F32, "bf16": HQA_PREC_BF16,
               "fp8": HQA_PREC_FP8J_BF16}
 

@@ -146,12 +146,12 @@ def bench_er800(args, hqa, torch):
     chosen = lowp[0] if lowp else "f32"
     c = forms[chosen]
     md_ms = float(np.mean(c["md_ms"]))
-    plan, tm, tn = c["plan"]
+    plan, tm, tn, cb = c["plan"]
     if plan == "resident":                      # two launches: before and inside the window
         kernel = f"k_md_resident<{JT_NAME[chosen]}, {2 if chosen == 'fp8' else 1}, false>"
         launches, srcs = 2, "resident"
     else:                                       # one launch per MD step
-        kernel = f"k_step_block<{JT_NAME[chosen]}, {tm or 2}, {tn or 4}, false>"
+        kernel = f"k_step_block<{JT_NAME[chosen]}, {tm or 2}, {tn or 4}, false, {cb or 4}>"
         launches, srcs = T, "dense"
     flop_per_launch = 2.0 * N * N * R * T / launches   # field contraction (2 N^2 R per step)
     launch_s = md_ms / 1e3 / launches

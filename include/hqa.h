@@ -190,22 +190,24 @@ hqa_status hqa_md_sync(hqa_md *md);
 int32_t hqa_md_last_plan(const hqa_md *md);
 
 /* Autotuner: for every dense binary32 instance, time each applicable plan and tile
- * shape (per-step blocks of 16 or 32 rows x 16, 32 or 64 replicas; cluster; resident) over `steps`
+ * shape (per-step blocks of 16 or 32 rows x 16, 32 or 64 replicas with 4 or 8 chunks
+ * of loads in flight; cluster; resident) over `steps`
  * MD steps from the current state with HIP events on the handle's stream, restore
  * the state, and keep the fastest for HQA_PLAN_AUTO.  Because the plans are
  * bit-identical the choice never changes results.  Synchronises.  HQA_EINVAL for
  * steps < 1; HQA_ESTATE if fewer than `steps` steps remain before T. */
 hqa_status hqa_md_tune(hqa_md *md, int32_t steps);
 
-/* The tuned plan of dense instance k (0 if not tuned, -1 for a bad argument); *tm and
- * *tn, if not NULL, receive the per-step block shape in row and replica tiles of 16
- * (0 = default). */
-int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn);
+/* The tuned plan of dense instance k (0 if not tuned, -1 for a bad argument); *tm, *tn
+ * and *cb, if not NULL, receive the per-step block shape in row and replica tiles of
+ * 16 and the K chunks per accumulation chain loaded together (0 = default). */
+int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn, int32_t *cb);
 
 /* Pin dense instance k to the per-step plan with blocks of tm row tiles (1 or 2) by
  * tn replica tiles (1, 2 or 4; 16 tn must divide the replica count padded to a
- * multiple of 16), as if the tuner had chosen it.  HQA_EINVAL otherwise. */
-hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn);
+ * multiple of 16), loading cb (4 or 8) K chunks of each chain together, as if the
+ * tuner had chosen it.  HQA_EINVAL otherwise. */
+hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn, int32_t cb);
 
 /* Current step index q (fluxes are phi^(q), momenta p^(q-1/2), or p^(0) at q = 0). */
 int64_t hqa_md_step_index(const hqa_md *md);

@@ -458,7 +458,7 @@ hqa_status hqa_md_reset(hqa_md *md, uint64_t seed) {
 // HIP events, restores it after each, and keeps the fastest for HQA_PLAN_AUTO.
 // ---------------------------------------------------------------------------
 struct TuneCand {
-    int plan, tm, tn;
+    int plan, tm, tn, cb;
 };
 
 hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
@@ -501,22 +501,24 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
             return e;
         };
         std::vector<TuneCand> cands;
-        for (int tm : {2, 1})
-            for (int tn : {4, 2, 1})
-                if (I.Rp % (16 * tn) == 0) cands.push_back({HQA_PLAN_STEP, tm, tn});
-        cands.push_back({HQA_PLAN_CLUSTER, 0, 0});
-        if (resident_fits(I, md->max_lds)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0});
+        for (int cb : {4, 8})
+            for (int tm : {2, 1})
+                for (int tn : {4, 2, 1})
+                    if (I.Rp % (16 * tn) == 0) cands.push_back({HQA_PLAN_STEP, tm, tn, cb});
+        cands.push_back({HQA_PLAN_CLUSTER, 0, 0, 0});
+        if (resident_fits(I, md->max_lds)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0});
         float best = 1e30f;
-        TuneCand pick{HQA_PLAN_STEP, 0, 0};
-        const int tn0 = I.step_tn, tm0 = I.step_tm;
+        TuneCand pick{HQA_PLAN_STEP, 0, 0, 0};
+        const int tn0 = I.step_tn, tm0 = I.step_tm, cb0 = I.step_cb;
         const char *stage = "snapshot";
         hipError_t he = copy(true);
-        TuneCand failed{0, 0, 0};
+        TuneCand failed{0, 0, 0, 0};
         for (const TuneCand &c : cands) {
             if (he != hipSuccess) break;
             failed = c;
             I.step_tn = c.tn;
             I.step_tm = c.tm;
+            I.step_cb = c.cb;
             float ms = 0.f;
             for (int pass = 0; pass < 2 && he == hipSuccess; pass++) {   // pass 0 warms up
                 int used = 0;
@@ -551,6 +553,7 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         }
         I.step_tn = tn0;
         I.step_tm = tm0;
+        I.step_cb = cb0;
         if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
         dfree(sx); dfree(sp); dfree(sS); dfree(sb);
         if (he != hipSuccess) {
@@ -561,6 +564,7 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         I.tuned_plan = pick.plan;
         I.step_tn = pick.tn;
         I.step_tm = pick.tm;
+        I.step_cb = pick.cb;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -569,23 +573,26 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
     return rs;
 }
 
-hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn) {
+hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn, int32_t cb) {
     if (!md) return fail(HQA_EINVAL, "null handle");
     if (k < 0 || k >= (int32_t)md->inst.size()) return fail(HQA_EINVAL, "instance %d out of range", k);
     Instance &I = md->inst[k];
     if (I.layout != HQA_DENSE) return fail(HQA_EINVAL, "instance %d is not dense", k);
     if ((tm != 1 && tm != 2) || (tn != 1 && tn != 2 && tn != 4) || I.Rp % (16 * tn) != 0)
         return fail(HQA_EINVAL, "block of %d x %d tiles does not fit (padded replicas %d)", tm, tn, I.Rp);
+    if (cb != 4 && cb != 8) return fail(HQA_EINVAL, "chunks in flight must be 4 or 8");
     I.step_tm = tm;
     I.step_tn = tn;
+    I.step_cb = cb;
     I.tuned_plan = HQA_PLAN_STEP;
     return HQA_OK;
 }
 
-int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn) {
+int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn, int32_t *cb) {
     if (!md || k < 0 || k >= (int32_t)md->inst.size()) return -1;
     if (tm) *tm = md->inst[k].step_tm;
     if (tn) *tn = md->inst[k].step_tn;
+    if (cb) *cb = md->inst[k].step_cb;
     return md->inst[k].tuned_plan;
 }
 

@@ -79,6 +79,7 @@ struct Instance {
     int32_t tuned_plan = 0;
     int32_t step_tn = 0;      // replica tiles of 16 per per-step block (0: widest that divides Rp)
     int32_t step_tm = 0;      // row tiles of 16 per per-step block (0: 2)
+    int32_t step_cb = 0;      // chunks per chain loaded together (0: 4)
 };
 
 struct Schedule64 {

@@ -65,10 +65,9 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint2 raw) {
 // Chain w of a block of TM x TN output tiles (rows i0 + 16 tm, replicas r0 + 16 tn):
 // per chunk the wavefront loads TM A fragments and TN B fragments and issues
 // TM * TN MFMAs, so each fragment is reused across the block.
-template <int JT, int TM, int TN>
+template <int JT, int TM, int TN, int CB>
 __device__ __forceinline__ void chain_block(const DenseArgs &a, int i0, int r0, int lane, int w,
                                             f32x4 (&acc)[TM][TN]) {
-    constexpr int CB = 4;
     const int kg = lane >> 4;
 #pragma unroll
     for (int tm = 0; tm < TM; tm++)
@@ -181,13 +180,13 @@ __device__ __forceinline__ void dense_update(const DenseArgs &a, int64_t q, int 
 // Block of TM x TN output tiles (32 rows x 16 TN replicas for TM = 2): each
 // wavefront accumulates one chain of every tile; the partial tiles meet in LDS
 // and wavefront w combines and updates tiles w, w + 4, ... in chain order.
-template <int JT, int TM, int TN, bool FIELD_ONLY>
+template <int JT, int TM, int TN, bool FIELD_ONLY, int CB = 4>
 __global__ __launch_bounds__(256) void k_step_block(DenseArgs a, int64_t q) {
     __shared__ f32x4 part[4][TM * TN][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i0 = blockIdx.x * 16 * TM, r0 = blockIdx.y * 16 * TN;
     f32x4 acc[TM][TN];
-    chain_block<JT, TM, TN>(a, i0, r0, lane, w, acc);
+    chain_block<JT, TM, TN, CB>(a, i0, r0, lane, w, acc);
 #pragma unroll
     for (int tm = 0; tm < TM; tm++)
 #pragma unroll
@@ -224,27 +223,35 @@ static DenseArgs dense_args(hqa_md *md, Instance &I) {
 // Replica tiles per block: 4 (64 replicas) when they divide Rp, else 2, else 1.
 static int block_tn(int Rp) { return Rp % 64 == 0 ? 4 : Rp % 32 == 0 ? 2 : 1; }
 
-// Blocks of tm x tn output tiles: 16 tm rows x 16 tn replicas per workgroup.
-template <int JT, bool FO>
-static void launch_jt(const DenseArgs &a, int tm, int tn, int64_t q, hipStream_t st) {
+// Blocks of tm x tn output tiles: 16 tm rows x 16 tn replicas per workgroup; cb
+// chunks of each chain's loads in flight together (8: a chain of up to eight chunks
+// costs one round trip to L2).
+template <int JT, bool FO, int CB>
+static void launch_cb(const DenseArgs &a, int tm, int tn, int64_t q, hipStream_t st) {
     dim3 grid(a.Np / (16 * tm), a.Rp / (16 * tn));
     if (tm == 2) {
-        if (tn == 4) k_step_block<JT, 2, 4, FO><<<grid, 256, 0, st>>>(a, q);
-        else if (tn == 2) k_step_block<JT, 2, 2, FO><<<grid, 256, 0, st>>>(a, q);
-        else k_step_block<JT, 2, 1, FO><<<grid, 256, 0, st>>>(a, q);
+        if (tn == 4) k_step_block<JT, 2, 4, FO, CB><<<grid, 256, 0, st>>>(a, q);
+        else if (tn == 2) k_step_block<JT, 2, 2, FO, CB><<<grid, 256, 0, st>>>(a, q);
+        else k_step_block<JT, 2, 1, FO, CB><<<grid, 256, 0, st>>>(a, q);
     } else {
-        if (tn == 4) k_step_block<JT, 1, 4, FO><<<grid, 256, 0, st>>>(a, q);
-        else if (tn == 2) k_step_block<JT, 1, 2, FO><<<grid, 256, 0, st>>>(a, q);
-        else k_step_block<JT, 1, 1, FO><<<grid, 256, 0, st>>>(a, q);
+        if (tn == 4) k_step_block<JT, 1, 4, FO, CB><<<grid, 256, 0, st>>>(a, q);
+        else if (tn == 2) k_step_block<JT, 1, 2, FO, CB><<<grid, 256, 0, st>>>(a, q);
+        else k_step_block<JT, 1, 1, FO, CB><<<grid, 256, 0, st>>>(a, q);
     }
 }
 
+template <int JT, bool FO>
+static void launch_jt(const DenseArgs &a, int tm, int tn, int cb, int64_t q, hipStream_t st) {
+    if (cb == 8) launch_cb<JT, FO, 8>(a, tm, tn, q, st);
+    else launch_cb<JT, FO, 4>(a, tm, tn, q, st);
+}
+
 template <bool FO>
-static void launch_one(const DenseArgs &a, int tm, int tn, int64_t q, hipStream_t st) {
+static void launch_one(const DenseArgs &a, int tm, int tn, int cb, int64_t q, hipStream_t st) {
     switch (a.jt) {
-        case JT_F32: launch_jt<JT_F32, FO>(a, tm, tn, q, st); break;
-        case JT_BF16: launch_jt<JT_BF16, FO>(a, tm, tn, q, st); break;
-        default: launch_jt<JT_FP8, FO>(a, tm, tn, q, st); break;
+        case JT_F32: launch_jt<JT_F32, FO>(a, tm, tn, cb, q, st); break;
+        case JT_BF16: launch_jt<JT_BF16, FO>(a, tm, tn, cb, q, st); break;
+        default: launch_jt<JT_FP8, FO>(a, tm, tn, cb, q, st); break;
     }
 }
 
@@ -255,10 +262,11 @@ hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1
                        ? I.step_tn
                        : block_tn(I.Rp);
     const int tm = I.step_tm == 1 ? 1 : 2;   // Np is a multiple of 128: both divide it
+    const int cb = I.step_cb == 8 ? 8 : 4;
     for (int64_t q = q0; q < q1; q++) {
         DenseArgs a = dense_args(md, I);
         if (I.st && q >= md->stats_k0 && q < md->stats_k1) a.st = I.st;
-        launch_one<false>(a, tm, tn, q, md->stream);
+        launch_one<false>(a, tm, tn, cb, q, md->stream);
         I.cur ^= 1;
     }
     return hipGetLastError();
@@ -267,7 +275,7 @@ hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1
 hipError_t launch_field_dense(hqa_md *md, Instance &I, float *u, hipStream_t st) {
     DenseArgs a = dense_args(md, I);
     a.u_out = u;
-    launch_one<true>(a, 2, block_tn(a.Rp), 0, st);
+    launch_one<true>(a, 2, block_tn(a.Rp), 4, 0, st);
     return hipGetLastError();
 }
 

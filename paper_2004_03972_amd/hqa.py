@@ -94,9 +94,9 @@ def lib():
         L.hqa_md_last_plan.argtypes = [P]
         L.hqa_md_last_plan.restype = i32
         L.hqa_md_tune.argtypes = [P, i32]
-        L.hqa_md_tuned_plan.argtypes = [P, i32, P, P]
+        L.hqa_md_tuned_plan.argtypes = [P, i32, P, P, P]
         L.hqa_md_tuned_plan.restype = i32
-        L.hqa_md_set_step_tiles.argtypes = [P, i32, i32, i32]
+        L.hqa_md_set_step_tiles.argtypes = [P, i32, i32, i32, i32]
         L.hqa_md_state.argtypes = [P, i32, i32, P, i32, i32]
         L.hqa_md_set_step.argtypes = [P, i64]
         L.hqa_md_field.argtypes = [P, i32, P, i32]
@@ -192,14 +192,14 @@ def hqa_md_tune(md, steps: int):
     _check(lib().hqa_md_tune(md, steps))
 
 
-def hqa_md_set_step_tiles(md, k: int, tm: int, tn: int):
-    _check(lib().hqa_md_set_step_tiles(md, k, tm, tn))
+def hqa_md_set_step_tiles(md, k: int, tm: int, tn: int, cb: int = 4):
+    _check(lib().hqa_md_set_step_tiles(md, k, tm, tn, cb))
 
 
-def hqa_md_tuned_plan(md, k: int = 0) -> tuple[int, int, int]:
-    tm, tn = C.c_int32(0), C.c_int32(0)
-    p = lib().hqa_md_tuned_plan(md, k, C.byref(tm), C.byref(tn))
-    return p, tm.value, tn.value
+def hqa_md_tuned_plan(md, k: int = 0) -> tuple[int, int, int, int]:
+    tm, tn, cb = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    p = lib().hqa_md_tuned_plan(md, k, C.byref(tm), C.byref(tn), C.byref(cb))
+    return p, tm.value, tn.value, cb.value
 
 
 def hqa_md_set_step(md, q: int):
@@ -425,14 +425,15 @@ class MD:
         """Time every bit-identical plan from the current state and keep the fastest."""
         hqa_md_tune(self.h, steps)
 
-    def set_step_tiles(self, tm: int, tn: int, k: int = 0):
-        """Pin instance k to per-step blocks of tm x tn tiles of 16 (rows x replicas)."""
-        hqa_md_set_step_tiles(self.h, k, tm, tn)
+    def set_step_tiles(self, tm: int, tn: int, cb: int = 4, k: int = 0):
+        """Pin instance k to per-step blocks of tm x tn tiles of 16 (rows x replicas)
+        with cb chunks of each accumulation chain loaded together."""
+        hqa_md_set_step_tiles(self.h, k, tm, tn, cb)
 
     def tuned_plan(self, k: int = 0):
-        """(plan, row tiles, replica tiles) chosen by tune() for instance k."""
-        p, tm, tn = hqa_md_tuned_plan(self.h, k)
-        return PLAN_NAMES.get(p), tm, tn
+        """(plan, row tiles, replica tiles, chunks in flight) chosen by tune() for k."""
+        p, tm, tn, cb = hqa_md_tuned_plan(self.h, k)
+        return PLAN_NAMES.get(p), tm, tn, cb
 
     def state(self, what: int, k: int = 0) -> np.ndarray:
         out = np.empty((self.R, self.problems[k].n))

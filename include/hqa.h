@@ -135,6 +135,10 @@ typedef struct hqa_md_opts {
  *                      their whole state in LDS and streams J from L2 (BF16/FP8 J,
  *                      N up to 800 on a device with 160 KB of LDS per workgroup).
  *   HQA_PLAN_BATCH     (reported only) several dense instances in one launch per step.
+ * Sparse (CSR) binary32 instances have two plans: STEP (one launch per step) and
+ * RESIDENT (all steps in one launch; one workgroup per 4 replicas keeps their fluxes
+ * in LDS and each thread's couplings, momenta and window sums in registers; for
+ * N <= 4096 and at most 8 couplings per row).  Both give bit-identical trajectories.
  * A plan that does not apply to an instance (too large, FP32 J, statistics window
  * live) falls back to STEP for that run; hqa_md_last_plan reports what ran. */
 enum {
@@ -184,12 +188,12 @@ hqa_status hqa_md_reset(hqa_md *md, uint64_t seed);
 /* Wait for queued work; HQA_ENONFINITE if any flux or momentum became non-finite. */
 hqa_status hqa_md_sync(hqa_md *md);
 
-/* The plan the last hqa_md_run used for the dense binary32 instances (HQA_PLAN_STEP,
+/* The plan the last hqa_md_run used for the binary32 instances (HQA_PLAN_STEP,
  * _CLUSTER, _RESIDENT or _BATCH; the last instance's when they differ), 0 if it
- * advanced none (sparse or binary64 instances only). */
+ * advanced none (binary64 reference mode). */
 int32_t hqa_md_last_plan(const hqa_md *md);
 
-/* Autotuner: for every dense binary32 instance, time each applicable plan and tile
+/* Autotuner: for every binary32 instance, time each applicable plan and tile
  * shape (per-step blocks of 16 or 32 rows x 16, 32 or 64 replicas with 4 or 8 chunks
  * of loads in flight; cluster; resident) over `steps`
  * MD steps from the current state with HIP events on the handle's stream, restore

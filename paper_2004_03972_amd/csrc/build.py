@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhqa.so")
 SOURCES = ["hqa_api.hip", "k_util.hip", "k_md_ref.hip", "k_md_dense.hip", "k_md_csr.hip",
-           "k_md_persist.hip", "k_md_resident.hip", "k_md_batch.hip", "k_readout.hip", "k_es.hip"]
+           "k_md_persist.hip", "k_md_resident.hip", "k_csr_resident.hip", "k_md_batch.hip", "k_readout.hip", "k_es.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

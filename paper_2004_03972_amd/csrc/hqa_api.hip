@@ -404,6 +404,22 @@ static hipError_t run_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1, boo
     return launch_md_steps_dense(md, I, q0, q1);
 }
 
+// Steps [q0, q1) of one sparse binary32 instance under `plan` (RESIDENT or STEP).
+static hipError_t run_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1, bool stats_live,
+                          int plan, int *used) {
+    if (plan == HQA_PLAN_AUTO) plan = I.tuned_plan ? I.tuned_plan : HQA_PLAN_STEP;
+    if (!stats_live && plan == HQA_PLAN_RESIDENT && csr_resident_fits(md, I)) {
+        hipError_t e = launch_md_csr_resident(md, I, q0, q1);
+        if (e == hipSuccess) {
+            *used = HQA_PLAN_RESIDENT;
+            return e;
+        }
+        (void)hipGetLastError();
+    }
+    *used = HQA_PLAN_STEP;
+    return launch_md_steps_csr(md, I, q0, q1);
+}
+
 hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     if (!md) return fail(HQA_EINVAL, "null handle");
     int64_t q1 = until_step < 0 ? md->sch.T : until_step;
@@ -429,7 +445,7 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
         if (md->prec == HQA_PREC_F64_REF) e = launch_md_steps_f64(md, I, md->q, q1);
         else if (I.layout == HQA_DENSE && batched) e = hipSuccess;
         else if (I.layout == HQA_DENSE) e = run_dense(md, I, md->q, q1, stats_live, md->plan, &md->last_plan);
-        else e = launch_md_steps_csr(md, I, md->q, q1);
+        else e = run_csr(md, I, md->q, q1, stats_live, md->plan, &md->last_plan);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "step launch: %s", hipGetErrorString(e));
     }
     md->q = q1;
@@ -475,8 +491,8 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         rs = fail(HQA_EDEVICE, "event creation failed");
     for (auto &I : md->inst) {
         if (rs != HQA_OK) break;
-        if (I.layout != HQA_DENSE) continue;
-        const size_t n = (size_t)I.Rp * I.ld;
+        const bool dense = I.layout == HQA_DENSE;
+        const size_t n = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
         float *sx = nullptr, *sp = nullptr, *sS = nullptr;
         bf16 *sb = nullptr;
         if (dalloc(&sx, n) != hipSuccess || dalloc(&sp, n) != hipSuccess ||
@@ -501,12 +517,17 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
             return e;
         };
         std::vector<TuneCand> cands;
-        for (int cb : {4, 8})
-            for (int tm : {2, 1})
-                for (int tn : {4, 2, 1})
-                    if (I.Rp % (16 * tn) == 0) cands.push_back({HQA_PLAN_STEP, tm, tn, cb});
-        cands.push_back({HQA_PLAN_CLUSTER, 0, 0, 0});
-        if (resident_fits(I, md->max_lds)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0});
+        if (dense) {
+            for (int cb : {4, 8})
+                for (int tm : {2, 1})
+                    for (int tn : {4, 2, 1})
+                        if (I.Rp % (16 * tn) == 0) cands.push_back({HQA_PLAN_STEP, tm, tn, cb});
+            cands.push_back({HQA_PLAN_CLUSTER, 0, 0, 0});
+            if (resident_fits(I, md->max_lds)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0});
+        } else {
+            cands.push_back({HQA_PLAN_STEP, 0, 0, 0});
+            if (csr_resident_fits(md, I)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0});
+        }
         float best = 1e30f;
         TuneCand pick{HQA_PLAN_STEP, 0, 0, 0};
         const int tn0 = I.step_tn, tm0 = I.step_tm, cb0 = I.step_cb;
@@ -526,7 +547,8 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
                 he = hipEventRecord(e0, md->stream);
                 if (he == hipSuccess) {
                     stage = "run";
-                    he = run_dense(md, I, md->q, md->q + steps, false, c.plan, &used);
+                    he = dense ? run_dense(md, I, md->q, md->q + steps, false, c.plan, &used)
+                               : run_csr(md, I, md->q, md->q + steps, false, c.plan, &used);
                 }
                 if (he == hipSuccess) {
                     stage = "event record";

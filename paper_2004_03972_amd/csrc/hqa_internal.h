@@ -80,6 +80,7 @@ struct Instance {
     int32_t step_tn = 0;      // replica tiles of 16 per per-step block (0: widest that divides Rp)
     int32_t step_tm = 0;      // row tiles of 16 per per-step block (0: 2)
     int32_t step_cb = 0;      // chunks per chain loaded together (0: 4)
+    int32_t max_deg = -1;     // CSR: largest row degree (computed on first need)
 };
 
 struct Schedule64 {
@@ -138,6 +139,8 @@ hipError_t launch_md_steps(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 size_t resident_lds_bytes(int N);
 bool resident_fits(const Instance &I, int max_lds);
 hipError_t launch_md_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+bool csr_resident_fits(hqa_md *md, Instance &I);
+hipError_t launch_md_csr_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_field(hqa_md *md, Instance &I, double *u, hipStream_t st);
 hipError_t launch_hamiltonian(hqa_md *md, Instance &I, double *H, hipStream_t st);
 

@@ -150,3 +150,75 @@ def test_every_step_block_shape_is_bit_identical(H, prec):
         for x, y in zip(ref, st):
             assert np.array_equal(x, y), key
 
+
+
+def _csr_pair(H, prob, T, W, R, seed, cuts=(None,)):
+    out = []
+    for plan in ("resident", "step"):
+        md = H.MD(prob, H.make_schedule(T, W), R, "f32", seed=seed, plan=plan)
+        for q in cuts:
+            md.run(-1 if q is None else q)
+            assert md.last_plan == plan
+        md.sync()
+        out.append(_states(H, md))
+        md.close()
+    return out
+
+
+@pytest.mark.parametrize("L,R,T", [(8, 4, 200), (8, 13, 150), (16, 64, 120), (16, 1024, 60)])
+def test_csr_resident_equals_per_step(H, L, R, T):
+    """Sparse replica-resident plan on the 3D +-J lattice: bit-identical to per step."""
+    print("csr resident", L, R, T, flush=True)
+    rp, ci, v = inst.ea3d(L, 300 + L)
+    a, b = _csr_pair(H, H.Problem(row_ptr=rp, col=ci, val=v), T, 25, R, seed=3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert np.abs(a[0]).max() > 0
+
+
+def test_csr_resident_field_ragged_rows_and_pieces(H):
+    """Rows of different degree (0..8), a field h, and runs split at arbitrary steps."""
+    N, R, T = 700, 9, 300
+    rng = np.random.default_rng(4)
+    rows, cols, vals = [], [], []
+    for i in range(N):
+        for j in rng.choice(N, size=int(rng.integers(0, 5)), replace=False):
+            if i != j:
+                rows += [i, j]
+                cols += [j, i]
+                w = float(rng.choice([-1.0, 1.0, 0.5]))
+                vals += [w, w]
+    J = np.zeros((N, N))
+    J[rows, cols] = vals                       # duplicates collapse to one symmetric value
+    deg = (J != 0).sum(1)
+    keep = deg <= 8
+    J = J * keep[:, None] * keep[None, :]
+    rp, ci, v = inst.dense_to_csr(J)
+    h = rng.uniform(-0.5, 0.5, size=N)
+    a, b = _csr_pair(H, H.Problem(row_ptr=rp, col=ci, val=v, h=h), T, 40, R, seed=6,
+                     cuts=(1, 2, 100, 270, T))
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_csr_resident_falls_back_and_tuner(H):
+    rp, ci, v = inst.er_sparse(500, 20, 7)            # degrees above 8: no resident plan
+    md = H.MD(H.Problem(row_ptr=rp, col=ci, val=v), H.make_schedule(50, 10), 8, "f32", seed=1,
+              plan="resident")
+    md.run()
+    assert md.last_plan == "step"
+    md.close()
+    rp, ci, v = inst.ea3d(16, 301)
+    prob = H.Problem(row_ptr=rp, col=ci, val=v)
+    ref = H.MD(prob, H.make_schedule(200, 20), 256, "f32", seed=2, plan="step")
+    ref.run()
+    want = _states(H, ref)
+    md = H.MD(prob, H.make_schedule(200, 20), 256, "f32", seed=2)
+    md.tune(20)
+    plan = md.tuned_plan()[0]
+    print("csr tuned plan", plan, flush=True)
+    assert plan in ("step", "resident")
+    md.run()
+    assert md.last_plan == plan
+    for x, y in zip(want, _states(H, md)):
+        assert np.array_equal(x, y)

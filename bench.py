@@ -223,7 +223,7 @@ def bench_ea3d(args, hqa, torch):
         out["roofline"] = {"bound": "alu", "achieved": flop / (ms / 1e3) / 1e12,
                            "peak": 157.3, "unit": "TFLOP/s",
                            "frac": flop / (ms / 1e3) / 157.3e12, "traffic": None,
-                           "kernel": "k_csr_resident<8>", "flop_per_update": flop / upd,
+                           "kernel": "k_csr_resident<4, 6>", "flop_per_update": flop / upd,
                            "hbm_equivalent_GBps": bytes_alg / (ms / 1e3) / 1e9}
     else:
         out["roofline"] = {"bound": "hbm", "achieved": bytes_alg / (ms / 1e3) / 1e9,

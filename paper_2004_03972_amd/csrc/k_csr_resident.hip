@@ -10,8 +10,9 @@
 //   * each thread's spins' couplings (column, value) in registers, loaded once;
 //   * each thread's momenta and window sums in registers.
 // A step then reads no global memory at all: six LDS gathers of 16 bytes and the
-// fused leapfrog per spin and replica, and one barrier.  The arithmetic is the
-// streamed CSR kernel's (field accumulated with fmaf in ascending column order
+// fused leapfrog per spin and replica, and one barrier.  1024 threads (four spins
+// each at N = 4096) keep four wavefronts per SIMD to hide the LDS latency.  The
+// arithmetic is the streamed CSR kernel's (field accumulated with fmaf in ascending column order
 // from +0, the shared binary32 leapfrog, the window sum), so both give
 // bit-identical trajectories.
 #include <algorithm>
@@ -21,7 +22,7 @@
 
 namespace hqa {
 
-constexpr int CSR_RES_THREADS = 512;
+constexpr int CSR_RES_THREADS = 1024;
 constexpr int CSR_RES_DMAX = 8;    // couplings per row held in registers
 constexpr int CSR_RES_RG = 4;      // replicas per workgroup
 
@@ -53,8 +54,9 @@ __device__ __forceinline__ StepCoef csr_res_coef(const CsrResArgs &a, int64_t q)
     return c;
 }
 
-// SPT spins per thread: spin i = tid + CSR_RES_THREADS k, k < SPT.
-template <int SPT>
+// SPT spins per thread: spin i = tid + CSR_RES_THREADS k, k < SPT.  MP: the potential
+// exponent when it is 6 (the paper's), else 0 for any even M.
+template <int SPT, int MP>
 __global__ __launch_bounds__(CSR_RES_THREADS) void k_csr_resident(CsrResArgs a) {
     extern __shared__ __align__(16) float lds_c[];
     float4 *ph0 = (float4 *)lds_c, *ph1 = ph0 + a.N;
@@ -96,7 +98,6 @@ __global__ __launch_bounds__(CSR_RES_THREADS) void k_csr_resident(CsrResArgs a) 
     }
     __syncthreads();
 
-    bool bad = false;
     int cur = 0;
     for (int64_t q = a.q0; q < a.q1; q++) {
         const StepCoef c = csr_res_coef(a, q);
@@ -122,36 +123,48 @@ __global__ __launch_bounds__(CSR_RES_THREADS) void k_csr_resident(CsrResArgs a) 
                 const float hi = hl[i];
                 const float4 x = X[i];
                 float4 xn;
-                leapfrog(c, x.x, u.x, hi, p[k].x, xn.x);
-                leapfrog(c, x.y, u.y, hi, p[k].y, xn.y);
-                leapfrog(c, x.z, u.z, hi, p[k].z, xn.z);
-                leapfrog(c, x.w, u.w, hi, p[k].w, xn.w);
+                if constexpr (MP == 6) {
+                    leapfrog_m<6>(c, x.x, u.x, hi, p[k].x, xn.x);
+                    leapfrog_m<6>(c, x.y, u.y, hi, p[k].y, xn.y);
+                    leapfrog_m<6>(c, x.z, u.z, hi, p[k].z, xn.z);
+                    leapfrog_m<6>(c, x.w, u.w, hi, p[k].w, xn.w);
+                } else {
+                    leapfrog(c, x.x, u.x, hi, p[k].x, xn.x);
+                    leapfrog(c, x.y, u.y, hi, p[k].y, xn.y);
+                    leapfrog(c, x.z, u.z, hi, p[k].z, xn.z);
+                    leapfrog(c, x.w, u.w, hi, p[k].w, xn.w);
+                }
                 Y[i] = xn;
                 if (win) {
                     S[k].x = S[k].x + xn.x; S[k].y = S[k].y + xn.y;
                     S[k].z = S[k].z + xn.z; S[k].w = S[k].w + xn.w;
                 }
-                bad |= !isfinite(xn.x) || !isfinite(xn.y) || !isfinite(xn.z) || !isfinite(xn.w) ||
-                       !isfinite(p[k].x) || !isfinite(p[k].y) || !isfinite(p[k].z) ||
-                       !isfinite(p[k].w);
             }
         }
         __syncthreads();
         cur ^= 1;
     }
-    if (bad) atomicOr(a.err, ERR_NONFINITE);
 
+    // A non-finite flux or momentum never becomes finite again under the leapfrog (and
+    // spreads to the neighbours through the field), so checking the final state raises
+    // the same flag as checking every step.
     const float4 *X = cur ? ph1 : ph0;
+    bool bad = false;
 #pragma unroll
     for (int k = 0; k < SPT; k++) {
         const int i = tid + CSR_RES_THREADS * k;
         if (i < a.N) {
             const int64_t base = (int64_t)i * a.ld + g0;
-            *(float4 *)(a.phi_out + base) = X[i];
+            const float4 xf = X[i];
+            bad |= !isfinite(xf.x) || !isfinite(xf.y) || !isfinite(xf.z) || !isfinite(xf.w) ||
+                   !isfinite(p[k].x) || !isfinite(p[k].y) || !isfinite(p[k].z) ||
+                   !isfinite(p[k].w);
+            *(float4 *)(a.phi_out + base) = xf;
             *(float4 *)(a.p + base) = p[k];
             *(float4 *)(a.S + base) = S[k];
         }
     }
+    if (bad) atomicOr(a.err, ERR_NONFINITE);
 }
 
 // Largest row degree of a CSR instance (computed once, on the host).
@@ -170,18 +183,23 @@ static int csr_max_degree(Instance &I, hipStream_t st) {
 
 bool csr_resident_fits(hqa_md *md, Instance &I) {
     if (I.layout != HQA_CSR || !I.smaj || I.Rp % CSR_RES_RG != 0) return false;
-    if (I.N > 8 * CSR_RES_THREADS) return false;
+    if (I.N > 4 * CSR_RES_THREADS) return false;
     if (csr_resident_lds_bytes(I.N) > (size_t)md->max_lds) return false;
     return csr_max_degree(I, md->stream) <= CSR_RES_DMAX;
 }
 
-template <int SPT>
-static hipError_t launch_cr(const CsrResArgs &a, int grid, size_t lds, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_csr_resident<SPT>,
+template <int SPT, int MP>
+static hipError_t launch_crm(const CsrResArgs &a, int grid, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_csr_resident<SPT, MP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    k_csr_resident<SPT><<<grid, CSR_RES_THREADS, lds, st>>>(a);
+    k_csr_resident<SPT, MP><<<grid, CSR_RES_THREADS, lds, st>>>(a);
     return hipGetLastError();
+}
+
+template <int SPT>
+static hipError_t launch_cr(const CsrResArgs &a, int grid, size_t lds, hipStream_t st) {
+    return a.M == 6 ? launch_crm<SPT, 6>(a, grid, lds, st) : launch_crm<SPT, 0>(a, grid, lds, st);
 }
 
 hipError_t launch_md_csr_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
@@ -197,8 +215,7 @@ hipError_t launch_md_csr_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q
     hipError_t e;
     if (spt <= 1) e = launch_cr<1>(a, grid, lds, md->stream);
     else if (spt <= 2) e = launch_cr<2>(a, grid, lds, md->stream);
-    else if (spt <= 4) e = launch_cr<4>(a, grid, lds, md->stream);
-    else e = launch_cr<8>(a, grid, lds, md->stream);
+    else e = launch_cr<4>(a, grid, lds, md->stream);
     if (e == hipSuccess) I.cur ^= 1;
     return e;
 }

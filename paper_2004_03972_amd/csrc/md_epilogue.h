@@ -43,6 +43,21 @@ __device__ __forceinline__ void leapfrog(const StepCoef &c, float x, float u, fl
     xn = x + c.ad * p;
 }
 
+// The same sequence with the potential exponent fixed at compile time (the power
+// loop unrolled; identical operations).
+template <int M>
+__device__ __forceinline__ void leapfrog_m(const StepCoef &c, float x, float u, float h, float &p,
+                                           float &xn) {
+    float v = x;
+#pragma unroll
+    for (int k = 0; k < M - 2; k++) v = v * x;
+    float g = u + (2.0f * h) * fabsf(x);
+    float F = (c.al * ((float)M * v)) + (c.be * g);
+    if (c.rg != 1.0f) F = c.rg * F;
+    p = p - c.kick * F;
+    xn = x + c.ad * p;
+}
+
 // Statistics of the learned early stop for one (spin, replica) and one step:
 // old flux xo = phi^(q), new flux xn = phi^(q+1), field u at phi^(q), momentum
 // p = p^(q+1/2), nu = u / ||J_i||_2 (inv_n2 = 1/||J_i||_2, 0 for an empty row).

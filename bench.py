@@ -55,8 +55,7 @@ def measured_traffic(name, sources="dense"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        srcs = {"dense": profsum.DENSE_SOURCES, "csr": profsum.CSR_SOURCES,
-                "resident": profsum.RESIDENT_SOURCES}[sources]
+        srcs = profsum.SOURCES[sources]
         if kv.get("source_sha256") != profsum.source_hash(srcs):
             return None
         return (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_factor"])
@@ -73,12 +72,15 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def run_form(hqa, torch, prob, prec, steps, warmup):
+def run_form(hqa, torch, prob, prec, steps, warmup, pin=None):
     """Timed bench steps of one precision; returns times and read-out quality."""
     stream = torch.cuda.current_stream()
     md = hqa.MD(prob, hqa.make_schedule(T, W), R, prec, seed=RUN_SEED, require_exact=True,
                 stream=stream.cuda_stream)
-    md.tune(20)                                    # plan and tile shape, untimed
+    if pin:                                        # a fixed per-step block (profiling runs)
+        md.set_step_tiles(*pin)
+    else:
+        md.tune(20)                                # plan and tile shape, untimed
     plan = md.tuned_plan()
     for k in range(warmup):
         md.reset(RUN_SEED + 1000 + k)
@@ -136,7 +138,7 @@ def bench_er800(args, hqa, torch):
     forms = {}
     for prec in args.forms:
         _log(f"bench: ER N={N} p={P_EDGE} R={R} T={T}; form {prec}")
-        forms[prec] = run_form(hqa, torch, prob, prec, args.steps, args.warmup)
+        forms[prec] = run_form(hqa, torch, prob, prec, args.steps, args.warmup, args.pin)
         _log(f"  {prec}: {forms[prec]['total_ms']:.1f} ms for {args.steps} steps")
     upd = N * R * T
     val = {p: upd * args.steps / (f["total_ms"] / 1e3) for p, f in forms.items()}
@@ -150,6 +152,9 @@ def bench_er800(args, hqa, torch):
     if plan == "resident":                      # two launches: before and inside the window
         kernel = f"k_md_resident<{JT_NAME[chosen]}, {2 if chosen == 'fp8' else 1}, false>"
         launches, srcs = 2, "resident"
+    elif plan == "cluster":                     # one cooperative launch for all steps
+        kernel = f"k_persist<{JT_NAME[chosen]}>"
+        launches, srcs = 1, "persist"
     else:                                       # one launch per MD step
         kernel = f"k_step_block<{JT_NAME[chosen]}, {tm or 2}, {tn or 4}, false, {cb or 4}>"
         launches, srcs = T, "dense"
@@ -200,8 +205,14 @@ def bench_ea3d(args, hqa, torch):
     st = torch.cuda.current_stream()
     md = hqa.MD(hqa.Problem(row_ptr=rp, col=ci, val=v), hqa.make_schedule(Tt, 100), Rr, "f32",
                 seed=3, stream=st.cuda_stream)
-    md.tune(20)                                   # per-step vs replica-resident, untimed
-    plan = md.tuned_plan()[0]
+    if args.pin:                                  # profiling runs: the resident plan, untuned
+        md.close()
+        md = hqa.MD(hqa.Problem(row_ptr=rp, col=ci, val=v), hqa.make_schedule(Tt, 100), Rr,
+                    "f32", seed=3, stream=st.cuda_stream, plan="resident")
+        plan = "resident"
+    else:
+        md.tune(20)                               # per-step vs replica-resident, untimed
+        plan = md.tuned_plan()[0]
     md.run(); md.sync()
     times = []
     for k in range(args.steps):
@@ -222,7 +233,9 @@ def bench_ea3d(args, hqa, torch):
         flop = (2.0 * v.size / Nn + 17.0) * upd
         out["roofline"] = {"bound": "alu", "achieved": flop / (ms / 1e3) / 1e12,
                            "peak": 157.3, "unit": "TFLOP/s",
-                           "frac": flop / (ms / 1e3) / 157.3e12, "traffic": None,
+                           "frac": flop / (ms / 1e3) / 157.3e12,
+                           "traffic": measured_traffic("k_csr_resident_ea3d_pmc.txt",
+                                                       "csr_resident"),
                            "kernel": "k_csr_resident<4, 6>", "flop_per_update": flop / upd,
                            "hbm_equivalent_GBps": bytes_alg / (ms / 1e3) / 1e9}
     else:
@@ -288,8 +301,10 @@ def main():
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--md-steps", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pin", default="", help="TM,TN,CB: fixed per-step block instead of tuning")
     args = ap.parse_args()
     args.forms = [f for f in args.forms.split(",") if f]
+    args.pin = tuple(int(x) for x in args.pin.split(",")) if args.pin else None
     if args.gpus != 1:
         print("this build runs on one GPU: replicas and instances would shard across GPUs "
               "without communication, but no multi-GPU path is built; use --gpus 1",

@@ -23,6 +23,10 @@ import sys
 DENSE_SOURCES = ("csrc/k_md_dense.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 CSR_SOURCES = ("csrc/k_md_csr.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 RESIDENT_SOURCES = ("csrc/k_md_resident.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
+PERSIST_SOURCES = ("csrc/k_md_persist.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
+CSR_RESIDENT_SOURCES = ("csrc/k_csr_resident.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
+SOURCES = {"dense": DENSE_SOURCES, "csr": CSR_SOURCES, "resident": RESIDENT_SOURCES,
+           "persist": PERSIST_SOURCES, "csr_resident": CSR_RESIDENT_SOURCES}
 
 
 def source_hash(files=DENSE_SOURCES) -> str:
@@ -96,7 +100,7 @@ def main(argv=None):
     ap.add_argument("--kernel", default="")
     ap.add_argument("--top", type=int, default=12)
     ap.add_argument("--bytes", type=int, default=0)
-    ap.add_argument("--sources", default="dense", choices=["dense", "csr", "resident"])
+    ap.add_argument("--sources", default="dense", choices=sorted(SOURCES))
     a = ap.parse_args(argv)
     if a.mode == "stats":
         stats(a.path, a.top)
@@ -107,8 +111,7 @@ def main(argv=None):
     elif a.mode == "calib":
         calib(a.path, a.bytes)
     else:
-        print(source_hash({"dense": DENSE_SOURCES, "csr": CSR_SOURCES,
-                           "resident": RESIDENT_SOURCES}[a.sources]))
+        print(source_hash(SOURCES[a.sources]))
 
 
 if __name__ == "__main__":

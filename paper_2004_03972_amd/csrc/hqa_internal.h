@@ -139,6 +139,7 @@ hipError_t launch_md_steps(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 size_t resident_lds_bytes(int N);
 bool resident_fits(const Instance &I, int max_lds);
 hipError_t launch_md_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+hipError_t ensure_tiled_j(Instance &I, hipStream_t st);
 bool csr_resident_fits(hqa_md *md, Instance &I);
 hipError_t launch_md_csr_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_field(hqa_md *md, Instance &I, double *u, hipStream_t st);

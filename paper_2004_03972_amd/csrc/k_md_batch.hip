@@ -2,7 +2,7 @@
 //
 // A batch of uneven instances (sizes N_k, one shared schedule and replica count)
 // advances step by step; each step is one launch per storage type over a tile
-// table.  A tile is (instance, 32 rows, 64 replicas): wavefront w takes rows
+// table.  FP32 storage: a tile is (instance, 32 rows, 64 replicas): wavefront w takes rows
 // i0 + 16 (w & 1) and the two replica tiles r0 + 32 (w >> 1) + {0, 16}, so every
 // J fragment it loads feeds two MFMA tiles and, with 64 replicas, each J row
 // block is read once per step.  The tile table is ordered longest-first (LPT by
@@ -33,6 +33,8 @@ __device__ __forceinline__ bf16x8 cvt_fp8x8_b(uint2 raw) {
 struct BatchInst {
     int N, Np, ld, pad;
     const void *J;
+    const void *Jt;       // MFMA-tiled copy of J (BF16 / FP8 storage)
+    int nrounds;          // 128-column groups per row (Np / 128)
     const float *h;
     float *phi[2];
     bf16 *xb[2];
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kg = lane >> 4;
     const int i0 = tl.i0 + 16 * (w & 1);
     const int rb = tl.r0 + 32 * (w >> 1);         // first of the wavefront's two replica tiles
-    if (i0 >= I.Np || rb >= a.R) return;
+    if (i0 >= I.N || rb >= a.R) return;           // rows all padding: nothing is written
     const int row = i0 + (lane & 15);
     const float *phi_in = I.phi[a.cur];
     const bf16 *xb_in = I.xb[a.cur];
@@ -98,16 +100,29 @@ __global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
                 }
         }
     } else {
+        // A fragments from the MFMA-tiled copy of J: the four chunks of group gi of this
+        // row tile are one contiguous 32-byte (FP8) or 64-byte (BF16) run per lane, so
+        // each 16-byte load fills whole cache lines
         typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
-        const uint8_t *Ja = (const uint8_t *)I.J + ((int64_t)row * I.Np + 8 * kg) * (JT == JT_BF16 ? 2 : 1);
+        constexpr int lane_bytes = JT == JT_BF16 ? 64 : 32;
+        const uint8_t *Jt = (const uint8_t *)I.Jt +
+                            ((int64_t)(i0 / 16) * I.nrounds * 64 + lane) * lane_bytes;
         const int ngroups = I.Np / 128;
         AT A[4], An[4];
         bf16x8 B[2][4], Bn[2][4];
         auto load = [&](int gi, AT (&Ag)[4], bf16x8 (&Bg)[2][4]) {
+            const uint8_t *src = Jt + (int64_t)gi * 64 * lane_bytes;
+            if constexpr (JT == JT_BF16) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) Ag[j] = *(const bf16x8 *)(src + 16 * j);
+            } else {
+                const uint4 lo = *(const uint4 *)src, hi = *(const uint4 *)(src + 16);
+                Ag[0] = make_uint2(lo.x, lo.y); Ag[1] = make_uint2(lo.z, lo.w);
+                Ag[2] = make_uint2(hi.x, hi.y); Ag[3] = make_uint2(hi.z, hi.w);
+            }
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int kk = gi * 128 + 32 * j;
-                Ag[j] = *(const AT *)(Ja + kk * (JT == JT_BF16 ? 2 : 1));
 #pragma unroll
                 for (int c = 0; c < 2; c++)
                     Bg[c][j] = *(const bf16x8 *)(xb_in + (int64_t)colr[c] * I.ld + kk + 8 * kg);
@@ -174,6 +189,139 @@ __global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
     if (bad) atomicOr(a.err, ERR_NONFINITE);
 }
 
+// BF16 / FP8 storage: tiles of 128 rows x 64 replicas, eight wavefronts, wavefront w
+// owning row tile i0 + 16 w and all four replica tiles.  Per 128-column group the
+// flux operand block (64 replicas x 128 columns, BF16) is staged once into LDS by
+// the whole workgroup with full-line loads and shared by the eight row tiles, so it
+// is read from L2 once per 128 rows instead of once per 32; the J fragments come
+// from the MFMA-tiled copy, one group ahead in registers; the LDS block is double-
+// buffered with one barrier per group.  Chains, operands and epilogue are those of
+// the other dense kernels (bit-identical results).  Wavefronts whose rows are all
+// padding keep zero J fragments and take part in the staging and the barriers.
+constexpr int BL_ROWS = 128, BL_REPS = 64, BL_LDB = 128 + 8;   // LDS row: 272 bytes
+
+template <int JT>
+__global__ __launch_bounds__(512) void k_step_batch_lds(BatchArgs a, int64_t q) {
+    __shared__ __align__(16) bf16 Bs[2][BL_REPS][BL_LDB];
+    const BatchTile tl = a.tiles[blockIdx.x];
+    const BatchInst I = a.inst[tl.inst];
+    const int tid = threadIdx.x, lane = tid & 63, kg = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i0 = tl.i0 + 16 * w;
+    const bool active = i0 < I.N;
+    const int r0 = tl.r0;
+    const float *phi_in = I.phi[a.cur];
+    const bf16 *xb_in = I.xb[a.cur];
+    const int ngroups = I.Np / 128;
+    typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
+    constexpr int lane_bytes = JT == JT_BF16 ? 64 : 32;
+    const uint8_t *Jt = (const uint8_t *)I.Jt +
+                        ((int64_t)(i0 / 16) * I.nrounds * 64 + lane) * lane_bytes;
+    // staging: thread -> (replica row, 16-column segment) of the 64 x 128 block
+    const int srow = tid >> 3, sseg = tid & 7;
+    const bf16 *bsrc = xb_in + (int64_t)min(r0 + srow, a.R - 1) * I.ld + 16 * sseg;
+
+    AT A[4], An[4];
+    auto loadA = [&](int gi, AT (&Ag)[4]) {
+        if (!active) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) Ag[j] = AT{};
+            return;
+        }
+        const uint8_t *src = Jt + (int64_t)gi * 64 * lane_bytes;
+        if constexpr (JT == JT_BF16) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) Ag[j] = *(const bf16x8 *)(src + 16 * j);
+        } else {
+            const uint4 lo = *(const uint4 *)src, hi = *(const uint4 *)(src + 16);
+            Ag[0] = make_uint2(lo.x, lo.y); Ag[1] = make_uint2(lo.z, lo.w);
+            Ag[2] = make_uint2(hi.x, hi.y); Ag[3] = make_uint2(hi.z, hi.w);
+        }
+    };
+    {
+        const uint4 b0 = *(const uint4 *)bsrc, b1 = *(const uint4 *)(bsrc + 8);
+        *(uint4 *)&Bs[0][srow][16 * sseg] = b0;
+        *(uint4 *)&Bs[0][srow][16 * sseg + 8] = b1;
+    }
+    loadA(0, A);
+    __syncthreads();
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[rt][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int gi = 0; gi < ngroups; gi++) {
+        const bool more = gi + 1 < ngroups;
+        uint4 s0, s1;
+        if (more) {
+            const bf16 *src = bsrc + 128 * (gi + 1);
+            s0 = *(const uint4 *)src;
+            s1 = *(const uint4 *)(src + 8);
+            loadA(gi + 1, An);
+        }
+        const int buf = gi & 1;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            bf16x8 av;
+            if constexpr (JT == JT_BF16) av = A[j];
+            else av = cvt_fp8x8_b(A[j]);
+#pragma unroll
+            for (int rt = 0; rt < 4; rt++) {
+                const bf16x8 bv = *(const bf16x8 *)&Bs[buf][16 * rt + (lane & 15)][32 * j + 8 * kg];
+                acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[rt][j], 0, 0, 0);
+            }
+        }
+        if (more) {
+            *(uint4 *)&Bs[buf ^ 1][srow][16 * sseg] = s0;
+            *(uint4 *)&Bs[buf ^ 1][srow][16 * sseg + 8] = s1;
+#pragma unroll
+            for (int j = 0; j < 4; j++) A[j] = An[j];
+        }
+        __syncthreads();
+    }
+
+    if (!active) return;
+    const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
+    const int ib = i0 + 4 * kg;
+    const bool win = q + 1 >= a.T - a.W + 1;
+    bool bad = false;
+    float *phi_out = I.phi[a.cur ^ 1];
+    bf16 *xb_out = I.xb[a.cur ^ 1];
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+        const int col = r0 + 16 * rt + (lane & 15);
+        if (col >= a.R || ib >= I.N) continue;
+        const f32x4 parts[4] = {acc[rt][0], acc[rt][1], acc[rt][2], acc[rt][3]};
+        const f32x4 u = combine4(parts);
+        const int64_t base = (int64_t)col * I.ld + ib;
+        float4 x = *(const float4 *)(phi_in + base);
+        float4 p = *(const float4 *)(I.p + base);
+        float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w}, xn[4];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            if (ib + v < I.N) {
+                leapfrog(cf, xs[v], u[v], I.h[ib + v], ps[v], xn[v]);
+                bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
+            } else {
+                xn[v] = 0.0f;
+                ps[v] = 0.0f;
+            }
+        }
+        *(float4 *)(phi_out + base) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+        *(float4 *)(I.p + base) = make_float4(ps[0], ps[1], ps[2], ps[3]);
+        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+        bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
+        *(bf16x4 *)(xb_out + base) = b;
+        if (win) {
+            float4 s = *(const float4 *)(I.S + base);
+            s.x = s.x + xn[0]; s.y = s.y + xn[1]; s.z = s.z + xn[2]; s.w = s.w + xn[3];
+            *(float4 *)(I.S + base) = s;
+        }
+    }
+    if (bad) atomicOr(a.err, ERR_NONFINITE);
+}
+
 // Device tables of a batch, built once per handle: instance descriptors and one
 // LPT-ordered tile list per storage type.
 struct BatchPlan {
@@ -200,6 +348,16 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
         BatchInst b;
         b.N = I.N; b.Np = I.Np; b.ld = I.ld; b.pad = 0;
         b.J = I.Js; b.h = I.h32;
+        b.Jt = nullptr;
+        b.nrounds = I.Np / 128;
+        if (I.layout == HQA_DENSE && (I.jt == JT_BF16 || I.jt == JT_FP8)) {
+            hipError_t e = ensure_tiled_j(I, md->stream);
+            if (e != hipSuccess) {
+                delete bp;
+                return e;
+            }
+            b.Jt = I.Jt;
+        }
         b.phi[0] = I.phi32[0]; b.phi[1] = I.phi32[1];
         b.xb[0] = I.phib[0]; b.xb[1] = I.phib[1];
         b.p = I.p32; b.S = I.S32;
@@ -213,8 +371,10 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
     std::vector<BatchTile> ht[3];
     for (int k : dense) {
         const Instance &I = md->inst[k];
-        for (int i0 = 0; i0 < I.Np; i0 += 32)
-            for (int r0 = 0; r0 < md->R; r0 += 64) ht[I.jt].push_back({k, i0, r0, 0});
+        const int rows = I.jt == JT_F32 ? 32 : BL_ROWS;   // tile height of the storage's kernel
+        for (int i0 = 0; i0 < I.Np; i0 += rows)
+            if (i0 < I.N)
+                for (int r0 = 0; r0 < md->R; r0 += 64) ht[I.jt].push_back({k, i0, r0, 0});
     }
     hipError_t e = hipMalloc((void **)&bp->dinst, sizeof(BatchInst) * hi.size());
     if (e == hipSuccess)
@@ -259,8 +419,8 @@ hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1) {
             a.tiles = bp->dtiles[t];
             a.ntiles = bp->ntiles[t];
             if (t == JT_F32) k_step_batch<JT_F32><<<a.ntiles, 256, 0, md->stream>>>(a, q);
-            else if (t == JT_BF16) k_step_batch<JT_BF16><<<a.ntiles, 256, 0, md->stream>>>(a, q);
-            else k_step_batch<JT_FP8><<<a.ntiles, 256, 0, md->stream>>>(a, q);
+            else if (t == JT_BF16) k_step_batch_lds<JT_BF16><<<a.ntiles, 512, 0, md->stream>>>(a, q);
+            else k_step_batch_lds<JT_FP8><<<a.ntiles, 512, 0, md->stream>>>(a, q);
         }
         cur ^= 1;
     }

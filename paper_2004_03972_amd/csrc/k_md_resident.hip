@@ -314,22 +314,28 @@ static hipError_t launch_res(const ResArgs &a, int grid, size_t lds, hipStream_t
 
 // Steps [q0, q1) in at most two launches: the part before the averaging window
 // and the part inside it.
-hipError_t launch_md_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
+// Build the MFMA-tiled copy of a BF16 or FP8 J once per instance (on first use).
+hipError_t ensure_tiled_j(Instance &I, hipStream_t st) {
+    if (I.Jt) return hipSuccess;
+    if (I.jt != JT_BF16 && I.jt != JT_FP8) return hipErrorNotSupported;
     const int esz = I.jt == JT_BF16 ? 2 : 1;
     const int64_t tb = resident_tile_bytes(I);
-    if (!I.Jt) {   // built once per instance, on first use
-        hipError_t e = hipMalloc(&I.Jt, tb);
-        if (e != hipSuccess) {
-            I.Jt = nullptr;
-            return e;
-        }
-        const int64_t n = tb / (8 * esz);
-        k_tile_j<<<(unsigned)((n + 255) / 256), 256, 0, md->stream>>>(
-            (const uint8_t *)I.Js, I.Np, (I.N + 15) / 16, ((I.N + 31) / 32 + 3) / 4, esz,
-            (uint8_t *)I.Jt);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    hipError_t e = hipMalloc(&I.Jt, tb);
+    if (e != hipSuccess) {
+        I.Jt = nullptr;
+        return e;
     }
+    const int64_t n = tb / (8 * esz);
+    k_tile_j<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+        (const uint8_t *)I.Js, I.Np, (I.N + 15) / 16, ((I.N + 31) / 32 + 3) / 4, esz,
+        (uint8_t *)I.Jt);
+    return hipGetLastError();
+}
+
+hipError_t launch_md_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
+    const int64_t tb = resident_tile_bytes(I);
+    hipError_t et = ensure_tiled_j(I, md->stream);
+    if (et != hipSuccess) return et;
     const int64_t qw = md->sch.T - md->sch.W;   // first step whose phi' enters the window
     const size_t lds = resident_lds_bytes(I.N);
     const int grid = I.Rp / 16;

@@ -10,6 +10,7 @@
 // the tail of the step.  The field uses the chunk-to-chain decomposition of the
 // other dense kernels, and the update the same binary32 sequence, so a batched
 // instance evolves bit-identically to the same instance run alone.
+#include <algorithm>
 #include <type_traits>
 
 #include "hqa_internal.h"
@@ -31,7 +32,7 @@ __device__ __forceinline__ bf16x8 cvt_fp8x8_b(uint2 raw) {
 }
 
 struct BatchInst {
-    int N, Np, ld, pad;
+    int N, Np, ld, jt;
     const void *J;
     const void *Jt;       // MFMA-tiled copy of J (BF16 / FP8 storage)
     int nrounds;          // 128-column groups per row (Np / 128)
@@ -201,10 +202,9 @@ __global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
 constexpr int BL_ROWS = 128, BL_REPS = 64, BL_LDB = 128 + 8;   // LDS row: 272 bytes
 
 template <int JT>
-__global__ __launch_bounds__(512) void k_step_batch_lds(BatchArgs a, int64_t q) {
-    __shared__ __align__(16) bf16 Bs[2][BL_REPS][BL_LDB];
-    const BatchTile tl = a.tiles[blockIdx.x];
-    const BatchInst I = a.inst[tl.inst];
+__device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, const BatchTile &tl,
+                                               const BatchInst &I,
+                                               bf16 (&Bs)[2][BL_REPS][BL_LDB]) {
     const int tid = threadIdx.x, lane = tid & 63, kg = lane >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i0 = tl.i0 + 16 * w;
@@ -322,8 +322,20 @@ __global__ __launch_bounds__(512) void k_step_batch_lds(BatchArgs a, int64_t q) 
     if (bad) atomicOr(a.err, ERR_NONFINITE);
 }
 
-// Device tables of a batch, built once per handle: instance descriptors and one
-// LPT-ordered tile list per storage type.
+// One launch per MD step for every BF16 and FP8 instance of the batch: the storage
+// type is uniform per tile.  A tile with instance index -1 is a placeholder of the
+// XCD placement and does nothing.
+__global__ __launch_bounds__(512, 4) void k_step_batch_lds(BatchArgs a, int64_t q) {
+    __shared__ __align__(16) bf16 Bs[2][BL_REPS][BL_LDB];
+    const BatchTile tl = a.tiles[blockIdx.x];
+    if (tl.inst < 0) return;
+    const BatchInst I = a.inst[tl.inst];
+    if (I.jt == JT_FP8) batch_lds_tile<JT_FP8>(a, q, tl, I, Bs);
+    else batch_lds_tile<JT_BF16>(a, q, tl, I, Bs);
+}
+
+// Device tables of a batch, built once per handle: instance descriptors and the
+// tile lists (FP32 storage; BF16 and FP8 storage together).
 struct BatchPlan {
     BatchInst *dinst = nullptr;
     BatchTile *dtiles[3] = {nullptr, nullptr, nullptr};
@@ -346,7 +358,7 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
     for (size_t k = 0; k < md->inst.size(); k++) {
         Instance &I = md->inst[k];
         BatchInst b;
-        b.N = I.N; b.Np = I.Np; b.ld = I.ld; b.pad = 0;
+        b.N = I.N; b.Np = I.Np; b.ld = I.ld; b.jt = I.jt;
         b.J = I.Js; b.h = I.h32;
         b.Jt = nullptr;
         b.nrounds = I.Np / 128;
@@ -369,12 +381,39 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
         return md->inst[x].Np > md->inst[y].Np;
     });
     std::vector<BatchTile> ht[3];
+    // FP32 storage: 32-row tiles, longest first
     for (int k : dense) {
         const Instance &I = md->inst[k];
-        const int rows = I.jt == JT_F32 ? 32 : BL_ROWS;   // tile height of the storage's kernel
-        for (int i0 = 0; i0 < I.Np; i0 += rows)
-            if (i0 < I.N)
-                for (int r0 = 0; r0 < md->R; r0 += 64) ht[I.jt].push_back({k, i0, r0, 0});
+        if (I.jt != JT_F32) continue;
+        for (int i0 = 0; i0 < I.N; i0 += 32)
+            for (int r0 = 0; r0 < md->R; r0 += 64) ht[JT_F32].push_back({k, i0, r0, 0});
+    }
+    // BF16 / FP8 storage: every tile of an instance on one XCD (workgroup b of a
+    // launch runs on XCD b mod 8), so the instance's flux operand is fetched into one
+    // L2; instances go to the least-loaded XCD, largest first (LPT on the tile count,
+    // i.e. on N^2 R work); the per-XCD lists are interleaved into the launch order
+    // and padded with placeholder tiles.
+    {
+        constexpr int NX = 8;
+        std::vector<BatchTile> xl[NX];
+        int64_t load[NX] = {0};
+        for (int k : dense) {
+            const Instance &I = md->inst[k];
+            if (I.jt == JT_F32) continue;
+            int x = 0;
+            for (int y = 1; y < NX; y++)
+                if (load[y] < load[x]) x = y;
+            for (int i0 = 0; i0 < I.N; i0 += BL_ROWS)
+                for (int r0 = 0; r0 < md->R; r0 += 64) {
+                    xl[x].push_back({k, i0, r0, 0});
+                    load[x] += (int64_t)I.Np;   // work of a tile ~ its row length
+                }
+        }
+        size_t longest = 0;
+        for (int x = 0; x < NX; x++) longest = std::max(longest, xl[x].size());
+        for (size_t j = 0; j < longest; j++)
+            for (int x = 0; x < NX; x++)
+                ht[JT_BF16].push_back(j < xl[x].size() ? xl[x][j] : BatchTile{-1, 0, 0, 0});
     }
     hipError_t e = hipMalloc((void **)&bp->dinst, sizeof(BatchInst) * hi.size());
     if (e == hipSuccess)
@@ -419,8 +458,7 @@ hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1) {
             a.tiles = bp->dtiles[t];
             a.ntiles = bp->ntiles[t];
             if (t == JT_F32) k_step_batch<JT_F32><<<a.ntiles, 256, 0, md->stream>>>(a, q);
-            else if (t == JT_BF16) k_step_batch_lds<JT_BF16><<<a.ntiles, 512, 0, md->stream>>>(a, q);
-            else k_step_batch_lds<JT_FP8><<<a.ntiles, 512, 0, md->stream>>>(a, q);
+            else k_step_batch_lds<<<a.ntiles, 512, 0, md->stream>>>(a, q);   // BF16 and FP8
         }
         cur ^= 1;
     }

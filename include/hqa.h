@@ -202,6 +202,15 @@ int32_t hqa_md_last_plan(const hqa_md *md);
  * steps < 1; HQA_ESTATE if fewer than `steps` steps remain before T. */
 hqa_status hqa_md_tune(hqa_md *md, int32_t steps);
 
+/* Error of the binary32 field of instance k against the binary64 field on the same
+ * fluxes (the current phi^(q), widened exactly): the field the instance's precision
+ * form computes (FP32, or BF16 operands with FP32 accumulation, J in its storage type)
+ * against sum_j J_ij phi_j in binary64 with the input J (Results, Eq. (3) force term).
+ * Writes max |u32 - u64| and max |u64| over all spins and replicas.  HQA_EUNSUPPORTED
+ * for the reference mode and for N > 8192.  Synchronises. */
+hqa_status hqa_md_field_error(hqa_md *md, int32_t instance, double *max_abs_err,
+                              double *max_abs_field);
+
 /* The tuned plan of dense instance k (0 if not tuned, -1 for a bad argument); *tm, *tn
  * and *cb, if not NULL, receive the per-step block shape in row and replica tiles of
  * 16 and the K chunks per accumulation chain loaded together (0 = default). */

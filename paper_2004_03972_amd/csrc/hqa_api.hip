@@ -166,6 +166,31 @@ struct DevBufs {
 };
 
 
+// Per-block maxima of |a - b| and |b| over n values (finished on the host).
+__global__ void k_maxdiff(const double *a, const double *b, int64_t n, double *out) {
+    __shared__ double m0[256], m1[256];
+    double d = 0.0, r = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        d = fmax(d, fabs(a[i] - b[i]));
+        r = fmax(r, fabs(b[i]));
+    }
+    m0[threadIdx.x] = d;
+    m1[threadIdx.x] = r;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            m0[threadIdx.x] = fmax(m0[threadIdx.x], m0[threadIdx.x + s]);
+            m1[threadIdx.x] = fmax(m1[threadIdx.x], m1[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = m0[0];
+        out[2 * blockIdx.x + 1] = m1[0];
+    }
+}
+
 extern "C" {
 
 int32_t hqa_abi_version(void) { return HQA_ABI_VERSION; }
@@ -673,6 +698,44 @@ hqa_status hqa_md_state(hqa_md *md, int32_t instance, int32_t what, void *dst, i
         HIPCHK(hipMemcpyAsync(dst, buf, n * 8, hipMemcpyDeviceToHost, md->stream));
     HIPCHK(hipStreamSynchronize(md->stream));
     if (dst_mem == HQA_HOST) dfree(buf);
+    return HQA_OK;
+}
+
+hqa_status hqa_md_field_error(hqa_md *md, int32_t instance, double *max_abs_err,
+                              double *max_abs_field) {
+    hqa_status s = check_instance(md, instance);
+    if (s != HQA_OK) return s;
+    if (!max_abs_err || !max_abs_field) return fail(HQA_EINVAL, "null output");
+    if (md->prec == HQA_PREC_F64_REF) return fail(HQA_EUNSUPPORTED, "the reference mode is binary64");
+    Instance &I = md->inst[instance];
+    if (I.N > 8192) return fail(HQA_EUNSUPPORTED, "binary64 field limited to N <= 8192");
+    const size_t n = (size_t)I.N * md->R;
+    const size_t m = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
+    DevBufs bufs;
+    double *u, *u64, *part;
+    float *u32;
+    const int blocks = 256;
+    HIPCHK(bufs.get(&u, n));
+    HIPCHK(bufs.get(&u64, n));
+    HIPCHK(bufs.get(&part, 2 * blocks));
+    HIPCHK(bufs.get(&u32, m));
+    if (I.layout == HQA_DENSE) HIPCHK(launch_field_dense(md, I, u32, md->stream));
+    else HIPCHK(launch_field_csr(md, I, u32, md->stream));
+    HIPCHK(launch_layout_to_f64(I.N, md->R, I.ld, I.smaj, u32, u, md->stream));
+    HIPCHK(launch_field_f64(md, I, u64, md->stream));
+    k_maxdiff<<<blocks, 256, 0, md->stream>>>(u, u64, (int64_t)n, part);
+    HIPCHK(hipGetLastError());
+    std::vector<double> h(2 * blocks);
+    HIPCHK(hipMemcpyAsync(h.data(), part, sizeof(double) * 2 * blocks, hipMemcpyDeviceToHost,
+                          md->stream));
+    HIPCHK(hipStreamSynchronize(md->stream));
+    double e = 0.0, r = 0.0;
+    for (int b = 0; b < blocks; b++) {
+        e = std::max(e, h[2 * b]);
+        r = std::max(r, h[2 * b + 1]);
+    }
+    *max_abs_err = e;
+    *max_abs_field = r;
     return HQA_OK;
 }
 

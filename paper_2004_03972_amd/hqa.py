@@ -26,7 +26,7 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_md_init", "hqa_md_run", "hqa_md_reset", "hqa_md_sync", "hqa_md_step_index", "hqa_md_state",
             "hqa_md_set_step", "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify",
             "hqa_ising_energy", "hqa_md_destroy", "hqa_md_last_plan", "hqa_md_tune",
-            "hqa_md_tuned_plan", "hqa_md_set_step_tiles",
+            "hqa_md_tuned_plan", "hqa_md_set_step_tiles", "hqa_md_field_error",
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
             "hqa_es_destroy")
@@ -97,6 +97,7 @@ def lib():
         L.hqa_md_tuned_plan.argtypes = [P, i32, P, P, P]
         L.hqa_md_tuned_plan.restype = i32
         L.hqa_md_set_step_tiles.argtypes = [P, i32, i32, i32, i32]
+        L.hqa_md_field_error.argtypes = [P, i32, P, P]
         L.hqa_md_state.argtypes = [P, i32, i32, P, i32, i32]
         L.hqa_md_set_step.argtypes = [P, i64]
         L.hqa_md_field.argtypes = [P, i32, P, i32]
@@ -117,7 +118,7 @@ def lib():
                   "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify", "hqa_ising_energy",
                   "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
                   "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
-                  "hqa_md_tune", "hqa_md_set_step_tiles"):
+                  "hqa_md_tune", "hqa_md_set_step_tiles", "hqa_md_field_error"):
             getattr(L, f).restype = C.c_int
         if L.hqa_abi_version() != ABI_VERSION:
             raise ImportError("libhqa ABI version mismatch")
@@ -190,6 +191,12 @@ def hqa_md_last_plan(md) -> int:
 
 def hqa_md_tune(md, steps: int):
     _check(lib().hqa_md_tune(md, steps))
+
+
+def hqa_md_field_error(md, k: int = 0) -> tuple[float, float]:
+    e, r = C.c_double(0.0), C.c_double(0.0)
+    _check(lib().hqa_md_field_error(md, k, C.byref(e), C.byref(r)))
+    return e.value, r.value
 
 
 def hqa_md_set_step_tiles(md, k: int, tm: int, tn: int, cb: int = 4):
@@ -424,6 +431,10 @@ class MD:
     def tune(self, steps: int = 20):
         """Time every bit-identical plan from the current state and keep the fastest."""
         hqa_md_tune(self.h, steps)
+
+    def field_error(self, k: int = 0) -> tuple[float, float]:
+        """(max |u32 - u64|, max |u64|) of instance k's field on the current fluxes."""
+        return hqa_md_field_error(self.h, k)
 
     def set_step_tiles(self, tm: int, tn: int, cb: int = 4, k: int = 0):
         """Pin instance k to per-step blocks of tm x tn tiles of 16 (rows x replicas)

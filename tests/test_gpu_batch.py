@@ -111,3 +111,24 @@ def test_batch_f32_tracks_oracle(H):
                                   orc.init_p0(9, N, R))
         assert np.max(np.abs(b.state(H.HQA_STATE_PHI, k) - phiT)) < 1e-4
         assert np.max(np.abs(b.state(H.HQA_STATE_PHIBAR, k) - bar)) < 1e-4
+
+
+def test_field_error_against_binary64(H):
+    """hqa_md_field_error: binary32 field of each instance's precision form against the
+    binary64 field on the same fluxes; the reference magnitude is checked against
+    numpy's J @ phi."""
+    R = 32
+    Js = [inst.sk(300, 11), inst.er_maxcut(500, 0.05, 12), inst.sk(200, 13)]
+    probs = [H.Problem(Js[0], storage="bf16"), H.Problem(Js[1], storage="fp8"),
+             H.Problem(Js[2], storage="f32")]
+    md = H.MD(probs, H.make_schedule(200, 20), R, "bf16", seed=3)
+    md.run(120)
+    for k, (J, bar) in enumerate(zip(Js, (2e-2, 2e-2, 1e-5))):
+        err, ref = md.field_error(k)
+        phi = md.state(H.HQA_STATE_PHI, k)
+        want = np.abs(phi @ J.T).max()
+        print("instance", k, "max|du|", err, "max|u|", ref, "relative", err / ref, flush=True)
+        assert ref == pytest.approx(want, rel=1e-12)
+        assert err / ref <= bar
+        if k < 2:
+            assert err > 0.0                  # BF16 flux operand: a rounding error exists

@@ -81,7 +81,7 @@ def _declare(L):
         "or_enumerate": (C.c_int, [i32, i32, P, P, P, P]),
         "or_merge": (V, [i32, i32, i32, P, P, P]),
         "or_energy": (C.c_int, [P, i32, P, P, P]),
-        "or_es_features": (C.c_int, [P, P, i32, P, P, i64, i64, P, P, P]),
+        "or_es_features": (C.c_int, [P, P, i32, P, P, i64, i64, i64, P, P, P]),
         "or_gelu": (d, [d]),
         "or_mlp_forward": (V, [P, i64, P, P]),
         "or_mlp_loss_grad": (d, [P, i64, P, P, P, P]),
@@ -277,14 +277,14 @@ def hqa(pb: Problem, mp: MDParams, p0, n: int, phi0=None, nthreads: int = 1):
 
 
 # ----------------------------------------------------------- learned early stop
-def es_features(pb: Problem, mp: MDParams, phi0, p0, K0: int, K1: int):
-    """Features [R, N, 12] at step K1 from statistics over steps [K0, K1); also
-    returns phi^(K1) and p^(K1-1/2)."""
+def es_features(pb: Problem, mp: MDParams, phi0, p0, K0: int, K1: int, every: int = 1):
+    """Features [R, N, 12] at step K1 from statistics over the steps K0, K0 + every, ...
+    below K1; also returns phi^(K1) and p^(K1-1/2)."""
     phi0, p0 = _f64(phi0), _f64(p0)
     R, N = phi0.shape
     feat = np.empty((R, N, NFEAT))
     phi, p = np.empty_like(phi0), np.empty_like(phi0)
-    st = lib().or_es_features(pb.c, mp.c, R, _ptr(phi0), _ptr(p0), K0, K1, _ptr(feat),
+    st = lib().or_es_features(pb.c, mp.c, R, _ptr(phi0), _ptr(p0), K0, K1, every, _ptr(feat),
                               _ptr(phi), _ptr(p))
     if st != 0:
         raise ValueError(f"or_es_features status {st}")

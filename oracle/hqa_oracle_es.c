@@ -75,10 +75,10 @@ static void row_norms(const or_problem *pb, double *n1, double *n2) {
  * the statistics over [K0, K1) and write the features [R][N][12] at q = K1.
  * phi_out / p_out receive phi^(K1), p^(K1-1/2). */
 int or_es_features(const or_problem *pb, const or_md_params *mp, int32_t R, const double *phi0,
-                   const double *p0, int64_t K0, int64_t K1, double *feat, double *phi_out,
-                   double *p_out) {
+                   const double *p0, int64_t K0, int64_t K1, int64_t every, double *feat,
+                   double *phi_out, double *p_out) {
     const int64_t N = pb->N;
-    if (K0 < 0 || K1 <= K0 || K1 > mp->T) return -1;
+    if (K0 < 0 || K1 <= K0 || K1 > mp->T || every < 1) return -1;
     double *x = malloc(sizeof(double) * N), *xn = malloc(sizeof(double) * N);
     double *p = malloc(sizeof(double) * N), *u = malloc(sizeof(double) * N);
     double *A = calloc((size_t)9 * N, sizeof(double));
@@ -108,7 +108,7 @@ int or_es_features(const or_problem *pb, const or_md_params *mp, int32_t R, cons
                 p[i] = q == 0 ? p[i] - 0.5 * F : p[i] - F;
                 xn[i] = xi + (ad * p[i]);
             }
-            if (q >= K0) {
+            if (q >= K0 && (q - K0) % every == 0) {   /* every-th step of the window */
                 for (int64_t i = 0; i < N; i++) {
                     double nu = n2[i] > 0.0 ? u[i] / n2[i] : 0.0;
                     double so = x[i] < 0.0 ? -1.0 : 1.0;
@@ -125,7 +125,7 @@ int or_es_features(const or_problem *pb, const or_md_params *mp, int32_t R, cons
             }
             memcpy(x, xn, sizeof(double) * N);
         }
-        const double K = (double)(K1 - K0);
+        const double K = (double)((K1 - K0 + every - 1) / every);   /* sampled steps */
         double s2 = 0.0, pm = 0.0;
         for (int64_t i = 0; i < N; i++) {
             s2 += x[i] * x[i];

@@ -101,22 +101,24 @@ def test_adam_first_steps_closed_form(orc):
     assert np.allclose(P, P0 - 2 * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-14)
 
 
-def test_features_of_harmonic_trajectory(orc):
+@pytest.mark.parametrize("every", [1, 3])
+def test_features_of_harmonic_trajectory(orc, every):
     # J = 0, h = 0, M = 2, frozen alpha: phi^(q) = alpha p0 sin(q th)/sin th, cos th = 1 - alpha^2,
-    # p^(q+1/2) = (phi^(q+1) - phi^(q)) / alpha; the field and the row norms vanish.
+    # p^(q+1/2) = (phi^(q+1) - phi^(q)) / alpha; the field and the row norms vanish.  With
+    # every > 1 the window statistics sample the steps K0, K0 + every, ... below K1.
     N, R, T, alpha = 6, 2, 60, 0.35
     K0, K1 = 10, 47
     pb = orc.Problem(N, J=np.zeros((N, N)))
     mp = orc.MDParams(T=T, W=1, M=2, schedule=(alpha, 0, 0, 0.5, 0, 0), frozen=True, tau_fix=1.0)
     p0 = inst.random_pm1((R, N), 11)
-    feat, phiK, _ = orc.es_features(pb, mp, np.zeros((R, N)), p0, K0, K1)
+    feat, phiK, _ = orc.es_features(pb, mp, np.zeros((R, N)), p0, K0, K1, every)
     th = math.acos(1 - alpha ** 2)
     q = np.arange(T + 1)[:, None, None]
     phi = alpha * p0[None] * np.sin(q * th) / math.sin(th)            # [T+1, R, N]
-    new = phi[K0 + 1:K1 + 1]
-    old = phi[K0:K1]
+    steps = np.arange(K0, K1, every)
+    new = phi[steps + 1]
+    old = phi[steps]
     p = (new - old) / alpha
-    K = K1 - K0
     sig = np.sqrt(np.mean(phi[K1] ** 2, axis=1))[:, None]
     pm = np.mean(np.mean(p ** 2, axis=0), axis=1)[:, None]
     m0 = new.mean(0)

@@ -14,6 +14,7 @@ chosen form's best cut must be within 0.1% of FP32's.
 Other workloads (measurement lines for the design notes, not the bench line):
   --workload ea3d      3D +-J lattice 16^3, CSR FP32, R = 1024, T = 10000
   --workload batch512  512 uneven instances (SK BF16 / ER FP8), R = 64, T = 5000
+  --workload es        learned early stop: train on ER runs, evaluate on ER N = 10^4
   --workload copy      a plain device copy of known size (HBM counter calibration)
 
   python bench.py [--steps K] [--warmup W] [--no-cpu] [--workload ...]
@@ -287,6 +288,79 @@ def bench_batch512(args, hqa, torch):
                          "frac": flops * Tt / (ms / 1e3) / 2.5e15, "kernel": "k_step_batch_lds"}}
 
 
+def bench_es(args, hqa, torch):
+    """Learned early stop on sparse ER MAX-CUT: train on runs of the method itself
+    (N ~ U{1000..4000}, mean degree ~ U[20, 100], T = 20000, checkpoints every K = 1000
+    steps with statistics sampled every 10th step of the last Ks = 100 steps before each),
+    calibrate the stop threshold on validation runs, then evaluate on
+    ER N = 10^4, p = 0.005 (mean degree ~50), R = 128: stop step, mislabel rate and
+    best cut against the full run, and the truncation ablation at the same step."""
+    from paper_2004_03972_amd import early_stop as E
+    from paper_2004_03972_amd import instances as inst
+    Tt, K, Ks = 20000, args.es_k, args.es_ks
+    nck = Tt // K
+    sched = hqa.make_schedule(Tt, 100)
+    rng = np.random.default_rng(5)
+    t0 = time.perf_counter()
+    recs = []
+    ntrain, nval, Rt = args.es_train, 8, 4
+    for k in range(ntrain + nval):
+        Nk = int(rng.integers(1000, 4001))
+        d = float(rng.uniform(20, 100))
+        rp, ci, v = inst.er_sparse(Nk, d, 5_000_000 + k)
+        n_lab = max(1, round(0.05 * Nk))
+        rec = E.record_run(hqa.Problem(row_ptr=rp, col=ci, val=v), sched, Rt, K, nck,
+                           seed=100 + k, n_amb=n_lab, every=2 if k < ntrain else 1, Ks=Ks,
+                           stride=args.es_stride)
+        rec.md.close()
+        recs.append(rec)
+        if k % 8 == 7:
+            _log(f"  recorded {k + 1} runs, {time.perf_counter() - t0:.1f} s")
+    X, y = E.dataset(recs[:ntrain])
+    es = hqa.ES(seed=1)
+    t1 = time.perf_counter()
+    losses = E.train(es, X, y, epochs=2, batch=16384, lr=2e-3, log=_log)
+    train_s = time.perf_counter() - t1
+    thr = E.calibrate(es, recs[ntrain:], target_mislabel=args.es_target)
+    _log(f"  trained on {X.shape[0]} samples in {train_s:.1f} s, threshold {thr:.4f}")
+    # evaluation instance: ER N = 10^4, p = 0.005
+    Ne, Re = 10000, 128
+    rp, ci, v = inst.er_sparse(Ne, 0.005 * (Ne - 1), 5001)
+    prob = hqa.Problem(row_ptr=rp, col=ci, val=v)
+    n_lab = round(0.05 * Ne)
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(torch)
+    e0.record(st)
+    full = E.record_run(prob, sched, Re, K, nck, seed=7, n_amb=n_lab, solve_n=20, every=nck,
+                        Ks=Ks, stride=args.es_stride)
+    e1.record(st)
+    torch.cuda.synchronize()
+    full_ms = e0.elapsed_time(e1)
+    full.md.close()
+    e0.record(st)
+    res = E.run_with_early_stop(es, prob, sched, Re, K, thr if np.isfinite(thr) else 1.1,
+                                n_amb=20, seed=7, labels=full.labels, n_label=n_lab, Ks=Ks,
+                                stride=args.es_stride)
+    e1.record(st)
+    torch.cuda.synchronize()
+    es_ms = e0.elapsed_time(e1)
+    cut_full = float(full.full["cut"].max())
+    cut_es = float(res.readout["cut"].max())
+    cut_tr = float(res.ablation["cut"].max())
+    return {"metric": "learned early stop: speedup T/K_stop at cut loss", "workload":
+            f"train {ntrain} ER runs (N 1000..4000, d 20..100, R={Rt}, T={Tt}, K={K}, "
+            f"Ks={Ks}, stride {args.es_stride}); eval ER N={Ne} p=0.005 R={Re} T={Tt}, n=20 exact",
+            "train_samples": int(X.shape[0]), "train_s": train_s,
+            "loss_first_last": [float(np.mean(losses[:20])), float(np.mean(losses[-20:]))],
+            "threshold": thr, "target_mislabel": args.es_target,
+            "stop_step": res.stop_step, "speedup_steps": Tt / res.stop_step,
+            "wall_ms_full": full_ms, "wall_ms_early": es_ms,
+            "mislabel": {"network": res.mislabel, "truncation_same_step": res.mislabel_ablation},
+            "best_cut": {"full_run_hqa": cut_full, "early_stop_hqa": cut_es,
+                         "truncation_hqa": cut_tr,
+                         "loss_vs_full": (cut_full - cut_es) / cut_full}}
+
+
 def bench_copy(args, hqa, torch):
     """A plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB): HBM counter calibration."""
     n = 1 << 28
@@ -303,7 +377,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="er800", choices=["er800", "ea3d", "batch512", "copy"])
+    ap.add_argument("--workload", default="er800",
+                    choices=["er800", "ea3d", "batch512", "es", "copy"])
+    ap.add_argument("--es-train", type=int, default=48)
+    ap.add_argument("--es-target", type=float, default=0.03)
+    ap.add_argument("--es-k", type=int, default=1000)
+    ap.add_argument("--es-ks", type=int, default=100)
+    ap.add_argument("--es-stride", type=int, default=10)
     ap.add_argument("--forms", default="fp8,bf16,f32")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--md-steps", type=int, default=0)
@@ -322,7 +402,7 @@ def main():
     hqa.lib()
     torch.cuda.set_device(0)
     fn = {"er800": bench_er800, "ea3d": bench_ea3d, "batch512": bench_batch512,
-          "copy": bench_copy}[args.workload]
+          "es": bench_es, "copy": bench_copy}[args.workload]
     print(json.dumps(fn(args, hqa, torch)), flush=True)
 
 

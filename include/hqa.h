@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 2
+#define HQA_ABI_VERSION 3
 
 typedef enum {
     HQA_OK = 0,
@@ -312,10 +312,11 @@ void hqa_md_destroy(hqa_md *md);
 #define HQA_ES_NFEAT 12
 #define HQA_ES_NPARAM 5187
 
-/* Collect the statistics over steps [k0, k1) of the following runs (cleared now).
- * Those steps run on the per-step kernels.  HQA_EUNSUPPORTED for the binary64
- * reference precision; HQA_EINVAL unless 0 <= k0 < k1 <= T. */
-hqa_status hqa_md_stats_window(hqa_md *md, int64_t k0, int64_t k1);
+/* Collect the statistics over the steps k0, k0 + every, k0 + 2 every, ... below k1 of
+ * the following runs (cleared now); the features are means over those samples.  Steps
+ * of the window run on the per-step kernels.  HQA_EUNSUPPORTED for the binary64
+ * reference precision; HQA_EINVAL unless 0 <= k0 < k1 <= T and every >= 1. */
+hqa_status hqa_md_stats_window(hqa_md *md, int64_t k0, int64_t k1, int64_t every);
 
 /* Features [R][N][12] (binary32) of instance k at the current step.  HQA_ESTATE if
  * no window step has run.  Synchronises. */
@@ -354,6 +355,13 @@ hqa_status hqa_es_train_step(hqa_es *es, const float *x, const int32_t *y, int64
  * layer inputs to bfloat16 (binary32 accumulation).  Synchronises. */
 hqa_status hqa_es_predict(hqa_es *es, const float *x, int64_t n, float *prob, int32_t bf16_infer,
                           int32_t mem);
+
+/* Stop-rule confidence of a prediction: the mean over the n rows of prob [n][3] of the
+ * largest class probability, summed in binary64.  prob is in host or device memory
+ * (mem); only the scalar comes back, so a checkpoint evaluated on device data moves
+ * one number to the host.  Synchronises the handle's stream. */
+hqa_status hqa_es_confidence(hqa_es *es, const float *prob, int64_t n, int32_t mem,
+                             double *mean_max);
 
 void hqa_es_destroy(hqa_es *es);
 

@@ -191,6 +191,22 @@ __global__ void k_maxdiff(const double *a, const double *b, int64_t n, double *o
     }
 }
 
+// Per-block sums over rows of max(p0, p1, p2) (finished on the host).
+__global__ void k_sum_maxprob(const float *p, int64_t n, double *out) {
+    __shared__ double sm[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        acc += (double)fmaxf(fmaxf(p[3 * i], p[3 * i + 1]), p[3 * i + 2]);
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+
 extern "C" {
 
 int32_t hqa_abi_version(void) { return HQA_ABI_VERSION; }
@@ -677,7 +693,7 @@ hqa_status hqa_md_state(hqa_md *md, int32_t instance, int32_t what, void *dst, i
     if (what == HQA_STATE_STATMEAN) {
         if (md->prec == HQA_PREC_F64_REF || !I.st)
             return fail(HQA_ESTATE, "no statistics window has been set");
-        nstat = std::min(std::max(md->q, md->stats_k0), md->stats_k1) - md->stats_k0;
+        nstat = stats_count(md);
         if (nstat < 1) return fail(HQA_ESTATE, "no step of the statistics window has run");
     }
     const size_t n = (size_t)I.N * md->R;
@@ -869,11 +885,13 @@ hqa_status hqa_classify_probs(hqa_md *md, int32_t instance, const float *prob, i
     return classify_impl(md, instance, n_amb, solve, out, out_mem, prob, prob_mem);
 }
 
-hqa_status hqa_md_stats_window(hqa_md *md, int64_t k0, int64_t k1) {
+hqa_status hqa_md_stats_window(hqa_md *md, int64_t k0, int64_t k1, int64_t every) {
     if (!md) return fail(HQA_EINVAL, "null handle");
     if (md->prec == HQA_PREC_F64_REF)
         return fail(HQA_EUNSUPPORTED, "early-stop statistics run on the binary32 paths");
     if (k0 < 0 || k1 <= k0 || k1 > md->sch.T) return fail(HQA_EINVAL, "need 0 <= k0 < k1 <= T");
+    if (every < 1) return fail(HQA_EINVAL, "every must be >= 1");
+    md->stats_every = every;
     for (auto &I : md->inst) {
         const size_t n = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
         if (!I.st) {
@@ -902,7 +920,7 @@ hqa_status hqa_md_features(hqa_md *md, int32_t instance, float *feat, int32_t ds
     if (!feat) return fail(HQA_EINVAL, "feat is NULL");
     Instance &I = md->inst[instance];
     if (!I.st) return fail(HQA_ESTATE, "no statistics window set");
-    const int64_t K = std::min(md->q, md->stats_k1) - md->stats_k0;
+    const int64_t K = stats_count(md);
     if (K < 1) return fail(HQA_ESTATE, "no step of the statistics window has run");
     const size_t n = (size_t)md->R * I.N * 12;
     float *buf = feat;
@@ -1038,6 +1056,32 @@ hqa_status hqa_es_predict(hqa_es *es, const float *x, int64_t n, float *prob, in
     if (mem == HQA_HOST)
         HIPCHK(hipMemcpyAsync(prob, dp, sizeof(float) * n * 3, hipMemcpyDeviceToHost, es->stream));
     HIPCHK(hipStreamSynchronize(es->stream));
+    return HQA_OK;
+}
+
+hqa_status hqa_es_confidence(hqa_es *es, const float *prob, int64_t n, int32_t mem,
+                             double *mean_max) {
+    if (!es || !prob || !mean_max || n < 1) return fail(HQA_EINVAL, "bad arguments");
+    if (mem != HQA_HOST && mem != HQA_DEVICE) return fail(HQA_EINVAL, "bad mem");
+    DevBufs B;
+    const float *dp = prob;
+    if (mem == HQA_HOST) {
+        float *t;
+        HIPCHK(B.get(&t, (size_t)n * 3));
+        HIPCHK(hipMemcpyAsync(t, prob, sizeof(float) * n * 3, hipMemcpyHostToDevice, es->stream));
+        dp = t;
+    }
+    const int blocks = 256;
+    double *part;
+    HIPCHK(B.get(&part, blocks));
+    k_sum_maxprob<<<blocks, 256, 0, es->stream>>>(dp, n, part);
+    HIPCHK(hipGetLastError());
+    std::vector<double> h(blocks);
+    HIPCHK(hipMemcpyAsync(h.data(), part, sizeof(double) * blocks, hipMemcpyDeviceToHost, es->stream));
+    HIPCHK(hipStreamSynchronize(es->stream));
+    double t = 0.0;
+    for (double v : h) t += v;
+    *mean_max = t / (double)n;
     return HQA_OK;
 }
 

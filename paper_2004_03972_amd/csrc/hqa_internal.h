@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -112,6 +113,7 @@ struct hqa_md {
     int last_plan = 0;                       // plan the last run used (HQA_PLAN_*)
     void *batch = nullptr;                   // device tile tables of a multi-instance batch
     int64_t stats_k0 = 0, stats_k1 = 0;      // early-stop statistics window [k0, k1)
+    int64_t stats_every = 1;                 // ... sampling steps k0, k0 + every, ...
 };
 
 namespace hqa {
@@ -174,3 +176,14 @@ hipError_t launch_probs_to_keys(int64_t n, const float *prob, int8_t *spins, flo
                                 hipStream_t st);
 
 }  // namespace hqa
+
+// Whether MD step q accumulates early-stop statistics.
+inline bool stats_step(const hqa_md *md, int64_t q) {
+    return q >= md->stats_k0 && q < md->stats_k1 && (q - md->stats_k0) % md->stats_every == 0;
+}
+
+// Number of statistics samples taken by the steps run so far.
+inline int64_t stats_count(const hqa_md *md) {
+    const int64_t m = std::min(md->q, md->stats_k1) - md->stats_k0;
+    return m <= 0 ? 0 : (m + md->stats_every - 1) / md->stats_every;
+}

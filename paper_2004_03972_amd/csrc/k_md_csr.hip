@@ -109,7 +109,7 @@ hipError_t launch_md_steps_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1) 
     unsigned blocks = (unsigned)((n + 255) / 256);
     for (int64_t q = q0; q < q1; q++) {
         CsrArgs a = csr_args(md, I);
-        if (I.st && q >= md->stats_k0 && q < md->stats_k1) a.st = I.st;
+        if (I.st && stats_step(md, q)) a.st = I.st;
         k_step_csr<false><<<blocks, 256, 0, md->stream>>>(a, q);
         I.cur ^= 1;
     }

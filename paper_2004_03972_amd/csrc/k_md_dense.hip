@@ -265,7 +265,7 @@ hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1
     const int cb = I.step_cb == 8 ? 8 : 4;
     for (int64_t q = q0; q < q1; q++) {
         DenseArgs a = dense_args(md, I);
-        if (I.st && q >= md->stats_k0 && q < md->stats_k1) a.st = I.st;
+        if (I.st && stats_step(md, q)) a.st = I.st;
         launch_one<false>(a, tm, tn, cb, q, md->stream);
         I.cur ^= 1;
     }

@@ -41,14 +41,17 @@ def labels_from_full(md, n_amb: int) -> tuple[np.ndarray, dict]:
 
 
 def record_run(problem, sched, R: int, K: int, n_ckpt: int, seed: int, n_amb: int,
-               precision="f32", solve_n: int = 0) -> RunRecord:
-    """Run to T with statistics windows ending at K, 2K, ..., n_ckpt K; return the
-    features and the trailing-window mean flux at each checkpoint and the labels from
-    the full run."""
+               precision="f32", solve_n: int = 0, every: int = 1, Ks: int | None = None,
+               stride: int = 1) -> RunRecord:
+    """Run to T with statistics windows of the last Ks steps (default K; sampling every
+    stride-th step) before every every-th checkpoint among K, 2K, ..., n_ckpt K; return the features and the trailing-
+    window mean flux at those checkpoints and the labels from the full run."""
+    Ks = K if Ks is None else Ks
     md = hqa.MD(problem, sched, R, precision, seed=seed)
     feats, steps, means = [], [], []
-    for j in range(1, n_ckpt + 1):
-        md.stats_window((j - 1) * K, j * K)
+    for j in range(every, n_ckpt + 1, every):
+        md.run(j * K - Ks)
+        md.stats_window(j * K - Ks, j * K, stride)
         md.run(j * K)
         feats.append(md.features())
         means.append(md.state(hqa.HQA_STATE_STATMEAN))
@@ -157,26 +160,33 @@ class StopResult:
 
 def run_with_early_stop(es, problem, sched, R: int, K: int, threshold: float, n_amb: int,
                         seed: int, labels=None, n_label: int | None = None,
-                        bf16: bool = True) -> StopResult:
-    """Run checkpoint by checkpoint; stop at the first confident checkpoint (or T).
-    n_amb spins go to the exact solver; mislabel rates (when the full run's labels are
+                        bf16: bool = True, Ks: int | None = None, stride: int = 1) -> StopResult:
+    """Run checkpoint by checkpoint (statistics over the last Ks steps before each); stop
+    at the first confident checkpoint (or T).  n_amb spins go to the exact solver; mislabel rates (when the full run's labels are
     given) count n_label ambivalent spins per replica (default n_amb)."""
+    import torch   # device memory for the checkpoint evaluation (the arithmetic is libhqa's)
     n_label = n_amb if n_label is None else n_label
     md = hqa.MD(problem, sched, R, "f32", seed=seed)
-    T = sched.T
+    T, N = sched.T, problem.n
+    # features and probabilities stay on the device; each checkpoint returns one number
+    feat = torch.empty((R * N, hqa.HQA_ES_NFEAT), dtype=torch.float32, device="cuda")
+    pdev = torch.empty((R * N, 3), dtype=torch.float32, device="cuda")
     q = 0
+    Ks = K if Ks is None else Ks
     while True:
         nxt = min(q + K, T)
-        md.stats_window(q, nxt)
+        md.run(max(q, nxt - Ks))
+        md.stats_window(max(q, nxt - Ks), nxt, stride)
         md.run(nxt)
         q = nxt
-        feat = md.features()
-        prob = es.predict(feat.reshape(-1, 12), bf16=bf16).reshape(feat.shape[0], feat.shape[1], 3)
-        if confidence(prob) >= threshold or q >= T:
+        md.features(out=feat)
+        es.predict(feat, bf16=bf16, out=pdev)
+        if es.confidence(pdev) >= threshold or q >= T:
             break
     stopped = q < T
     tp = truncation_probs(md.state(hqa.HQA_STATE_STATMEAN))
-    out = md.classify(n_amb, solve=True, prob=prob)
+    out = md.classify(n_amb, solve=True, prob=pdev)
+    prob = pdev.cpu().numpy().reshape(R, N, 3)
     abl = md.classify(n_amb, solve=True, prob=tp)
     mis = mis_a = float("nan")
     if labels is not None:

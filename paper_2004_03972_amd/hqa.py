@@ -29,9 +29,9 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_md_tuned_plan", "hqa_md_set_step_tiles", "hqa_md_field_error",
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
-            "hqa_es_destroy")
+            "hqa_es_confidence", "hqa_es_destroy")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
-ABI_VERSION = 2
+ABI_VERSION = 3
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
          "resident": HQA_PLAN_RESIDENT}
@@ -98,6 +98,7 @@ def lib():
         L.hqa_md_tuned_plan.restype = i32
         L.hqa_md_set_step_tiles.argtypes = [P, i32, i32, i32, i32]
         L.hqa_md_field_error.argtypes = [P, i32, P, P]
+        L.hqa_es_confidence.argtypes = [P, P, i64, i32, P]
         L.hqa_md_state.argtypes = [P, i32, i32, P, i32, i32]
         L.hqa_md_set_step.argtypes = [P, i64]
         L.hqa_md_field.argtypes = [P, i32, P, i32]
@@ -105,7 +106,7 @@ def lib():
         L.hqa_classify.argtypes = [P, i32, i32, i32, P, i32]
         L.hqa_ising_energy.argtypes = [P, P, i32, P, P, i32, P]
         L.hqa_md_destroy.argtypes = [P]
-        L.hqa_md_stats_window.argtypes = [P, i64, i64]
+        L.hqa_md_stats_window.argtypes = [P, i64, i64, i64]
         L.hqa_md_features.argtypes = [P, i32, P, i32]
         L.hqa_classify_probs.argtypes = [P, i32, P, i32, i32, i32, P, i32]
         L.hqa_es_create.argtypes = [C.c_uint64, P, P]
@@ -118,7 +119,8 @@ def lib():
                   "hqa_md_field", "hqa_md_hamiltonian", "hqa_classify", "hqa_ising_energy",
                   "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
                   "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
-                  "hqa_md_tune", "hqa_md_set_step_tiles", "hqa_md_field_error"):
+                  "hqa_md_tune", "hqa_md_set_step_tiles", "hqa_md_field_error",
+                  "hqa_es_confidence"):
             getattr(L, f).restype = C.c_int
         if L.hqa_abi_version() != ABI_VERSION:
             raise ImportError("libhqa ABI version mismatch")
@@ -193,6 +195,13 @@ def hqa_md_tune(md, steps: int):
     _check(lib().hqa_md_tune(md, steps))
 
 
+def hqa_es_confidence(es, prob, n: int, mem: int) -> float:
+    out = C.c_double(0.0)
+    pa, _ = _addr(prob)
+    _check(lib().hqa_es_confidence(es, pa, n, mem, C.byref(out)))
+    return out.value
+
+
 def hqa_md_field_error(md, k: int = 0) -> tuple[float, float]:
     e, r = C.c_double(0.0), C.c_double(0.0)
     _check(lib().hqa_md_field_error(md, k, C.byref(e), C.byref(r)))
@@ -244,8 +253,8 @@ def hqa_md_destroy(md):
     lib().hqa_md_destroy(md)
 
 
-def hqa_md_stats_window(md, k0: int, k1: int):
-    _check(lib().hqa_md_stats_window(md, k0, k1))
+def hqa_md_stats_window(md, k0: int, k1: int, every: int = 1):
+    _check(lib().hqa_md_stats_window(md, k0, k1, every))
 
 
 def hqa_md_features(md, instance: int, feat, dst_mem: int):
@@ -338,11 +347,24 @@ class ES:
         hqa_es_train_step(self.h, x, y, x.shape[0], cw, lr, loss, HQA_HOST)
         return float(loss[0])
 
-    def predict(self, x, bf16: bool = False) -> np.ndarray:
+    def predict(self, x, bf16: bool = False, out=None):
+        """Class probabilities [n][3].  With a device tensor x (float32, contiguous [n][12])
+        and a device tensor out ([n][3]) the call stays on the device."""
+        if out is not None:
+            hqa_es_predict(self.h, x, x.shape[0], out, int(bf16), HQA_DEVICE)
+            return out
         x, _, _ = self._xy(x)
         prob = np.empty((x.shape[0], 3), dtype=np.float32)
         hqa_es_predict(self.h, x, x.shape[0], prob, int(bf16), HQA_HOST)
         return prob
+
+    def confidence(self, prob) -> float:
+        """Mean over rows of the largest class probability (host array or device tensor)."""
+        dev = not isinstance(prob, np.ndarray)
+        if not dev:
+            prob = np.ascontiguousarray(prob, dtype=np.float32).reshape(-1, 3)
+        return hqa_es_confidence(self.h, prob, prob.shape[0] if not dev else prob.numel() // 3,
+                                 HQA_DEVICE if dev else HQA_HOST)
 
 
 # ------------------------------------------------------ marshalling conveniences
@@ -465,10 +487,15 @@ class MD:
         hqa_md_hamiltonian(self.h, k, out, HQA_HOST)
         return out
 
-    def stats_window(self, k0: int, k1: int):
-        hqa_md_stats_window(self.h, k0, k1)
+    def stats_window(self, k0: int, k1: int, every: int = 1):
+        """Statistics over the steps k0, k0 + every, ... below k1 of the following runs."""
+        hqa_md_stats_window(self.h, k0, k1, every)
 
-    def features(self, k: int = 0) -> np.ndarray:
+    def features(self, k: int = 0, out=None):
+        """Features [R][N][12]; into a device tensor `out` when given (no host copy)."""
+        if out is not None:
+            hqa_md_features(self.h, k, out, HQA_DEVICE)
+            return out
         out = np.empty((self.R, self.problems[k].n, HQA_ES_NFEAT), dtype=np.float32)
         hqa_md_features(self.h, k, out, HQA_HOST)
         return out
@@ -484,6 +511,8 @@ class MD:
                                ("spins", "amb_idx", "energy", "cut", "h_eff", "code", "e_reduced")))
         if prob is None:
             hqa_classify(self.h, k, n_amb, int(solve), o, HQA_HOST)
+        elif not isinstance(prob, np.ndarray) and hasattr(prob, "data_ptr"):
+            hqa_classify_probs(self.h, k, prob, HQA_DEVICE, n_amb, int(solve), o, HQA_HOST)
         else:
             prob = np.ascontiguousarray(prob, dtype=np.float32)
             hqa_classify_probs(self.h, k, prob, HQA_HOST, n_amb, int(solve), o, HQA_HOST)

@@ -27,8 +27,8 @@ def H():
     return hqa
 
 
-@pytest.mark.parametrize("layout", ["dense", "csr"])
-def test_features_match_oracle(H, layout):
+@pytest.mark.parametrize("layout,every", [("dense", 1), ("csr", 1), ("dense", 3), ("csr", 7)])
+def test_features_match_oracle(H, layout, every):
     N, R, T, K0, K1 = 300, 6, 2000, 60, 260
     if layout == "dense":
         J = inst.er_maxcut(N, 0.05, 31)
@@ -37,11 +37,11 @@ def test_features_match_oracle(H, layout):
         rp, ci, v = inst.er_sparse(N, 12, 31)
         P, pb = H.Problem(row_ptr=rp, col=ci, val=v), orc.Problem(N, row_ptr=rp, col=ci, val=v)
     md = H.MD(P, H.make_schedule(T, 100), R, "f32", seed=5)
-    md.stats_window(K0, K1)
+    md.stats_window(K0, K1, every)
     md.run(K1)
     f = md.features()
     fo, phi, _ = orc.es_features(pb, orc.MDParams(T=T, W=100), np.zeros((R, N)),
-                                 orc.init_p0(5, N, R), K0, K1)
+                                 orc.init_p0(5, N, R), K0, K1, every)
     assert np.max(np.abs(md.state(H.HQA_STATE_PHI) - phi)) < 1e-4
     err = np.max(np.abs(f - fo), axis=(0, 1))
     print(layout, "max |feature err| per feature", err, flush=True)

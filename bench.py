@@ -15,6 +15,7 @@ Other workloads (measurement lines for the design notes, not the bench line):
   --workload ea3d      3D +-J lattice 16^3, CSR FP32, R = 1024, T = 10000
   --workload batch512  512 uneven instances (SK BF16 / ER FP8), R = 64, T = 5000
   --workload es        learned early stop: train on ER runs, evaluate on ER N = 10^4
+  --workload k2000     MAX-CUT on K_2000 with +-1 weights: deviation from C* vs MD steps
   --workload copy      a plain device copy of known size (HBM counter calibration)
 
   python bench.py [--steps K] [--warmup W] [--no-cpu] [--workload ...]
@@ -361,6 +362,45 @@ def bench_es(args, hqa, torch):
                          "loss_vs_full": (cut_full - cut_es) / cut_full}}
 
 
+def bench_k2000(args, hqa, torch):
+    """MAX-CUT on K_2000 with +-1 weights (the paper's headline experiment, reduced to a
+    few instances): J = +w stored exactly in FP8, each instance and its mirror -J, R
+    replicas, MD alone (sign of phibar) and HQA (n = 20 solved exactly).  Deviation from
+    the theoretical maximum cut C* = 33,932.6 (recomputed from the paper's formula, see
+    tests/golden/kn_maxcut_cstar.txt), for replica 0 (one initial condition per
+    instance, as in the paper) and for the best of the R replicas."""
+    from paper_2004_03972_amd import instances as inst
+    Nk, Rr, cstar = 2000, args.k2000_replicas, 33932.6
+    out = {"metric": "MAX-CUT deviation from C* (K2000, +-1 weights)", "C_star": cstar,
+           "instances": args.k2000_instances, "mirrors": True, "replicas": Rr, "by_T": {}}
+    st = torch.cuda.current_stream()
+    for Tt in [int(x) for x in args.k2000_steps.split(",")]:
+        dev = {"md_one_init": [], "hqa_one_init": [], "md_best": [], "hqa_best": []}
+        ms_tot = 0.0
+        for k in range(args.k2000_instances):
+            J = inst.pm_complete(Nk, 9000 + k)
+            for sign in (1.0, -1.0):
+                md = hqa.MD(hqa.Problem(sign * J), hqa.make_schedule(Tt, 100), Rr, "fp8",
+                            seed=11 + k, require_exact=True, stream=st.cuda_stream)
+                md.tune(20)
+                e0, e1 = _events(torch)
+                e0.record(st); md.run(); e1.record(st); md.sync()
+                ms_tot += e0.elapsed_time(e1)
+                g0 = md.classify(20, solve=False)
+                g1 = md.classify(20, solve=True)
+                dev["md_one_init"].append((cstar - g0["cut"][0]) / cstar)
+                dev["hqa_one_init"].append((cstar - g1["cut"][0]) / cstar)
+                dev["md_best"].append((cstar - g0["cut"].max()) / cstar)
+                dev["hqa_best"].append((cstar - g1["cut"].max()) / cstar)
+                md.close()
+            _log(f"  T={Tt}: instance {k} done")
+        out["by_T"][str(Tt)] = {kk: {"mean": float(np.mean(v)), "min": float(np.min(v)),
+                                     "max": float(np.max(v))} for kk, v in dev.items()}
+        out["by_T"][str(Tt)]["md_ms_per_run"] = ms_tot / (2 * args.k2000_instances)
+    out["paper"] = "MD alone about 0.4% below C* at 5e5 MD steps (one init per instance)"
+    return out
+
+
 def bench_copy(args, hqa, torch):
     """A plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB): HBM counter calibration."""
     n = 1 << 28
@@ -378,7 +418,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="er800",
-                    choices=["er800", "ea3d", "batch512", "es", "copy"])
+                    choices=["er800", "ea3d", "batch512", "es", "k2000", "copy"])
+    ap.add_argument("--k2000-instances", type=int, default=4)
+    ap.add_argument("--k2000-replicas", type=int, default=16)
+    ap.add_argument("--k2000-steps", default="50000,500000")
     ap.add_argument("--es-train", type=int, default=48)
     ap.add_argument("--es-target", type=float, default=0.03)
     ap.add_argument("--es-k", type=int, default=1000)
@@ -402,7 +445,7 @@ def main():
     hqa.lib()
     torch.cuda.set_device(0)
     fn = {"er800": bench_er800, "ea3d": bench_ea3d, "batch512": bench_batch512,
-          "es": bench_es, "copy": bench_copy}[args.workload]
+          "es": bench_es, "k2000": bench_k2000, "copy": bench_copy}[args.workload]
     print(json.dumps(fn(args, hqa, torch)), flush=True)
 
 

@@ -82,7 +82,7 @@ def run_form(hqa, torch, prob, prec, steps, warmup, pin=None):
     if pin:                                        # a fixed per-step block (profiling runs)
         md.set_step_tiles(*pin)
     else:
-        md.tune(20)                                # plan and tile shape, untimed
+        md.tune(50)                                # plan and tile shape, untimed
     plan = md.tuned_plan()
     for k in range(warmup):
         md.reset(RUN_SEED + 1000 + k)
@@ -152,7 +152,7 @@ def bench_er800(args, hqa, torch):
     md_ms = float(np.mean(c["md_ms"]))
     plan, tm, tn, cb = c["plan"]
     if plan == "resident":                      # two launches: before and inside the window
-        kernel = f"k_md_resident<{JT_NAME[chosen]}, {2 if chosen == 'fp8' else 1}, false>"
+        kernel = f"k_md_resident<{JT_NAME[chosen]}, {2 if chosen == 'fp8' else 1}, false, 6>"
         launches, srcs = 2, "resident"
     elif plan == "cluster":                     # one cooperative launch for all steps
         kernel = f"k_persist<{JT_NAME[chosen]}>"

@@ -194,12 +194,14 @@ hqa_status hqa_md_sync(hqa_md *md);
 int32_t hqa_md_last_plan(const hqa_md *md);
 
 /* Autotuner: for every binary32 instance, time each applicable plan and tile
- * shape (per-step blocks of 16 or 32 rows x 16, 32 or 64 replicas with 4 or 8 chunks
- * of loads in flight; cluster; resident) over `steps`
- * MD steps from the current state with HIP events on the handle's stream, restore
- * the state, and keep the fastest for HQA_PLAN_AUTO.  Because the plans are
- * bit-identical the choice never changes results.  Synchronises.  HQA_EINVAL for
- * steps < 1; HQA_ESTATE if fewer than `steps` steps remain before T. */
+ * shape (dense: per-step blocks of 16 or 32 rows x 16, 32 or 64 replicas with 4 or 8
+ * chunks of loads in flight, cluster, resident; sparse: per step, resident) from the
+ * current state with HIP events on the handle's stream: runs of `steps` and 2 `steps`
+ * MD steps, whose difference is the per-step cost without a plan's fixed per-run
+ * cost.  The state is restored after each run, and the fastest is kept for
+ * HQA_PLAN_AUTO.  Because the plans are bit-identical the choice never changes
+ * results.  Synchronises.  HQA_EINVAL for steps < 1; HQA_ESTATE if fewer than
+ * 2 `steps` steps remain before T. */
 hqa_status hqa_md_tune(hqa_md *md, int32_t steps);
 
 /* Error of the binary32 field of instance k against the binary64 field on the same

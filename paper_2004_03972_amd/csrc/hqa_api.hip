@@ -521,7 +521,8 @@ struct TuneCand {
 hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
     if (!md) return fail(HQA_EINVAL, "null handle");
     if (steps < 1) return fail(HQA_EINVAL, "steps must be >= 1");
-    if (md->q + steps > md->sch.T) return fail(HQA_ESTATE, "fewer than %d steps remain before T", steps);
+    if (md->q + 2 * (int64_t)steps > md->sch.T)
+        return fail(HQA_ESTATE, "fewer than %d steps remain before T", 2 * steps);
     if (md->prec == HQA_PREC_F64_REF) return HQA_OK;
     HIPCHK(hipStreamSynchronize(md->stream));
     const int64_t k0 = md->stats_k0, k1 = md->stats_k1;
@@ -581,15 +582,19 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
             I.step_tn = c.tn;
             I.step_tm = c.tm;
             I.step_cb = c.cb;
-            float ms = 0.f;
-            for (int pass = 0; pass < 2 && he == hipSuccess; pass++) {   // pass 0 warms up
+            // pass 0 warms up; passes 1 and 2 run `steps` and 2 `steps` steps, and the
+            // difference is the cost of `steps` steps without the plan's fixed per-run
+            // cost (state staging of the one-launch plans, first-use set-up)
+            float ms = 0.f, t[3] = {0.f, 0.f, 0.f};
+            for (int pass = 0; pass < 3 && he == hipSuccess; pass++) {
+                const int64_t len = pass == 2 ? 2 * (int64_t)steps : steps;
                 int used = 0;
                 stage = "event record";
                 he = hipEventRecord(e0, md->stream);
                 if (he == hipSuccess) {
                     stage = "run";
-                    he = dense ? run_dense(md, I, md->q, md->q + steps, false, c.plan, &used)
-                               : run_csr(md, I, md->q, md->q + steps, false, c.plan, &used);
+                    he = dense ? run_dense(md, I, md->q, md->q + len, false, c.plan, &used)
+                               : run_csr(md, I, md->q, md->q + len, false, c.plan, &used);
                 }
                 if (he == hipSuccess) {
                     stage = "event record";
@@ -601,14 +606,15 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
                 }
                 if (he == hipSuccess) {
                     stage = "elapsed time";
-                    he = hipEventElapsedTime(&ms, e0, e1);
+                    he = hipEventElapsedTime(&t[pass], e0, e1);
                 }
                 if (he == hipSuccess) {
                     stage = "restore";
                     he = copy(false);
                 }
-                if (he == hipSuccess && used != c.plan) ms = 1e30f;   // not applicable
+                if (he == hipSuccess && used != c.plan) t[pass] = 1e30f;   // not applicable
             }
+            ms = t[2] >= 1e30f || t[1] >= 1e30f ? 1e30f : std::max(t[2] - t[1], 0.0f);
             if (he == hipSuccess && ms < best) {
                 best = ms;
                 pick = c;

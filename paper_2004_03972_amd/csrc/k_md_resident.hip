@@ -88,7 +88,7 @@ __device__ __forceinline__ StepCoef res_coef(const ResArgs &a, int64_t q) {
 // WIN: every step of the launch adds phi' to the window sum (the host splits a run
 // at the start of the averaging window, so the loop of the other launch carries no
 // global-memory access besides the J stream).
-template <int JT, int PF, bool WIN>
+template <int JT, int PF, bool WIN, int MP>
 __global__ __launch_bounds__(256) void k_md_resident(ResArgs a) {
     typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
     constexpr int esz = JT == JT_BF16 ? 2 : 1;
@@ -215,7 +215,8 @@ __global__ __launch_bounds__(256) void k_md_resident(ResArgs a) {
 #pragma unroll
                 for (int v = 0; v < 4; v++) {
                     if (ib + v < a.N) {
-                        leapfrog(cf, xs[v], u[v], hl[ib + v], ps[v], xn[v]);
+                        if constexpr (MP == 6) leapfrog_m<6>(cf, xs[v], u[v], hl[ib + v], ps[v], xn[v]);
+                        else leapfrog(cf, xs[v], u[v], hl[ib + v], ps[v], xn[v]);
                         bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
                     } else {
                         xn[v] = 0.0f;
@@ -303,13 +304,20 @@ bool resident_fits(const Instance &I, int max_lds) {
     return resident_lds_bytes(I.N) <= (size_t)max_lds;
 }
 
-template <int JT, int PF, bool WIN>
-static hipError_t launch_res(const ResArgs &a, int grid, size_t lds, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_md_resident<JT, PF, WIN>,
+template <int JT, int PF, bool WIN, int MP>
+static hipError_t launch_resm(const ResArgs &a, int grid, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_md_resident<JT, PF, WIN, MP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    k_md_resident<JT, PF, WIN><<<grid, 256, lds, st>>>(a);
+    k_md_resident<JT, PF, WIN, MP><<<grid, 256, lds, st>>>(a);
     return hipGetLastError();
+}
+
+// MP: the potential exponent when it is the paper's M = 6 (power loop unrolled), else 0.
+template <int JT, int PF, bool WIN>
+static hipError_t launch_res(const ResArgs &a, int grid, size_t lds, hipStream_t st) {
+    return a.M == 6 ? launch_resm<JT, PF, WIN, 6>(a, grid, lds, st)
+                    : launch_resm<JT, PF, WIN, 0>(a, grid, lds, st);
 }
 
 // Steps [q0, q1) in at most two launches: the part before the averaging window

@@ -209,7 +209,8 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps);
  * form computes (FP32, or BF16 operands with FP32 accumulation, J in its storage type)
  * against sum_j J_ij phi_j in binary64 with the input J (Results, Eq. (3) force term).
  * Writes max |u32 - u64| and max |u64| over all spins and replicas.  HQA_EUNSUPPORTED
- * for the reference mode and for N > 8192.  Synchronises. */
+ * for the reference mode and when one replica's binary64 fluxes (8 N bytes) do not fit
+ * the workgroup LDS (N above about 19,000 with 160 KB).  Synchronises. */
 hqa_status hqa_md_field_error(hqa_md *md, int32_t instance, double *max_abs_err,
                               double *max_abs_field);
 

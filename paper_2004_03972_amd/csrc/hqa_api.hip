@@ -115,8 +115,12 @@ static hqa_status ingest(const hqa_problem &P, int k, hipStream_t st, int32_t *d
         HIPCHK(hipStreamSynchronize(st));
         if (rp[0] != 0 || rp[N] != P.nnz)
             return fail(HQA_EINVAL, "instance %d: row_ptr[0] must be 0 and row_ptr[n] = nnz", k);
-        for (int i = 0; i < N; i++)
+        int max_deg = 0;
+        for (int i = 0; i < N; i++) {
             if (rp[i + 1] < rp[i]) return fail(HQA_EINVAL, "instance %d: row_ptr decreases", k);
+            max_deg = std::max(max_deg, rp[i + 1] - rp[i]);
+        }
+        I.max_deg = max_deg;
         I.nnz = P.nnz;
         HIPCHK(dalloc(&I.J64, (size_t)P.nnz));
         HIPCHK(dalloc(&I.rp, (size_t)N + 1));
@@ -575,6 +579,12 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         const int tn0 = I.step_tn, tm0 = I.step_tm, cb0 = I.step_cb;
         const char *stage = "snapshot";
         hipError_t he = copy(true);
+        // the error word as the caller left it: a candidate that raises a flag is
+        // disqualified and the word is put back, so timing never leaks a status
+        int32_t err0 = 0;
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(&err0, md->err, sizeof err0, hipMemcpyDeviceToHost, md->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
         TuneCand failed{0, 0, 0, 0};
         for (const TuneCand &c : cands) {
             if (he != hipSuccess) break;
@@ -615,6 +625,17 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
                 if (he == hipSuccess && used != c.plan) t[pass] = 1e30f;   // not applicable
             }
             ms = t[2] >= 1e30f || t[1] >= 1e30f ? 1e30f : std::max(t[2] - t[1], 0.0f);
+            int32_t errc = err0;
+            if (he == hipSuccess) {
+                stage = "error word";
+                he = hipMemcpyAsync(&errc, md->err, sizeof errc, hipMemcpyDeviceToHost, md->stream);
+                if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
+            }
+            if (he == hipSuccess && errc != err0) {
+                ms = 1e30f;
+                he = hipMemcpyAsync(md->err, &err0, sizeof err0, hipMemcpyHostToDevice, md->stream);
+                if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
+            }
             if (he == hipSuccess && ms < best) {
                 best = ms;
                 pick = c;
@@ -730,7 +751,8 @@ hqa_status hqa_md_field_error(hqa_md *md, int32_t instance, double *max_abs_err,
     if (!max_abs_err || !max_abs_field) return fail(HQA_EINVAL, "null output");
     if (md->prec == HQA_PREC_F64_REF) return fail(HQA_EUNSUPPORTED, "the reference mode is binary64");
     Instance &I = md->inst[instance];
-    if (I.N > 8192) return fail(HQA_EUNSUPPORTED, "binary64 field limited to N <= 8192");
+    if ((size_t)I.N * 8 + 8192 > (size_t)md->max_lds)
+        return fail(HQA_EUNSUPPORTED, "binary64 field: N = %d exceeds the LDS capacity", I.N);
     const size_t n = (size_t)I.N * md->R;
     const size_t m = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
     DevBufs bufs;
@@ -770,7 +792,8 @@ hqa_status hqa_md_field(hqa_md *md, int32_t instance, double *u, int32_t dst_mem
     double *buf = u;
     if (dst_mem == HQA_HOST) HIPCHK(dalloc(&buf, n));
     if (md->prec == HQA_PREC_F64_REF) {
-        if (I.N > 8192) return fail(HQA_EUNSUPPORTED, "binary64 field limited to N <= 8192");
+        if ((size_t)I.N * 8 + 8192 > (size_t)md->max_lds)
+        return fail(HQA_EUNSUPPORTED, "binary64 field: N = %d exceeds the LDS capacity", I.N);
         HIPCHK(launch_field_f64(md, I, buf, md->stream));
     } else {
         float *u32;
@@ -793,7 +816,8 @@ hqa_status hqa_md_hamiltonian(hqa_md *md, int32_t instance, double *H, int32_t d
     if (s != HQA_OK) return s;
     if (!H) return fail(HQA_EINVAL, "H is NULL");
     Instance &I = md->inst[instance];
-    if (I.N > 8192) return fail(HQA_EUNSUPPORTED, "binary64 Hamiltonian limited to N <= 8192");
+    if ((size_t)I.N * 8 + 8192 > (size_t)md->max_lds)
+        return fail(HQA_EUNSUPPORTED, "binary64 Hamiltonian: N = %d exceeds the LDS capacity", I.N);
     double *buf = H;
     if (dst_mem == HQA_HOST) HIPCHK(dalloc(&buf, (size_t)md->R));
     HIPCHK(launch_hamiltonian(md, I, buf, md->stream));

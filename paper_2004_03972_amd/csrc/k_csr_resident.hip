@@ -15,8 +15,6 @@
 // arithmetic is the streamed CSR kernel's (field accumulated with fmaf in ascending column order
 // from +0, the shared binary32 leapfrog, the window sum), so both give
 // bit-identical trajectories.
-#include <algorithm>
-
 #include "hqa_internal.h"
 #include "md_epilogue.h"
 
@@ -167,25 +165,11 @@ __global__ __launch_bounds__(CSR_RES_THREADS) void k_csr_resident(CsrResArgs a) 
     if (bad) atomicOr(a.err, ERR_NONFINITE);
 }
 
-// Largest row degree of a CSR instance (computed once, on the host).
-static int csr_max_degree(Instance &I, hipStream_t st) {
-    if (I.max_deg >= 0) return I.max_deg;
-    std::vector<int32_t> rp(I.N + 1);
-    if (hipMemcpyAsync(rp.data(), I.rp, sizeof(int32_t) * (I.N + 1), hipMemcpyDeviceToHost, st) !=
-            hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return INT32_MAX;
-    int m = 0;
-    for (int i = 0; i < I.N; i++) m = std::max(m, rp[i + 1] - rp[i]);
-    I.max_deg = m;
-    return m;
-}
-
 bool csr_resident_fits(hqa_md *md, Instance &I) {
     if (I.layout != HQA_CSR || !I.smaj || I.Rp % CSR_RES_RG != 0) return false;
     if (I.N > 4 * CSR_RES_THREADS) return false;
     if (csr_resident_lds_bytes(I.N) > (size_t)md->max_lds) return false;
-    return csr_max_degree(I, md->stream) <= CSR_RES_DMAX;
+    return I.max_deg >= 0 && I.max_deg <= CSR_RES_DMAX;   // max_deg: set at ingest
 }
 
 template <int SPT, int MP>

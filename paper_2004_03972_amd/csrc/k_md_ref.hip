@@ -124,7 +124,11 @@ __global__ void k_field_f64(RefArgs a, F64View xv, double *u) {
 hipError_t launch_field_f64(hqa_md *md, Instance &I, double *u, hipStream_t st) {
     RefArgs a = ref_args(md, I);
     F64View xv = make_view(md, I, true);
-    k_field_f64<<<md->R, 256, (size_t)I.N * sizeof(double), st>>>(a, xv, u);
+    const size_t lds = (size_t)I.N * sizeof(double);   // one replica's fluxes in binary64
+    hipError_t e = hipFuncSetAttribute((const void *)k_field_f64,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_field_f64<<<md->R, 256, lds, st>>>(a, xv, u);
     return hipGetLastError();
 }
 
@@ -163,7 +167,11 @@ __global__ void k_hamiltonian(RefArgs a, F64View xv, F64View pv, int64_t q, doub
 hipError_t launch_hamiltonian(hqa_md *md, Instance &I, double *H, hipStream_t st) {
     RefArgs a = ref_args(md, I);
     F64View xv = make_view(md, I, true), pv = make_view(md, I, false);
-    k_hamiltonian<<<md->R, 256, (size_t)I.N * sizeof(double), st>>>(a, xv, pv, md->q, H);
+    const size_t lds = (size_t)I.N * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)k_hamiltonian,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_hamiltonian<<<md->R, 256, lds, st>>>(a, xv, pv, md->q, H);
     return hipGetLastError();
 }
 

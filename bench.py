@@ -16,6 +16,8 @@ Other workloads (measurement lines for the design notes, not the bench line):
   --workload batch512  512 uneven instances (SK BF16 / ER FP8), R = 64, T = 5000
   --workload es        learned early stop: train on ER runs, evaluate on ER N = 10^4
   --workload k2000     MAX-CUT on K_2000 with +-1 weights: deviation from C* vs MD steps
+  --workload glass     spin glass with fields, N = 1000, 2000, 10^4: energy vs MD steps
+  --workload dense8k   enlarged dense shape N = 8192, R = 512 (BF16 SK, FP8 +-1): MFMA fraction
   --workload sweep     kappa2 and M sweeps on the spin glass with fields, N = 10^4
   --workload copy      a plain device copy of known size (HBM counter calibration)
 
@@ -402,6 +404,93 @@ def bench_k2000(args, hqa, torch):
     return out
 
 
+def bench_glass(args, hqa, torch):
+    """Ising spin glass with fields (J_ij ~ U[-1, 1], h_i ~ U[-2, 2], dense, BF16 storage
+    of J for the dynamics, exact binary64 energies): mean Ising energy per spin over
+    instances against MD steps, for N = 1000, 2000 and 10^4.  Read-outs: MD alone
+    (sign of phibar) for replica 0 (one initial condition per instance) and the best
+    of R replicas; HQA with the n = 20 most ambivalent spins solved exactly."""
+    from paper_2004_03972_amd import instances as inst
+    Rr = args.glass_replicas
+    sizes = [int(x) for x in args.glass_n.split(",")]
+    counts = [int(x) for x in args.glass_instances.split(",")]
+    steps = [int(x) for x in args.glass_steps.split(",")]
+    st = torch.cuda.current_stream()
+    out = {"metric": "Ising energy per spin vs MD steps (spin glass with fields)",
+           "workload": "J~U[-1,1], h~U[-2,2], dense, BF16 J in the dynamics", "replicas": Rr,
+           "by_N": {}}
+    for Nn, cnt in zip(sizes, counts):
+        rows = {}
+        for Tt in steps:
+            e = {"md_one_init": [], "md_best": [], "hqa_one_init": [], "hqa_best": []}
+            bad_tot, ms_tot = 0, 0.0
+            for k in range(cnt):
+                J, h = inst.uniform_glass(Nn, 7000 + 31 * Nn + k)
+                md = hqa.MD(hqa.Problem(J, h=h, storage="bf16"), hqa.make_schedule(Tt, 100), Rr,
+                            "bf16", seed=40 + k, stream=st.cuda_stream)
+                md.tune(min(20, Tt // 4))
+                e0, e1 = _events(torch)
+                e0.record(st); md.run(); e1.record(st); st.synchronize()
+                ms_tot += e0.elapsed_time(e1)
+                bad = int(np.sum(~np.isfinite(md.hamiltonian())))
+                bad_tot += bad
+                if bad == 0:
+                    g0 = md.classify(20, solve=False)
+                    g1 = md.classify(20, solve=True)
+                    e["md_one_init"].append(g0["energy"][0] / Nn)
+                    e["md_best"].append(g0["energy"].min() / Nn)
+                    e["hqa_one_init"].append(g1["energy"][0] / Nn)
+                    e["hqa_best"].append(g1["energy"].min() / Nn)
+                md.close()
+            rows[str(Tt)] = {kk: (float(np.mean(v)) if v else None) for kk, v in e.items()}
+            rows[str(Tt)]["instances"] = cnt
+            rows[str(Tt)]["diverged_replicas"] = bad_tot
+            rows[str(Tt)]["md_ms_per_run"] = ms_tot / cnt
+            _log(f"  N={Nn} T={Tt}: MD one init {rows[str(Tt)]['md_one_init']}, "
+                 f"HQA best {rows[str(Tt)]['hqa_best']}")
+        out["by_N"][str(Nn)] = rows
+    out["paper"] = ("energies decrease with MD steps from 10^3 to 5*10^5 for N = 1000, 2000 and "
+                    "10^4; the figure's values are not printed in the text")
+    return out
+
+
+def bench_dense8k(args, hqa, torch):
+    """The enlarged dense shape where the MFMA roofline can bind: N = 8192, R = 512.
+    SK couplings J ~ N(0, 1/N) in BF16 (inexact) and +-1 couplings in FP8 (exact), the
+    paper's schedule.  Per plan (the tuner's choice, the per-step kernel, the batched
+    kernel), the time of 200 MD steps with HIP events on the handle's stream; 2 N^2 R
+    flop per step of the field against the dense BF16 MFMA peak."""
+    from paper_2004_03972_amd import instances as inst
+    Nn, Rr, Tt, steps = 8192, 512, 2000, 200
+    st = torch.cuda.current_stream()
+    out = {"metric": "field TFLOP/s and MFMA fraction at the enlarged dense shape",
+           "workload": f"dense N={Nn}, R={Rr}", "peak_tflops": PEAK_MFMA["bf16"] / 1e12,
+           "forms": {}}
+    for name, J, form in (("sk_bf16", inst.sk(Nn, 8192), "bf16"),
+                          ("pm1_fp8", inst.pm_complete(Nn, 8193), "fp8")):
+        prob = hqa.Problem(J, storage=form)
+        del J
+        res = {}
+        for plan in ("auto", "step", "batch"):
+            md = hqa.MD(prob, hqa.make_schedule(Tt, 100), Rr, form, seed=8, plan=plan,
+                        stream=st.cuda_stream)
+            if plan == "auto":
+                md.tune(10)
+            md.run(40)
+            e0, e1 = _events(torch)
+            e0.record(st); md.run(40 + steps); e1.record(st); st.synchronize()
+            md.sync()
+            us = e0.elapsed_time(e1) * 1e3 / steps
+            tf = 2.0 * Nn * Nn * Rr / (us * 1e-6) / 1e12
+            key = plan if plan != "auto" else "tuned:" + "/".join(str(x) for x in md.tuned_plan())
+            res[key] = {"us_per_step": us, "tflops": tf, "mfma_frac": tf * 1e12 / PEAK_MFMA["bf16"],
+                        "ran": md.last_plan}
+            _log(f"  {name} {key}: {us:.1f} us/step, {tf:.0f} TFLOP/s ({md.last_plan})")
+            md.close()
+        out["forms"][name] = res
+    return out
+
+
 def bench_sweep(args, hqa, torch):
     """Schedule and potential sweeps on the Ising spin glass with fields (J_ij ~ U[-1, 1],
     h_i ~ U[-2, 2], dense N = 10^4, BF16 storage, 10 initial conditions): H_MD at tau = 1
@@ -478,7 +567,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="er800",
-                    choices=["er800", "ea3d", "batch512", "es", "k2000", "sweep", "copy"])
+                    choices=["er800", "ea3d", "batch512", "es", "k2000", "glass", "dense8k", "sweep", "copy"])
+    ap.add_argument("--glass-n", default="1000,2000,10000")
+    ap.add_argument("--glass-instances", default="8,8,2")
+    ap.add_argument("--glass-steps", default="1000,10000,100000,500000")
+    ap.add_argument("--glass-replicas", type=int, default=16)
     ap.add_argument("--sweep-n", type=int, default=10000)
     ap.add_argument("--sweep-steps", default="2000,10000,50000")
     ap.add_argument("--sweep-best", type=int, default=200000)
@@ -508,7 +601,7 @@ def main():
     hqa.lib()
     torch.cuda.set_device(0)
     fn = {"er800": bench_er800, "ea3d": bench_ea3d, "batch512": bench_batch512,
-          "es": bench_es, "k2000": bench_k2000, "sweep": bench_sweep,
+          "es": bench_es, "k2000": bench_k2000, "glass": bench_glass, "dense8k": bench_dense8k, "sweep": bench_sweep,
           "copy": bench_copy}[args.workload]
     print(json.dumps(fn(args, hqa, torch)), flush=True)
 

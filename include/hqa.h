@@ -134,7 +134,11 @@ typedef struct hqa_md_opts {
  *   HQA_PLAN_RESIDENT  all steps in one launch; one workgroup per 16 replicas keeps
  *                      their whole state in LDS and streams J from L2 (BF16/FP8 J,
  *                      N up to 800 on a device with 160 KB of LDS per workgroup).
- *   HQA_PLAN_BATCH     (reported only) several dense instances in one launch per step.
+ *   HQA_PLAN_BATCH     one launch per MD step over tiles of 128 rows x 64 replicas
+ *                      with the flux operand staged in LDS: AUTO's plan for several
+ *                      dense instances; selectable for a handle whose only dense
+ *                      instance has BF16 or FP8 storage (row blocks of a large
+ *                      instance spread over all XCDs).
  * Sparse (CSR) binary32 instances have two plans: STEP (one launch per step) and
  * RESIDENT (all steps in one launch; one workgroup per 4 replicas keeps their fluxes
  * in LDS and each thread's couplings, momenta and window sums in registers; for

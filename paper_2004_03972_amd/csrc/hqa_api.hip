@@ -260,7 +260,7 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
         return fail(HQA_EINVAL, "unknown precision");
     if ((opts->p0 || opts->phi0) && opts->init_mem != HQA_HOST && opts->init_mem != HQA_DEVICE)
         return fail(HQA_EINVAL, "bad init_mem");
-    if (opts->plan < HQA_PLAN_AUTO || opts->plan > HQA_PLAN_RESIDENT)
+    if (opts->plan < HQA_PLAN_AUTO || opts->plan > HQA_PLAN_BATCH)
         return fail(HQA_EINVAL, "unknown plan %d", opts->plan);
     for (int k = 0; k < count; k++) {
         hqa_status s = check_problem(probs[k], k);
@@ -426,6 +426,15 @@ hqa_status hqa_md_set_step(hqa_md *md, int64_t q) {
 
 // Steps [q0, q1) of one dense binary32 instance under `plan`; a plan that does not
 // apply (or whose launch is refused) falls back to one launch per step.
+// The batched kernel as the plan of a single instance: the handle's only dense
+// instance, with BF16 or FP8 storage (tiles of 128 rows x 64 replicas spread over
+// the XCDs).
+static bool batch_alone(const hqa_md *md, const Instance &I) {
+    int ndense = 0;
+    for (const auto &J : md->inst) ndense += J.layout == HQA_DENSE;
+    return ndense == 1 && I.layout == HQA_DENSE && (I.jt == JT_BF16 || I.jt == JT_FP8);
+}
+
 static hipError_t run_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1, bool stats_live,
                             int plan, int *used) {
     if (plan == HQA_PLAN_AUTO) plan = I.tuned_plan ? I.tuned_plan : HQA_PLAN_STEP;
@@ -433,6 +442,14 @@ static hipError_t run_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1, boo
         hipError_t e = launch_md_resident(md, I, q0, q1);
         if (e == hipSuccess) {
             *used = HQA_PLAN_RESIDENT;
+            return e;
+        }
+        (void)hipGetLastError();
+    }
+    if (!stats_live && plan == HQA_PLAN_BATCH && batch_alone(md, I)) {
+        hipError_t e = launch_md_steps_batch(md, q0, q1);
+        if (e == hipSuccess) {
+            *used = HQA_PLAN_BATCH;
             return e;
         }
         (void)hipGetLastError();
@@ -570,6 +587,7 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
                         if (I.Rp % (16 * tn) == 0) cands.push_back({HQA_PLAN_STEP, tm, tn, cb});
             cands.push_back({HQA_PLAN_CLUSTER, 0, 0, 0});
             if (resident_fits(I, md->max_lds)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0});
+            if (batch_alone(md, I)) cands.push_back({HQA_PLAN_BATCH, 0, 0, 0});
         } else {
             cands.push_back({HQA_PLAN_STEP, 0, 0, 0});
             if (csr_resident_fits(md, I)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0});

@@ -392,14 +392,35 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
     // launch runs on XCD b mod 8), so the instance's flux operand is fetched into one
     // L2; instances go to the least-loaded XCD, largest first (LPT on the tile count,
     // i.e. on N^2 R work); the per-XCD lists are interleaved into the launch order
-    // and padded with placeholder tiles.
+    // and padded with placeholder tiles.  An instance with at least an eighth of all
+    // the work is split instead: its row blocks are cut into eight contiguous ranges,
+    // one per XCD, each with all replica tiles, so every XCD reads an eighth of J and
+    // the 64-replica tiles of a row block share its J lines in one L2.
     {
         constexpr int NX = 8;
         std::vector<BatchTile> xl[NX];
         int64_t load[NX] = {0};
+        int64_t total = 0;
         for (int k : dense) {
             const Instance &I = md->inst[k];
             if (I.jt == JT_F32) continue;
+            total += (int64_t)((I.N + BL_ROWS - 1) / BL_ROWS) * ((md->R + 63) / 64) * I.Np;
+        }
+        for (int k : dense) {
+            const Instance &I = md->inst[k];
+            if (I.jt == JT_F32) continue;
+            const int nrb = (I.N + BL_ROWS - 1) / BL_ROWS;
+            const int64_t work = (int64_t)nrb * ((md->R + 63) / 64) * I.Np;
+            if (nrb >= NX && NX * work >= total) {
+                for (int x = 0; x < NX; x++) {
+                    for (int rb = x * nrb / NX; rb < (x + 1) * nrb / NX; rb++)
+                        for (int r0 = 0; r0 < md->R; r0 += 64) {
+                            xl[x].push_back({k, rb * BL_ROWS, r0, 0});
+                            load[x] += (int64_t)I.Np;
+                        }
+                }
+                continue;
+            }
             int x = 0;
             for (int y = 1; y < NX; y++)
                 if (load[y] < load[x]) x = y;

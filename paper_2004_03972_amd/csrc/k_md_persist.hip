@@ -29,6 +29,10 @@
 // the whole grid leaves the kernel.  Cluster members are placed on one XCD
 // (workgroups are dispatched round-robin over the 8 XCDs); correctness does not
 // depend on the placement.
+//
+// For BF16 / FP8 storage with Np <= 1024 a second kernel (k_persist_rj) keeps each
+// wavefront's 16 rows of J in registers instead of LDS, so that the staged flux
+// block is the only LDS operand of a step.
 #include <type_traits>
 
 #include "hqa_internal.h"
@@ -129,15 +133,16 @@ __device__ __forceinline__ void gather(const PersistArgs &a, int par, int r0, ui
             const int idx = b0 + m * 256 + tid;
             if (idx < nw && !tag_ok<JT>(v[m], tag)) miss |= 1u << m;
         }
+        // re-load every stale word together, then check them all: one memory round
+        // trip per retry, not one per stale word
         while (miss && !wt.dead) {
             if (!keep_waiting(a, wt)) break;
 #pragma unroll
-            for (int m = 0; m < GB; m++) {
-                if ((miss >> m) & 1u) {
-                    v[m] = ld_relaxed(src + b0 + m * 256 + tid);
-                    if (tag_ok<JT>(v[m], tag)) miss &= ~(1u << m);
-                }
-            }
+            for (int m = 0; m < GB; m++)
+                if ((miss >> m) & 1u) v[m] = ld_relaxed(src + b0 + m * 256 + tid);
+#pragma unroll
+            for (int m = 0; m < GB; m++)
+                if (((miss >> m) & 1u) && tag_ok<JT>(v[m], tag)) miss &= ~(1u << m);
         }
 #pragma unroll
         for (int m = 0; m < GB; m++) {
@@ -362,9 +367,112 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
     if (bad) atomicOr(a.err, ERR_NONFINITE);
 }
 
+// Register-resident J (BF16 / FP8 storage, Np <= 1024): workgroups of 64 rows,
+// each wavefront holding the fragments of its 16 rows of J in registers for the
+// whole run (NG groups of four 32-column chunks, NG = Np / 128).  A step then
+// reads only the staged flux block from LDS (the J operand costs no load), and
+// the cluster has Np / 64 members.  Gather, chains, update and publication are
+// those of k_persist, so the trajectories are identical.
+template <int JT, int NG>
+__global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int cl_in_xcd = slot / a.G, g = slot % a.G;
+    const int c = cl_in_xcd * 8 + xcd;
+    if (c >= a.C) return;
+    const int row0 = g * 64;          // G = Np / 64: every member's rows lie below Np
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = 16 * c;
+    const int kg = lane >> 4;
+    uint8_t *phis = lds;              // staged flux block [16][pstride]
+
+    typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
+    constexpr int esz = JT == JT_BF16 ? 2 : 1;
+    AT A[NG][4];
+    {
+        const uint8_t *Jr = (const uint8_t *)a.J +
+                            (int64_t)(row0 + 16 * w + (lane & 15)) * a.Np * esz;
+#pragma unroll
+        for (int gi = 0; gi < NG; gi++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                A[gi][j] = *(const AT *)(Jr + (gi * 128 + 32 * j + 8 * kg) * esz);
+    }
+
+    const int col = r0 + (lane & 15);
+    const bool rvalid = col < a.R;
+    const int ib = row0 + 16 * w + 4 * kg;
+    float xs[4], ps[4], ss[4], hs[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const int i = ib + v;
+        const bool ok = rvalid && i < a.N;
+        const int64_t k = (int64_t)col * a.ld + i;
+        xs[v] = ok ? a.phi_in[k] : 0.f;
+        ps[v] = ok ? a.p[k] : 0.f;
+        ss[v] = ok ? a.S[k] : 0.f;
+        hs[v] = (i < a.N) ? a.h[i] : 0.f;
+    }
+    publish<JT>(a, 0, col, ib, xs, 1u);
+    Waiter wt{0, false};
+    bool bad = false;
+    const int nsteps = (int)(a.q1 - a.q0);
+    const uint8_t *Xb = phis + (size_t)(lane & 15) * a.pstride;
+    for (int s = 0; s < nsteps; s++) {
+        const int64_t q = a.q0 + s;
+        const int par = s & 1;
+        const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
+        gather<JT>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
+        if (__syncthreads_or(wt.dead)) return;   // aborted: the workgroup leaves
+        // chunk 4 gi + j feeds chain j, in ascending gi (combine4's order)
+        f32x4 acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int gi = 0; gi < NG; gi++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const bf16x8 bv = *(const bf16x8 *)(Xb + (gi * 128 + 32 * j + 8 * kg) * 2);
+                bf16x8 av;
+                if constexpr (JT == JT_BF16) av = A[gi][j];
+                else av = cvt_fp8x8(A[gi][j]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+            }
+        const bool win = q + 1 >= a.T - a.W + 1;
+        const f32x4 u = combine4(acc);
+        float xn[4];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            if (rvalid && ib + v < a.N) {
+                leapfrog(cf, xs[v], u[v], hs[v], ps[v], xn[v]);
+                bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
+                if (win) ss[v] = ss[v] + xn[v];
+            } else {
+                xn[v] = 0.f;
+            }
+            xs[v] = xn[v];
+        }
+        if (s + 1 < nsteps) publish<JT>(a, par ^ 1, col, ib, xn, (uint32_t)((s + 1) % 65535) + 1u);
+        __syncthreads();   // the staged block is rewritten by the next gather
+    }
+    if (rvalid) {
+        const int64_t base = (int64_t)col * a.ld + ib;
+        *(float4 *)(a.phi_out + base) = make_float4(xs[0], xs[1], xs[2], xs[3]);
+        *(float4 *)(a.p + base) = make_float4(ps[0], ps[1], ps[2], ps[3]);
+        *(float4 *)(a.S + base) = make_float4(ss[0], ss[1], ss[2], ss[3]);
+        if (a.xb_out) {
+            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+            bf16x4 b = {(bf16)xs[0], (bf16)xs[1], (bf16)xs[2], (bf16)xs[3]};
+            *(bf16x4 *)(a.xb_out + base) = b;
+        }
+    }
+    if (bad) atomicOr(a.err, ERR_NONFINITE);
+}
+
 // Plan of a persistent launch for one dense instance.
 struct PersistPlan {
     int TRW, G, C, grid, jlds, jstride, jbytes, pstride;
+    int rj;          // J fragments in registers (k_persist_rj)
     size_t lds;
 };
 
@@ -376,7 +484,24 @@ static bool plan_persist(const Instance &I, int R, JType jt, int max_wg, Persist
     p.pstride = I.Np * eb + 16;
     const size_t stage = (size_t)16 * p.pstride;
     if (stage > lds_cap) return false;
-    // prefer a J block resident in LDS, then two row tiles per wavefront
+    p.rj = 0;
+    // first choice: J in registers (BF16 / FP8, at most eight 128-column groups)
+    if (jt != JT_F32 && I.Np <= 1024) {
+        const int G = I.Np / 64;
+        const int need_xcd_slots = (p.C + 7) / 8;
+        if (G <= 32 && need_xcd_slots <= 32 / G && 8 * need_xcd_slots * G <= max_wg) {
+            p.rj = 1;
+            p.TRW = 1;
+            p.G = G;
+            p.jlds = 0;
+            p.jstride = 0;
+            p.jbytes = 0;
+            p.lds = stage;
+            p.grid = 8 * need_xcd_slots * G;
+            return true;
+        }
+    }
+    // then a J block resident in LDS, then two row tiles per wavefront
     for (int want_lds : {1, 0}) {
         for (int trw : {2, 1}) {
             int NB = 64 * trw;
@@ -409,8 +534,32 @@ static hipError_t launch_p(const PersistArgs &a, const PersistPlan &pl, hipStrea
                                       dim3(256), args, (unsigned)pl.lds, st);
 }
 
+template <int JT, int NG>
+static hipError_t launch_rj(const PersistArgs &a, const PersistPlan &pl, hipStream_t st) {
+    void *args[] = {(void *)&a};
+    return hipLaunchCooperativeKernel((const void *)k_persist_rj<JT, NG>, dim3(pl.grid), dim3(256),
+                                      args, (unsigned)pl.lds, st);
+}
+
+template <int JT>
+static hipError_t launch_rj_ng(const PersistArgs &a, const PersistPlan &pl, hipStream_t st) {
+    switch (a.Np / 128) {
+        case 1: return launch_rj<JT, 1>(a, pl, st);
+        case 2: return launch_rj<JT, 2>(a, pl, st);
+        case 3: return launch_rj<JT, 3>(a, pl, st);
+        case 4: return launch_rj<JT, 4>(a, pl, st);
+        case 5: return launch_rj<JT, 5>(a, pl, st);
+        case 6: return launch_rj<JT, 6>(a, pl, st);
+        case 7: return launch_rj<JT, 7>(a, pl, st);
+        case 8: return launch_rj<JT, 8>(a, pl, st);
+        default: return hipErrorNotSupported;
+    }
+}
+
 template <int JT>
 static hipError_t launch_jt(const PersistArgs &a, const PersistPlan &pl, hipStream_t st) {
+    if constexpr (JT != JT_F32)
+        if (pl.rj) return launch_rj_ng<JT>(a, pl, st);
     if (pl.TRW == 2) return pl.jlds ? launch_p<JT, 2, true>(a, pl, st) : launch_p<JT, 2, false>(a, pl, st);
     return pl.jlds ? launch_p<JT, 1, true>(a, pl, st) : launch_p<JT, 1, false>(a, pl, st);
 }

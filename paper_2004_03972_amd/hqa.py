@@ -34,7 +34,7 @@ HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
 ABI_VERSION = 3
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
-         "resident": HQA_PLAN_RESIDENT}
+         "resident": HQA_PLAN_RESIDENT, "batch": HQA_PLAN_BATCH}
 PLAN_NAMES = {0: None, 1: "step", 2: "cluster", 3: "resident", 4: "batch"}
 
 

@@ -132,3 +132,29 @@ def test_field_error_against_binary64(H):
         assert err / ref <= bar
         if k < 2:
             assert err > 0.0                  # BF16 flux operand: a rounding error exists
+
+
+@pytest.mark.parametrize("kind,N,R", [("glass", 1100, 72), ("pm", 1030, 64), ("glass", 300, 16)])
+def test_single_instance_batch_plan_equals_step(H, kind, N, R):
+    """The batched kernel as the plan of a lone dense instance (row blocks spread over
+    the XCDs when the instance has at least eight of them) gives the per-step plan's
+    trajectory bit for bit, with fields, ragged replica tiles and a padded last row block."""
+    print("single batch", kind, N, R, flush=True)
+    if kind == "glass":
+        J, h = inst.uniform_glass(N, 21)
+        prob, prec = H.Problem(J, h=h, storage="bf16"), "bf16"
+    else:
+        J, h = inst.pm_complete(N, 22), None
+        prob, prec = H.Problem(J, storage="fp8"), "fp8"
+    T = 140
+    out = []
+    for plan in ("batch", "step"):
+        md = H.MD(prob, H.make_schedule(T, 30), R, prec, seed=5, plan=plan)
+        md.run(T // 2)
+        md.run()
+        md.sync()
+        assert md.last_plan == plan
+        out.append([md.state(w) for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM)])
+        md.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)

@@ -46,16 +46,20 @@ METRIC = "MD spin-updates/s (N×replicas×steps) at matched best cut; plain FP32
 JT_NAME = {"f32": 0, "bf16": 1, "fp8": 2}
 
 
-def measured_traffic(name, sources="dense"):
+def measured_traffic(name, sources="dense", kernel=None):
     """HBM bytes per launch from a committed PMC summary (FETCH_SIZE and WRITE_SIZE in KiB
     per dispatch, each scaled by the factor a plain copy of known size gives), or None when
-    the summary is missing or the kernel's sources changed since the counters were taken."""
+    the summary is missing, was taken for another kernel instance than `kernel`, or the
+    kernel's sources changed since the counters were taken."""
     from paper_2004_03972_amd import profsum
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
+    text = open(path).read()
+    if kernel is not None and f"hqa::{kernel}(" not in text:
+        return None
     kv = {}
-    for line in open(path):
+    for line in text.splitlines():
         if ":" in line and not line.startswith((" ", "#", "$")):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -153,15 +157,18 @@ def bench_er800(args, hqa, torch):
     chosen = lowp[0] if lowp else "f32"
     c = forms[chosen]
     md_ms = float(np.mean(c["md_ms"]))
-    plan, tm, tn, cb = c["plan"]
+    plan, tm, tn, cb, tj = c["plan"]
     if plan == "resident":                      # two launches: before and inside the window
         kernel = f"k_md_resident<{JT_NAME[chosen]}, {2 if chosen == 'fp8' else 1}, false, 6>"
         launches, srcs = 2, "resident"
     elif plan == "cluster":                     # one cooperative launch for all steps
-        kernel = f"k_persist<{JT_NAME[chosen]}>"
+        np_ = -(-N // 128) * 128
+        kernel = (f"k_persist_rj<{JT_NAME[chosen]}, {np_ // 128}>" if chosen != "f32" and np_ <= 1024
+                  else f"k_persist<{JT_NAME[chosen]}")
         launches, srcs = 1, "persist"
     else:                                       # one launch per MD step
-        kernel = f"k_step_block<{JT_NAME[chosen]}, {tm or 2}, {tn or 4}, false, {cb or 4}>"
+        kernel = (f"k_step_block<{JT_NAME[chosen]}, {tm or 2}, {tn or 4}, false, {cb or 4}, "
+                  f"{'true' if tj else 'false'}>")
         launches, srcs = T, "dense"
     flop_per_launch = 2.0 * N * N * R * T / launches   # field contraction (2 N^2 R per step)
     launch_s = md_ms / 1e3 / launches
@@ -187,7 +194,7 @@ def bench_er800(args, hqa, torch):
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(f"{kernel.split('<')[0]}_{chosen}_er800_pmc.txt",
-                                                 srcs),
+                                                 srcs, kernel),
                      "kernel": kernel, "plan": plan,
                      "flop_per_launch": flop_per_launch, "launch_us": launch_s * 1e6},
     }
@@ -587,7 +594,8 @@ def main():
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--md-steps", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--pin", default="", help="TM,TN,CB: fixed per-step block instead of tuning")
+    ap.add_argument("--pin", default="",
+                    help="TM,TN,CB[,TILED]: fixed per-step block instead of tuning")
     args = ap.parse_args()
     args.forms = [f for f in args.forms.split(",") if f]
     args.pin = tuple(int(x) for x in args.pin.split(",")) if args.pin else None

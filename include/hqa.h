@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 3
+#define HQA_ABI_VERSION 4
 
 typedef enum {
     HQA_OK = 0,
@@ -220,14 +220,20 @@ hqa_status hqa_md_field_error(hqa_md *md, int32_t instance, double *max_abs_err,
 
 /* The tuned plan of dense instance k (0 if not tuned, -1 for a bad argument); *tm, *tn
  * and *cb, if not NULL, receive the per-step block shape in row and replica tiles of
- * 16 and the K chunks per accumulation chain loaded together (0 = default). */
-int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn, int32_t *cb);
+ * 16 and the K chunks per accumulation chain loaded together (0 = default); *tiled
+ * receives 1 when the per-step kernel reads J from its MFMA-tiled copy. */
+int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn, int32_t *cb,
+                          int32_t *tiled);
 
 /* Pin dense instance k to the per-step plan with blocks of tm row tiles (1 or 2) by
  * tn replica tiles (1, 2 or 4; 16 tn must divide the replica count padded to a
- * multiple of 16), loading cb (4 or 8) K chunks of each chain together, as if the
- * tuner had chosen it.  HQA_EINVAL otherwise. */
-hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn, int32_t cb);
+ * multiple of 16), loading cb (4 or 8) K chunks of each chain together, with the A
+ * operand read from the row-major J (tiled = 0) or from an MFMA-tiled copy of it
+ * (tiled = 1, BF16 and FP8 storage; the copy, N^2 storage bytes, is built on first
+ * use and kept with the instance), as if the tuner had chosen it.  Same results
+ * either way.  HQA_EINVAL otherwise. */
+hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn, int32_t cb,
+                                 int32_t tiled);
 
 /* Current step index q (fluxes are phi^(q), momenta p^(q-1/2), or p^(0) at q = 0). */
 int64_t hqa_md_step_index(const hqa_md *md);

@@ -536,7 +536,7 @@ hqa_status hqa_md_reset(hqa_md *md, uint64_t seed) {
 // HIP events, restores it after each, and keeps the fastest for HQA_PLAN_AUTO.
 // ---------------------------------------------------------------------------
 struct TuneCand {
-    int plan, tm, tn, cb;
+    int plan, tm, tn, cb, tj;
 };
 
 hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
@@ -581,20 +581,24 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         };
         std::vector<TuneCand> cands;
         if (dense) {
-            for (int cb : {4, 8})
-                for (int tm : {2, 1})
-                    for (int tn : {4, 2, 1})
-                        if (I.Rp % (16 * tn) == 0) cands.push_back({HQA_PLAN_STEP, tm, tn, cb});
-            cands.push_back({HQA_PLAN_CLUSTER, 0, 0, 0});
-            if (resident_fits(I, md->max_lds)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0});
-            if (batch_alone(md, I)) cands.push_back({HQA_PLAN_BATCH, 0, 0, 0});
+            const bool lowp = I.jt == JT_BF16 || I.jt == JT_FP8;
+            for (int tj : {0, 1}) {
+                if (tj && !lowp) continue;
+                for (int cb : {4, 8})
+                    for (int tm : {2, 1})
+                        for (int tn : {4, 2, 1})
+                            if (I.Rp % (16 * tn) == 0) cands.push_back({HQA_PLAN_STEP, tm, tn, cb, tj});
+            }
+            cands.push_back({HQA_PLAN_CLUSTER, 0, 0, 0, 0});
+            if (resident_fits(I, md->max_lds)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0, 0});
+            if (batch_alone(md, I)) cands.push_back({HQA_PLAN_BATCH, 0, 0, 0, 0});
         } else {
-            cands.push_back({HQA_PLAN_STEP, 0, 0, 0});
-            if (csr_resident_fits(md, I)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0});
+            cands.push_back({HQA_PLAN_STEP, 0, 0, 0, 0});
+            if (csr_resident_fits(md, I)) cands.push_back({HQA_PLAN_RESIDENT, 0, 0, 0, 0});
         }
         float best = 1e30f;
-        TuneCand pick{HQA_PLAN_STEP, 0, 0, 0};
-        const int tn0 = I.step_tn, tm0 = I.step_tm, cb0 = I.step_cb;
+        TuneCand pick{HQA_PLAN_STEP, 0, 0, 0, 0};
+        const int tn0 = I.step_tn, tm0 = I.step_tm, cb0 = I.step_cb, tj0 = I.step_tj;
         const char *stage = "snapshot";
         hipError_t he = copy(true);
         // the error word as the caller left it: a candidate that raises a flag is
@@ -603,13 +607,14 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         if (he == hipSuccess)
             he = hipMemcpyAsync(&err0, md->err, sizeof err0, hipMemcpyDeviceToHost, md->stream);
         if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
-        TuneCand failed{0, 0, 0, 0};
+        TuneCand failed{0, 0, 0, 0, 0};
         for (const TuneCand &c : cands) {
             if (he != hipSuccess) break;
             failed = c;
             I.step_tn = c.tn;
             I.step_tm = c.tm;
             I.step_cb = c.cb;
+            I.step_tj = c.tj;
             // pass 0 warms up; passes 1 and 2 run `steps` and 2 `steps` steps, and the
             // difference is the cost of `steps` steps without the plan's fixed per-run
             // cost (state staging of the one-launch plans, first-use set-up)
@@ -662,6 +667,7 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         I.step_tn = tn0;
         I.step_tm = tm0;
         I.step_cb = cb0;
+        I.step_tj = tj0;
         if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
         dfree(sx); dfree(sp); dfree(sS); dfree(sb);
         if (he != hipSuccess) {
@@ -673,6 +679,7 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         I.step_tn = pick.tn;
         I.step_tm = pick.tm;
         I.step_cb = pick.cb;
+        I.step_tj = pick.tj;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -681,7 +688,8 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
     return rs;
 }
 
-hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn, int32_t cb) {
+hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn, int32_t cb,
+                                 int32_t tiled) {
     if (!md) return fail(HQA_EINVAL, "null handle");
     if (k < 0 || k >= (int32_t)md->inst.size()) return fail(HQA_EINVAL, "instance %d out of range", k);
     Instance &I = md->inst[k];
@@ -689,18 +697,24 @@ hqa_status hqa_md_set_step_tiles(hqa_md *md, int32_t k, int32_t tm, int32_t tn, 
     if ((tm != 1 && tm != 2) || (tn != 1 && tn != 2 && tn != 4) || I.Rp % (16 * tn) != 0)
         return fail(HQA_EINVAL, "block of %d x %d tiles does not fit (padded replicas %d)", tm, tn, I.Rp);
     if (cb != 4 && cb != 8) return fail(HQA_EINVAL, "chunks in flight must be 4 or 8");
+    if (tiled != 0 && tiled != 1) return fail(HQA_EINVAL, "tiled must be 0 or 1");
+    if (tiled && I.jt != JT_BF16 && I.jt != JT_FP8)
+        return fail(HQA_EINVAL, "the tiled copy of J exists for BF16 and FP8 storage only");
     I.step_tm = tm;
     I.step_tn = tn;
     I.step_cb = cb;
+    I.step_tj = tiled;
     I.tuned_plan = HQA_PLAN_STEP;
     return HQA_OK;
 }
 
-int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn, int32_t *cb) {
+int32_t hqa_md_tuned_plan(const hqa_md *md, int32_t k, int32_t *tm, int32_t *tn, int32_t *cb,
+                          int32_t *tiled) {
     if (!md || k < 0 || k >= (int32_t)md->inst.size()) return -1;
     if (tm) *tm = md->inst[k].step_tm;
     if (tn) *tn = md->inst[k].step_tn;
     if (cb) *cb = md->inst[k].step_cb;
+    if (tiled) *tiled = md->inst[k].step_tj;
     return md->inst[k].tuned_plan;
 }
 

@@ -81,6 +81,7 @@ struct Instance {
     int32_t step_tn = 0;      // replica tiles of 16 per per-step block (0: widest that divides Rp)
     int32_t step_tm = 0;      // row tiles of 16 per per-step block (0: 2)
     int32_t step_cb = 0;      // chunks per chain loaded together (0: 4)
+    int32_t step_tj = 0;      // per-step A fragments from the MFMA-tiled J (BF16 / FP8)
     int32_t max_deg = -1;     // CSR: largest row degree (computed on first need)
 };
 

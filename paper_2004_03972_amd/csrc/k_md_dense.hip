@@ -48,6 +48,8 @@ struct DenseArgs {
     int64_t sst;
     const float *inv_n2;
     int32_t *err;
+    const void *Jt;     // MFMA-tiled copy of a BF16 / FP8 J (tiled plans), else null
+    int ntile, nrounds; // its row tiles (of 16) and 128-column groups
 };
 
 // Eight FP8 e4m3 codes to eight BF16 values (exact: e4m3 embeds in bf16).
@@ -64,8 +66,11 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint2 raw) {
 
 // Chain w of a block of TM x TN output tiles (rows i0 + 16 tm, replicas r0 + 16 tn):
 // per chunk the wavefront loads TM A fragments and TN B fragments and issues
-// TM * TN MFMAs, so each fragment is reused across the block.
-template <int JT, int TM, int TN, int CB>
+// TM * TN MFMAs, so each fragment is reused across the block.  TJ: the A fragments
+// come from the MFMA-tiled copy of J (a 16-row x 128-column group is one contiguous
+// block whose four chunks the four wavefronts read together) instead of from the
+// row-major storage (16 rows of 64 or 32 bytes per load); same fragments.
+template <int JT, int TM, int TN, int CB, bool TJ = false>
 __device__ __forceinline__ void chain_block(const DenseArgs &a, int i0, int r0, int lane, int w,
                                             f32x4 (&acc)[TM][TN]) {
     const int kg = lane >> 4;
@@ -117,9 +122,19 @@ __device__ __forceinline__ void chain_block(const DenseArgs &a, int i0, int r0, 
                 if (m0 + m >= nch) continue;
                 const int kk = 32 * (w + 4 * (m0 + m)) + 8 * kg;
 #pragma unroll
-                for (int tm = 0; tm < TM; tm++)
-                    A[m][tm] = *(const AT *)((const uint8_t *)a.J +
-                                             ((int64_t)(i0 + 16 * tm + (lane & 15)) * a.Np + kk) * esz);
+                for (int tm = 0; tm < TM; tm++) {
+                    if constexpr (TJ) {
+                        const int t = i0 / 16 + tm;   // row tiles past the copy are padding
+                        A[m][tm] = t < a.ntile
+                                       ? *(const AT *)((const uint8_t *)a.Jt +
+                                                       ((((int64_t)t * a.nrounds + m0 + m) * 64 + lane) * 4 + w) *
+                                                           8 * esz)
+                                       : AT{};
+                    } else {
+                        A[m][tm] = *(const AT *)((const uint8_t *)a.J +
+                                                 ((int64_t)(i0 + 16 * tm + (lane & 15)) * a.Np + kk) * esz);
+                    }
+                }
 #pragma unroll
                 for (int tn = 0; tn < TN; tn++)
                     B[m][tn] = *(const bf16x8 *)(a.xb_in + (int64_t)(r0 + 16 * tn + (lane & 15)) * a.ld + kk);
@@ -180,13 +195,13 @@ __device__ __forceinline__ void dense_update(const DenseArgs &a, int64_t q, int 
 // Block of TM x TN output tiles (32 rows x 16 TN replicas for TM = 2): each
 // wavefront accumulates one chain of every tile; the partial tiles meet in LDS
 // and wavefront w combines and updates tiles w, w + 4, ... in chain order.
-template <int JT, int TM, int TN, bool FIELD_ONLY, int CB = 4>
+template <int JT, int TM, int TN, bool FIELD_ONLY, int CB = 4, bool TJ = false>
 __global__ __launch_bounds__(256) void k_step_block(DenseArgs a, int64_t q) {
     __shared__ f32x4 part[4][TM * TN][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i0 = blockIdx.x * 16 * TM, r0 = blockIdx.y * 16 * TN;
     f32x4 acc[TM][TN];
-    chain_block<JT, TM, TN, CB>(a, i0, r0, lane, w, acc);
+    chain_block<JT, TM, TN, CB, TJ>(a, i0, r0, lane, w, acc);
 #pragma unroll
     for (int tm = 0; tm < TM; tm++)
 #pragma unroll
@@ -217,6 +232,7 @@ static DenseArgs dense_args(hqa_md *md, Instance &I) {
     a.phi_out = I.phi32[I.cur ^ 1]; a.xb_out = I.phib[I.cur ^ 1];
     a.p = I.p32; a.S = I.S32; a.u_out = nullptr; a.err = md->err; a.jt = I.jt;
     a.st = nullptr; a.sst = (int64_t)I.Rp * I.ld; a.inv_n2 = I.inv_n2;
+    a.Jt = nullptr; a.ntile = (I.N + 15) / 16; a.nrounds = I.Np / 128;
     return a;
 }
 
@@ -226,24 +242,31 @@ static int block_tn(int Rp) { return Rp % 64 == 0 ? 4 : Rp % 32 == 0 ? 2 : 1; }
 // Blocks of tm x tn output tiles: 16 tm rows x 16 tn replicas per workgroup; cb
 // chunks of each chain's loads in flight together (8: a chain of up to eight chunks
 // costs one round trip to L2).
-template <int JT, bool FO, int CB>
+template <int JT, bool FO, int CB, bool TJ>
 static void launch_cb(const DenseArgs &a, int tm, int tn, int64_t q, hipStream_t st) {
     dim3 grid(a.Np / (16 * tm), a.Rp / (16 * tn));
     if (tm == 2) {
-        if (tn == 4) k_step_block<JT, 2, 4, FO, CB><<<grid, 256, 0, st>>>(a, q);
-        else if (tn == 2) k_step_block<JT, 2, 2, FO, CB><<<grid, 256, 0, st>>>(a, q);
-        else k_step_block<JT, 2, 1, FO, CB><<<grid, 256, 0, st>>>(a, q);
+        if (tn == 4) k_step_block<JT, 2, 4, FO, CB, TJ><<<grid, 256, 0, st>>>(a, q);
+        else if (tn == 2) k_step_block<JT, 2, 2, FO, CB, TJ><<<grid, 256, 0, st>>>(a, q);
+        else k_step_block<JT, 2, 1, FO, CB, TJ><<<grid, 256, 0, st>>>(a, q);
     } else {
-        if (tn == 4) k_step_block<JT, 1, 4, FO, CB><<<grid, 256, 0, st>>>(a, q);
-        else if (tn == 2) k_step_block<JT, 1, 2, FO, CB><<<grid, 256, 0, st>>>(a, q);
-        else k_step_block<JT, 1, 1, FO, CB><<<grid, 256, 0, st>>>(a, q);
+        if (tn == 4) k_step_block<JT, 1, 4, FO, CB, TJ><<<grid, 256, 0, st>>>(a, q);
+        else if (tn == 2) k_step_block<JT, 1, 2, FO, CB, TJ><<<grid, 256, 0, st>>>(a, q);
+        else k_step_block<JT, 1, 1, FO, CB, TJ><<<grid, 256, 0, st>>>(a, q);
     }
 }
 
 template <int JT, bool FO>
 static void launch_jt(const DenseArgs &a, int tm, int tn, int cb, int64_t q, hipStream_t st) {
-    if (cb == 8) launch_cb<JT, FO, 8>(a, tm, tn, q, st);
-    else launch_cb<JT, FO, 4>(a, tm, tn, q, st);
+    if constexpr (JT != JT_F32 && !FO) {
+        if (a.Jt) {
+            if (cb == 8) launch_cb<JT, FO, 8, true>(a, tm, tn, q, st);
+            else launch_cb<JT, FO, 4, true>(a, tm, tn, q, st);
+            return;
+        }
+    }
+    if (cb == 8) launch_cb<JT, FO, 8, false>(a, tm, tn, q, st);
+    else launch_cb<JT, FO, 4, false>(a, tm, tn, q, st);
 }
 
 template <bool FO>
@@ -263,8 +286,13 @@ hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1
                        : block_tn(I.Rp);
     const int tm = I.step_tm == 1 ? 1 : 2;   // Np is a multiple of 128: both divide it
     const int cb = I.step_cb == 8 ? 8 : 4;
+    if (I.step_tj) {
+        hipError_t e = ensure_tiled_j(I, md->stream);
+        if (e != hipSuccess) return e;
+    }
     for (int64_t q = q0; q < q1; q++) {
         DenseArgs a = dense_args(md, I);
+        if (I.step_tj) a.Jt = I.Jt;
         if (I.st && stats_step(md, q)) a.st = I.st;
         launch_one<false>(a, tm, tn, cb, q, md->stream);
         I.cur ^= 1;

@@ -31,7 +31,7 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
             "hqa_es_confidence", "hqa_es_destroy")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
-ABI_VERSION = 3
+ABI_VERSION = 4
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
          "resident": HQA_PLAN_RESIDENT, "batch": HQA_PLAN_BATCH}
@@ -94,9 +94,9 @@ def lib():
         L.hqa_md_last_plan.argtypes = [P]
         L.hqa_md_last_plan.restype = i32
         L.hqa_md_tune.argtypes = [P, i32]
-        L.hqa_md_tuned_plan.argtypes = [P, i32, P, P, P]
+        L.hqa_md_tuned_plan.argtypes = [P, i32, P, P, P, P]
         L.hqa_md_tuned_plan.restype = i32
-        L.hqa_md_set_step_tiles.argtypes = [P, i32, i32, i32, i32]
+        L.hqa_md_set_step_tiles.argtypes = [P, i32, i32, i32, i32, i32]
         L.hqa_md_field_error.argtypes = [P, i32, P, P]
         L.hqa_es_confidence.argtypes = [P, P, i64, i32, P]
         L.hqa_md_state.argtypes = [P, i32, i32, P, i32, i32]
@@ -208,14 +208,14 @@ def hqa_md_field_error(md, k: int = 0) -> tuple[float, float]:
     return e.value, r.value
 
 
-def hqa_md_set_step_tiles(md, k: int, tm: int, tn: int, cb: int = 4):
-    _check(lib().hqa_md_set_step_tiles(md, k, tm, tn, cb))
+def hqa_md_set_step_tiles(md, k: int, tm: int, tn: int, cb: int = 4, tiled: int = 0):
+    _check(lib().hqa_md_set_step_tiles(md, k, tm, tn, cb, int(tiled)))
 
 
-def hqa_md_tuned_plan(md, k: int = 0) -> tuple[int, int, int, int]:
-    tm, tn, cb = C.c_int32(0), C.c_int32(0), C.c_int32(0)
-    p = lib().hqa_md_tuned_plan(md, k, C.byref(tm), C.byref(tn), C.byref(cb))
-    return p, tm.value, tn.value, cb.value
+def hqa_md_tuned_plan(md, k: int = 0) -> tuple[int, int, int, int, int]:
+    tm, tn, cb, tj = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    p = lib().hqa_md_tuned_plan(md, k, C.byref(tm), C.byref(tn), C.byref(cb), C.byref(tj))
+    return p, tm.value, tn.value, cb.value, tj.value
 
 
 def hqa_md_set_step(md, q: int):
@@ -458,15 +458,16 @@ class MD:
         """(max |u32 - u64|, max |u64|) of instance k's field on the current fluxes."""
         return hqa_md_field_error(self.h, k)
 
-    def set_step_tiles(self, tm: int, tn: int, cb: int = 4, k: int = 0):
+    def set_step_tiles(self, tm: int, tn: int, cb: int = 4, k: int = 0, tiled: bool = False):
         """Pin instance k to per-step blocks of tm x tn tiles of 16 (rows x replicas)
-        with cb chunks of each accumulation chain loaded together."""
-        hqa_md_set_step_tiles(self.h, k, tm, tn, cb)
+        with cb chunks of each accumulation chain loaded together, J read from its
+        MFMA-tiled copy when tiled (BF16 / FP8 storage)."""
+        hqa_md_set_step_tiles(self.h, k, tm, tn, cb, tiled)
 
     def tuned_plan(self, k: int = 0):
-        """(plan, row tiles, replica tiles, chunks in flight) chosen by tune() for k."""
-        p, tm, tn, cb = hqa_md_tuned_plan(self.h, k)
-        return PLAN_NAMES.get(p), tm, tn, cb
+        """(plan, row tiles, replica tiles, chunks in flight, tiled J) chosen by tune() for k."""
+        p, tm, tn, cb, tj = hqa_md_tuned_plan(self.h, k)
+        return PLAN_NAMES.get(p), tm, tn, cb, tj
 
     def state(self, what: int, k: int = 0) -> np.ndarray:
         out = np.empty((self.R, self.problems[k].n))

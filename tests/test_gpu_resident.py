@@ -99,9 +99,9 @@ def test_auto_plan_and_tuner_keep_results(H):
     md.run(37)
     assert md.last_plan == "step"            # the untuned default
     md.tune(20)
-    plan, tm, tn, cb = md.tuned_plan()
-    print("tuned plan", plan, tm, tn, cb, flush=True)
-    assert plan in ("step", "cluster", "resident")
+    plan, tm, tn, cb, tj = md.tuned_plan()
+    print("tuned plan", plan, tm, tn, cb, tj, flush=True)
+    assert plan in ("step", "cluster", "resident", "batch")
     assert md.step == 37
     md.run()
     assert md.last_plan == plan
@@ -122,8 +122,8 @@ def test_tuner_at_bench_shape(H, prec):
     want = _states(H, ref)
     md = H.MD(H.Problem(J), H.make_schedule(200, 20), 256, prec, seed=2, stream=st.cuda_stream)
     md.tune(10)
-    plan, tm, tn, cb = md.tuned_plan()
-    print(prec, "tuned", plan, tm, tn, cb, flush=True)
+    plan, tm, tn, cb, tj = md.tuned_plan()
+    print(prec, "tuned", plan, tm, tn, cb, tj, flush=True)
     md.run()
     for x, y in zip(want, _states(H, md)):
         assert np.array_equal(x, y)
@@ -132,20 +132,22 @@ def test_tuner_at_bench_shape(H, prec):
 @pytest.mark.parametrize("prec", ["f32", "bf16", "fp8"])
 def test_every_step_block_shape_is_bit_identical(H, prec):
     """Per-step blocks of 16/32 rows x 16/32/64 replicas, with 4 or 8 chunks of loads in
-    flight, accumulate the same chains."""
+    flight and (BF16 / FP8) J read row-major or from its MFMA-tiled copy, accumulate the
+    same chains.  N = 333 leaves padding row tiles past the tiled copy."""
     N, R, T = 333, 64, 60
     J = inst.er_maxcut(N, 0.06, 3)
     out = {}
-    for cb in (4, 8):
-        for tm in (1, 2):
-            for tn in (1, 2, 4):
-                md = H.MD(H.Problem(J), H.make_schedule(T, 20), R, prec, seed=9)
-                md.set_step_tiles(tm, tn, cb)
-                md.run()
-                assert md.last_plan == "step"
-                out[(tm, tn, cb)] = _states(H, md)
-                md.close()
-    ref = out[(2, 4, 4)]
+    for tj in ((0, 1) if prec != "f32" else (0,)):
+        for cb in (4, 8):
+            for tm in (1, 2):
+                for tn in (1, 2, 4):
+                    md = H.MD(H.Problem(J), H.make_schedule(T, 20), R, prec, seed=9)
+                    md.set_step_tiles(tm, tn, cb, tiled=bool(tj))
+                    md.run()
+                    assert md.last_plan == "step"
+                    out[(tm, tn, cb, tj)] = _states(H, md)
+                    md.close()
+    ref = out[(2, 4, 4, 0)]
     for key, st in out.items():
         for x, y in zip(ref, st):
             assert np.array_equal(x, y), key

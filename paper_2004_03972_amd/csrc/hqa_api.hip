@@ -78,6 +78,7 @@ static std::string err_text(int e) {
     if (e & ERR_INEXACT) s += " J does not convert exactly to the storage type;";
     if (e & ERR_NONFINITE) s += " a flux or momentum became non-finite;";
     if (e & ERR_BARRIER) s += " a persistent-kernel barrier wait exceeded its bound;";
+    if (e & ERR_PLACEMENT) s += " a persistent-kernel workgroup ran outside its cluster's XCD;";
     return s;
 }
 

@@ -29,6 +29,7 @@ enum {
     ERR_CSR_ORDER = 32,     // CSR columns not strictly ascending / out of range
     ERR_FP8_SUBNORMAL = 64, // J value whose e4m3 code would be subnormal
     ERR_BARRIER = 128,      // persistent-kernel barrier wait exceeded its bound
+    ERR_PLACEMENT = 256,    // persistent-kernel workgroup not on the XCD its cluster assumes
 };
 
 // Exponent statistics of an instance for the exact accumulator:

@@ -156,19 +156,33 @@ __device__ __forceinline__ void chain_block(const DenseArgs &a, int i0, int r0, 
     }
 }
 
+// State of four consecutive rows (ib..ib+3) of one replica that the update reads,
+// loaded before the field so that its latency overlaps the field's loads.
+struct TileState {
+    float4 x, p, s;
+    float h[4];
+};
+
+__device__ __forceinline__ void load_tile_state(const DenseArgs &a, int64_t q, int col, int ib,
+                                                TileState &ts) {
+    const int64_t base = (int64_t)col * a.ld + ib;
+    ts.x = *(const float4 *)(a.phi_in + base);
+    ts.p = *(const float4 *)(a.p + base);
+    ts.s = q + 1 >= a.T - a.W + 1 ? *(const float4 *)(a.S + base) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int v = 0; v < 4; v++) ts.h[v] = ib + v < a.N ? a.h[ib + v] : 0.f;
+}
+
 // Leapfrog of four consecutive rows (ib..ib+3) of replica col with field u.
 __device__ __forceinline__ void dense_update(const DenseArgs &a, int64_t q, int col, int ib,
-                                             const f32x4 &u) {
+                                             const f32x4 &u, const StepCoef &c, const TileState &ts) {
     const int64_t base = (int64_t)col * a.ld + ib;
-    const StepCoef c = step_coef(a.a32, a.b32, q, a.rg, a.M);
-    float4 x = *(const float4 *)(a.phi_in + base);
-    float4 p = *(const float4 *)(a.p + base);
-    float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w}, xn[4];
+    float xs[4] = {ts.x.x, ts.x.y, ts.x.z, ts.x.w}, ps[4] = {ts.p.x, ts.p.y, ts.p.z, ts.p.w}, xn[4];
     bool bad = false;
 #pragma unroll
     for (int v = 0; v < 4; v++) {
         if (ib + v < a.N) {
-            leapfrog(c, xs[v], u[v], a.h[ib + v], ps[v], xn[v]);
+            leapfrog(c, xs[v], u[v], ts.h[v], ps[v], xn[v]);
             if (a.st) es_accumulate(a.st, a.sst, base + v, xs[v], xn[v], u[v], ps[v],
                                     a.inv_n2[ib + v]);
             bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
@@ -185,7 +199,7 @@ __device__ __forceinline__ void dense_update(const DenseArgs &a, int64_t q, int 
         *(bf16x4 *)(a.xb_out + base) = b;
     }
     if (q + 1 >= a.T - a.W + 1) {
-        float4 s = *(const float4 *)(a.S + base);
+        float4 s = ts.s;
         s.x = s.x + xn[0]; s.y = s.y + xn[1]; s.z = s.z + xn[2]; s.w = s.w + xn[3];
         *(float4 *)(a.S + base) = s;
     }
@@ -194,12 +208,27 @@ __device__ __forceinline__ void dense_update(const DenseArgs &a, int64_t q, int 
 
 // Block of TM x TN output tiles (32 rows x 16 TN replicas for TM = 2): each
 // wavefront accumulates one chain of every tile; the partial tiles meet in LDS
-// and wavefront w combines and updates tiles w, w + 4, ... in chain order.
+// and wavefront w combines and updates tiles w, w + 4, ... in chain order.  The
+// state these updates read is loaded first, together with the field operands.
 template <int JT, int TM, int TN, bool FIELD_ONLY, int CB = 4, bool TJ = false>
 __global__ __launch_bounds__(256) void k_step_block(DenseArgs a, int64_t q) {
+    constexpr int NT = (TM * TN + 3) / 4;   // tiles updated per wavefront
     __shared__ f32x4 part[4][TM * TN][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i0 = blockIdx.x * 16 * TM, r0 = blockIdx.y * 16 * TN;
+    StepCoef cf;
+    TileState ts[NT];
+    if constexpr (!FIELD_ONLY) {
+        cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
+#pragma unroll
+        for (int k = 0; k < NT; k++) {
+            const int t = w + 4 * k;
+            const int tm = t / TN, tn = t % TN;
+            const int col = r0 + 16 * tn + (lane & 15);
+            const int ib = i0 + 16 * tm + 4 * (lane >> 4);
+            if (t < TM * TN && col < a.R && ib < a.N) load_tile_state(a, q, col, ib, ts[k]);
+        }
+    }
     f32x4 acc[TM][TN];
     chain_block<JT, TM, TN, CB, TJ>(a, i0, r0, lane, w, acc);
 #pragma unroll
@@ -207,7 +236,10 @@ __global__ __launch_bounds__(256) void k_step_block(DenseArgs a, int64_t q) {
 #pragma unroll
         for (int tn = 0; tn < TN; tn++) part[w][tm * TN + tn][lane] = acc[tm][tn];
     __syncthreads();
-    for (int t = w; t < TM * TN; t += 4) {
+#pragma unroll
+    for (int k = 0; k < NT; k++) {
+        const int t = w + 4 * k;
+        if (t >= TM * TN) continue;
         const int tm = t / TN, tn = t % TN;
         const int col = r0 + 16 * tn + (lane & 15);
         const int ib = i0 + 16 * tm + 4 * (lane >> 4);
@@ -218,7 +250,7 @@ __global__ __launch_bounds__(256) void k_step_block(DenseArgs a, int64_t q) {
         if constexpr (FIELD_ONLY) {
             *(float4 *)(a.u_out + (int64_t)col * a.ld + ib) = make_float4(u[0], u[1], u[2], u[3]);
         } else {
-            dense_update(a, q, col, ib, u);
+            dense_update(a, q, col, ib, u, cf, ts[k]);
         }
     }
 }

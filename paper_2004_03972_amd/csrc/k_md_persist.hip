@@ -11,24 +11,36 @@
 //     accumulator layout).
 // Step q needs the fluxes phi^(q) of all N spins of the cluster's replicas, which
 // the other workgroups of the cluster produce.  They travel through an exchange
-// buffer of tagged words: each flux is stored together with a step tag by a
-// relaxed agent-scope atomic store.  At the start of a step the workgroup
-// gathers the cluster's whole flux block with relaxed agent-scope atomic loads,
-// all in flight together, re-loads only the words whose tag is not yet the
-// step's, and stages the values in LDS, from which every wavefront reads its
-// MFMA operands.  Each word validates itself, so no fence, grid barrier or L2
-// write-back is needed.  Two exchange buffers (by step parity) cannot be
-// overwritten early: a producer writes step q+2 into the buffer of step q only
-// after it has gathered step q+1, which every consumer produced after finishing
-// its gather of step q.  Tags run 1..65535 within a launch and the buffers are
-// cleared before it, so stale words never match.
+// buffer of tagged entries, each flux stored together with a step tag.  A
+// producer stores its entries, waits until the stores are acknowledged (they are
+// then in the L2) and sets its flag in the cluster's flag row to the step tag.
+// At the start of a step one wavefront of each consumer polls the G flags of its
+// cluster (one load per member), and then the workgroup reads the cluster's whole
+// flux block once, all loads in flight together, and stages the values in LDS,
+// from which every wavefront reads its MFMA operands.  The tags in the entries
+// are checked as well: a stale entry, which the flags make impossible, would
+// only cause the block to be read again.  No fence, grid barrier or L2
+// write-back is needed.  Two exchange buffers and flag rows (by step parity)
+// cannot be overwritten early: a producer writes step q+2 into the buffer of step
+// q only after it has gathered step q+1, which every consumer produced after
+// finishing its gather of step q.  Tags run 1..65535 within a launch and the
+// buffers are cleared before it, so stale entries never match.
+//
+// The members of a cluster share one XCD (workgroup b runs on XCD b mod 8), and
+// the L2 of an XCD is the coherence point of its CUs.  So a flux only has to
+// reach that L2: producers write it with ordinary stores (the vector L1 writes
+// through, and the line stays in the L2 without a write-back to memory), and
+// consumers read it with agent-scope loads, which miss in the L1 and are served
+// by the L2.  Agent-scope stores would also write every entry through to memory,
+// which the exchange does not need.  Each workgroup checks at start that it runs
+// on the XCD its cluster assumes and otherwise aborts the launch (ERR_PLACEMENT);
+// an agent-scope acquire at start drops any copy of the cleared buffer that the
+// L2 may hold from an earlier launch.
 //
 // The binary32 update applies the same operation sequence as the per-step
 // kernel, so both paths give identical states.  Every wait is bounded: past the
 // bound a workgroup raises an abort flag that all other waiters observe, and
-// the whole grid leaves the kernel.  Cluster members are placed on one XCD
-// (workgroups are dispatched round-robin over the 8 XCDs); correctness does not
-// depend on the placement.
+// the whole grid leaves the kernel.
 //
 // For BF16 / FP8 storage with Np <= 1024 a second kernel (k_persist_rj) keeps each
 // wavefront's 16 rows of J in registers instead of LDS, so that the staged flux
@@ -56,6 +68,7 @@ struct PersistArgs {
     float *p, *S;
     uint64_t *xch;           // [2][Rp][Np] tagged entries: u32 (bf16|tag<<16) or u64 (f32|tag<<32)
     int64_t xch_half;        // entries per parity buffer
+    uint32_t *flags;         // [2][C][32] step tag published by each cluster member
     int32_t *abort_flag;
     int32_t *err;
     int jstride;             // LDS row stride of the J block (bytes)
@@ -75,11 +88,40 @@ __device__ __forceinline__ bf16x8 cvt_fp8x8(uint2 raw) {
     return o;
 }
 
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// An ordinary 64-bit store (single-copy atomic): it reaches the XCD's L2.  The
+// compiler barrier keeps it ahead of the waits that follow.
+__device__ __forceinline__ void st_l2(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Four BF16 entries (flux | tag << 16, one 32-bit word each) in one 16-byte store.
+__device__ __forceinline__ void st4_l2(uint32_t *p, u32x4 v) {
+    *(u32x4 *)p = v;
+}
+// 16 bytes of a raw buffer at byte offset off, loaded at agent scope (sc1: misses
+// in the L1, served by the L2); offsets past the buffer's size read zeros.
+__device__ __forceinline__ u32x4 ld16_agent(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 16);
+}
+
+// Aborts the launch unless the workgroup runs on XCD `xcd`; then drops stale L2
+// copies of the exchange buffer.  Returns false when the workgroup must leave.
+__device__ __forceinline__ bool check_placement(int32_t *abort_flag, int32_t *err, int xcd) {
+    uint32_t xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    if ((int)(xcc & 0xfu) != xcd) {   // uniform over the workgroup
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicOr(err, ERR_PLACEMENT);
+        }
+        return false;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
 }
 
 struct Waiter {
@@ -103,57 +145,105 @@ __device__ __forceinline__ bool keep_waiting(const PersistArgs &a, Waiter &wt) {
     return true;
 }
 
-template <int JT>
-__device__ __forceinline__ bool tag_ok(uint64_t v, uint32_t tag) {
-    if constexpr (JT == JT_F32) return (uint32_t)(v >> 32) == tag;
-    else return ((uint32_t)(v >> 16) & 0xffffu) == tag && (uint32_t)(v >> 48) == tag;
+// Wait until every member of cluster c has published step tag `tag` (parity par):
+// wavefront 0 polls the cluster's flag row, one lane per member.  The caller
+// synchronises the workgroup afterwards.
+__device__ __forceinline__ void wait_flags(const PersistArgs &a, int par, int c, uint32_t tag,
+                                           Waiter &wt) {
+    if (threadIdx.x >= 64) return;
+    const uint32_t *f = a.flags + ((size_t)par * a.C + c) * 32;
+    bool ok = (int)threadIdx.x >= a.G;
+    while (true) {
+        if (!ok)
+            ok = __hip_atomic_load(f + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == tag;
+        if (__all(ok) || !keep_waiting(a, wt)) break;
+    }
 }
 
-// Gather the cluster's flux block of one step into LDS.  FP32: one entry per
-// 64-bit word; BF16: two entries per word, stored to LDS as a packed bf16 pair.
-template <int JT>
+// After a member's entries of one step are stored: wait for their acknowledgement
+// (each wavefront), then one thread raises the member's flag.  Contains a
+// workgroup barrier.
+__device__ __forceinline__ void raise_flag(const PersistArgs &a, int par, int c, int g,
+                                           uint32_t tag) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(a.flags + ((size_t)par * a.C + c) * 32 + g, tag, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    asm volatile("" ::: "memory");
+}
+
+// Gather the cluster's flux block of one step into LDS (after wait_flags).  The
+// block is [ld / 4 units of four rows][16 replicas][4 entries]: unit idx holds
+// rows 4 (idx >> 4) .. +3 of replica idx & 15.  FP32: 64-bit entries, two 64-bit
+// atomic loads per unit; BF16: 32-bit entries, one 16-byte load per unit, stored
+// to LDS as four packed bf16 values.  The unit count 4 ld is a multiple of 512,
+// so every batch of 256 units is whole and its guard is uniform.  NBC > 0: the
+// batch count 4 ld / 256 known at compile time (no guards; at most 16).
+template <int JT, int NBC = 0>
 __device__ __forceinline__ void gather(const PersistArgs &a, int par, int r0, uint32_t tag,
                                        uint8_t *phis, Waiter &wt) {
-    constexpr int GB = 32;
-    const int wpr = JT == JT_F32 ? a.ld : a.ld / 2;       // words per replica row
-    const int nw = 16 * wpr;
-    const uint64_t *src = a.xch + (JT == JT_F32 ? par * a.xch_half + (int64_t)r0 * a.ld
-                                                : (par * a.xch_half + (int64_t)r0 * a.ld) / 2);
+    constexpr int GB = NBC > 0 ? NBC : JT == JT_F32 ? 8 : 16;   // units per thread in flight
     const int tid = threadIdx.x;
-    for (int b0 = 0; b0 < nw; b0 += 256 * GB) {
-        uint64_t v[GB];
-        uint32_t miss = 0;
+    const int nb = NBC > 0 ? NBC : 4 * a.ld / 256;             // batches of 256 units
+    const int rr = tid & 15;                          // replica of this thread's units
+    for (int b0 = 0; b0 < nb; b0 += GB) {
+        if constexpr (JT == JT_F32) {
+            const uint64_t *src = a.xch + par * a.xch_half + (int64_t)r0 * a.ld;
+            const uint64_t tg = (uint64_t)tag << 32;
+            uint64_t v[GB][4];
+            while (true) {
+                uint64_t bad = 0;
 #pragma unroll
-        for (int m = 0; m < GB; m++) {
-            const int idx = b0 + m * 256 + tid;
-            v[m] = idx < nw ? ld_relaxed(src + idx) : 0ull;
-        }
+                for (int m = 0; m < GB; m++) {
+                    const uint64_t *u = src + ((b0 + m) * 256 + tid) * 4;
+                    if (b0 + m < nb) {
 #pragma unroll
-        for (int m = 0; m < GB; m++) {
-            const int idx = b0 + m * 256 + tid;
-            if (idx < nw && !tag_ok<JT>(v[m], tag)) miss |= 1u << m;
-        }
-        // re-load every stale word together, then check them all: one memory round
-        // trip per retry, not one per stale word
-        while (miss && !wt.dead) {
-            if (!keep_waiting(a, wt)) break;
+                        for (int e = 0; e < 4; e++) v[m][e] = ld_relaxed(u + e);
+                    }
+                }
 #pragma unroll
-            for (int m = 0; m < GB; m++)
-                if ((miss >> m) & 1u) v[m] = ld_relaxed(src + b0 + m * 256 + tid);
+                for (int m = 0; m < GB; m++) {
+                    if (b0 + m < nb) {
 #pragma unroll
-            for (int m = 0; m < GB; m++)
-                if (((miss >> m) & 1u) && tag_ok<JT>(v[m], tag)) miss &= ~(1u << m);
-        }
+                        for (int e = 0; e < 4; e++) bad |= v[m][e] ^ tg;
+                    }
+                }
+                if ((bad >> 32) == 0 || !keep_waiting(a, wt)) break;
+            }
 #pragma unroll
-        for (int m = 0; m < GB; m++) {
-            const int idx = b0 + m * 256 + tid;
-            if (idx < nw) {
-                const int rr = idx / wpr, kk = idx % wpr;
-                uint32_t val = JT == JT_F32
-                                   ? (uint32_t)v[m]
-                                   : __builtin_amdgcn_perm((uint32_t)(v[m] >> 32), (uint32_t)v[m],
-                                                           0x05040100u);
-                *(uint32_t *)(phis + (size_t)rr * a.pstride + kk * 4) = val;
+            for (int m = 0; m < GB; m++) {
+                const int kk = (((b0 + m) * 256 + tid) >> 4) * 4;
+                if (b0 + m < nb)
+                    *(uint4 *)(phis + (size_t)rr * a.pstride + kk * 4) =
+                    make_uint4((uint32_t)v[m][0], (uint32_t)v[m][1], (uint32_t)v[m][2], (uint32_t)v[m][3]);
+            }
+        } else {
+            const uint32_t *src = (const uint32_t *)a.xch + par * a.xch_half + (int64_t)r0 * a.ld;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, 64 * a.ld, 0x00020000);
+            const uint32_t tg = tag << 16;
+            u32x4 v[GB];
+            while (true) {
+                uint32_t bad = 0;
+#pragma unroll
+                for (int m = 0; m < GB; m++)
+                    if (b0 + m < nb) v[m] = ld16_agent(rs, ((b0 + m) * 256 + tid) * 16);
+#pragma unroll
+                for (int m = 0; m < GB; m++)
+                    if (b0 + m < nb) bad |= (v[m][0] ^ tg) | (v[m][1] ^ tg) | (v[m][2] ^ tg) | (v[m][3] ^ tg);
+                if ((bad >> 16) == 0 || !keep_waiting(a, wt)) break;
+                asm volatile("" ::: "memory");   // the re-loads must read memory again
+            }
+#pragma unroll
+            for (int m = 0; m < GB; m++) {
+                if (b0 + m < nb) {
+                    const int kk = (((b0 + m) * 256 + tid) >> 4) * 4;
+                    uint2 o;
+                    o.x = __builtin_amdgcn_perm(v[m][1], v[m][0], 0x05040100u);
+                    o.y = __builtin_amdgcn_perm(v[m][3], v[m][2], 0x05040100u);
+                    *(uint2 *)(phis + (size_t)rr * a.pstride + kk * 2) = o;
+                }
             }
         }
     }
@@ -169,15 +259,20 @@ template <int JT>
 __device__ __forceinline__ void publish(const PersistArgs &a, int par, int col, int ib,
                                         const float *xn, uint32_t tag) {
     if constexpr (JT == JT_F32) {
-        uint64_t *dst = a.xch + par * a.xch_half + (int64_t)col * a.ld + ib;
+        uint64_t *dst = a.xch + par * a.xch_half + (int64_t)(col & ~15) * a.ld +
+                        ((ib >> 2) * 16 + (col & 15)) * 4;
 #pragma unroll
         for (int v = 0; v < 4; v++)
-            st_relaxed(dst + v, (uint64_t)__float_as_uint(xn[v]) | ((uint64_t)tag << 32));
+            st_l2(dst + v, (uint64_t)__float_as_uint(xn[v]) | ((uint64_t)tag << 32));
     } else {
-        uint64_t *dst = a.xch + (par * a.xch_half + (int64_t)col * a.ld + ib) / 2;
-        st_relaxed(dst, bf16_word(xn[0], tag) | (bf16_word(xn[1], tag) << 32));
-        st_relaxed(dst + 1, bf16_word(xn[2], tag) | (bf16_word(xn[3], tag) << 32));
+        // [ld / 4][16][4] block of the cluster of replica col (see gather): a
+        // wavefront's 16 replicas x 16 rows are one contiguous kilobyte
+        uint32_t *dst = (uint32_t *)a.xch + par * a.xch_half + (int64_t)(col & ~15) * a.ld +
+                        ((ib >> 2) * 16 + (col & 15)) * 4;
+        st4_l2(dst, (u32x4){(uint32_t)bf16_word(xn[0], tag), (uint32_t)bf16_word(xn[1], tag),
+                            (uint32_t)bf16_word(xn[2], tag), (uint32_t)bf16_word(xn[3], tag)});
     }
+    asm volatile("" ::: "memory");   // issued before the next gather's waits
 }
 
 template <int JT, int TRW, bool JLDS>
@@ -188,6 +283,7 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
     const int cl_in_xcd = slot / a.G, g = slot % a.G;
     const int c = cl_in_xcd * 8 + xcd;
     if (c >= a.C) return;
+    if (!check_placement(a.abort_flag, a.err, xcd)) return;
     const int NB = 64 * TRW;
     const int row0 = g * NB;
     if (row0 >= a.Np) return;
@@ -228,14 +324,19 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
         }
         if (tile_ok[t]) publish<JT>(a, 0, col, ib, xs[t], 1u);
     }
+    raise_flag(a, 0, c, g, 1u);
     Waiter wt{0, false};
     bool bad = false;
     const int nsteps = (int)(a.q1 - a.q0);
+    // coefficients are loaded one step ahead, so their latency is never waited for
+    StepCoef cfn = step_coef(a.a32, a.b32, a.q0, a.rg, a.M);
     for (int s = 0; s < nsteps; s++) {
         const int64_t q = a.q0 + s;
         const int par = s & 1;
-        // coefficients of this step first: their loads overlap the gather
-        const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
+        const StepCoef cf = cfn;
+        if (s + 1 < nsteps) cfn = step_coef(a.a32, a.b32, q + 1, a.rg, a.M);
+        wait_flags(a, par, c, (uint32_t)(s % 65535) + 1u, wt);
+        __syncthreads();
         gather<JT>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
         if (__syncthreads_or(wt.dead)) return;   // aborted: the workgroup leaves
         // field in the four chains of combine4 (chunk c -> chain c mod 4)
@@ -348,7 +449,8 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
             }
             if (s + 1 < nsteps) publish<JT>(a, par ^ 1, col, ib, xn, ntag);
         }
-        __syncthreads();   // the staged block is rewritten by the next gather
+        // (the barrier also keeps the staged block until every wavefront has read it)
+        if (s + 1 < nsteps) raise_flag(a, par ^ 1, c, g, ntag);
     }
 #pragma unroll
     for (int t = 0; t < TRW; t++) {
@@ -373,13 +475,14 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
 // reads only the staged flux block from LDS (the J operand costs no load), and
 // the cluster has Np / 64 members.  Gather, chains, update and publication are
 // those of k_persist, so the trajectories are identical.
-template <int JT, int NG>
+template <int JT, int NG, int MP>
 __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
     const int cl_in_xcd = slot / a.G, g = slot % a.G;
     const int c = cl_in_xcd * 8 + xcd;
     if (c >= a.C) return;
+    if (!check_placement(a.abort_flag, a.err, xcd)) return;
     const int row0 = g * 64;          // G = Np / 64: every member's rows lie below Np
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r0 = 16 * c;
@@ -414,15 +517,21 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
         hs[v] = (i < a.N) ? a.h[i] : 0.f;
     }
     publish<JT>(a, 0, col, ib, xs, 1u);
+    raise_flag(a, 0, c, g, 1u);
     Waiter wt{0, false};
     bool bad = false;
     const int nsteps = (int)(a.q1 - a.q0);
     const uint8_t *Xb = phis + (size_t)(lane & 15) * a.pstride;
+    // coefficients are loaded one step ahead, so their latency is never waited for
+    StepCoef cfn = step_coef(a.a32, a.b32, a.q0, a.rg, a.M);
     for (int s = 0; s < nsteps; s++) {
         const int64_t q = a.q0 + s;
         const int par = s & 1;
-        const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
-        gather<JT>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
+        const StepCoef cf = cfn;
+        if (s + 1 < nsteps) cfn = step_coef(a.a32, a.b32, q + 1, a.rg, a.M);
+        wait_flags(a, par, c, (uint32_t)(s % 65535) + 1u, wt);
+        __syncthreads();
+        gather<JT, 2 * NG>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
         if (__syncthreads_or(wt.dead)) return;   // aborted: the workgroup leaves
         // chunk 4 gi + j feeds chain j, in ascending gi (combine4's order)
         f32x4 acc[4];
@@ -443,17 +552,24 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
         float xn[4];
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            if (rvalid && ib + v < a.N) {
-                leapfrog(cf, xs[v], u[v], hs[v], ps[v], xn[v]);
-                bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
-                if (win) ss[v] = ss[v] + xn[v];
-            } else {
-                xn[v] = 0.f;
-            }
+            // padding rows and replicas hold zero state and a zero field; their update
+            // is computed and discarded, so the lanes do not branch
+            const bool ok = rvalid && ib + v < a.N;
+            float pv = ps[v], x1;
+            if constexpr (MP == 6) leapfrog_m<6>(cf, xs[v], u[v], hs[v], pv, x1);
+            else leapfrog(cf, xs[v], u[v], hs[v], pv, x1);
+            xn[v] = ok ? x1 : 0.f;
+            ps[v] = ok ? pv : ps[v];
+            bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
+            ss[v] = win && ok ? ss[v] + xn[v] : ss[v];
             xs[v] = xn[v];
         }
-        if (s + 1 < nsteps) publish<JT>(a, par ^ 1, col, ib, xn, (uint32_t)((s + 1) % 65535) + 1u);
-        __syncthreads();   // the staged block is rewritten by the next gather
+        if (s + 1 < nsteps) {
+            // (the barrier in raise_flag also keeps the staged block until every
+            // wavefront has read it)
+            publish<JT>(a, par ^ 1, col, ib, xn, (uint32_t)((s + 1) % 65535) + 1u);
+            raise_flag(a, par ^ 1, c, g, (uint32_t)((s + 1) % 65535) + 1u);
+        }
     }
     if (rvalid) {
         const int64_t base = (int64_t)col * a.ld + ib;
@@ -534,11 +650,12 @@ static hipError_t launch_p(const PersistArgs &a, const PersistPlan &pl, hipStrea
                                       dim3(256), args, (unsigned)pl.lds, st);
 }
 
+// MP: the potential exponent when it is the paper's M = 6 (power unrolled), else 0.
 template <int JT, int NG>
 static hipError_t launch_rj(const PersistArgs &a, const PersistPlan &pl, hipStream_t st) {
     void *args[] = {(void *)&a};
-    return hipLaunchCooperativeKernel((const void *)k_persist_rj<JT, NG>, dim3(pl.grid), dim3(256),
-                                      args, (unsigned)pl.lds, st);
+    const void *k = a.M == 6 ? (const void *)k_persist_rj<JT, NG, 6> : (const void *)k_persist_rj<JT, NG, 0>;
+    return hipLaunchCooperativeKernel(k, dim3(pl.grid), dim3(256), args, (unsigned)pl.lds, st);
 }
 
 template <int JT>
@@ -578,7 +695,8 @@ hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
     if (!plan_persist(I, md->R, I.jt, max_wg, pl)) return hipErrorNotSupported;
     const size_t esz = I.jt == JT_F32 ? 8 : 4;
     const int64_t half = (int64_t)I.Rp * I.ld;
-    const size_t bytes = 2 * (size_t)half * esz;
+    const size_t xbytes = 2 * (size_t)half * esz;
+    const size_t bytes = xbytes + 2 * (size_t)pl.C * 32 * sizeof(uint32_t);   // + flag rows
     if (!I.xch || I.xch_bytes < bytes) {
         if (I.xch) (void)hipFree(I.xch);
         I.xch = nullptr;
@@ -606,6 +724,7 @@ hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
     a.p = I.p32; a.S = I.S32;
     a.xch = (uint64_t *)I.xch;
     a.xch_half = half;
+    a.flags = (uint32_t *)((uint8_t *)I.xch + xbytes);
     a.abort_flag = md->bar + 63; a.err = md->err;
     a.jstride = pl.jstride;
     a.jbytes = pl.jbytes;

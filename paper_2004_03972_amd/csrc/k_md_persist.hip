@@ -11,19 +11,15 @@
 //     accumulator layout).
 // Step q needs the fluxes phi^(q) of all N spins of the cluster's replicas, which
 // the other workgroups of the cluster produce.  They travel through an exchange
-// buffer of tagged entries, each flux stored together with a step tag.  A
-// producer stores its entries, waits until the stores are acknowledged (they are
-// then in the L2) and sets its flag in the cluster's flag row to the step tag.
-// At the start of a step one wavefront of each consumer polls the G flags of its
-// cluster (one load per member), and then the workgroup reads the cluster's whole
-// flux block once, all loads in flight together, and stages the values in LDS,
-// from which every wavefront reads its MFMA operands.  The tags in the entries
-// are checked as well: a stale entry, which the flags make impossible, would
-// only cause the block to be read again.  No fence, grid barrier or L2
-// write-back is needed.  Two exchange buffers and flag rows (by step parity)
-// cannot be overwritten early: a producer writes step q+2 into the buffer of step
-// q only after it has gathered step q+1, which every consumer produced after
-// finishing its gather of step q.  Tags run 1..65535 within a launch and the
+// buffer of tagged entries, each flux stored together with a step tag.  At the
+// start of a step the workgroup reads the cluster's whole flux block, all loads
+// in flight together; a thread that finds an entry whose tag is not yet the
+// step's reads its part again, and the values are staged in LDS, from which every
+// wavefront reads its MFMA operands.  Each entry validates itself, so no flag,
+// fence, grid barrier or L2 write-back is needed.  Two exchange buffers (by step
+// parity) cannot be overwritten early: a producer writes step q+2 into the buffer
+// of step q only after it has gathered step q+1, which every consumer produced
+// after finishing its gather of step q.  Tags run 1..65535 within a launch and the
 // buffers are cleared before it, so stale entries never match.
 //
 // The members of a cluster share one XCD (workgroup b runs on XCD b mod 8), and
@@ -68,7 +64,6 @@ struct PersistArgs {
     float *p, *S;
     uint64_t *xch;           // [2][Rp][Np] tagged entries: u32 (bf16|tag<<16) or u64 (f32|tag<<32)
     int64_t xch_half;        // entries per parity buffer
-    uint32_t *flags;         // [2][C][32] step tag published by each cluster member
     int32_t *abort_flag;
     int32_t *err;
     int jstride;             // LDS row stride of the J block (bytes)
@@ -145,52 +140,30 @@ __device__ __forceinline__ bool keep_waiting(const PersistArgs &a, Waiter &wt) {
     return true;
 }
 
-// Wait until every member of cluster c has published step tag `tag` (parity par):
-// wavefront 0 polls the cluster's flag row, one lane per member.  The caller
-// synchronises the workgroup afterwards.
-__device__ __forceinline__ void wait_flags(const PersistArgs &a, int par, int c, uint32_t tag,
-                                           Waiter &wt) {
-    if (threadIdx.x >= 64) return;
-    const uint32_t *f = a.flags + ((size_t)par * a.C + c) * 32;
-    bool ok = (int)threadIdx.x >= a.G;
-    while (true) {
-        if (!ok)
-            ok = __hip_atomic_load(f + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == tag;
-        if (__all(ok) || !keep_waiting(a, wt)) break;
-    }
-}
-
-// After a member's entries of one step are stored: wait for their acknowledgement
-// (each wavefront), then one thread raises the member's flag.  Contains a
-// workgroup barrier.
-__device__ __forceinline__ void raise_flag(const PersistArgs &a, int par, int c, int g,
-                                           uint32_t tag) {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (threadIdx.x == 0)
-        __hip_atomic_store(a.flags + ((size_t)par * a.C + c) * 32 + g, tag, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-    asm volatile("" ::: "memory");
-}
-
-// Gather the cluster's flux block of one step into LDS (after wait_flags).  The
+// Gather the cluster's flux block of one step into LDS.  The
 // block is [ld / 4 units of four rows][16 replicas][4 entries]: unit idx holds
-// rows 4 (idx >> 4) .. +3 of replica idx & 15.  FP32: 64-bit entries, two 64-bit
-// atomic loads per unit; BF16: 32-bit entries, one 16-byte load per unit, stored
-// to LDS as four packed bf16 values.  The unit count 4 ld is a multiple of 512,
-// so every batch of 256 units is whole and its guard is uniform.  NBC > 0: the
-// batch count 4 ld / 256 known at compile time (no guards; at most 16).
+// rows 4 (idx >> 4) .. +3 of replica idx & 15.
+//  - FP32: 64-bit entries, four 64-bit atomic loads per unit, one 16-byte LDS
+//    store; batches of 256 units (4 ld is a multiple of 512, so every batch is
+//    whole and its guard uniform).
+//  - BF16: 32-bit entries, one 16-byte load per unit.  A thread takes two units
+//    of one replica with adjacent row groups, idx and idx + 16, and stores their
+//    eight bf16 values to LDS with one 16-byte store (the row stride of the staged
+//    block is 4 dwords modulo 64 banks, so a quarter-wavefront's stores cover the
+//    banks once); batches of 512 units.  NBC > 0: the batch count ld / 128 known at
+//    compile time (no guards; at most 16).
+// A thread that gives up waiting sets *dead; the caller synchronises and leaves.
 template <int JT, int NBC = 0>
 __device__ __forceinline__ void gather(const PersistArgs &a, int par, int r0, uint32_t tag,
                                        uint8_t *phis, Waiter &wt) {
-    constexpr int GB = NBC > 0 ? NBC : JT == JT_F32 ? 8 : 16;   // units per thread in flight
     const int tid = threadIdx.x;
-    const int nb = NBC > 0 ? NBC : 4 * a.ld / 256;             // batches of 256 units
     const int rr = tid & 15;                          // replica of this thread's units
-    for (int b0 = 0; b0 < nb; b0 += GB) {
-        if constexpr (JT == JT_F32) {
-            const uint64_t *src = a.xch + par * a.xch_half + (int64_t)r0 * a.ld;
-            const uint64_t tg = (uint64_t)tag << 32;
+    if constexpr (JT == JT_F32) {
+        constexpr int GB = 8;                         // units per thread in flight
+        const int nb = 4 * a.ld / 256;
+        const uint64_t *src = a.xch + par * a.xch_half + (int64_t)r0 * a.ld;
+        const uint64_t tg = (uint64_t)tag << 32;
+        for (int b0 = 0; b0 < nb; b0 += GB) {
             uint64_t v[GB][4];
             while (true) {
                 uint64_t bad = 0;
@@ -216,33 +189,47 @@ __device__ __forceinline__ void gather(const PersistArgs &a, int par, int r0, ui
                 const int kk = (((b0 + m) * 256 + tid) >> 4) * 4;
                 if (b0 + m < nb)
                     *(uint4 *)(phis + (size_t)rr * a.pstride + kk * 4) =
-                    make_uint4((uint32_t)v[m][0], (uint32_t)v[m][1], (uint32_t)v[m][2], (uint32_t)v[m][3]);
+                        make_uint4((uint32_t)v[m][0], (uint32_t)v[m][1], (uint32_t)v[m][2], (uint32_t)v[m][3]);
             }
-        } else {
-            const uint32_t *src = (const uint32_t *)a.xch + par * a.xch_half + (int64_t)r0 * a.ld;
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, 64 * a.ld, 0x00020000);
-            const uint32_t tg = tag << 16;
-            u32x4 v[GB];
+        }
+    } else {
+        constexpr int GB = NBC > 0 ? NBC : 8;         // unit pairs per thread in flight
+        const int nb = NBC > 0 ? NBC : a.ld / 128;
+        const uint32_t *src = (const uint32_t *)a.xch + par * a.xch_half + (int64_t)r0 * a.ld;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, 64 * a.ld, 0x00020000);
+        const uint32_t tg = tag << 16;
+        const int u0 = (tid >> 4) * 32 + rr;          // first unit of the pair in a batch
+        for (int b0 = 0; b0 < nb; b0 += GB) {
+            u32x4 v[GB][2];
             while (true) {
                 uint32_t bad = 0;
 #pragma unroll
                 for (int m = 0; m < GB; m++)
-                    if (b0 + m < nb) v[m] = ld16_agent(rs, ((b0 + m) * 256 + tid) * 16);
+                    if (b0 + m < nb) {
+                        v[m][0] = ld16_agent(rs, ((b0 + m) * 512 + u0) * 16);
+                        v[m][1] = ld16_agent(rs, ((b0 + m) * 512 + u0 + 16) * 16);
+                    }
 #pragma unroll
                 for (int m = 0; m < GB; m++)
-                    if (b0 + m < nb) bad |= (v[m][0] ^ tg) | (v[m][1] ^ tg) | (v[m][2] ^ tg) | (v[m][3] ^ tg);
+                    if (b0 + m < nb)
+#pragma unroll
+                        for (int h = 0; h < 2; h++)
+                            bad |= (v[m][h][0] ^ tg) | (v[m][h][1] ^ tg) | (v[m][h][2] ^ tg) |
+                                   (v[m][h][3] ^ tg);
                 if ((bad >> 16) == 0 || !keep_waiting(a, wt)) break;
                 asm volatile("" ::: "memory");   // the re-loads must read memory again
             }
 #pragma unroll
             for (int m = 0; m < GB; m++) {
                 if (b0 + m < nb) {
-                    const int kk = (((b0 + m) * 256 + tid) >> 4) * 4;
-                    uint2 o;
-                    o.x = __builtin_amdgcn_perm(v[m][1], v[m][0], 0x05040100u);
-                    o.y = __builtin_amdgcn_perm(v[m][3], v[m][2], 0x05040100u);
-                    *(uint2 *)(phis + (size_t)rr * a.pstride + kk * 2) = o;
+                    const int ku = (b0 + m) * 32 + (tid >> 4) * 2;   // row group of the pair
+                    uint4 o;
+                    o.x = __builtin_amdgcn_perm(v[m][0][1], v[m][0][0], 0x05040100u);
+                    o.y = __builtin_amdgcn_perm(v[m][0][3], v[m][0][2], 0x05040100u);
+                    o.z = __builtin_amdgcn_perm(v[m][1][1], v[m][1][0], 0x05040100u);
+                    o.w = __builtin_amdgcn_perm(v[m][1][3], v[m][1][2], 0x05040100u);
+                    *(uint4 *)(phis + (size_t)rr * a.pstride + ku * 8) = o;
                 }
             }
         }
@@ -284,6 +271,9 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
     const int c = cl_in_xcd * 8 + xcd;
     if (c >= a.C) return;
     if (!check_placement(a.abort_flag, a.err, xcd)) return;
+    __shared__ int s_dead;   // a thread gave up waiting
+    if (threadIdx.x == 0) s_dead = 0;
+    __syncthreads();
     const int NB = 64 * TRW;
     const int row0 = g * NB;
     if (row0 >= a.Np) return;
@@ -324,7 +314,6 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
         }
         if (tile_ok[t]) publish<JT>(a, 0, col, ib, xs[t], 1u);
     }
-    raise_flag(a, 0, c, g, 1u);
     Waiter wt{0, false};
     bool bad = false;
     const int nsteps = (int)(a.q1 - a.q0);
@@ -335,10 +324,10 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
         const int par = s & 1;
         const StepCoef cf = cfn;
         if (s + 1 < nsteps) cfn = step_coef(a.a32, a.b32, q + 1, a.rg, a.M);
-        wait_flags(a, par, c, (uint32_t)(s % 65535) + 1u, wt);
-        __syncthreads();
         gather<JT>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
-        if (__syncthreads_or(wt.dead)) return;   // aborted: the workgroup leaves
+        if (wt.dead) s_dead = 1;
+        __syncthreads();
+        if (s_dead) return;   // aborted: the workgroup leaves
         // field in the four chains of combine4 (chunk c -> chain c mod 4)
         f32x4 acc[TRW][4];
 #pragma unroll
@@ -449,8 +438,7 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
             }
             if (s + 1 < nsteps) publish<JT>(a, par ^ 1, col, ib, xn, ntag);
         }
-        // (the barrier also keeps the staged block until every wavefront has read it)
-        if (s + 1 < nsteps) raise_flag(a, par ^ 1, c, g, ntag);
+        __syncthreads();   // the staged block is rewritten by the next gather
     }
 #pragma unroll
     for (int t = 0; t < TRW; t++) {
@@ -483,6 +471,9 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
     const int c = cl_in_xcd * 8 + xcd;
     if (c >= a.C) return;
     if (!check_placement(a.abort_flag, a.err, xcd)) return;
+    __shared__ int s_dead;   // a thread gave up waiting
+    if (threadIdx.x == 0) s_dead = 0;
+    __syncthreads();
     const int row0 = g * 64;          // G = Np / 64: every member's rows lie below Np
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r0 = 16 * c;
@@ -517,7 +508,6 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
         hs[v] = (i < a.N) ? a.h[i] : 0.f;
     }
     publish<JT>(a, 0, col, ib, xs, 1u);
-    raise_flag(a, 0, c, g, 1u);
     Waiter wt{0, false};
     bool bad = false;
     const int nsteps = (int)(a.q1 - a.q0);
@@ -529,10 +519,10 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
         const int par = s & 1;
         const StepCoef cf = cfn;
         if (s + 1 < nsteps) cfn = step_coef(a.a32, a.b32, q + 1, a.rg, a.M);
-        wait_flags(a, par, c, (uint32_t)(s % 65535) + 1u, wt);
+        gather<JT, NG>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
+        if (wt.dead) s_dead = 1;
         __syncthreads();
-        gather<JT, 2 * NG>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
-        if (__syncthreads_or(wt.dead)) return;   // aborted: the workgroup leaves
+        if (s_dead) return;   // aborted: the workgroup leaves
         // chunk 4 gi + j feeds chain j, in ascending gi (combine4's order)
         f32x4 acc[4];
 #pragma unroll
@@ -564,12 +554,8 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
             ss[v] = win && ok ? ss[v] + xn[v] : ss[v];
             xs[v] = xn[v];
         }
-        if (s + 1 < nsteps) {
-            // (the barrier in raise_flag also keeps the staged block until every
-            // wavefront has read it)
-            publish<JT>(a, par ^ 1, col, ib, xn, (uint32_t)((s + 1) % 65535) + 1u);
-            raise_flag(a, par ^ 1, c, g, (uint32_t)((s + 1) % 65535) + 1u);
-        }
+        if (s + 1 < nsteps) publish<JT>(a, par ^ 1, col, ib, xn, (uint32_t)((s + 1) % 65535) + 1u);
+        __syncthreads();   // the staged block is rewritten by the next gather
     }
     if (rvalid) {
         const int64_t base = (int64_t)col * a.ld + ib;
@@ -695,8 +681,7 @@ hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
     if (!plan_persist(I, md->R, I.jt, max_wg, pl)) return hipErrorNotSupported;
     const size_t esz = I.jt == JT_F32 ? 8 : 4;
     const int64_t half = (int64_t)I.Rp * I.ld;
-    const size_t xbytes = 2 * (size_t)half * esz;
-    const size_t bytes = xbytes + 2 * (size_t)pl.C * 32 * sizeof(uint32_t);   // + flag rows
+    const size_t bytes = 2 * (size_t)half * esz;
     if (!I.xch || I.xch_bytes < bytes) {
         if (I.xch) (void)hipFree(I.xch);
         I.xch = nullptr;
@@ -724,7 +709,6 @@ hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
     a.p = I.p32; a.S = I.S32;
     a.xch = (uint64_t *)I.xch;
     a.xch_half = half;
-    a.flags = (uint32_t *)((uint8_t *)I.xch + xbytes);
     a.abort_flag = md->bar + 63; a.err = md->err;
     a.jstride = pl.jstride;
     a.jbytes = pl.jbytes;

@@ -163,7 +163,7 @@ def bench_er800(args, hqa, torch):
         launches, srcs = 2, "resident"
     elif plan == "cluster":                     # one cooperative launch for all steps
         np_ = -(-N // 128) * 128
-        kernel = (f"k_persist_rj<{JT_NAME[chosen]}, {np_ // 128}>" if chosen != "f32" and np_ <= 1024
+        kernel = (f"k_persist_rj<{JT_NAME[chosen]}, {np_ // 128}, 6>" if chosen != "f32" and np_ <= 1024
                   else f"k_persist<{JT_NAME[chosen]}")
         launches, srcs = 1, "persist"
     else:                                       # one launch per MD step

@@ -51,11 +51,14 @@ def stats(path, top=12):
               f"{float(r['TotalDurationNs']) / 1e6:>10.2f} {float(r['Percentage']):>6.2f}")
 
 
-def trace(path, kernel):
+def trace(path, kernel, last=0):
     rows = [r for r in _rows(path) if kernel in r["Kernel_Name"]]
     if not rows:
         sys.exit(f"no dispatch matches {kernel!r}")
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    if last:                                   # only the last dispatches (the timed runs)
+        rows = rows[-last:]
+        print(f"last {len(rows)} dispatches of the kernel")
     dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
     gap = [int(b["Start_Timestamp"]) - int(a["End_Timestamp"]) for a, b in zip(rows, rows[1:])]
     per = [int(b["Start_Timestamp"]) - int(a["Start_Timestamp"]) for a, b in zip(rows, rows[1:])]
@@ -72,10 +75,14 @@ def trace(path, kernel):
               f"{statistics.median(gap) / 1e3:.3f}")
 
 
-def pmc(path, kernel):
+def pmc(path, kernel, last=0):
     rows = [r for r in _rows(path) if kernel in r["Kernel_Name"]]
     if not rows:
         sys.exit(f"no dispatch matches {kernel!r}")
+    if last:                                   # only the last dispatches (the timed runs)
+        rows.sort(key=lambda r: int(r.get("Dispatch_Id", 0)))
+        rows = rows[-last:]
+        print(f"last {len(rows)} dispatches of the kernel")
     by = {}
     for r in rows:
         by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
@@ -101,13 +108,14 @@ def main(argv=None):
     ap.add_argument("--top", type=int, default=12)
     ap.add_argument("--bytes", type=int, default=0)
     ap.add_argument("--sources", default="dense", choices=sorted(SOURCES))
+    ap.add_argument("--last", type=int, default=0, help="only the last N dispatches")
     a = ap.parse_args(argv)
     if a.mode == "stats":
         stats(a.path, a.top)
     elif a.mode == "trace":
-        trace(a.path, a.kernel)
+        trace(a.path, a.kernel, a.last)
     elif a.mode == "pmc":
-        pmc(a.path, a.kernel)
+        pmc(a.path, a.kernel, a.last)
     elif a.mode == "calib":
         calib(a.path, a.bytes)
     else:

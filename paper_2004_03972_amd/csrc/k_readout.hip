@@ -391,12 +391,178 @@ __global__ __launch_bounds__(256) void k_enumerate(EnumArgs a) {
     }
 }
 
+// Integer instances with small sums: 1024 threads per replica, thread t fixes the
+// top pt = n - NL <= 10 bits of the code to t and walks the NL low bits in Gray-code
+// order in int32.  The low bits of every thread follow the same sequence, so the
+// flipped bit a and the sign x_a before the flip are the same for all lanes: 15 of
+// every 16 flips have a compile-time a (the ruler sequence of the block), the local
+// fields sit in registers and each update f_b += (-x_a) 2 J_ab is one 24-bit
+// multiply-add with a wavefront-uniform factor.  The walk keeps the minimum of the
+// key (E' + S) << NL | low code, so equal energies resolve to the smallest code.
+// Requires every |J_ab|, |h_a| integral with S = sum_{a<b} |J_ab| + sum_a |h_a| below
+// 2^22 and 2 S < 2^(31 - NL) (all terms then fit the 24-bit products and the key);
+// other integer replicas take the int64 walk.
+#define ENUM_PT 10
+
+__device__ __forceinline__ int32_t mad24(int32_t x, int32_t y, int32_t z) {
+    return __mul24(x, y) + z;
+}
+
+template <int NL>
+__device__ __forceinline__ void walk_i32(const int32_t *Jv, const int32_t *J2, const int32_t *hv,
+                                         int n, uint32_t top, int32_t S, int64_t &bestE,
+                                         int64_t &bestC) {
+    // start: low bits all 0 (x = +1), top bits from `top`
+    auto xof = [&](int c) -> int32_t {
+        return c < NL ? 1 : (((top >> (c - NL)) & 1u) ? -1 : 1);
+    };
+    int32_t E = S;
+    for (int aa = 0; aa < n; aa++) {
+        int32_t acc = hv[aa];
+        for (int bb = aa + 1; bb < n; bb++) acc += Jv[aa * n + bb] * xof(bb);
+        E += xof(aa) * acc;
+    }
+    uint32_t key = (uint32_t)E << NL;
+    if constexpr (NL > 0) {
+        int32_t f[NL];
+#pragma unroll
+        for (int b = 0; b < NL; b++) {
+            int32_t acc = hv[b];
+            for (int c = 0; c < n; c++) acc += Jv[b * n + c] * xof(c);   // J_bb = 0
+            f[b] = acc;
+        }
+        constexpr int NA = NL < 4 ? NL : 4;           // bits flipped inside a block of 16
+        int32_t D[NA][NL];
+#pragma unroll
+        for (int aa = 0; aa < NA; aa++)
+#pragma unroll
+            for (int b = 0; b < NL; b++) D[aa][b] = J2[aa * n + b];
+        uint32_t g = 0;                                // low code (uniform)
+        constexpr int NBLK = NL >= 4 ? 1 << (NL - 4) : 1;
+        for (int m = 0; m < NBLK; m++) {
+#pragma unroll
+            for (int j = 1; j < 16; j++) {
+                if (j >= (1 << NL)) break;
+                constexpr int dummy = 0;
+                (void)dummy;
+                const int aa = __builtin_ctz(j);
+                const int32_t sgn = ((g >> aa) & 1u) ? 1 : -1;   // -x_a before the flip
+                E = mad24(f[aa], 2 * sgn, E);
+#pragma unroll
+                for (int b = 0; b < NL; b++)
+                    if (b != aa) f[b] = mad24(D[aa][b], sgn, f[b]);
+                g ^= 1u << aa;
+                key = min(key, ((uint32_t)E << NL) | g);
+            }
+            if (m + 1 < NBLK) {                        // flip of bit 4 + ctz(m + 1)
+                const int aa = 4 + __builtin_ctz(m + 1);
+                const int32_t sgn = ((g >> aa) & 1u) ? 1 : -1;
+                int32_t fa = f[0];
+#pragma unroll
+                for (int b = 1; b < NL; b++) fa = b == aa ? f[b] : fa;
+                E = mad24(fa, 2 * sgn, E);
+#pragma unroll
+                for (int b = 0; b < NL; b++) f[b] = mad24(J2[aa * n + b], sgn, f[b]);   // J_aa = 0
+                g ^= 1u << aa;
+                key = min(key, ((uint32_t)E << NL) | g);
+            }
+        }
+    }
+    bestE = (int64_t)(key >> NL) - S;
+    bestC = ((int64_t)top << NL) | (key & ((1u << NL) - 1u));
+}
+
+template <int NL>
+__global__ __launch_bounds__(1024) void k_enumerate_int(EnumArgs a) {
+    __shared__ int32_t Jv[ENUM_MAXN * ENUM_MAXN], J2[ENUM_MAXN * ENUM_MAXN], hv[ENUM_MAXN];
+    __shared__ int64_t Jl[ENUM_MAXN * ENUM_MAXN], hl[ENUM_MAXN];
+    __shared__ int64_t sEi[1024], sC[1024];
+    __shared__ unsigned long long sS;
+    const int r = blockIdx.x, tid = threadIdx.x, n = a.n;
+    if (tid == 0) sS = 0;
+    __syncthreads();
+    for (int k = tid; k < n * n; k += 1024) {
+        const int64_t v = (int64_t)a.J_eff[(int64_t)r * n * n + k];
+        Jl[k] = v;
+        if (k / n < k % n) atomicAdd(&sS, (unsigned long long)(v < 0 ? -v : v));
+    }
+    for (int k = tid; k < n; k += 1024) {
+        const int64_t v = (int64_t)a.h_eff[(int64_t)r * n + k];
+        hl[k] = v;
+        atomicAdd(&sS, (unsigned long long)(v < 0 ? -v : v));
+    }
+    __syncthreads();
+    const unsigned long long S = sS;
+    const bool fast = S < (1ull << 22) && 2 * S < (1ull << (31 - NL));   // uniform
+    if (fast) {
+        for (int k = tid; k < n * n; k += 1024) {
+            Jv[k] = (int32_t)Jl[k];
+            J2[k] = 2 * (int32_t)Jl[k];
+        }
+        for (int k = tid; k < n; k += 1024) hv[k] = (int32_t)hl[k];
+        __syncthreads();
+    }
+    const bool active = tid < (1 << (n - NL));
+    int64_t bestE = INT64_MAX, bestC = INT64_MAX;
+    if (active) {
+        if (fast) {
+            walk_i32<NL>(Jv, J2, hv, n, (uint32_t)tid, (int32_t)S, bestE, bestC);
+        } else {
+            int64_t f[ENUM_MAXLOW];
+            gray_walk<int64_t>(Jl, hl, n, NL, (uint32_t)tid, f, [&](int64_t E, uint32_t c) {
+                if (better_i(E, c, bestE, bestC)) { bestE = E; bestC = c; }
+            });
+        }
+    }
+    // argmin over the workgroup, ties to the smaller code
+    sEi[tid] = bestE;
+    sC[tid] = bestC;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (tid < st && better_i(sEi[tid + st], sC[tid + st], sEi[tid], sC[tid])) {
+            sEi[tid] = sEi[tid + st];
+            sC[tid] = sC[tid + st];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.code[r] = sC[0];
+        a.e_red[r] = (double)sEi[0];
+    }
+}
+
+template <int NL>
+static void launch_enum_int(const EnumArgs &a, hipStream_t st) {
+    k_enumerate_int<NL><<<a.R, 1024, 0, st>>>(a);
+}
+
 hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_eff, int b0,
                             int integral, int64_t *code, double *e_red, hipStream_t st) {
     EnumArgs a;
     a.n = n; a.R = R; a.b0 = b0; a.integral = integral;
     a.J_eff = J_eff; a.h_eff = h_eff; a.code = code; a.e_red = e_red;
-    k_enumerate<<<R, 256, 0, st>>>(a);
+    if (R == 0) return hipSuccess;
+    if (!integral) {
+        k_enumerate<<<R, 256, 0, st>>>(a);
+        return hipGetLastError();
+    }
+    switch (n > ENUM_PT ? n - ENUM_PT : 0) {   // low bits walked per thread
+        case 0: launch_enum_int<0>(a, st); break;
+        case 1: launch_enum_int<1>(a, st); break;
+        case 2: launch_enum_int<2>(a, st); break;
+        case 3: launch_enum_int<3>(a, st); break;
+        case 4: launch_enum_int<4>(a, st); break;
+        case 5: launch_enum_int<5>(a, st); break;
+        case 6: launch_enum_int<6>(a, st); break;
+        case 7: launch_enum_int<7>(a, st); break;
+        case 8: launch_enum_int<8>(a, st); break;
+        case 9: launch_enum_int<9>(a, st); break;
+        case 10: launch_enum_int<10>(a, st); break;
+        case 11: launch_enum_int<11>(a, st); break;
+        case 12: launch_enum_int<12>(a, st); break;
+        case 13: launch_enum_int<13>(a, st); break;
+        default: launch_enum_int<14>(a, st); break;
+    }
     return hipGetLastError();
 }
 

@@ -212,6 +212,7 @@ hipError_t launch_reduce(const Instance &I, int R, int n, const int32_t *amb,
 // pass-1 minimum.
 // ---------------------------------------------------------------------------
 #define ENUM_MAXN 24
+#define ENERGY_MAXN_LDS 16384
 #define ENUM_MAXLOW 16
 
 template <typename T>
@@ -592,6 +593,7 @@ hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *
 // ---------------------------------------------------------------------------
 struct EnArgs {
     int N, V, csr, b0;
+    int fast;          // plain binary64 sums are exact (see launch_energy)
     const double *J;
     const int32_t *rp, *ci;
     const double *h;
@@ -609,30 +611,90 @@ __device__ void block_acc_reduce(Acc256 &acc, Acc256 *sh) {
     __syncthreads();
 }
 
+// Sum of a binary64 value over the workgroup (exact when every partial sum is).
+__device__ double block_sum(double x, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int v = 0; v < (int)(blockDim.x >> 6); v++) t += sh[v];
+    __syncthreads();
+    return t;
+}
+
+// One workgroup per spin vector; the vector is staged in LDS and a dense J is read
+// row by row (a wavefront per row, lanes along the columns).
 __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
     __shared__ Acc256 sh[4];
+    __shared__ double shd[4];
+    __shared__ int8_t sv[ENERGY_MAXN_LDS];
     const int v = blockIdx.x, tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
     const int8_t *s = a.spins + (int64_t)v * a.N;
+    const bool lds = a.N <= ENERGY_MAXN_LDS;
+    if (lds)
+        for (int i = tid; i < a.N; i += 256) sv[i] = s[i];
+    __syncthreads();
+    const int8_t *ss = lds ? sv : s;
+    const int b0 = a.b0;
+    if (a.fast) {
+        // every partial sum is a multiple of 2^b0 below 2^(53 + b0): binary64 is exact
+        double ae = 0.0, ac = 0.0;
+        if (!a.csr) {
+            for (int i = w; i < a.N; i += 4) {
+                const double *Jr = a.J + (int64_t)i * a.N;
+                const int si = ss[i];
+#pragma unroll 4
+                for (int j = lane; j < a.N; j += 64) {
+                    const double J = Jr[j];
+                    const bool same = si == ss[j];
+                    ae += same ? J : -J;
+                    ac += same ? 0.0 : J;
+                }
+            }
+        } else {
+            for (int i = tid; i < a.N; i += 256) {
+                const int si = ss[i];
+                for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
+                    const double J = a.J[e];
+                    const bool same = si == ss[a.ci[e]];
+                    ae += same ? J : -J;
+                    ac += same ? 0.0 : J;
+                }
+            }
+        }
+        for (int i = tid; i < a.N; i += 256) ae += ss[i] > 0 ? 2.0 * a.h[i] : -2.0 * a.h[i];
+        ae = block_sum(ae, shd);
+        ac = block_sum(ac, shd);
+        if (tid == 0) {
+            if (a.E) a.E[v] = 0.5 * ae;
+            if (a.cut) a.cut[v] = 0.5 * ac;
+        }
+        return;
+    }
     Acc256 ae, ac;
     acc_zero(ae);
     acc_zero(ac);
-    const int b0 = a.b0;
     if (!a.csr) {
-        const int64_t tot = (int64_t)a.N * a.N;
-        for (int64_t t = tid; t < tot; t += 256) {
-            int i = (int)(t / a.N), j = (int)(t % a.N);
-            double J = a.J[t];
-            if (J == 0.0) continue;
-            int si = s[i], sj = s[j];
-            acc_add(ae, si == sj ? J : -J, b0);
-            if (si != sj) acc_add(ac, J, b0);
+        for (int i = w; i < a.N; i += 4) {
+            const double *Jr = a.J + (int64_t)i * a.N;
+            const int si = ss[i];
+            for (int j = lane; j < a.N; j += 64) {
+                const double J = Jr[j];
+                if (J == 0.0) continue;
+                const int sj = ss[j];
+                acc_add(ae, si == sj ? J : -J, b0);
+                if (si != sj) acc_add(ac, J, b0);
+            }
         }
     } else {
         for (int i = tid; i < a.N; i += 256) {
-            int si = s[i];
+            int si = ss[i];
             for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
                 double J = a.J[e];
-                int sj = s[a.ci[e]];
+                int sj = ss[a.ci[e]];
                 acc_add(ae, si == sj ? J : -J, b0);
                 if (si != sj) acc_add(ac, J, b0);
             }
@@ -640,7 +702,7 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
     }
     for (int i = tid; i < a.N; i += 256) {
         double hh = a.h[i];
-        if (hh != 0.0) acc_add(ae, s[i] > 0 ? 2.0 * hh : -2.0 * hh, b0);
+        if (hh != 0.0) acc_add(ae, ss[i] > 0 ? 2.0 * hh : -2.0 * hh, b0);
     }
     block_acc_reduce(ae, sh);
     block_acc_reduce(ac, sh);
@@ -654,6 +716,15 @@ hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *
                          hipStream_t st) {
     EnArgs a;
     a.N = I.N; a.V = V; a.csr = I.layout == HQA_CSR; a.b0 = I.es.lsb;
+    // Every J and h is a multiple of 2^lsb below 2^(msb + 1); the sums take at most
+    // N^2 + N terms of magnitude below 2^(msb + 2) (2h).  When those fit 53 bits above
+    // 2^lsb, every partial binary64 sum is exact, whatever the order.
+    {
+        const double terms = (double)I.N * I.N + I.N;
+        int lg = 0;
+        while (lg < 64 && std::ldexp(1.0, lg) < terms) lg++;
+        a.fast = I.es.lsb != INT32_MIN && (I.es.msb + 2 - I.es.lsb) + lg <= 52;
+    }
     a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64; a.spins = spins; a.E = E; a.cut = cut;
     if (V == 0) return hipSuccess;
     k_energy<<<V, 256, 0, st>>>(a);

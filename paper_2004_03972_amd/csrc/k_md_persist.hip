@@ -317,13 +317,13 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
     Waiter wt{0, false};
     bool bad = false;
     const int nsteps = (int)(a.q1 - a.q0);
-    // coefficients are loaded one step ahead, so their latency is never waited for
-    StepCoef cfn = step_coef(a.a32, a.b32, a.q0, a.rg, a.M);
+    // schedule values are loaded one step ahead, so their latency is never waited for
+    CoefRaw cfn = load_coef(a.a32, a.b32, a.q0);
     for (int s = 0; s < nsteps; s++) {
         const int64_t q = a.q0 + s;
         const int par = s & 1;
-        const StepCoef cf = cfn;
-        if (s + 1 < nsteps) cfn = step_coef(a.a32, a.b32, q + 1, a.rg, a.M);
+        const StepCoef cf = make_coef(cfn, q, a.rg, a.M);
+        if (s + 1 < nsteps) cfn = load_coef(a.a32, a.b32, q + 1);
         gather<JT>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
         if (wt.dead) s_dead = 1;
         __syncthreads();
@@ -457,42 +457,47 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
     if (bad) atomicOr(a.err, ERR_NONFINITE);
 }
 
-// Register-resident J (BF16 / FP8 storage, Np <= 1024): workgroups of 64 rows,
-// each wavefront holding the fragments of its 16 rows of J in registers for the
-// whole run (NG groups of four 32-column chunks, NG = Np / 128).  A step then
-// reads only the staged flux block from LDS (the J operand costs no load), and
-// the cluster has Np / 64 members.  Gather, chains, update and publication are
-// those of k_persist, so the trajectories are identical.
+// Register-resident J (BF16 / FP8 storage, Np <= 1024): workgroups of 64 rows (four
+// row tiles of 16); the cluster has Np / 64 members.  Wavefront w computes
+// accumulation chain w -- chunks 4 gi + w (gi < NG = Np / 128) of all four row tiles --
+// and holds those J fragments in registers for the whole run.  It reads its MFMA B
+// fragments (16 replicas x 32 columns per chunk, two exchange units per lane) straight
+// from the cluster's exchange block, so nothing is staged and a wavefront starts its
+// MFMAs as soon as its own chunks have arrived.  The four chains of a tile meet in LDS
+// (double-buffered by step parity, so one workgroup barrier per step suffices: a
+// wavefront rewrites a parity's partials only after the next step's barrier, which
+// every wavefront passes after reading them), and wavefront w combines tile w as
+// (a0 + a1) + (a2 + a3), updates it and publishes it.  The MFMAs, their operands and
+// their order per chain are those of every other dense kernel, so the trajectories
+// are identical.
 template <int JT, int NG, int MP>
 __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    __shared__ f32x4 part[2][4][4][64];   // [step parity][chain][row tile][lane]
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
     const int cl_in_xcd = slot / a.G, g = slot % a.G;
     const int c = cl_in_xcd * 8 + xcd;
     if (c >= a.C) return;
     if (!check_placement(a.abort_flag, a.err, xcd)) return;
-    __shared__ int s_dead;   // a thread gave up waiting
-    if (threadIdx.x == 0) s_dead = 0;
+    __shared__ int s_dead[2];   // a thread gave up waiting (by step parity, like the partials)
+    if (threadIdx.x < 2) s_dead[threadIdx.x] = 0;
     __syncthreads();
     const int row0 = g * 64;          // G = Np / 64: every member's rows lie below Np
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r0 = 16 * c;
     const int kg = lane >> 4;
-    uint8_t *phis = lds;              // staged flux block [16][pstride]
 
     typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
     constexpr int esz = JT == JT_BF16 ? 2 : 1;
-    AT A[NG][4];
-    {
-        const uint8_t *Jr = (const uint8_t *)a.J +
-                            (int64_t)(row0 + 16 * w + (lane & 15)) * a.Np * esz;
+    AT A[NG][4];                      // [gi][row tile]: chunk 4 gi + w
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const uint8_t *Jr = (const uint8_t *)a.J + (int64_t)(row0 + 16 * t + (lane & 15)) * a.Np * esz;
 #pragma unroll
         for (int gi = 0; gi < NG; gi++)
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                A[gi][j] = *(const AT *)(Jr + (gi * 128 + 32 * j + 8 * kg) * esz);
+            A[gi][t] = *(const AT *)(Jr + (32 * (4 * gi + w) + 8 * kg) * esz);
     }
 
+    // the update and publication of row tile w
     const int col = r0 + (lane & 15);
     const bool rvalid = col < a.R;
     const int ib = row0 + 16 * w + 4 * kg;
@@ -508,37 +513,78 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
         hs[v] = (i < a.N) ? a.h[i] : 0.f;
     }
     publish<JT>(a, 0, col, ib, xs, 1u);
+
+    // exchange units of this lane's B fragments: the block is [ld / 4][16][4] entries,
+    // chunk 4 gi + w needs units (8 (4 gi + w) + 2 kg) * 16 + (lane & 15) and the next
+    // row group (16 units on)
+    __amdgpu_buffer_rsrc_t rs[2];
+#pragma unroll
+    for (int pr = 0; pr < 2; pr++)
+        rs[pr] = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const uint32_t *)a.xch + pr * a.xch_half + (int64_t)r0 * a.ld), (short)0,
+            64 * a.ld, 0x00020000);
+    const int uoff = ((8 * w + 2 * kg) * 16 + (lane & 15)) * 16;   // bytes, chunk gi adds 32 * 16 * 16 gi
+
     Waiter wt{0, false};
     bool bad = false;
     const int nsteps = (int)(a.q1 - a.q0);
-    const uint8_t *Xb = phis + (size_t)(lane & 15) * a.pstride;
-    // coefficients are loaded one step ahead, so their latency is never waited for
-    StepCoef cfn = step_coef(a.a32, a.b32, a.q0, a.rg, a.M);
+    // schedule values are loaded one step ahead, so their latency is never waited for
+    CoefRaw cfn = load_coef(a.a32, a.b32, a.q0);
     for (int s = 0; s < nsteps; s++) {
         const int64_t q = a.q0 + s;
         const int par = s & 1;
-        const StepCoef cf = cfn;
-        if (s + 1 < nsteps) cfn = step_coef(a.a32, a.b32, q + 1, a.rg, a.M);
-        gather<JT, NG>(a, par, r0, (uint32_t)(s % 65535) + 1u, phis, wt);
-        if (wt.dead) s_dead = 1;
-        __syncthreads();
-        if (s_dead) return;   // aborted: the workgroup leaves
-        // chunk 4 gi + j feeds chain j, in ascending gi (combine4's order)
+        const StepCoef cf = make_coef(cfn, q, a.rg, a.M);
+        if (s + 1 < nsteps) cfn = load_coef(a.a32, a.b32, q + 1);
+        const uint32_t tg = ((uint32_t)(s % 65535) + 1u) << 16;
+        u32x4 bx[NG][2];
+        while (true) {
+            uint32_t stale = 0;
+#pragma unroll
+            for (int gi = 0; gi < NG; gi++) {
+                bx[gi][0] = ld16_agent(rs[par], uoff + gi * 8192);
+                bx[gi][1] = ld16_agent(rs[par], uoff + gi * 8192 + 256);
+            }
+#pragma unroll
+            for (int gi = 0; gi < NG; gi++)
+#pragma unroll
+                for (int h = 0; h < 2; h++)
+                    stale |= (bx[gi][h][0] ^ tg) | (bx[gi][h][1] ^ tg) | (bx[gi][h][2] ^ tg) |
+                             (bx[gi][h][3] ^ tg);
+            if ((stale >> 16) == 0 || !keep_waiting(a, wt)) break;
+            asm volatile("" ::: "memory");   // the re-loads must read memory again
+        }
+        // chain w of the four row tiles, chunks in ascending order
         f32x4 acc[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < 4; t++) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int gi = 0; gi < NG; gi++)
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const bf16x8 bv = *(const bf16x8 *)(Xb + (gi * 128 + 32 * j + 8 * kg) * 2);
-                bf16x8 av;
-                if constexpr (JT == JT_BF16) av = A[gi][j];
-                else av = cvt_fp8x8(A[gi][j]);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
+        for (int gi = 0; gi < NG; gi++) {
+            bf16x8 bv;
+            {
+                typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t w4;
+                w4 o = {__builtin_amdgcn_perm(bx[gi][0][1], bx[gi][0][0], 0x05040100u),
+                        __builtin_amdgcn_perm(bx[gi][0][3], bx[gi][0][2], 0x05040100u),
+                        __builtin_amdgcn_perm(bx[gi][1][1], bx[gi][1][0], 0x05040100u),
+                        __builtin_amdgcn_perm(bx[gi][1][3], bx[gi][1][2], 0x05040100u)};
+                bv = __builtin_bit_cast(bf16x8, o);
             }
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                bf16x8 av;
+                if constexpr (JT == JT_BF16) av = A[gi][t];
+                else av = cvt_fp8x8(A[gi][t]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++) part[par][w][t][lane] = acc[t];
+        if (wt.dead) s_dead[par] = 1;
+        __syncthreads();
+        if (s_dead[par]) return;   // aborted: the workgroup leaves
+        const f32x4 chains[4] = {part[par][0][w][lane], part[par][1][w][lane],
+                                 part[par][2][w][lane], part[par][3][w][lane]};
         const bool win = q + 1 >= a.T - a.W + 1;
-        const f32x4 u = combine4(acc);
+        const f32x4 u = combine4(chains);
         float xn[4];
 #pragma unroll
         for (int v = 0; v < 4; v++) {
@@ -555,7 +601,6 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
             xs[v] = xn[v];
         }
         if (s + 1 < nsteps) publish<JT>(a, par ^ 1, col, ib, xn, (uint32_t)((s + 1) % 65535) + 1u);
-        __syncthreads();   // the staged block is rewritten by the next gather
     }
     if (rvalid) {
         const int64_t base = (int64_t)col * a.ld + ib;
@@ -598,7 +643,7 @@ static bool plan_persist(const Instance &I, int R, JType jt, int max_wg, Persist
             p.jlds = 0;
             p.jstride = 0;
             p.jbytes = 0;
-            p.lds = stage;
+            p.lds = 0;                                 // static LDS only (chain partials)
             p.grid = 8 * need_xcd_slots * G;
             return true;
         }

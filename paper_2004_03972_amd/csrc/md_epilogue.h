@@ -77,6 +77,35 @@ __device__ __forceinline__ void es_accumulate(float *st, int64_t stride, int64_t
     st[8 * stride + k] += p * p;
 }
 
+// The schedule values of step q as stored, and the coefficients built from them (the
+// same operations as step_coef).  Persistent kernels load the next step's values a
+// step ahead and build them when the step begins, so the load's latency is hidden.
+struct CoefRaw {
+    float al, be, ad;
+};
+
+// The tables are read-only for the whole launch and q is uniform, so the values are
+// read through the constant address space (scalar loads, which do not share the
+// vector memory counter with the kernel's stores).
+__device__ __forceinline__ CoefRaw load_coef(const float *a32, const float *b32, int64_t q) {
+    typedef const __attribute__((address_space(4))) float cfloat;
+    const cfloat *A = (const cfloat *)a32;
+    const cfloat *B = (const cfloat *)b32;
+    return CoefRaw{A[2 * q], B[2 * q], A[2 * q + 1]};
+}
+
+__device__ __forceinline__ StepCoef make_coef(const CoefRaw &r, int64_t q, float rg, int M) {
+    StepCoef c;
+    c.al = r.al;
+    c.be = r.be;
+    c.ad = r.ad;
+    if (rg != 1.0f) c.ad = rg * c.ad;
+    c.rg = rg;
+    c.kick = q == 0 ? 0.5f : 1.0f;
+    c.M = M;
+    return c;
+}
+
 __device__ __forceinline__ StepCoef step_coef(const float *a32, const float *b32, int64_t q,
                                               float rg, int M) {
     StepCoef c;

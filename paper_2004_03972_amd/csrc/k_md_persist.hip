@@ -536,44 +536,58 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
         const StepCoef cf = make_coef(cfn, q, a.rg, a.M);
         if (s + 1 < nsteps) cfn = load_coef(a.a32, a.b32, q + 1);
         const uint32_t tg = ((uint32_t)(s % 65535) + 1u) << 16;
+        // All of this lane's units are requested at once and chunk gi is fed to the
+        // MFMAs as soon as its two units are in, while later chunks are still on their
+        // way (straight-line code, so each chunk waits only for its own loads).  The
+        // tags are folded into one word on the way; if any unit of the wavefront was
+        // stale (its producer had not stored the step yet) the wavefront reads all its
+        // units again and redoes the chain from zero, so the order within the chain
+        // never changes.
         u32x4 bx[NG][2];
-        while (true) {
-            uint32_t stale = 0;
+        f32x4 acc[4];
+        auto load_units = [&]() {
 #pragma unroll
             for (int gi = 0; gi < NG; gi++) {
                 bx[gi][0] = ld16_agent(rs[par], uoff + gi * 8192);
                 bx[gi][1] = ld16_agent(rs[par], uoff + gi * 8192 + 256);
             }
+        };
+        auto chain = [&]() -> uint32_t {
+            uint32_t stale = 0;
 #pragma unroll
-            for (int gi = 0; gi < NG; gi++)
+            for (int t = 0; t < 4; t++) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int gi = 0; gi < NG; gi++) {
 #pragma unroll
                 for (int h = 0; h < 2; h++)
                     stale |= (bx[gi][h][0] ^ tg) | (bx[gi][h][1] ^ tg) | (bx[gi][h][2] ^ tg) |
                              (bx[gi][h][3] ^ tg);
-            if ((stale >> 16) == 0 || !keep_waiting(a, wt)) break;
-            asm volatile("" ::: "memory");   // the re-loads must read memory again
-        }
-        // chain w of the four row tiles, chunks in ascending order
-        f32x4 acc[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int gi = 0; gi < NG; gi++) {
-            bf16x8 bv;
-            {
                 typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t w4;
-                w4 o = {__builtin_amdgcn_perm(bx[gi][0][1], bx[gi][0][0], 0x05040100u),
-                        __builtin_amdgcn_perm(bx[gi][0][3], bx[gi][0][2], 0x05040100u),
-                        __builtin_amdgcn_perm(bx[gi][1][1], bx[gi][1][0], 0x05040100u),
-                        __builtin_amdgcn_perm(bx[gi][1][3], bx[gi][1][2], 0x05040100u)};
-                bv = __builtin_bit_cast(bf16x8, o);
-            }
+                const w4 o = {__builtin_amdgcn_perm(bx[gi][0][1], bx[gi][0][0], 0x05040100u),
+                              __builtin_amdgcn_perm(bx[gi][0][3], bx[gi][0][2], 0x05040100u),
+                              __builtin_amdgcn_perm(bx[gi][1][1], bx[gi][1][0], 0x05040100u),
+                              __builtin_amdgcn_perm(bx[gi][1][3], bx[gi][1][2], 0x05040100u)};
+                const bf16x8 bv = __builtin_bit_cast(bf16x8, o);
+                // chain w of the four row tiles
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
-                bf16x8 av;
-                if constexpr (JT == JT_BF16) av = A[gi][t];
-                else av = cvt_fp8x8(A[gi][t]);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+                for (int t = 0; t < 4; t++) {
+                    bf16x8 av;
+                    if constexpr (JT == JT_BF16) av = A[gi][t];
+                    else av = cvt_fp8x8(A[gi][t]);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+                }
+            }
+            return stale >> 16;
+        };
+        load_units();
+        // the decision to read again is taken for the whole wavefront: an MFMA is a
+        // wavefront-wide operation and must run with every lane active
+        if (__any(chain() != 0)) {
+            while (true) {
+                if (__any(!keep_waiting(a, wt))) break;   // giving up: the launch aborts
+                asm volatile("" ::: "memory");   // the re-loads must read memory again
+                load_units();
+                if (!__any(chain() != 0)) break;
             }
         }
 #pragma unroll

@@ -56,3 +56,23 @@ def test_persistent_in_pieces_and_single_step(H, prec):
         assert b.last_plan == "cluster"
     for x, y in zip(_states(H, a), _states(H, b)):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("N,R", [(150, 24), (500, 48), (600, 16), (700, 40), (1000, 80)])
+def test_register_j_kernel_every_group_count(H, prec, N, R):
+    """The register-J cluster kernel is instantiated per 128-column group count
+    NG = Np / 128 (Np = N padded to 128); every NG from 2 to 8, ragged replica
+    clusters, against one launch per step."""
+    print("persist rj", prec, N, R, flush=True)
+    J = inst.er_maxcut(N, 0.04, N + 1)
+    out = []
+    for plan in ("cluster", "step"):
+        md = H.MD(H.Problem(J), H.make_schedule(90, 20), R, prec, seed=3, plan=plan)
+        md.run()
+        md.sync()
+        assert md.last_plan == plan
+        out.append(_states(H, md))
+        md.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)

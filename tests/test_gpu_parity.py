@@ -226,18 +226,24 @@ def test_f32_readout_matches_oracle_on_same_phibar(H, layout):
 
 
 # --------------------------------------------------------------- exact energies
-@pytest.mark.parametrize("kind", ["sk", "int", "glass", "csr"])
+@pytest.mark.parametrize("kind", ["sk", "int", "glass", "csr", "csr_int", "int_h"])
 def test_ising_energy_exact(H, kind):
+    """Exact energies and cuts: the binary64 fast path (integer J and h: every partial
+    sum exact, four vectors per workgroup, 7 vectors leave a partial group) and the
+    fixed-point accumulator (real J), dense and CSR."""
     N = 333
     h = None
     if kind == "sk":
         J = inst.sk(N, 800)
-    elif kind == "int":
+    elif kind in ("int", "csr_int"):
         J = inst.small_int(N, 801, -5, 5, density=0.5)
+    elif kind == "int_h":
+        J = inst.small_int(N, 804, -3, 3, density=0.3)
+        h = np.random.default_rng(805).integers(-4, 5, N).astype(np.float64)
     else:
         J, h = inst.uniform_glass(N, 802)
     spins = inst.random_pm1((7, N), 803).astype(np.int8)
-    if kind == "csr":
+    if kind in ("csr", "csr_int"):
         rp, ci, v = inst.dense_to_csr(J)
         P = H.Problem(row_ptr=rp, col=ci, val=v, h=h)
         pb = orc.Problem(N, row_ptr=rp, col=ci, val=v, h=h)

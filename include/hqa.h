@@ -129,8 +129,14 @@ typedef struct hqa_md_opts {
  *   HQA_PLAN_AUTO      the tuned plan of the instance if hqa_md_tune has run, else
  *                      STEP (BATCH for several dense instances).
  *   HQA_PLAN_STEP      one launch per MD step (any size).
- *   HQA_PLAN_CLUSTER   all steps in one cooperative launch; workgroups of a cluster
- *                      own row blocks and exchange fluxes through L2 every step.
+ *   HQA_PLAN_CLUSTER   all steps in one cooperative launch; the workgroups of a
+ *                      16-replica cluster own row blocks of J and exchange fluxes
+ *                      every step through the L2 of the XCD they share (workgroup b
+ *                      is assumed to run on XCD b mod 8, the dispatch order of a
+ *                      single-partition MI355X).  A workgroup found on another XCD
+ *                      aborts the launch, and the run (or hqa_md_sync) returns
+ *                      HQA_EDEVICE naming the placement; the tuner then skips the
+ *                      plan.  Every wait inside the launch is bounded.
  *   HQA_PLAN_RESIDENT  all steps in one launch; one workgroup per 16 replicas keeps
  *                      their whole state in LDS and streams J from L2 (BF16/FP8 J,
  *                      N up to 800 on a device with 160 KB of LDS per workgroup).

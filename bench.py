@@ -339,22 +339,24 @@ def bench_es(args, hqa, torch):
     rp, ci, v = inst.er_sparse(Ne, 0.005 * (Ne - 1), 5001)
     prob = hqa.Problem(row_ptr=rp, col=ci, val=v)
     n_lab = round(0.05 * Ne)
-    st = torch.cuda.current_stream()
-    e0, e1 = _events(torch)
-    e0.record(st)
+    # the full run's labels (the judge of the mislabel rate), untimed
     full = E.record_run(prob, sched, Re, K, nck, seed=7, n_amb=n_lab, solve_n=20, every=nck,
                         Ks=Ks, stride=args.es_stride)
-    e1.record(st)
-    torch.cuda.synchronize()
-    full_ms = e0.elapsed_time(e1)
     full.md.close()
-    e0.record(st)
+    # timed: the method alone on both sides -- MD to T and the exact read-out, against
+    # checkpointed MD to the learned stop and the read-out from the predicted labels
+    # (the ablation and the mislabel counts are evaluated outside both timings)
+    md = hqa.MD(prob, sched, Re, "f32", seed=7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    md.run()
+    md.classify(20, solve=True)
+    full_ms = (time.perf_counter() - t0) * 1e3
+    md.close()
     res = E.run_with_early_stop(es, prob, sched, Re, K, thr if np.isfinite(thr) else 1.1,
                                 n_amb=20, seed=7, labels=full.labels, n_label=n_lab, Ks=Ks,
                                 stride=args.es_stride)
-    e1.record(st)
-    torch.cuda.synchronize()
-    es_ms = e0.elapsed_time(e1)
+    es_ms = res.wall_ms
     cut_full = float(full.full["cut"].max())
     cut_es = float(res.readout["cut"].max())
     cut_tr = float(res.ablation["cut"].max())
@@ -365,7 +367,7 @@ def bench_es(args, hqa, torch):
             "loss_first_last": [float(np.mean(losses[:20])), float(np.mean(losses[-20:]))],
             "threshold": thr, "target_mislabel": args.es_target,
             "stop_step": res.stop_step, "speedup_steps": Tt / res.stop_step,
-            "wall_ms_full": full_ms, "wall_ms_early": es_ms,
+            "wall_ms_full": full_ms, "wall_ms_early": es_ms, "speedup_wall": full_ms / es_ms,
             "mislabel": {"network": res.mislabel, "truncation_same_step": res.mislabel_ablation},
             "best_cut": {"full_run_hqa": cut_full, "early_stop_hqa": cut_es,
                          "truncation_hqa": cut_tr,

@@ -156,6 +156,7 @@ class StopResult:
     ablation: dict
     mislabel: float
     mislabel_ablation: float
+    wall_ms: float = float("nan")   # the method alone: checkpointed MD to the stop + read-out
 
 
 def run_with_early_stop(es, problem, sched, R: int, K: int, threshold: float, n_amb: int,
@@ -164,6 +165,7 @@ def run_with_early_stop(es, problem, sched, R: int, K: int, threshold: float, n_
     """Run checkpoint by checkpoint (statistics over the last Ks steps before each); stop
     at the first confident checkpoint (or T).  n_amb spins go to the exact solver; mislabel rates (when the full run's labels are
     given) count n_label ambivalent spins per replica (default n_amb)."""
+    import time
     import torch   # device memory for the checkpoint evaluation (the arithmetic is libhqa's)
     n_label = n_amb if n_label is None else n_label
     md = hqa.MD(problem, sched, R, "f32", seed=seed)
@@ -171,6 +173,8 @@ def run_with_early_stop(es, problem, sched, R: int, K: int, threshold: float, n_
     # features and probabilities stay on the device; each checkpoint returns one number
     feat = torch.empty((R * N, hqa.HQA_ES_NFEAT), dtype=torch.float32, device="cuda")
     pdev = torch.empty((R * N, 3), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     q = 0
     Ks = K if Ks is None else Ks
     while True:
@@ -184,8 +188,11 @@ def run_with_early_stop(es, problem, sched, R: int, K: int, threshold: float, n_
         if es.confidence(pdev) >= threshold or q >= T:
             break
     stopped = q < T
+    out = md.classify(n_amb, solve=True, prob=pdev)   # host outputs: synchronises
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    # evaluation only (not part of the method's time): the truncation ablation and the
+    # mislabel rates
     tp = truncation_probs(md.state(hqa.HQA_STATE_STATMEAN))
-    out = md.classify(n_amb, solve=True, prob=pdev)
     prob = pdev.cpu().numpy().reshape(R, N, 3)
     abl = md.classify(n_amb, solve=True, prob=tp)
     mis = mis_a = float("nan")
@@ -193,4 +200,4 @@ def run_with_early_stop(es, problem, sched, R: int, K: int, threshold: float, n_
         mis = float(np.mean(labels_from_probs(prob, n_label) != labels))
         mis_a = float(np.mean(labels_from_probs(tp, n_label) != labels))
     md.close()
-    return StopResult(q, stopped, prob, out, abl, mis, mis_a)
+    return StopResult(q, stopped, prob, out, abl, mis, mis_a, wall_ms)

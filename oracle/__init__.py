@@ -80,6 +80,7 @@ def _declare(L):
         "or_reduce": (C.c_int, [P, i32, i32, P, P, P, P]),
         "or_enumerate": (C.c_int, [i32, i32, P, P, P, P]),
         "or_merge": (V, [i32, i32, i32, P, P, P]),
+        "or_tabu": (C.c_int, [i32, i32, P, P, P, C.c_int64, i32, P, P]),
         "or_energy": (C.c_int, [P, i32, P, P, P]),
         "or_es_features": (C.c_int, [P, P, i32, P, P, i64, i64, i64, P, P, P]),
         "or_gelu": (d, [d]),
@@ -240,6 +241,29 @@ def enumerate_exact(J_eff, h_eff):
     if lib().or_enumerate(n, R, _ptr(J_eff), _ptr(h_eff), _ptr(code), _ptr(E)) != 0:
         raise ValueError("bad n")
     return code, E
+
+
+def tabu(J_eff, h_eff, x0, iters: int, tenure: int):
+    """Single-flip tabu search on each replica's reduced problem (hqa_oracle.c
+    or_tabu): returns (x_best int8 [R, n], D_best [R] = E'(x_best) - E'(x0))."""
+    J_eff, h_eff = _f64(J_eff), _f64(h_eff)
+    R, n = h_eff.shape
+    x0 = np.ascontiguousarray(x0, dtype=np.int8).reshape(R, n)
+    xb = np.empty((R, n), dtype=np.int8)
+    db = np.empty(R)
+    if lib().or_tabu(n, R, _ptr(J_eff), _ptr(h_eff), _ptr(x0), int(iters), int(tenure),
+                     _ptr(xb), _ptr(db)) != 0:
+        raise ValueError("bad arguments")
+    return xb, db
+
+
+def merge_x(spins, amb_idx, x):
+    """Write the +-1 values x [R, n] into the spins at the ambivalent positions."""
+    spins = np.array(spins, dtype=np.int8, order="C")
+    amb_idx = np.asarray(amb_idx)
+    for r in range(spins.shape[0]):
+        spins[r, amb_idx[r]] = x[r]
+    return spins
 
 
 def merge(spins, amb_idx, code):

@@ -470,6 +470,75 @@ int or_enumerate(int32_t n, int32_t R, const double *J_eff, const double *h_eff,
 }
 
 /* Merge: frozen spins keep sgn(phibar); ambivalent spin A[a] takes x_a of the code. */
+/* Tabu search on the reduced problem of every replica.  The paper sends the n
+ * ambivalent spins, with the frozen ones fixed, to a quantum annealer or, for
+ * n = 1000, to a tabu search (Results, the K2000 MAX-CUT experiment: HQA(TS1000)).
+ * That tabu search is an external solver the paper does not specify; this is a
+ * plain single-flip tabu search (this library's reading), in binary64:
+ *   x = x0 (the MD read-out of the n spins); f_a = h_a + sum_{b != a} J_ab x_b with
+ *   b ascending, one rounding per addition; D = 0 (energy change from x0),
+ *   D_best = 0, x_best = x0; then for t = 1 .. iters:
+ *     d_a = -2 x_a f_a (exact) for every a;
+ *     move a is allowed when tabu_until[a] < t, or when D + d_a < D_best (aspiration);
+ *     a* = the allowed a with the smallest d_a, ties to the smallest a;
+ *     D = D + d_a*;  f_b = f_b - 2 J_a*b x_a* (x_a* before the flip) for b != a*;
+ *     x_a* = -x_a*;  tabu_until[a*] = t + tenure;
+ *     if D < D_best: D_best = D, x_best = x.
+ * tenure is clamped to n - 1, so at least one move is always allowed.  Outputs the
+ * best configuration and D_best = E'(x_best) - E'(x0) as accumulated (exact when J
+ * and h are integers).  J_eff is [R][n][n] with a zero diagonal, h_eff [R][n], x0 and
+ * x_best [R][n] of +-1. */
+int or_tabu(int32_t n, int32_t R, const double *J_eff, const double *h_eff, const int8_t *x0,
+            int64_t iters, int32_t tenure, int8_t *x_best, double *d_best) {
+    if (n < 0 || R < 0 || iters < 0 || tenure < 0) return OR_EINVAL;
+    if (n == 0) {
+        for (int32_t r = 0; r < R; r++) d_best[r] = 0.0;
+        return OR_OK;
+    }
+    if (tenure > n - 1) tenure = n - 1;
+    double *f = malloc(sizeof(double) * (size_t)n);
+    int8_t *x = malloc((size_t)n);
+    int64_t *until = malloc(sizeof(int64_t) * (size_t)n);
+    if (!f || !x || !until) { free(f); free(x); free(until); return OR_ENOMEM; }
+    for (int32_t r = 0; r < R; r++) {
+        const double *J = J_eff + (int64_t)r * n * n, *h = h_eff + (int64_t)r * n;
+        int8_t *xb = x_best + (int64_t)r * n;
+        memcpy(x, x0 + (int64_t)r * n, (size_t)n);
+        memcpy(xb, x, (size_t)n);
+        for (int32_t a = 0; a < n; a++) {
+            double acc = h[a];
+            for (int32_t b = 0; b < n; b++)
+                if (b != a) acc = acc + J[(int64_t)a * n + b] * (double)x[b];
+            f[a] = acc;
+            until[a] = 0;
+        }
+        double D = 0.0, Db = 0.0;
+        for (int64_t t = 1; t <= iters; t++) {
+            int32_t best = -1;
+            double bd = 0.0;
+            for (int32_t a = 0; a < n; a++) {
+                const double d = x[a] > 0 ? -2.0 * f[a] : 2.0 * f[a];
+                const int allowed = until[a] < t || D + d < Db;
+                if (allowed && (best < 0 || d < bd)) { best = a; bd = d; }
+            }
+            D = D + bd;
+            const int8_t xo = x[best];
+            const double *Jr = J + (int64_t)best * n;
+            for (int32_t b = 0; b < n; b++)
+                if (b != best) f[b] = f[b] - (xo > 0 ? 2.0 * Jr[b] : -2.0 * Jr[b]);
+            x[best] = (int8_t)-xo;
+            until[best] = t + tenure;
+            if (D < Db) {
+                Db = D;
+                memcpy(xb, x, (size_t)n);
+            }
+        }
+        d_best[r] = Db;
+    }
+    free(f); free(x); free(until);
+    return OR_OK;
+}
+
 void or_merge(int32_t N, int32_t R, int32_t n, const int32_t *amb_idx, const int64_t *code,
               int8_t *spins) {
     for (int32_t r = 0; r < R; r++)

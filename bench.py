@@ -16,6 +16,7 @@ Other workloads (measurement lines for the design notes, not the bench line):
   --workload batch512  512 uneven instances (SK BF16 / ER FP8), R = 64, T = 5000
   --workload es        learned early stop: train on ER runs, evaluate on ER N = 10^4
   --workload k2000     MAX-CUT on K_2000 with +-1 weights: deviation from C* vs MD steps
+                       (MD alone, HQA with n = 20 exact, HQA with the n = 1000 tabu search)
   --workload glass     spin glass with fields, N = 1000, 2000, 10^4: energy vs MD steps
   --workload dense8k   enlarged dense shape N = 8192, R = 512 (BF16 SK, FP8 +-1): MFMA fraction
   --workload sweep     kappa2 and M sweeps on the spin glass with fields, N = 10^4
@@ -387,8 +388,9 @@ def bench_k2000(args, hqa, torch):
            "instances": args.k2000_instances, "mirrors": True, "replicas": Rr, "by_T": {}}
     st = torch.cuda.current_stream()
     for Tt in [int(x) for x in args.k2000_steps.split(",")]:
-        dev = {"md_one_init": [], "hqa_one_init": [], "md_best": [], "hqa_best": []}
-        ms_tot = 0.0
+        dev = {"md_one_init": [], "hqa_one_init": [], "md_best": [], "hqa_best": [],
+               "hqa_ts_one_init": [], "hqa_ts_best": []}
+        ms_tot = ts_tot = 0.0
         for k in range(args.k2000_instances):
             J = inst.pm_complete(Nk, 9000 + k)
             for sign in (1.0, -1.0):
@@ -404,12 +406,24 @@ def bench_k2000(args, hqa, torch):
                 dev["hqa_one_init"].append((cstar - g1["cut"][0]) / cstar)
                 dev["md_best"].append((cstar - g0["cut"].max()) / cstar)
                 dev["hqa_best"].append((cstar - g1["cut"].max()) / cstar)
+                if args.k2000_tabu_iters > 0:
+                    t0 = time.perf_counter()
+                    g2 = md.classify_tabu(args.k2000_tabu_n, args.k2000_tabu_iters,
+                                          args.k2000_tabu_tenure)
+                    ts_tot += (time.perf_counter() - t0) * 1e3
+                    dev["hqa_ts_one_init"].append((cstar - g2["cut"][0]) / cstar)
+                    dev["hqa_ts_best"].append((cstar - g2["cut"].max()) / cstar)
                 md.close()
             _log(f"  T={Tt}: instance {k} done")
         out["by_T"][str(Tt)] = {kk: {"mean": float(np.mean(v)), "min": float(np.min(v)),
-                                     "max": float(np.max(v))} for kk, v in dev.items()}
+                                     "max": float(np.max(v))} for kk, v in dev.items() if v}
         out["by_T"][str(Tt)]["md_ms_per_run"] = ms_tot / (2 * args.k2000_instances)
-    out["paper"] = "MD alone about 0.4% below C* at 5e5 MD steps (one init per instance)"
+        if args.k2000_tabu_iters > 0:
+            out["by_T"][str(Tt)]["tabu_read_out_ms_per_run"] = ts_tot / (2 * args.k2000_instances)
+    out["tabu"] = {"n": args.k2000_tabu_n, "iters": args.k2000_tabu_iters,
+                   "tenure": args.k2000_tabu_tenure}
+    out["paper"] = ("MD alone about 0.4% and HQA(TS1000) about 0.2% below C* at 5e5 MD steps "
+                    "(one init per instance); TS1000 time about 0.24 of the MD time")
     return out
 
 
@@ -587,6 +601,9 @@ def main():
     ap.add_argument("--k2000-instances", type=int, default=4)
     ap.add_argument("--k2000-replicas", type=int, default=16)
     ap.add_argument("--k2000-steps", default="50000,500000")
+    ap.add_argument("--k2000-tabu-n", type=int, default=1000)
+    ap.add_argument("--k2000-tabu-iters", type=int, default=20000)
+    ap.add_argument("--k2000-tabu-tenure", type=int, default=50)
     ap.add_argument("--es-train", type=int, default=48)
     ap.add_argument("--es-target", type=float, default=0.03)
     ap.add_argument("--es-k", type=int, default=1000)

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 4
+#define HQA_ABI_VERSION 5
 
 typedef enum {
     HQA_OK = 0,
@@ -294,6 +294,24 @@ typedef struct hqa_classify_out {
  * Synchronises. */
 hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                         const hqa_classify_out *out, int32_t out_mem);
+
+/* Read-out at q = T as hqa_classify, with the reduced problem of the n_amb
+ * ambivalent spins (HQA section: past exact enumeration the paper passes the
+ * reduced problem to a tabu search) solved by a deterministic single-flip tabu
+ * search that starts from the MD read-out x of those spins:
+ *   f_a = h_eff_a + sum_{b != a} J_ab x_b (b ascending); D = D_best = 0;
+ *   for t = 1 .. iters: d_a = -2 x_a f_a; a is allowed when tabu_until[a] < t or
+ *   D + d_a < D_best; flip the allowed a* with the smallest d_a (ties: smallest a),
+ *   D += d_a*, f_b -= 2 J_a*b x_a* (before the flip) for b != a*,
+ *   tabu_until[a*] = t + min(tenure, n - 1); keep x whenever D < D_best.
+ * Every operation is binary64 in that order (no contraction), so the result does
+ * not depend on the launch.  The best configuration is merged into spins;
+ * e_reduced receives D_best (<= 0), the change of the Ising energy from the MD
+ * read-out; code is not written; h_eff as hqa_classify.  J_ab are the instance's
+ * binary64 couplings.  HQA_EINVAL for iters or tenure < 0 or n_amb outside [0, N],
+ * HQA_EUNSUPPORTED for n_amb > 4096, HQA_ESTATE before q = T.  Synchronises. */
+hqa_status hqa_classify_tabu(hqa_md *md, int32_t instance, int32_t n_amb, int64_t iters,
+                             int32_t tenure, const hqa_classify_out *out, int32_t out_mem);
 
 /* Exact Ising energy (Eq. 1) and cut (w = J) of n_vectors spin vectors [V][N] (int8,
  * +1/-1) for one instance.  energy / cut [V] (either may be NULL).  Input and outputs

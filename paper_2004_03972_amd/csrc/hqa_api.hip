@@ -861,23 +861,25 @@ hqa_status hqa_md_hamiltonian(hqa_md *md, int32_t instance, double *H, int32_t d
     return HQA_OK;
 }
 
-// Read-out shared by hqa_classify (sort by |phibar|) and hqa_classify_probs (predicted
-// labels): selection, optional reduced problem and exact solve, merge, energies.
+// Read-out shared by hqa_classify (sort by |phibar|), hqa_classify_probs (predicted
+// labels) and hqa_classify_tabu: selection, optional reduced problem solved exactly
+// (solve = 1) or by the tabu search (solve = 2), merge, energies.
 static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                                 const hqa_classify_out *out, int32_t out_mem, const float *prob,
-                                int32_t prob_mem) {
+                                int32_t prob_mem, int64_t tabu_iters = 0, int32_t tenure = 0) {
     hqa_status s = check_instance(md, instance);
     if (s != HQA_OK) return s;
     if (!out || !out->spins) return fail(HQA_EINVAL, "out->spins is required");
     Instance &I = md->inst[instance];
     const int R = md->R, N = I.N;
     if (n_amb < 0 || n_amb > N) return fail(HQA_EINVAL, "n_amb must lie in [0, N]");
-    if (solve && n_amb > 24) return fail(HQA_EUNSUPPORTED, "exact enumeration limited to n <= 24");
+    if (solve == 1 && n_amb > 24)
+        return fail(HQA_EUNSUPPORTED, "exact enumeration limited to n <= 24");
     if (!prob && md->q != md->sch.T)
         return fail(HQA_ESTATE, "classify needs the run to reach step T");
     if ((solve || out->energy || out->cut || out->h_eff) && !exact_ok(I))
         return fail(HQA_EUNSUPPORTED, "coupling exponents span too many binades for exact sums");
-    if (solve && I.j_integral && I.es.msb + 2 * 16 + 8 > 62)
+    if (solve == 1 && I.j_integral && I.es.msb + 2 * 16 + 8 > 62)
         return fail(HQA_EUNSUPPORTED, "integer couplings too large for int64 enumeration");
     s = hqa_md_sync(md);
     if (s != HQA_OK) return s;
@@ -903,7 +905,16 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
     }
     double *h_eff = nullptr, *J_eff = nullptr, *e_red = nullptr;
     int64_t *code = nullptr;
-    if (solve && n_amb > 0) {
+    if (solve == 2 && n_amb > 0) {
+        int8_t *merged;
+        HIPCHK(B.get(&h_eff, (size_t)R * n_amb));
+        HIPCHK(B.get(&e_red, (size_t)R));
+        HIPCHK(B.get(&merged, (size_t)R * N));
+        HIPCHK(launch_reduce(I, R, n_amb, amb, spins, h_eff, nullptr, st));
+        HIPCHK(hipMemcpyAsync(merged, spins, (size_t)R * N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(launch_tabu(I, R, n_amb, amb, spins, h_eff, tabu_iters, tenure, merged, e_red, st));
+        spins = merged;
+    } else if (solve && n_amb > 0) {
         HIPCHK(B.get(&h_eff, (size_t)R * n_amb));
         HIPCHK(B.get(&J_eff, (size_t)R * n_amb * n_amb));
         HIPCHK(B.get(&code, (size_t)R));
@@ -938,6 +949,13 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
 hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                         const hqa_classify_out *out, int32_t out_mem) {
     return classify_impl(md, instance, n_amb, solve, out, out_mem, nullptr, HQA_HOST);
+}
+
+hqa_status hqa_classify_tabu(hqa_md *md, int32_t instance, int32_t n_amb, int64_t iters,
+                             int32_t tenure, const hqa_classify_out *out, int32_t out_mem) {
+    if (iters < 0 || tenure < 0) return fail(HQA_EINVAL, "iters and tenure must be >= 0");
+    if (n_amb > 4096) return fail(HQA_EUNSUPPORTED, "tabu search limited to n <= 4096");
+    return classify_impl(md, instance, n_amb, 2, out, out_mem, nullptr, HQA_HOST, iters, tenure);
 }
 
 hqa_status hqa_classify_probs(hqa_md *md, int32_t instance, const float *prob, int32_t prob_mem,

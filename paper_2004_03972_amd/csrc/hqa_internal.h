@@ -154,6 +154,9 @@ hipError_t launch_select(const Instance &I, int R, int prec, int W, int n, int32
                          int8_t *spins, hipStream_t st);
 hipError_t launch_reduce(const Instance &I, int R, int n, const int32_t *amb,
                          const int8_t *spins, double *h_eff, double *J_eff, hipStream_t st);
+hipError_t launch_tabu(const Instance &I, int R, int n, const int32_t *amb, const int8_t *spins,
+                       const double *h_eff, int64_t iters, int tenure, int8_t *spins_out,
+                       double *d_best, hipStream_t st);
 hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_eff, int b0,
                             int integral, int64_t *code, double *e_red, hipStream_t st);
 hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,

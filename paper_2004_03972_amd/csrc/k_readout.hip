@@ -184,8 +184,9 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
     }
     acc_wave_allreduce(acc);
     if (lane == 0) a.h_eff[(int64_t)r * a.n + ai] = acc_round(acc, a.b0);
-    for (int b = lane; b < a.n; b += 64)
-        a.J_eff[((int64_t)r * a.n + ai) * a.n + b] = jlookup(a, row, A[b]);
+    if (a.J_eff)   // optional: the tabu search reads J[A, A] from the instance itself
+        for (int b = lane; b < a.n; b += 64)
+            a.J_eff[((int64_t)r * a.n + ai) * a.n + b] = jlookup(a, row, A[b]);
 }
 
 hipError_t launch_reduce(const Instance &I, int R, int n, const int32_t *amb,
@@ -728,6 +729,142 @@ hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *
     a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64; a.spins = spins; a.E = E; a.cut = cut;
     if (V == 0) return hipSuccess;
     k_energy<<<V, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Single-flip tabu search on each replica's reduced problem, for n beyond exact
+// enumeration (the paper hands n = 1000 ambivalent spins to a tabu search in its
+// K2000 experiment; the search itself is this library's reading):
+//   x = the read-out of the ambivalent spins; f_a = h_eff_a + sum_{b != a} J_ab x_b
+//   (b ascending); D = 0, D_best = 0; for t = 1 .. iters: d_a = -2 x_a f_a; a move is
+//   allowed when tabu_until[a] < t or D + d_a < D_best; a* = the allowed a with the
+//   smallest d_a (ties: smallest a); D += d_a*; f_b -= 2 J_a*b x_a* (old value) for
+//   b != a*; x_a* = -x_a*; tabu_until[a*] = t + tenure; if D < D_best keep x.
+// One workgroup of 1024 threads per replica, up to TABU_SPT spins per thread; J_ab is
+// read from the instance's binary64 couplings at the ambivalent indices.  The
+// operations are those of the definition in binary64 without contraction, so the
+// trajectory is the same whatever the launch shape.  Each move costs one workgroup
+// barrier (the wavefronts' candidates go to LDS slots double-buffered by parity).
+// ---------------------------------------------------------------------------
+#define TABU_SPT 4
+struct TabuArgs {
+    int N, R, n, csr, tenure;
+    int64_t iters;
+    const double *J;
+    const int32_t *rp, *ci;
+    const int32_t *amb;
+    const int8_t *spins;
+    const double *h_eff;
+    int8_t *spins_out;    // read-out with the best configuration merged in
+    double *d_best;
+};
+
+__device__ __forceinline__ double tabu_j(const TabuArgs &a, int i, int j) {
+    if (!a.csr) return a.J[(int64_t)i * a.N + j];
+    int lo = a.rp[i], hi = a.rp[i + 1];
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a.ci[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < a.rp[i + 1] && a.ci[lo] == j) ? a.J[lo] : 0.0;
+}
+
+// (d, index, old spin) of the better candidate: smaller d, ties to the smaller index
+__device__ __forceinline__ void tabu_better(double &d, int &i, int &xo, double d2, int i2, int x2) {
+    if (d2 < d || (d2 == d && i2 < i)) { d = d2; i = i2; xo = x2; }
+}
+
+__global__ __launch_bounds__(1024) void k_tabu(TabuArgs a) {
+    __shared__ int8_t sx[TABU_SPT * 1024];
+    __shared__ double sd[2][16];
+    __shared__ int si[2][16], so[2][16];
+    const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int n = a.n, N = a.N;
+    const int32_t *A = a.amb + (int64_t)r * n;
+    const int8_t *s0 = a.spins + (int64_t)r * N;
+    for (int b = tid; b < n; b += 1024) sx[b] = s0[A[b]];
+    __syncthreads();
+    double f[TABU_SPT];
+    int x[TABU_SPT], xb[TABU_SPT], Ai[TABU_SPT];
+    int64_t until[TABU_SPT];
+#pragma unroll
+    for (int k = 0; k < TABU_SPT; k++) {
+        const int ai = tid + 1024 * k;
+        f[k] = 0.0; x[k] = 1; xb[k] = 1; Ai[k] = 0; until[k] = 0;
+        if (ai < n) {
+            Ai[k] = A[ai];
+            x[k] = xb[k] = sx[ai];
+            double acc = a.h_eff[(int64_t)r * n + ai];
+            for (int b = 0; b < n; b++)
+                if (b != ai) acc = acc + tabu_j(a, Ai[k], A[b]) * (double)sx[b];
+            f[k] = acc;
+        }
+    }
+    const int tenure = min(a.tenure, n - 1);
+    double D = 0.0, Db = 0.0;
+    for (int64_t t = 1; t <= a.iters; t++) {
+        const int par = (int)(t & 1);
+        double bd = INFINITY;
+        int bi = INT_MAX, bo = 0;
+#pragma unroll
+        for (int k = 0; k < TABU_SPT; k++) {
+            const int ai = tid + 1024 * k;
+            if (ai >= n) continue;
+            const double d = x[k] > 0 ? -2.0 * f[k] : 2.0 * f[k];
+            if (until[k] < t || D + d < Db) tabu_better(bd, bi, bo, d, ai, x[k]);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double d2 = __shfl_xor(bd, o);
+            const int i2 = __shfl_xor(bi, o), o2 = __shfl_xor(bo, o);
+            tabu_better(bd, bi, bo, d2, i2, o2);
+        }
+        if (lane == 0) { sd[par][w] = bd; si[par][w] = bi; so[par][w] = bo; }
+        __syncthreads();
+        bd = sd[par][0]; bi = si[par][0]; bo = so[par][0];
+        for (int v = 1; v < 16; v++) tabu_better(bd, bi, bo, sd[par][v], si[par][v], so[par][v]);
+        // At most tenure < n spins are tabu, so some move is allowed; only gains that
+        // are all NaN (fields overflowed) leave none.  bi is the same in every thread.
+        if (bi >= n) break;
+        D = D + bd;
+        const int rowj = A[bi];
+#pragma unroll
+        for (int k = 0; k < TABU_SPT; k++) {
+            const int ai = tid + 1024 * k;
+            if (ai >= n) continue;
+            if (ai == bi) {
+                x[k] = -x[k];
+                until[k] = t + tenure;
+            } else {
+                const double J = tabu_j(a, rowj, Ai[k]);
+                f[k] = f[k] - (bo > 0 ? 2.0 * J : -2.0 * J);
+            }
+        }
+        if (D < Db) {   // uniform
+            Db = D;
+#pragma unroll
+            for (int k = 0; k < TABU_SPT; k++) xb[k] = x[k];
+        }
+    }
+    int8_t *so_r = a.spins_out + (int64_t)r * N;
+#pragma unroll
+    for (int k = 0; k < TABU_SPT; k++) {
+        const int ai = tid + 1024 * k;
+        if (ai < n) so_r[Ai[k]] = (int8_t)xb[k];
+    }
+    if (tid == 0) a.d_best[r] = Db;
+}
+
+hipError_t launch_tabu(const Instance &I, int R, int n, const int32_t *amb, const int8_t *spins,
+                       const double *h_eff, int64_t iters, int tenure, int8_t *spins_out,
+                       double *d_best, hipStream_t st) {
+    TabuArgs a;
+    a.N = I.N; a.R = R; a.n = n; a.csr = I.layout == HQA_CSR; a.tenure = tenure; a.iters = iters;
+    a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.amb = amb; a.spins = spins; a.h_eff = h_eff;
+    a.spins_out = spins_out; a.d_best = d_best;
+    if (R == 0 || n == 0) return hipSuccess;
+    k_tabu<<<R, 1024, 0, st>>>(a);
     return hipGetLastError();
 }
 

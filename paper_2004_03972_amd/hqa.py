@@ -29,9 +29,9 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_md_tuned_plan", "hqa_md_set_step_tiles", "hqa_md_field_error",
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
-            "hqa_es_confidence", "hqa_es_destroy")
+            "hqa_es_confidence", "hqa_es_destroy", "hqa_classify_tabu")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
-ABI_VERSION = 4
+ABI_VERSION = 5
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
          "resident": HQA_PLAN_RESIDENT, "batch": HQA_PLAN_BATCH}
@@ -109,6 +109,7 @@ def lib():
         L.hqa_md_stats_window.argtypes = [P, i64, i64, i64]
         L.hqa_md_features.argtypes = [P, i32, P, i32]
         L.hqa_classify_probs.argtypes = [P, i32, P, i32, i32, i32, P, i32]
+        L.hqa_classify_tabu.argtypes = [P, i32, i32, i64, i32, P, i32]
         L.hqa_es_create.argtypes = [C.c_uint64, P, P]
         L.hqa_es_params.argtypes = [P, P, i32, i32]
         L.hqa_es_grad.argtypes = [P, P, P, i64, P, P, P, i32]
@@ -120,7 +121,7 @@ def lib():
                   "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
                   "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
                   "hqa_md_tune", "hqa_md_set_step_tiles", "hqa_md_field_error",
-                  "hqa_es_confidence"):
+                  "hqa_es_confidence", "hqa_classify_tabu"):
             getattr(L, f).restype = C.c_int
         if L.hqa_abi_version() != ABI_VERSION:
             raise ImportError("libhqa ABI version mismatch")
@@ -239,6 +240,11 @@ def hqa_md_hamiltonian(md, instance: int, H, dst_mem: int):
 
 def hqa_classify(md, instance: int, n_amb: int, solve: int, out: hqa_classify_out, out_mem: int):
     _check(lib().hqa_classify(md, instance, n_amb, solve, C.byref(out), out_mem))
+
+
+def hqa_classify_tabu(md, instance: int, n_amb: int, iters: int, tenure: int,
+                      out: hqa_classify_out, out_mem: int):
+    _check(lib().hqa_classify_tabu(md, instance, n_amb, iters, tenure, C.byref(out), out_mem))
 
 
 def hqa_ising_energy(prob: hqa_problem, spins, n_vectors: int, energy, cut, mem: int,
@@ -501,7 +507,7 @@ class MD:
         hqa_md_features(self.h, k, out, HQA_HOST)
         return out
 
-    def classify(self, n_amb: int, solve: bool = False, k: int = 0, prob=None) -> dict:
+    def _classify_out(self, n_amb: int, k: int):
         N, R = self.problems[k].n, self.R
         res = dict(spins=np.empty((R, N), dtype=np.int8),
                    amb_idx=np.empty((R, max(n_amb, 1)), dtype=np.int32),
@@ -510,6 +516,19 @@ class MD:
                    e_reduced=np.full(R, np.nan))
         o = hqa_classify_out(*(res[f].ctypes.data for f in
                                ("spins", "amb_idx", "energy", "cut", "h_eff", "code", "e_reduced")))
+        return res, o
+
+    def classify_tabu(self, n_amb: int, iters: int, tenure: int, k: int = 0) -> dict:
+        """Read-out with the reduced problem solved by the tabu search; e_reduced holds
+        the best energy change D_best relative to the MD read-out."""
+        res, o = self._classify_out(n_amb, k)
+        hqa_classify_tabu(self.h, k, n_amb, iters, tenure, o, HQA_HOST)
+        res["amb_idx"] = res["amb_idx"][:, :n_amb]
+        res["h_eff"] = res["h_eff"][:, :n_amb]
+        return res
+
+    def classify(self, n_amb: int, solve: bool = False, k: int = 0, prob=None) -> dict:
+        res, o = self._classify_out(n_amb, k)
         if prob is None:
             hqa_classify(self.h, k, n_amb, int(solve), o, HQA_HOST)
         elif not isinstance(prob, np.ndarray) and hasattr(prob, "data_ptr"):

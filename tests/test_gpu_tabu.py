@@ -1,0 +1,119 @@
+"""GPU parity of the tabu-search read-out (hqa_classify_tabu) against the oracle.
+
+The oracle path takes the exported window means, sorts them (orc.classify), forms the
+reduced problem (orc.reduce), runs the single-flip tabu search from the MD read-out of
+the ambivalent spins (orc.tabu) and merges the best configuration (orc.merge_x).  The
+search is binary64 with a fixed operation order on both sides, so every output is
+compared bit for bit: spins, D_best, effective fields, energies and cuts.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2004_03972_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    from paper_2004_03972_amd import hqa
+    hqa.lib()
+    return hqa
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _case(H, kind, N, seed):
+    if kind == "dense_int":
+        J = inst.er_maxcut(N, 0.1, seed)
+        return H.Problem(J), orc.Problem(N, J=J)
+    if kind == "dense_real_h":
+        J, h = inst.uniform_glass(N, seed)
+        return H.Problem(J, h=h), orc.Problem(N, J=J, h=h)
+    if kind == "sk":
+        J = inst.sk(N, seed)
+        return H.Problem(J), orc.Problem(N, J=J)
+    rp, ci, v = inst.er_sparse(N, 6.0, seed)
+    return (H.Problem(row_ptr=rp, col=ci, val=v),
+            orc.Problem(N, row_ptr=rp, col=ci, val=v))
+
+
+def _check(H, kind, N, R, n, iters, tenure, seed=5, T=300):
+    _say(f"tabu parity: {kind} N={N} R={R} n={n} iters={iters} tenure={tenure}")
+    P, pb = _case(H, kind, N, seed)
+    md = H.MD(P, H.make_schedule(T, T // 5), R, "f32", seed=seed)
+    md.run()
+    g = md.classify_tabu(n, iters, tenure)
+    bar = md.state(H.HQA_STATE_PHIBAR)
+    A, s = orc.classify(bar, n)
+    assert np.array_equal(g["amb_idx"], A)
+    he, Je = orc.reduce(pb, A, s)
+    assert np.array_equal(g["h_eff"], he)
+    x0 = np.stack([s[r, A[r]] for r in range(R)])
+    xb, db = orc.tabu(Je, he, x0, iters, tenure)
+    sh = orc.merge_x(s, A, xb)
+    assert np.array_equal(g["e_reduced"], db), (g["e_reduced"], db)
+    assert np.array_equal(g["spins"], sh)
+    E, C = orc.energy(pb, sh)
+    assert np.array_equal(g["energy"], E) and np.array_equal(g["cut"], C)
+    assert (db <= 0).all()
+    return g, db
+
+
+@pytest.mark.parametrize("kind,N,R,n,iters,tenure", [
+    ("dense_int", 300, 6, 200, 600, 20),      # integer J, several wavefronts' spins
+    ("sk", 160, 4, 150, 400, 15),             # Gaussian J, real arithmetic
+    ("dense_real_h", 200, 3, 120, 300, 9),    # real J and fields h
+    ("csr", 3000, 2, 2500, 400, 50),          # CSR couplings, n spans three spins per thread
+])
+def test_tabu_matches_oracle(H, kind, N, R, n, iters, tenure):
+    _check(H, kind, N, R, n, iters, tenure)
+
+
+def test_tabu_maximum_size(H):
+    """n = 4096: four spins in every thread of the workgroup."""
+    _check(H, "csr", 4400, 2, 4096, 200, 100, T=200)
+
+
+def test_tabu_edge_cases(H):
+    # tenure above n - 1 (clamped: one spin is always allowed), odd tiny n
+    _check(H, "dense_int", 60, 3, 7, 200, 1000)
+    # no moves: the read-out of the MD alone, D_best = 0
+    g, db = _check(H, "sk", 80, 2, 30, 0, 5)
+    assert (db == 0).all()
+    # tenure 0: steepest descent that may climb back out
+    _check(H, "dense_int", 90, 2, 40, 150, 0)
+    # n = 1 and n = 0
+    _check(H, "sk", 40, 2, 1, 10, 3)
+    P, _ = _case(H, "sk", 40, 5)
+    md = H.MD(P, H.make_schedule(60, 12), 2, "f32", seed=5)
+    md.run()
+    g0 = md.classify_tabu(0, 10, 3)
+    base = md.classify(0)
+    assert np.array_equal(g0["spins"], base["spins"])
+
+
+def test_tabu_errors(H):
+    J = inst.sk(30, 1000)
+    md = H.MD(H.Problem(J), H.make_schedule(10, 5), 2, "f32")
+    with pytest.raises(H.HQAError) as e:
+        md.classify_tabu(5, 10, 2)
+    assert e.value.status == H.HQA_ESTATE
+    md.run()
+    for n, it, ten, st in [(5, -1, 2, H.HQA_EINVAL), (5, 10, -1, H.HQA_EINVAL),
+                           (31, 10, 2, H.HQA_EINVAL)]:
+        with pytest.raises(H.HQAError) as e:
+            md.classify_tabu(n, it, ten)
+        assert e.value.status == st
+    big = inst.er_sparse(4200, 4.0, 3)
+    md = H.MD(H.Problem(row_ptr=big[0], col=big[1], val=big[2]), H.make_schedule(10, 5), 1, "f32")
+    md.run()
+    with pytest.raises(H.HQAError) as e:
+        md.classify_tabu(4097, 10, 2)
+    assert e.value.status == H.HQA_EUNSUPPORTED

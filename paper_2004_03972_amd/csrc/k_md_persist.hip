@@ -38,7 +38,7 @@
 // bound a workgroup raises an abort flag that all other waiters observe, and
 // the whole grid leaves the kernel.
 //
-// For BF16 / FP8 storage with Np <= 1024 a second kernel (k_persist_rj) keeps each
+// For BF16 / FP8 storage with Np <= 2048 a second kernel (k_persist_rj) keeps each
 // wavefront's 16 rows of J in registers instead of LDS, so that the staged flux
 // block is the only LDS operand of a step.
 #include <type_traits>
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
     if (bad) atomicOr(a.err, ERR_NONFINITE);
 }
 
-// Register-resident J (BF16 / FP8 storage, Np <= 1024): workgroups of 64 rows (four
+// Register-resident J (BF16 / FP8 storage, Np <= 2048): workgroups of 64 rows (four
 // row tiles of 16); the cluster has Np / 64 members.  Wavefront w computes
 // accumulation chain w -- chunks 4 gi + w (gi < NG = Np / 128) of all four row tiles --
 // and holds those J fragments in registers for the whole run.  It reads its MFMA B
@@ -469,7 +469,8 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
 // every wavefront passes after reading them), and wavefront w combines tile w as
 // (a0 + a1) + (a2 + a3), updates it and publishes it.  The MFMAs, their operands and
 // their order per chain are those of every other dense kernel, so the trajectories
-// are identical.
+// are identical.  Past NG = 8 the fragments no longer fit the 256 architectural
+// registers and the compiler keeps part of them in the accumulation registers.
 template <int JT, int NG, int MP>
 __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
     __shared__ f32x4 part[2][4][4][64];   // [step parity][chain][row tile][lane]
@@ -646,8 +647,8 @@ static bool plan_persist(const Instance &I, int R, JType jt, int max_wg, Persist
     const size_t stage = (size_t)16 * p.pstride;
     if (stage > lds_cap) return false;
     p.rj = 0;
-    // first choice: J in registers (BF16 / FP8, at most eight 128-column groups)
-    if (jt != JT_F32 && I.Np <= 1024) {
+    // first choice: J in registers (BF16 / FP8, at most sixteen 128-column groups)
+    if (jt != JT_F32 && I.Np <= 2048) {
         const int G = I.Np / 64;
         const int need_xcd_slots = (p.C + 7) / 8;
         if (G <= 32 && need_xcd_slots <= 32 / G && 8 * need_xcd_slots * G <= max_wg) {
@@ -714,6 +715,14 @@ static hipError_t launch_rj_ng(const PersistArgs &a, const PersistPlan &pl, hipS
         case 6: return launch_rj<JT, 6>(a, pl, st);
         case 7: return launch_rj<JT, 7>(a, pl, st);
         case 8: return launch_rj<JT, 8>(a, pl, st);
+        case 9: return launch_rj<JT, 9>(a, pl, st);
+        case 10: return launch_rj<JT, 10>(a, pl, st);
+        case 11: return launch_rj<JT, 11>(a, pl, st);
+        case 12: return launch_rj<JT, 12>(a, pl, st);
+        case 13: return launch_rj<JT, 13>(a, pl, st);
+        case 14: return launch_rj<JT, 14>(a, pl, st);
+        case 15: return launch_rj<JT, 15>(a, pl, st);
+        case 16: return launch_rj<JT, 16>(a, pl, st);
         default: return hipErrorNotSupported;
     }
 }

@@ -59,11 +59,14 @@ def test_persistent_in_pieces_and_single_step(H, prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
-@pytest.mark.parametrize("N,R", [(150, 24), (500, 48), (600, 16), (700, 40), (1000, 80)])
+@pytest.mark.parametrize("N,R", [(150, 24), (500, 48), (600, 16), (700, 40), (1000, 80),
+                                 (1100, 20), (1250, 40), (1500, 36), (1650, 16), (1900, 40),
+                                 (2000, 16)])
 def test_register_j_kernel_every_group_count(H, prec, N, R):
     """The register-J cluster kernel is instantiated per 128-column group count
-    NG = Np / 128 (Np = N padded to 128); every NG from 2 to 8, ragged replica
-    clusters, against one launch per step."""
+    NG = Np / 128 (Np = N padded to 128); NG from 2 to 16 (past 8 part of the J
+    fragments live in accumulation registers; 2000 x 16 is the K2000 shape), ragged
+    replica clusters, against one launch per step."""
     print("persist rj", prec, N, R, flush=True)
     J = inst.er_maxcut(N, 0.04, N + 1)
     out = []

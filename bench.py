@@ -385,13 +385,13 @@ def bench_k2000(args, hqa, torch):
     from paper_2004_03972_amd import instances as inst
     Nk, Rr, cstar = 2000, args.k2000_replicas, 33932.6
     out = {"metric": "MAX-CUT deviation from C* (K2000, +-1 weights)", "C_star": cstar,
-           "instances": args.k2000_instances, "mirrors": True, "replicas": Rr, "by_T": {}}
+           "instances": args.k2000_instances, "first_instance": args.k2000_first, "mirrors": True, "replicas": Rr, "by_T": {}}
     st = torch.cuda.current_stream()
     for Tt in [int(x) for x in args.k2000_steps.split(",")]:
         dev = {"md_one_init": [], "hqa_one_init": [], "md_best": [], "hqa_best": [],
                "hqa_ts_one_init": [], "hqa_ts_best": []}
         ms_tot = ts_tot = 0.0
-        for k in range(args.k2000_instances):
+        for k in range(args.k2000_first, args.k2000_first + args.k2000_instances):
             J = inst.pm_complete(Nk, 9000 + k)
             for sign in (1.0, -1.0):
                 md = hqa.MD(hqa.Problem(sign * J), hqa.make_schedule(Tt, 100), Rr, "fp8",
@@ -417,6 +417,8 @@ def bench_k2000(args, hqa, torch):
             _log(f"  T={Tt}: instance {k} done")
         out["by_T"][str(Tt)] = {kk: {"mean": float(np.mean(v)), "min": float(np.min(v)),
                                      "max": float(np.max(v))} for kk, v in dev.items() if v}
+        if args.k2000_per_run:
+            out["by_T"][str(Tt)]["per_run"] = {kk: [float(x) for x in v] for kk, v in dev.items()}
         out["by_T"][str(Tt)]["md_ms_per_run"] = ms_tot / (2 * args.k2000_instances)
         if args.k2000_tabu_iters > 0:
             out["by_T"][str(Tt)]["tabu_read_out_ms_per_run"] = ts_tot / (2 * args.k2000_instances)
@@ -432,9 +434,12 @@ def bench_glass(args, hqa, torch):
     of J for the dynamics, exact binary64 energies): mean Ising energy per spin over
     instances against MD steps, for N = 1000, 2000 and 10^4.  Read-outs: MD alone
     (sign of phibar) for replica 0 (one initial condition per instance) and the best
-    of R replicas; HQA with the n = 20 most ambivalent spins solved exactly."""
+    of R replicas; HQA with the n = 20 most ambivalent spins solved exactly; HQA with
+    the n most ambivalent spins (each n of --glass-tabu-n up to N) handed to the tabu
+    search for --glass-tabu-sweeps * n moves, tenure n / 20."""
     from paper_2004_03972_amd import instances as inst
     Rr = args.glass_replicas
+    tabu_ns = [int(x) for x in args.glass_tabu_n.split(",") if x]
     sizes = [int(x) for x in args.glass_n.split(",")]
     counts = [int(x) for x in args.glass_instances.split(",")]
     steps = [int(x) for x in args.glass_steps.split(",")]
@@ -446,6 +451,9 @@ def bench_glass(args, hqa, torch):
         rows = {}
         for Tt in steps:
             e = {"md_one_init": [], "md_best": [], "hqa_one_init": [], "hqa_best": []}
+            for nt in tabu_ns:
+                if nt <= Nn:
+                    e[f"hqa_ts{nt}_one_init"], e[f"hqa_ts{nt}_best"] = [], []
             bad_tot, ms_tot = 0, 0.0
             for k in range(cnt):
                 J, h = inst.uniform_glass(Nn, 7000 + 31 * Nn + k)
@@ -464,13 +472,19 @@ def bench_glass(args, hqa, torch):
                     e["md_best"].append(g0["energy"].min() / Nn)
                     e["hqa_one_init"].append(g1["energy"][0] / Nn)
                     e["hqa_best"].append(g1["energy"].min() / Nn)
+                    for nt in tabu_ns:
+                        if nt <= Nn:
+                            g2 = md.classify_tabu(nt, args.glass_tabu_sweeps * nt, max(1, nt // 20))
+                            e[f"hqa_ts{nt}_one_init"].append(g2["energy"][0] / Nn)
+                            e[f"hqa_ts{nt}_best"].append(g2["energy"].min() / Nn)
                 md.close()
             rows[str(Tt)] = {kk: (float(np.mean(v)) if v else None) for kk, v in e.items()}
             rows[str(Tt)]["instances"] = cnt
             rows[str(Tt)]["diverged_replicas"] = bad_tot
             rows[str(Tt)]["md_ms_per_run"] = ms_tot / cnt
-            _log(f"  N={Nn} T={Tt}: MD one init {rows[str(Tt)]['md_one_init']}, "
-                 f"HQA best {rows[str(Tt)]['hqa_best']}")
+            _log(f"  N={Nn} T={Tt}: " + ", ".join(
+                f"{kk} {rows[str(Tt)][kk]:.5f}" for kk in e if rows[str(Tt)][kk] is not None
+                and kk.endswith("one_init")))
         out["by_N"][str(Nn)] = rows
     out["paper"] = ("energies decrease with MD steps from 10^3 to 5*10^5 for N = 1000, 2000 and "
                     "10^4; the figure's values are not printed in the text")
@@ -595,12 +609,16 @@ def main():
     ap.add_argument("--glass-instances", default="8,8,2")
     ap.add_argument("--glass-steps", default="1000,10000,100000,500000")
     ap.add_argument("--glass-replicas", type=int, default=16)
+    ap.add_argument("--glass-tabu-n", default="500,1000,4000")
+    ap.add_argument("--glass-tabu-sweeps", type=int, default=20)
     ap.add_argument("--sweep-n", type=int, default=10000)
     ap.add_argument("--sweep-steps", default="2000,10000,50000")
     ap.add_argument("--sweep-best", type=int, default=200000)
     ap.add_argument("--k2000-instances", type=int, default=4)
     ap.add_argument("--k2000-replicas", type=int, default=16)
     ap.add_argument("--k2000-steps", default="50000,500000")
+    ap.add_argument("--k2000-first", type=int, default=0)
+    ap.add_argument("--k2000-per-run", action="store_true")
     ap.add_argument("--k2000-tabu-n", type=int, default=1000)
     ap.add_argument("--k2000-tabu-iters", type=int, default=20000)
     ap.add_argument("--k2000-tabu-tenure", type=int, default=50)

@@ -914,6 +914,9 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
         HIPCHK(hipMemcpyAsync(merged, spins, (size_t)R * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(launch_tabu(I, R, n_amb, amb, spins, h_eff, tabu_iters, tenure, merged, e_red, st));
         spins = merged;
+    } else if (solve == 2) {   // nothing to search: D_best = 0
+        HIPCHK(B.get(&e_red, (size_t)R));
+        HIPCHK(hipMemsetAsync(e_red, 0, sizeof(double) * R, st));
     } else if (solve && n_amb > 0) {
         HIPCHK(B.get(&h_eff, (size_t)R * n_amb));
         HIPCHK(B.get(&J_eff, (size_t)R * n_amb * n_amb));

@@ -97,6 +97,7 @@ def test_tabu_edge_cases(H):
     g0 = md.classify_tabu(0, 10, 3)
     base = md.classify(0)
     assert np.array_equal(g0["spins"], base["spins"])
+    assert (g0["e_reduced"] == 0).all()
 
 
 def test_tabu_errors(H):
@@ -117,3 +118,29 @@ def test_tabu_errors(H):
     with pytest.raises(H.HQAError) as e:
         md.classify_tabu(4097, 10, 2)
     assert e.value.status == H.HQA_EUNSUPPORTED
+
+
+def test_tabu_k2000_bench_shape(H):
+    """The launch the K2000 bench times: +-1 couplings on K_2000 stored in FP8, R = 16,
+    n = 1000 ambivalent spins, 20000 moves, tenure 50 (a shorter MD run feeds it)."""
+    N, R, n, iters, tenure = 2000, 16, 1000, 20000, 50
+    _say(f"tabu parity at the K2000 bench shape: N={N} R={R} n={n} iters={iters}")
+    J = inst.pm_complete(N, 9000)
+    md = H.MD(H.Problem(J), H.make_schedule(2000, 100), R, "fp8", seed=11, require_exact=True)
+    md.run()
+    g = md.classify_tabu(n, iters, tenure)
+    bar = md.state(H.HQA_STATE_PHIBAR)
+    pb = orc.Problem(N, J=J)
+    A, s = orc.classify(bar, n)
+    assert np.array_equal(g["amb_idx"], A)
+    he, Je = orc.reduce(pb, A, s)
+    assert np.array_equal(g["h_eff"], he)
+    x0 = np.stack([s[r, A[r]] for r in range(R)])
+    xb, db = orc.tabu(Je, he, x0, iters, tenure)
+    del Je
+    sh = orc.merge_x(s, A, xb)
+    assert np.array_equal(g["e_reduced"], db)
+    assert np.array_equal(g["spins"], sh)
+    E, C = orc.energy(pb, sh)
+    assert np.array_equal(g["energy"], E) and np.array_equal(g["cut"], C)
+    assert (db < 0).all()

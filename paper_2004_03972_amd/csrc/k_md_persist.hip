@@ -541,9 +541,9 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
         // MFMAs as soon as its two units are in, while later chunks are still on their
         // way (straight-line code, so each chunk waits only for its own loads).  The
         // tags are folded into one word on the way; if any unit of the wavefront was
-        // stale (its producer had not stored the step yet) the wavefront reads all its
-        // units again and redoes the chain from zero, so the order within the chain
-        // never changes.
+        // stale (its producer had not stored the step yet) the wavefront reads its units
+        // again (all of them, or past eight chunk groups only the stale ones) and redoes
+        // the chain from zero, so the order within the chain never changes.
         u32x4 bx[NG][2];
         f32x4 acc[4];
         auto load_units = [&]() {
@@ -551,6 +551,20 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
             for (int gi = 0; gi < NG; gi++) {
                 bx[gi][0] = ld16_agent(rs[par], uoff + gi * 8192);
                 bx[gi][1] = ld16_agent(rs[par], uoff + gi * 8192 + 256);
+            }
+        };
+        // a lane reads again only those of its units that are stale: for large blocks
+        // this saves L2 traffic (at Np = 2048 each member reads 128 KB per step); for
+        // small ones the per-unit branches cost more than reading everything again
+        auto reload_stale = [&]() {
+#pragma unroll
+            for (int gi = 0; gi < NG; gi++) {
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const uint32_t x = (bx[gi][h][0] ^ tg) | (bx[gi][h][1] ^ tg) |
+                                       (bx[gi][h][2] ^ tg) | (bx[gi][h][3] ^ tg);
+                    if (x >> 16) bx[gi][h] = ld16_agent(rs[par], uoff + gi * 8192 + 256 * h);
+                }
             }
         };
         auto chain = [&]() -> uint32_t {
@@ -587,7 +601,8 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
             while (true) {
                 if (__any(!keep_waiting(a, wt))) break;   // giving up: the launch aborts
                 asm volatile("" ::: "memory");   // the re-loads must read memory again
-                load_units();
+                if constexpr (NG > 8) reload_stale();
+                else load_units();
                 if (!__any(chain() != 0)) break;
             }
         }

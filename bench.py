@@ -396,7 +396,7 @@ def bench_k2000(args, hqa, torch):
             for sign in (1.0, -1.0):
                 md = hqa.MD(hqa.Problem(sign * J), hqa.make_schedule(Tt, 100), Rr, "fp8",
                             seed=11 + k, require_exact=True, stream=st.cuda_stream)
-                md.tune(20)
+                md.tune(100)   # 100-step slopes: plans 10% apart are told apart reliably
                 e0, e1 = _events(torch)
                 e0.record(st); md.run(); e1.record(st); md.sync()
                 ms_tot += e0.elapsed_time(e1)
@@ -459,7 +459,7 @@ def bench_glass(args, hqa, torch):
                 J, h = inst.uniform_glass(Nn, 7000 + 31 * Nn + k)
                 md = hqa.MD(hqa.Problem(J, h=h, storage="bf16"), hqa.make_schedule(Tt, 100), Rr,
                             "bf16", seed=40 + k, stream=st.cuda_stream)
-                md.tune(min(20, Tt // 4))
+                md.tune(max(20, min(100, Tt // 10)))
                 e0, e1 = _events(torch)
                 e0.record(st); md.run(); e1.record(st); st.synchronize()
                 ms_tot += e0.elapsed_time(e1)

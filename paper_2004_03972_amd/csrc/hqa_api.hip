@@ -935,7 +935,9 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
     if (out->energy || out->cut) {
         HIPCHK(B.get(&E, (size_t)R));
         HIPCHK(B.get(&C, (size_t)R));
-        HIPCHK(launch_energy(I, R, spins, E, C, st));
+        uint8_t *part;
+        HIPCHK(B.get(&part, energy_part_bytes(N, R)));
+        HIPCHK(launch_energy(I, R, spins, E, C, part, st));
     }
     hipMemcpyKind kd = kind_out(out_mem);
     HIPCHK(hipMemcpyAsync(out->spins, spins, (size_t)R * N, kd, st));
@@ -1196,7 +1198,9 @@ hqa_status hqa_ising_energy(const hqa_problem *prob, const int8_t *spins, int32_
         if (e == hipSuccess && energy) e = B.get(&dE, V);
         if (e == hipSuccess && cut) e = B.get(&dC, V);
     }
-    if (e == hipSuccess) e = launch_energy(I, n_vectors, dsp, dE, dC, st);
+    uint8_t *part = nullptr;
+    if (e == hipSuccess) e = B.get(&part, energy_part_bytes(I.N, n_vectors));
+    if (e == hipSuccess) e = launch_energy(I, n_vectors, dsp, dE, dC, part, st);
     if (e == hipSuccess && mem == HQA_HOST && energy)
         e = hipMemcpyAsync(energy, dE, V * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && mem == HQA_HOST && cut)

@@ -161,8 +161,12 @@ hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_e
                             int integral, int64_t *code, double *e_red, hipStream_t st);
 hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
                         int8_t *spins, hipStream_t st);
+// Exact energies and cuts of V spin vectors; `part` holds energy_part_bytes(N, V)
+// bytes of device scratch for the per-slice partial sums.
+int energy_slices(int N, int V);
+size_t energy_part_bytes(int N, int V);
 hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
-                         hipStream_t st);
+                         void *part, hipStream_t st);
 hipError_t launch_select_keys(int N, int R, const float *keys, int n, int32_t *amb,
                               int8_t *spins, hipStream_t st);
 

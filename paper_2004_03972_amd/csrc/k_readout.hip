@@ -590,15 +590,18 @@ hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *
 // Exact Ising energy (Eq. 1) and cut (Methods, MAX-CUT with w = J).  The sum over
 // ordered pairs i != j counts each pair twice, so 2E = sum_{i!=j} J s s + 2 sum h s
 // and 2C = sum_{i!=j, s_i != s_j} J are accumulated exactly and rounded with the
-// scale halved.  One workgroup per spin vector.
+// scale halved.  Each spin vector is split into P row slices, one workgroup per
+// (vector, slice), so that a few vectors still fill the device; the slices' partial
+// sums are exact, and so is their total, whatever the split.
 // ---------------------------------------------------------------------------
 struct EnArgs {
-    int N, V, csr, b0;
+    int N, V, P, csr, b0;
     int fast;          // plain binary64 sums are exact (see launch_energy)
     const double *J;
     const int32_t *rp, *ci;
     const double *h;
     const int8_t *spins;
+    void *part;        // [V][P] partials: two doubles (fast) or two Acc256
     double *E, *cut;
 };
 
@@ -625,13 +628,14 @@ __device__ double block_sum(double x, double *sh) {
     return t;
 }
 
-// One workgroup per spin vector; the vector is staged in LDS and a dense J is read
-// row by row (a wavefront per row, lanes along the columns).
+// Workgroup b takes slice p = b mod P of vector b / P: the vector is staged in LDS;
+// a dense J is read row by row (rows p*4 + w, then every 4P; lanes along the
+// columns), a CSR J a row per thread (rows p*256 + tid, then every 256P).
 __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
     __shared__ Acc256 sh[4];
     __shared__ double shd[4];
     __shared__ int8_t sv[ENERGY_MAXN_LDS];
-    const int v = blockIdx.x, tid = threadIdx.x;
+    const int v = blockIdx.x / a.P, p = blockIdx.x % a.P, tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int8_t *s = a.spins + (int64_t)v * a.N;
     const bool lds = a.N <= ENERGY_MAXN_LDS;
@@ -640,11 +644,12 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
     __syncthreads();
     const int8_t *ss = lds ? sv : s;
     const int b0 = a.b0;
+    const int64_t slot = (int64_t)v * a.P + p;
     if (a.fast) {
         // every partial sum is a multiple of 2^b0 below 2^(53 + b0): binary64 is exact
         double ae = 0.0, ac = 0.0;
         if (!a.csr) {
-            for (int i = w; i < a.N; i += 4) {
+            for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
                 const double *Jr = a.J + (int64_t)i * a.N;
                 const int si = ss[i];
 #pragma unroll 4
@@ -656,7 +661,7 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
                 }
             }
         } else {
-            for (int i = tid; i < a.N; i += 256) {
+            for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
                 const int si = ss[i];
                 for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
                     const double J = a.J[e];
@@ -666,12 +671,14 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
                 }
             }
         }
-        for (int i = tid; i < a.N; i += 256) ae += ss[i] > 0 ? 2.0 * a.h[i] : -2.0 * a.h[i];
+        for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
+            ae += ss[i] > 0 ? 2.0 * a.h[i] : -2.0 * a.h[i];
         ae = block_sum(ae, shd);
         ac = block_sum(ac, shd);
         if (tid == 0) {
-            if (a.E) a.E[v] = 0.5 * ae;
-            if (a.cut) a.cut[v] = 0.5 * ac;
+            double *o = (double *)a.part + 2 * slot;
+            o[0] = ae;
+            o[1] = ac;
         }
         return;
     }
@@ -679,7 +686,7 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
     acc_zero(ae);
     acc_zero(ac);
     if (!a.csr) {
-        for (int i = w; i < a.N; i += 4) {
+        for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
             const double *Jr = a.J + (int64_t)i * a.N;
             const int si = ss[i];
             for (int j = lane; j < a.N; j += 64) {
@@ -691,7 +698,7 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
             }
         }
     } else {
-        for (int i = tid; i < a.N; i += 256) {
+        for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
             int si = ss[i];
             for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
                 double J = a.J[e];
@@ -701,22 +708,60 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
             }
         }
     }
-    for (int i = tid; i < a.N; i += 256) {
+    for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
         double hh = a.h[i];
         if (hh != 0.0) acc_add(ae, ss[i] > 0 ? 2.0 * hh : -2.0 * hh, b0);
     }
     block_acc_reduce(ae, sh);
     block_acc_reduce(ac, sh);
     if (tid == 0) {
-        if (a.E) a.E[v] = acc_round(ae, b0 - 1);
-        if (a.cut) a.cut[v] = acc_round(ac, b0 - 1);
+        Acc256 *o = (Acc256 *)a.part + 2 * slot;
+        o[0] = ae;
+        o[1] = ac;
     }
 }
 
+// Totals of the P slices of each vector (a thread per vector), rounded once.
+__global__ __launch_bounds__(64) void k_energy_merge(EnArgs a) {
+    const int v = blockIdx.x * 64 + threadIdx.x;
+    if (v >= a.V) return;
+    const int64_t s0 = (int64_t)v * a.P;
+    if (a.fast) {
+        const double *o = (const double *)a.part;
+        double ae = 0.0, ac = 0.0;
+        for (int p = 0; p < a.P; p++) {
+            ae += o[2 * (s0 + p)];
+            ac += o[2 * (s0 + p) + 1];
+        }
+        if (a.E) a.E[v] = 0.5 * ae;
+        if (a.cut) a.cut[v] = 0.5 * ac;
+        return;
+    }
+    const Acc256 *o = (const Acc256 *)a.part;
+    Acc256 ae = o[2 * s0], ac = o[2 * s0 + 1];
+    for (int p = 1; p < a.P; p++) {
+        acc_merge(ae, o[2 * (s0 + p)]);
+        acc_merge(ac, o[2 * (s0 + p) + 1]);
+    }
+    if (a.E) a.E[v] = acc_round(ae, a.b0 - 1);
+    if (a.cut) a.cut[v] = acc_round(ac, a.b0 - 1);
+}
+
+int energy_slices(int N, int V) {
+    if (V <= 0) return 1;
+    const int want = (512 + V - 1) / V;          // at least 512 workgroups in all
+    const int most = (N + 63) / 64;              // at least 64 rows per slice
+    return std::max(1, std::min(want, most));
+}
+
+size_t energy_part_bytes(int N, int V) {
+    return (size_t)std::max(V, 1) * energy_slices(N, V) * 2 * sizeof(Acc256);
+}
+
 hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
-                         hipStream_t st) {
+                         void *part, hipStream_t st) {
     EnArgs a;
-    a.N = I.N; a.V = V; a.csr = I.layout == HQA_CSR; a.b0 = I.es.lsb;
+    a.N = I.N; a.V = V; a.P = energy_slices(I.N, V); a.csr = I.layout == HQA_CSR; a.b0 = I.es.lsb;
     // Every J and h is a multiple of 2^lsb below 2^(msb + 1); the sums take at most
     // N^2 + N terms of magnitude below 2^(msb + 2) (2h).  When those fit 53 bits above
     // 2^lsb, every partial binary64 sum is exact, whatever the order.
@@ -726,9 +771,11 @@ hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *
         while (lg < 64 && std::ldexp(1.0, lg) < terms) lg++;
         a.fast = I.es.lsb != INT32_MIN && (I.es.msb + 2 - I.es.lsb) + lg <= 52;
     }
-    a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64; a.spins = spins; a.E = E; a.cut = cut;
+    a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64; a.spins = spins; a.part = part;
+    a.E = E; a.cut = cut;
     if (V == 0) return hipSuccess;
-    k_energy<<<V, 256, 0, st>>>(a);
+    k_energy<<<V * a.P, 256, 0, st>>>(a);
+    k_energy_merge<<<(V + 63) / 64, 64, 0, st>>>(a);
     return hipGetLastError();
 }
 

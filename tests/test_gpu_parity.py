@@ -229,8 +229,8 @@ def test_f32_readout_matches_oracle_on_same_phibar(H, layout):
 @pytest.mark.parametrize("kind", ["sk", "int", "glass", "csr", "csr_int", "int_h"])
 def test_ising_energy_exact(H, kind):
     """Exact energies and cuts: the binary64 fast path (integer J and h: every partial
-    sum exact, four vectors per workgroup, 7 vectors leave a partial group) and the
-    fixed-point accumulator (real J), dense and CSR."""
+    sum exact) and the fixed-point accumulator (real J), dense and CSR; 7 vectors of
+    333 spins, each split into 6 row slices whose partial sums are added exactly."""
     N = 333
     h = None
     if kind == "sk":
@@ -245,6 +245,31 @@ def test_ising_energy_exact(H, kind):
     spins = inst.random_pm1((7, N), 803).astype(np.int8)
     if kind in ("csr", "csr_int"):
         rp, ci, v = inst.dense_to_csr(J)
+        P = H.Problem(row_ptr=rp, col=ci, val=v, h=h)
+        pb = orc.Problem(N, row_ptr=rp, col=ci, val=v, h=h)
+    else:
+        P, pb = H.Problem(J, h=h), orc.Problem(N, J=J, h=h)
+    E, C = H.ising_energy(P, spins)
+    Eo, Co = orc.energy(pb, spins)
+    assert np.array_equal(E, Eo) and np.array_equal(C, Co)
+
+
+@pytest.mark.parametrize("kind,N,V", [("glass", 3000, 1), ("int", 3000, 1), ("glass", 2000, 3),
+                                      ("csr", 2500, 2), ("int", 100, 600)])
+def test_ising_energy_exact_slices(H, kind, N, V):
+    """One vector split into up to 47 row slices (few vectors fill the device), and 600
+    vectors of one slice each: the same exact energies and cuts as the oracle."""
+    _say("energy slices", kind, N, V)
+    h = None
+    if kind == "int":
+        J = inst.small_int(N, 811, -4, 4, density=0.4)
+        h = np.random.default_rng(812).integers(-3, 4, N).astype(np.float64)
+    else:
+        J, h = inst.uniform_glass(N, 813)
+    spins = inst.random_pm1((V, N), 814).astype(np.int8)
+    if kind == "csr":
+        keep = np.triu(inst.random_pm1((N, N), 815) > 0, 1)   # half the couplings, symmetric
+        rp, ci, v = inst.dense_to_csr(J * (keep | keep.T))
         P = H.Problem(row_ptr=rp, col=ci, val=v, h=h)
         pb = orc.Problem(N, row_ptr=rp, col=ci, val=v, h=h)
     else:

@@ -376,32 +376,42 @@ def bench_es(args, hqa, torch):
 
 
 def bench_k2000(args, hqa, torch):
-    """MAX-CUT on K_2000 with +-1 weights (the paper's headline experiment, reduced to a
-    few instances): J = +w stored exactly in FP8, each instance and its mirror -J, R
-    replicas, MD alone (sign of phibar) and HQA (n = 20 solved exactly).  Deviation from
-    the theoretical maximum cut C* = 33,932.6 (recomputed from the paper's formula, see
-    tests/golden/kn_maxcut_cstar.txt), for replica 0 (one initial condition per
-    instance, as in the paper) and for the best of the R replicas."""
+    """MAX-CUT on K_2000 with +-1 weights (the paper's headline experiment): J = +w stored
+    exactly in FP8, each instance and its mirror -J, R replicas, MD alone (sign of
+    phibar), HQA with n = 20 solved exactly and HQA with the n most ambivalent spins
+    handed to the tabu search.  Deviation from the theoretical maximum cut C* = 33,932.6
+    (recomputed from the paper's formula, see tests/golden/kn_maxcut_cstar.txt), for
+    replica 0 (one initial condition per instance, as in the paper) and for the best of
+    the R replicas.  --k2000-group instances (instance and mirror pairs) share one
+    handle and one cluster launch, each 16-replica cluster on its own XCD; the
+    initial momenta come from the seed 11 + (first instance of the group)."""
     from paper_2004_03972_amd import instances as inst
     Nk, Rr, cstar = 2000, args.k2000_replicas, 33932.6
+    pairs = max(1, args.k2000_group // 2)
     out = {"metric": "MAX-CUT deviation from C* (K2000, +-1 weights)", "C_star": cstar,
-           "instances": args.k2000_instances, "first_instance": args.k2000_first, "mirrors": True, "replicas": Rr, "by_T": {}}
+           "instances": args.k2000_instances, "first_instance": args.k2000_first,
+           "mirrors": True, "replicas": Rr, "handle_group": 2 * pairs, "by_T": {}}
     st = torch.cuda.current_stream()
+    ks_all = list(range(args.k2000_first, args.k2000_first + args.k2000_instances))
     for Tt in [int(x) for x in args.k2000_steps.split(",")]:
         dev = {"md_one_init": [], "hqa_one_init": [], "md_best": [], "hqa_best": [],
                "hqa_ts_one_init": [], "hqa_ts_best": []}
         ms_tot = ts_tot = 0.0
-        for k in range(args.k2000_first, args.k2000_first + args.k2000_instances):
-            J = inst.pm_complete(Nk, 9000 + k)
-            for sign in (1.0, -1.0):
-                md = hqa.MD(hqa.Problem(sign * J), hqa.make_schedule(Tt, 100), Rr, "fp8",
-                            seed=11 + k, require_exact=True, stream=st.cuda_stream)
-                md.tune(100)   # 100-step slopes: plans 10% apart are told apart reliably
-                e0, e1 = _events(torch)
-                e0.record(st); md.run(); e1.record(st); md.sync()
-                ms_tot += e0.elapsed_time(e1)
-                g0 = md.classify(20, solve=False)
-                g1 = md.classify(20, solve=True)
+        for g in range(0, len(ks_all), pairs):
+            ks = ks_all[g:g + pairs]
+            Js = []
+            for k in ks:
+                J = inst.pm_complete(Nk, 9000 + k)
+                Js += [J, -J]
+            md = hqa.MD([hqa.Problem(J) for J in Js], hqa.make_schedule(Tt, 100), Rr, "fp8",
+                        seed=11 + ks[0], require_exact=True, stream=st.cuda_stream,
+                        plan="cluster")
+            e0, e1 = _events(torch)
+            e0.record(st); md.run(); e1.record(st); md.sync()
+            ms_tot += e0.elapsed_time(e1)
+            for kk in range(len(Js)):
+                g0 = md.classify(20, solve=False, k=kk)
+                g1 = md.classify(20, solve=True, k=kk)
                 dev["md_one_init"].append((cstar - g0["cut"][0]) / cstar)
                 dev["hqa_one_init"].append((cstar - g1["cut"][0]) / cstar)
                 dev["md_best"].append((cstar - g0["cut"].max()) / cstar)
@@ -409,19 +419,20 @@ def bench_k2000(args, hqa, torch):
                 if args.k2000_tabu_iters > 0:
                     t0 = time.perf_counter()
                     g2 = md.classify_tabu(args.k2000_tabu_n, args.k2000_tabu_iters,
-                                          args.k2000_tabu_tenure)
+                                          args.k2000_tabu_tenure, k=kk)
                     ts_tot += (time.perf_counter() - t0) * 1e3
                     dev["hqa_ts_one_init"].append((cstar - g2["cut"][0]) / cstar)
                     dev["hqa_ts_best"].append((cstar - g2["cut"].max()) / cstar)
-                md.close()
-            _log(f"  T={Tt}: instance {k} done")
+            md.close()
+            _log(f"  T={Tt}: instances {ks[0]}..{ks[-1]} done")
+        runs = 2 * len(ks_all)
         out["by_T"][str(Tt)] = {kk: {"mean": float(np.mean(v)), "min": float(np.min(v)),
                                      "max": float(np.max(v))} for kk, v in dev.items() if v}
         if args.k2000_per_run:
             out["by_T"][str(Tt)]["per_run"] = {kk: [float(x) for x in v] for kk, v in dev.items()}
-        out["by_T"][str(Tt)]["md_ms_per_run"] = ms_tot / (2 * args.k2000_instances)
+        out["by_T"][str(Tt)]["md_ms_per_run"] = ms_tot / runs
         if args.k2000_tabu_iters > 0:
-            out["by_T"][str(Tt)]["tabu_read_out_ms_per_run"] = ts_tot / (2 * args.k2000_instances)
+            out["by_T"][str(Tt)]["tabu_read_out_ms_per_run"] = ts_tot / runs
     out["tabu"] = {"n": args.k2000_tabu_n, "iters": args.k2000_tabu_iters,
                    "tenure": args.k2000_tabu_tenure}
     out["paper"] = ("MD alone about 0.4% and HQA(TS1000) about 0.2% below C* at 5e5 MD steps "
@@ -618,6 +629,7 @@ def main():
     ap.add_argument("--k2000-replicas", type=int, default=16)
     ap.add_argument("--k2000-steps", default="50000,500000")
     ap.add_argument("--k2000-first", type=int, default=0)
+    ap.add_argument("--k2000-group", type=int, default=8)
     ap.add_argument("--k2000-per-run", action="store_true")
     ap.add_argument("--k2000-tabu-n", type=int, default=1000)
     ap.add_argument("--k2000-tabu-iters", type=int, default=20000)

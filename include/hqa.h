@@ -136,7 +136,10 @@ typedef struct hqa_md_opts {
  *                      single-partition MI355X).  A workgroup found on another XCD
  *                      aborts the launch, and the run (or hqa_md_sync) returns
  *                      HQA_EDEVICE naming the placement; the tuner then skips the
- *                      plan.  Every wait inside the launch is bounded.
+ *                      plan.  Every wait inside the launch is bounded.  With several
+ *                      dense instances (BF16/FP8, N <= 2048), runs of up to 8
+ *                      consecutive instances of one size share a launch, each cluster
+ *                      on its own XCD; an instance no launch takes runs alone.
  *   HQA_PLAN_RESIDENT  all steps in one launch; one workgroup per 16 replicas keeps
  *                      their whole state in LDS and streams J from L2 (BF16/FP8 J,
  *                      N up to 800 on a device with 160 KB of LDS per workgroup).

@@ -18,6 +18,8 @@ hipError_t launch_md_steps_f64(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_steps_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_steps_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
+hipError_t launch_md_persist_set(hqa_md *md, Instance *const *set, int K, int64_t q0,
+                                 int64_t q1);
 hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1);
 void free_batch_plan(void *p);
 hipError_t launch_field_f64(hqa_md *md, Instance &I, double *u, hipStream_t st);
@@ -467,6 +469,35 @@ static hipError_t run_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1, boo
     return launch_md_steps_dense(md, I, q0, q1);
 }
 
+// The cluster plan over several dense instances: runs of consecutive instances of one
+// size and storage share a register-J launch (the largest run the device fits, at
+// most 8), so that instances whose clusters fill only part of the device advance
+// together, each cluster on its own XCD.  An instance no launch takes runs alone.
+static hipError_t run_dense_clusters(hqa_md *md, int64_t q0, int64_t q1, int *used) {
+    std::vector<Instance *> d;
+    for (auto &I : md->inst)
+        if (I.layout == HQA_DENSE) d.push_back(&I);
+    size_t i = 0;
+    while (i < d.size()) {
+        int k = 1;
+        while (i + k < d.size() && k < 8 && d[i + k]->N == d[i]->N && d[i + k]->jt == d[i]->jt) k++;
+        hipError_t e = hipErrorNotSupported;
+        for (; k > 1; k--) {
+            e = launch_md_persist_set(md, &d[i], k, q0, q1);
+            if (e != hipErrorNotSupported) break;
+        }
+        if (e == hipErrorNotSupported) {
+            k = 1;
+            e = run_dense(md, *d[i], q0, q1, false, HQA_PLAN_CLUSTER, used);
+        } else {
+            *used = HQA_PLAN_CLUSTER;
+        }
+        if (e != hipSuccess) return e;
+        i += k;
+    }
+    return hipSuccess;
+}
+
 // Steps [q0, q1) of one sparse binary32 instance under `plan` (RESIDENT or STEP).
 static hipError_t run_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1, bool stats_live,
                           int plan, int *used) {
@@ -498,15 +529,21 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     const bool stats_live = md->stats_k1 > md->q && md->stats_k0 < q1;
     const bool batched = md->prec != HQA_PREC_F64_REF && ndense > 1 &&
                          md->plan == HQA_PLAN_AUTO && !stats_live;
+    const bool clustered = md->prec != HQA_PREC_F64_REF && ndense > 1 &&
+                           md->plan == HQA_PLAN_CLUSTER && !stats_live;
     if (batched) {
         hipError_t e = launch_md_steps_batch(md, md->q, q1);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
         md->last_plan = HQA_PLAN_BATCH;
     }
+    if (clustered) {
+        hipError_t e = run_dense_clusters(md, md->q, q1, &md->last_plan);
+        if (e != hipSuccess) return fail(HQA_EDEVICE, "cluster launch: %s", hipGetErrorString(e));
+    }
     for (auto &I : md->inst) {
         hipError_t e;
         if (md->prec == HQA_PREC_F64_REF) e = launch_md_steps_f64(md, I, md->q, q1);
-        else if (I.layout == HQA_DENSE && batched) e = hipSuccess;
+        else if (I.layout == HQA_DENSE && (batched || clustered)) e = hipSuccess;
         else if (I.layout == HQA_DENSE) e = run_dense(md, I, md->q, q1, stats_live, md->plan, &md->last_plan);
         else e = run_csr(md, I, md->q, q1, stats_live, md->plan, &md->last_plan);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "step launch: %s", hipGetErrorString(e));

@@ -50,8 +50,22 @@ namespace hqa {
 
 typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
 
+// Buffers of one instance; a register-J launch may serve several instances of one
+// size (cluster c belongs to instance c / C1).
+#define PERSIST_MAXK 8
+struct PersistInst {
+    const void *J;
+    const float *h, *phi_in;
+    float *phi_out;
+    bf16 *xb_out;
+    float *p, *S;
+    uint64_t *xch;
+};
+
 struct PersistArgs {
     int N, Np, R, ld, M, G, C;
+    int K, C1;               // instances in the launch, clusters per instance (C = K C1)
+    PersistInst ins[PERSIST_MAXK];
     int64_t T, q0, q1;
     int W;
     float rg;
@@ -471,13 +485,31 @@ __global__ __launch_bounds__(256) void k_persist(PersistArgs a) {
 // their order per chain are those of every other dense kernel, so the trajectories
 // are identical.  Past NG = 8 the fragments no longer fit the 256 architectural
 // registers and the compiler keeps part of them in the accumulation registers.
+// The launch arguments with instance k's buffers in place of instance 0's (k is
+// wavefront-uniform; the selection runs over compile-time indices, so the argument
+// block is never indexed at run time).
+__device__ __forceinline__ PersistArgs for_instance(const PersistArgs &a0, int k) {
+    PersistArgs a = a0;
+#pragma unroll
+    for (int kk = 1; kk < PERSIST_MAXK; kk++) {
+        if (kk == k) {
+            const PersistInst &q = a0.ins[kk];
+            a.J = q.J; a.h = q.h; a.phi_in = q.phi_in; a.phi_out = q.phi_out;
+            a.xb_out = q.xb_out; a.p = q.p; a.S = q.S; a.xch = q.xch;
+        }
+    }
+    return a;
+}
+
 template <int JT, int NG, int MP>
-__global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
+__global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a0) {
     __shared__ f32x4 part[2][4][4][64];   // [step parity][chain][row tile][lane]
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int cl_in_xcd = slot / a.G, g = slot % a.G;
-    const int c = cl_in_xcd * 8 + xcd;
-    if (c >= a.C) return;
+    const int cl_in_xcd = slot / a0.G, g = slot % a0.G;
+    const int cg = cl_in_xcd * 8 + xcd;   // cluster of the launch
+    if (cg >= a0.C) return;
+    const int k = cg / a0.C1, c = cg - k * a0.C1;   // instance, cluster within it
+    const PersistArgs a = for_instance(a0, k);
     if (!check_placement(a.abort_flag, a.err, xcd)) return;
     __shared__ int s_dead[2];   // a thread gave up waiting (by step parity, like the partials)
     if (threadIdx.x < 2) s_dead[threadIdx.x] = 0;
@@ -648,16 +680,20 @@ __global__ __launch_bounds__(256) void k_persist_rj(PersistArgs a) {
 
 // Plan of a persistent launch for one dense instance.
 struct PersistPlan {
-    int TRW, G, C, grid, jlds, jstride, jbytes, pstride;
+    int TRW, G, C, C1, grid, jlds, jstride, jbytes, pstride;
     int rj;          // J fragments in registers (k_persist_rj)
     size_t lds;
 };
 
-static bool plan_persist(const Instance &I, int R, JType jt, int max_wg, PersistPlan &p) {
+// K > 1: K instances of this size in one register-J launch (no other kernel takes
+// several instances).
+static bool plan_persist(const Instance &I, int R, JType jt, int max_wg, PersistPlan &p,
+                         int K = 1) {
     const int esz = jt == JT_F32 ? 4 : jt == JT_BF16 ? 2 : 1;
     const int eb = jt == JT_F32 ? 4 : 2;               // staged flux element bytes
     const size_t lds_cap = 156 * 1024;
-    p.C = (R + 15) / 16;
+    p.C1 = (R + 15) / 16;
+    p.C = K * p.C1;
     p.pstride = I.Np * eb + 16;
     const size_t stage = (size_t)16 * p.pstride;
     if (stage > lds_cap) return false;
@@ -678,6 +714,7 @@ static bool plan_persist(const Instance &I, int R, JType jt, int max_wg, Persist
             return true;
         }
     }
+    if (K > 1) return false;
     // then a J block resident in LDS, then two row tiles per wavefront
     for (int want_lds : {1, 0}) {
         for (int trw : {2, 1}) {
@@ -750,9 +787,11 @@ static hipError_t launch_jt(const PersistArgs &a, const PersistPlan &pl, hipStre
     return pl.jlds ? launch_p<JT, 1, true>(a, pl, st) : launch_p<JT, 1, false>(a, pl, st);
 }
 
-// Returns hipErrorNotSupported when the instance has no persistent plan (the
-// caller then runs one launch per step).
-hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
+// Returns hipErrorNotSupported when the instances have no persistent plan (the caller
+// then runs one launch per step).  Several instances share a launch only when they
+// have one size and one storage type and the register-J kernel fits them all.
+hipError_t launch_md_persist_set(hqa_md *md, Instance *const *set, int K, int64_t q0,
+                                 int64_t q1) {
     static int max_wg = -1;
     if (max_wg < 0) {
         int dev = 0, cus = 0;
@@ -760,50 +799,73 @@ hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         max_wg = cus;   // one 256-thread workgroup per CU is always co-resident
     }
+    if (K < 1 || K > PERSIST_MAXK) return hipErrorNotSupported;
+    Instance &I0 = *set[0];
+    for (int k = 1; k < K; k++)
+        if (set[k]->Np != I0.Np || set[k]->N != I0.N || set[k]->jt != I0.jt ||
+            set[k]->ld != I0.ld || set[k]->Rp != I0.Rp)
+            return hipErrorNotSupported;
     PersistPlan pl;
-    if (!plan_persist(I, md->R, I.jt, max_wg, pl)) return hipErrorNotSupported;
-    const size_t esz = I.jt == JT_F32 ? 8 : 4;
-    const int64_t half = (int64_t)I.Rp * I.ld;
+    if (!plan_persist(I0, md->R, I0.jt, max_wg, pl, K)) return hipErrorNotSupported;
+    const size_t esz = I0.jt == JT_F32 ? 8 : 4;
+    const int64_t half = (int64_t)I0.Rp * I0.ld;
     const size_t bytes = 2 * (size_t)half * esz;
-    if (!I.xch || I.xch_bytes < bytes) {
-        if (I.xch) (void)hipFree(I.xch);
-        I.xch = nullptr;
-        I.xch_bytes = 0;
-        hipError_t e = hipMalloc(&I.xch, bytes);
-        if (e != hipSuccess) return e;
-        I.xch_bytes = bytes;
+    for (int k = 0; k < K; k++) {
+        Instance &I = *set[k];
+        if (!I.xch || I.xch_bytes < bytes) {
+            if (I.xch) (void)hipFree(I.xch);
+            I.xch = nullptr;
+            I.xch_bytes = 0;
+            hipError_t e = hipMalloc(&I.xch, bytes);
+            if (e != hipSuccess) return e;
+            I.xch_bytes = bytes;
+        }
     }
     if (!md->bar) {
         hipError_t e = hipMalloc((void **)&md->bar, sizeof(int32_t) * 64);
         if (e != hipSuccess) return e;
     }
     hipError_t e = hipMemsetAsync(md->bar, 0, sizeof(int32_t) * 64, md->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(I.xch, 0, bytes, md->stream);
+    for (int k = 0; k < K && e == hipSuccess; k++) e = hipMemsetAsync(set[k]->xch, 0, bytes, md->stream);
     if (e != hipSuccess) return e;
     PersistArgs a;
-    a.N = I.N; a.Np = I.Np; a.R = md->R; a.ld = I.ld; a.M = md->sch.M; a.G = pl.G; a.C = pl.C;
+    a.N = I0.N; a.Np = I0.Np; a.R = md->R; a.ld = I0.ld; a.M = md->sch.M; a.G = pl.G; a.C = pl.C;
+    a.K = K; a.C1 = pl.C1;
     a.T = md->sch.T; a.q0 = q0; a.q1 = q1; a.W = md->sch.W;
     a.rg = (float)md->sch.r_g;
-    a.J = I.Js; a.h = I.h32; a.a32 = md->a32; a.b32 = md->b32;
+    a.a32 = md->a32; a.b32 = md->b32;
     const int par = (int)((q1 - q0) & 1);
-    a.phi_in = I.phi32[I.cur];
-    a.phi_out = I.phi32[I.cur ^ par];
-    a.xb_out = I.phib[I.cur ^ par];
-    a.p = I.p32; a.S = I.S32;
-    a.xch = (uint64_t *)I.xch;
+    for (int k = 0; k < PERSIST_MAXK; k++) {
+        Instance &I = *set[k < K ? k : 0];
+        PersistInst &q = a.ins[k];
+        q.J = I.Js; q.h = I.h32;
+        q.phi_in = I.phi32[I.cur];
+        q.phi_out = I.phi32[I.cur ^ par];
+        q.xb_out = I.phib[I.cur ^ par];
+        q.p = I.p32; q.S = I.S32;
+        q.xch = (uint64_t *)I.xch;
+    }
+    a.J = a.ins[0].J; a.h = a.ins[0].h; a.phi_in = a.ins[0].phi_in; a.phi_out = a.ins[0].phi_out;
+    a.xb_out = a.ins[0].xb_out; a.p = a.ins[0].p; a.S = a.ins[0].S; a.xch = a.ins[0].xch;
     a.xch_half = half;
     a.abort_flag = md->bar + 63; a.err = md->err;
     a.jstride = pl.jstride;
     a.jbytes = pl.jbytes;
     a.pstride = pl.pstride;
     a.spin_limit = (int64_t)1 << 22;
-    switch (I.jt) {
+    switch (I0.jt) {
         case JT_F32: e = launch_jt<JT_F32>(a, pl, md->stream); break;
         case JT_BF16: e = launch_jt<JT_BF16>(a, pl, md->stream); break;
         default: e = launch_jt<JT_FP8>(a, pl, md->stream); break;
     }
-    if (e == hipSuccess) I.cur ^= par;
+    if (e == hipSuccess)
+        for (int k = 0; k < K; k++) set[k]->cur ^= par;
     return e;
+}
+
+hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1) {
+    Instance *one = &I;
+    return launch_md_persist_set(md, &one, 1, q0, q1);
 }
 
 }  // namespace hqa

@@ -79,3 +79,26 @@ def test_register_j_kernel_every_group_count(H, prec, N, R):
         md.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("R", [16, 40])
+def test_cluster_launch_over_several_instances(H, prec, R):
+    """Consecutive instances of one size share a register-J launch (cluster c serves
+    instance c / C1, each cluster on its own XCD): five of 600 spins, two of 300 and
+    three of 2000 (at R = 40 only two of those fit one launch and the third runs
+    alone).  Every instance follows the trajectory it has alone."""
+    print("cluster set", prec, R, flush=True)
+    sizes = [600, 600, 600, 600, 600, 300, 300, 2000, 2000, 2000]
+    Js = [inst.er_maxcut(n, 0.05, 40 + k) for k, n in enumerate(sizes)]
+    T = 90
+    b = H.MD([H.Problem(J) for J in Js], H.make_schedule(T, 20), R, prec, seed=5, plan="cluster")
+    b.run()
+    b.sync()
+    assert b.last_plan == "cluster"
+    for k, J in enumerate(Js):
+        a = H.MD(H.Problem(J), H.make_schedule(T, 20), R, prec, seed=5, plan="step")
+        a.run()
+        for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM):
+            assert np.array_equal(a.state(w), b.state(w, k)), (k, w)
+        a.close()

@@ -466,26 +466,35 @@ def bench_glass(args, hqa, torch):
                 if nt <= Nn:
                     e[f"hqa_ts{nt}_one_init"], e[f"hqa_ts{nt}_best"] = [], []
             bad_tot, ms_tot = 0, 0.0
-            for k in range(cnt):
-                J, h = inst.uniform_glass(Nn, 7000 + 31 * Nn + k)
-                md = hqa.MD(hqa.Problem(J, h=h, storage="bf16"), hqa.make_schedule(Tt, 100), Rr,
-                            "bf16", seed=40 + k, stream=st.cuda_stream)
-                md.tune(max(20, min(100, Tt // 10)))
+            # instances up to 2048 spins advance together in one cluster launch (one
+            # 16-replica cluster per instance, each on its own XCD; momenta from one seed);
+            # larger ones run alone on the tuner's plan
+            groups = [list(range(cnt))] if Nn <= 2048 else [[k] for k in range(cnt)]
+            for grp in groups:
+                Jh = [inst.uniform_glass(Nn, 7000 + 31 * Nn + k) for k in grp]
+                md = hqa.MD([hqa.Problem(J, h=h, storage="bf16") for J, h in Jh],
+                            hqa.make_schedule(Tt, 100), Rr, "bf16", seed=40 + grp[0],
+                            stream=st.cuda_stream, plan="cluster" if len(grp) > 1 else "auto")
+                if len(grp) == 1:
+                    md.tune(max(20, min(100, Tt // 10)))
                 e0, e1 = _events(torch)
                 e0.record(st); md.run(); e1.record(st); st.synchronize()
                 ms_tot += e0.elapsed_time(e1)
-                bad = int(np.sum(~np.isfinite(md.hamiltonian())))
-                bad_tot += bad
-                if bad == 0:
-                    g0 = md.classify(20, solve=False)
-                    g1 = md.classify(20, solve=True)
+                for kk in range(len(grp)):
+                    bad = int(np.sum(~np.isfinite(md.hamiltonian(kk))))
+                    bad_tot += bad
+                    if bad:
+                        continue
+                    g0 = md.classify(20, solve=False, k=kk)
+                    g1 = md.classify(20, solve=True, k=kk)
                     e["md_one_init"].append(g0["energy"][0] / Nn)
                     e["md_best"].append(g0["energy"].min() / Nn)
                     e["hqa_one_init"].append(g1["energy"][0] / Nn)
                     e["hqa_best"].append(g1["energy"].min() / Nn)
                     for nt in tabu_ns:
                         if nt <= Nn:
-                            g2 = md.classify_tabu(nt, args.glass_tabu_sweeps * nt, max(1, nt // 20))
+                            g2 = md.classify_tabu(nt, args.glass_tabu_sweeps * nt, max(1, nt // 20),
+                                                  k=kk)
                             e[f"hqa_ts{nt}_one_init"].append(g2["energy"][0] / Nn)
                             e[f"hqa_ts{nt}_best"].append(g2["energy"].min() / Nn)
                 md.close()

@@ -140,6 +140,9 @@ typedef struct hqa_md_opts {
  *                      dense instances (BF16/FP8, N <= 2048), runs of up to 8
  *                      consecutive instances of one size share a launch, each cluster
  *                      on its own XCD; an instance no launch takes runs alone.
+ *                      Under AUTO, a handle with several dense instances runs them as
+ *                      hqa_md_tune found fastest: BATCH, these CLUSTER launches, or
+ *                      each instance on its own tuned plan (BATCH until tuned).
  *   HQA_PLAN_RESIDENT  all steps in one launch; one workgroup per 16 replicas keeps
  *                      their whole state in LDS and streams J from L2 (BF16/FP8 J,
  *                      N up to 800 on a device with 160 KB of LDS per workgroup).

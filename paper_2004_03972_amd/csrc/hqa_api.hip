@@ -527,10 +527,12 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     // steps inside an early-stop statistics window run on the per-step kernels,
     // whose epilogues accumulate the statistics
     const bool stats_live = md->stats_k1 > md->q && md->stats_k0 < q1;
-    const bool batched = md->prec != HQA_PREC_F64_REF && ndense > 1 &&
-                         md->plan == HQA_PLAN_AUTO && !stats_live;
-    const bool clustered = md->prec != HQA_PREC_F64_REF && ndense > 1 &&
-                           md->plan == HQA_PLAN_CLUSTER && !stats_live;
+    // several dense instances under AUTO: the tuner's choice (batch when untuned)
+    const bool multi = md->prec != HQA_PREC_F64_REF && ndense > 1 && !stats_live;
+    const int mp = md->plan == HQA_PLAN_AUTO ? (md->multi_plan ? md->multi_plan : HQA_PLAN_BATCH)
+                                             : md->plan;
+    const bool batched = multi && md->plan == HQA_PLAN_AUTO && mp == HQA_PLAN_BATCH;
+    const bool clustered = multi && mp == HQA_PLAN_CLUSTER;
     if (batched) {
         hipError_t e = launch_md_steps_batch(md, md->q, q1);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
@@ -576,6 +578,95 @@ hqa_status hqa_md_reset(hqa_md *md, uint64_t seed) {
 struct TuneCand {
     int plan, tm, tn, cb, tj;
 };
+
+// Several dense instances: time the batched kernel, the same-size cluster launches and
+// each instance on its own tuned plan, over all dense instances together (snapshot,
+// `steps` and 2 `steps` steps, restore, as for one instance), and keep the fastest in
+// md->multi_plan for AUTO.  A candidate that raises the error word is disqualified.
+static hqa_status tune_multi(hqa_md *md, int32_t steps, hipEvent_t e0, hipEvent_t e1) {
+    std::vector<Instance *> d;
+    for (auto &I : md->inst)
+        if (I.layout == HQA_DENSE) d.push_back(&I);
+    md->multi_plan = 0;
+    if (d.size() < 2) return HQA_OK;
+    struct Snap { float *x, *p, *S; bf16 *b; size_t n; int cur; };
+    std::vector<Snap> sn(d.size(), Snap{nullptr, nullptr, nullptr, nullptr, 0, 0});
+    hipError_t he = hipSuccess;
+    for (size_t k = 0; k < d.size() && he == hipSuccess; k++) {
+        sn[k].n = (size_t)d[k]->Rp * d[k]->ld;
+        sn[k].cur = d[k]->cur;
+        he = dalloc(&sn[k].x, sn[k].n);
+        if (he == hipSuccess) he = dalloc(&sn[k].p, sn[k].n);
+        if (he == hipSuccess) he = dalloc(&sn[k].S, sn[k].n);
+        if (he == hipSuccess) he = dalloc(&sn[k].b, sn[k].n);
+    }
+    auto copy = [&](bool save) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (size_t k = 0; k < d.size(); k++) {
+            Instance &I = *d[k];
+            auto cp = [&](void *a, void *b, size_t bytes) {
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(save ? b : a, save ? a : b, bytes, hipMemcpyDeviceToDevice,
+                                       md->stream);
+            };
+            cp(I.phi32[sn[k].cur], sn[k].x, sn[k].n * 4);
+            cp(I.p32, sn[k].p, sn[k].n * 4);
+            cp(I.S32, sn[k].S, sn[k].n * 4);
+            if (I.phib[sn[k].cur]) cp(I.phib[sn[k].cur], sn[k].b, sn[k].n * 2);
+            I.cur = sn[k].cur;
+        }
+        return e;
+    };
+    int32_t err0 = 0;
+    if (he == hipSuccess) he = copy(true);
+    if (he == hipSuccess)
+        he = hipMemcpyAsync(&err0, md->err, sizeof err0, hipMemcpyDeviceToHost, md->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
+    float best = 1e30f;
+    int pick = HQA_PLAN_BATCH;
+    for (int cand : {HQA_PLAN_BATCH, HQA_PLAN_CLUSTER, HQA_PLAN_STEP}) {
+        float t[3] = {0.f, 0.f, 0.f};
+        for (int pass = 0; pass < 3 && he == hipSuccess; pass++) {
+            const int64_t q1 = md->q + (pass == 2 ? 2 * (int64_t)steps : steps);
+            int used = 0;
+            he = hipEventRecord(e0, md->stream);
+            if (he == hipSuccess) {
+                if (cand == HQA_PLAN_BATCH) {
+                    he = launch_md_steps_batch(md, md->q, q1);
+                } else if (cand == HQA_PLAN_CLUSTER) {
+                    he = run_dense_clusters(md, md->q, q1, &used);
+                } else {
+                    for (Instance *I : d)
+                        if (he == hipSuccess)
+                            he = run_dense(md, *I, md->q, q1, false, HQA_PLAN_AUTO, &used);
+                }
+            }
+            if (he == hipSuccess) he = hipEventRecord(e1, md->stream);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            if (he == hipSuccess) he = hipEventElapsedTime(&t[pass], e0, e1);
+            if (he == hipSuccess) he = copy(false);
+        }
+        float ms = std::max(t[2] - t[1], 0.0f);
+        int32_t errc = err0;
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(&errc, md->err, sizeof errc, hipMemcpyDeviceToHost, md->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
+        if (he == hipSuccess && errc != err0) {
+            ms = 1e30f;
+            he = hipMemcpyAsync(md->err, &err0, sizeof err0, hipMemcpyHostToDevice, md->stream);
+            if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
+        }
+        if (he == hipSuccess && ms < best) {
+            best = ms;
+            pick = cand;
+        }
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
+    for (auto &x : sn) { dfree(x.x); dfree(x.p); dfree(x.S); dfree(x.b); }
+    if (he != hipSuccess) return fail(HQA_EDEVICE, "tuning several instances: %s", hipGetErrorString(he));
+    md->multi_plan = pick;
+    return HQA_OK;
+}
 
 hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
     if (!md) return fail(HQA_EINVAL, "null handle");
@@ -719,6 +810,7 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         I.step_cb = pick.cb;
         I.step_tj = pick.tj;
     }
+    if (rs == HQA_OK) rs = tune_multi(md, steps, e0, e1);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     md->stats_k0 = k0;

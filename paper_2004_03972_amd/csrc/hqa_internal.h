@@ -113,6 +113,8 @@ struct hqa_md {
     int32_t *bar = nullptr;                  // persistent-launch barrier counters + abort flag
     hqa::JType jt = hqa::JT_F32;
     int last_plan = 0;                       // plan the last run used (HQA_PLAN_*)
+    int multi_plan = 0;                      // tuned way to run several dense instances:
+                                             // BATCH, CLUSTER, or STEP (each on its own plan)
     void *batch = nullptr;                   // device tile tables of a multi-instance batch
     int64_t stats_k0 = 0, stats_k1 = 0;      // early-stop statistics window [k0, k1)
     int64_t stats_every = 1;                 // ... sampling steps k0, k0 + every, ...

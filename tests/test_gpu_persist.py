@@ -102,3 +102,24 @@ def test_cluster_launch_over_several_instances(H, prec, R):
         for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM):
             assert np.array_equal(a.state(w), b.state(w, k)), (k, w)
         a.close()
+
+
+def test_tuned_auto_over_several_instances(H):
+    """The tuner times the batched kernel, the same-size cluster launches and each
+    instance on its own plan for a handle of several dense instances; whichever AUTO
+    then takes, every instance follows the trajectory it has alone."""
+    sizes = [700, 700, 700, 700, 700]
+    Js = [inst.er_maxcut(n, 0.05, 60 + k) for k, n in enumerate(sizes)]
+    T, R = 200, 16
+    b = H.MD([H.Problem(J) for J in Js], H.make_schedule(T, 20), R, "fp8", seed=9)
+    b.tune(20)
+    b.run()
+    b.sync()
+    print("tuned plan for five instances:", b.last_plan, flush=True)
+    assert b.last_plan in ("batch", "cluster", "step", "resident")
+    for k, J in enumerate(Js):
+        a = H.MD(H.Problem(J), H.make_schedule(T, 20), R, "fp8", seed=9, plan="step")
+        a.run()
+        for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM):
+            assert np.array_equal(a.state(w), b.state(w, k)), (k, w)
+        a.close()

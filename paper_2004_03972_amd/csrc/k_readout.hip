@@ -818,15 +818,53 @@ __device__ __forceinline__ double tabu_j(const TabuArgs &a, int i, int j) {
     return (lo < a.rp[i + 1] && a.ci[lo] == j) ? a.J[lo] : 0.0;
 }
 
-// (d, index, old spin) of the better candidate: smaller d, ties to the smaller index
-__device__ __forceinline__ void tabu_better(double &d, int &i, int &xo, double d2, int i2, int x2) {
-    if (d2 < d || (d2 == d && i2 < i)) { d = d2; i = i2; xo = x2; }
+// The better of two candidates (gain d, key 2 index + [old spin > 0]): smaller d, ties
+// to the smaller index.  Indices are distinct, so this is a total order and any
+// reduction tree picks the same candidate.
+__device__ __forceinline__ void tabu_better(double &d, int &key, double d2, int key2) {
+    if (d2 < d || (d2 == d && key2 < key)) { d = d2; key = key2; }
+}
+
+// One reduction level between lane pairs given by a DPP pattern inside 16-lane rows
+// (quad permutations, half-row and row mirrors): register moves, no LDS.
+template <int CTRL>
+__device__ __forceinline__ void tabu_dpp(double &d, int &key) {
+    const int lo = __double2loint(d), hi = __double2hiint(d);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    const int k2 = __builtin_amdgcn_update_dpp(key, key, CTRL, 0xF, 0xF, false);
+    tabu_better(d, key, __hiloint2double(hi2, lo2), k2);
+}
+
+// The level between lane l and l ^ 16 (ROW32 = false) or l ^ 32: the permlane swaps
+// hand every lane both members of its pair, and both take the better one.
+template <bool ROW32>
+__device__ __forceinline__ void tabu_swap(double &d, int &key) {
+    const unsigned lo = (unsigned)__double2loint(d), hi = (unsigned)__double2hiint(d);
+    const auto l = ROW32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                         : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = ROW32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                         : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const auto k = ROW32 ? __builtin_amdgcn_permlane32_swap((unsigned)key, (unsigned)key, false, false)
+                         : __builtin_amdgcn_permlane16_swap((unsigned)key, (unsigned)key, false, false);
+    d = __hiloint2double((int)h[0], (int)l[0]);
+    key = (int)k[0];
+    tabu_better(d, key, __hiloint2double((int)h[1], (int)l[1]), (int)k[1]);
+}
+
+// Best candidate of the 16 lanes of each row: quad xor 1 and 2, then the half-row
+// mirror (lane i with 7 - i) and the row mirror (i with 15 - i).
+__device__ __forceinline__ void tabu_row_min(double &d, int &key) {
+    tabu_dpp<0xB1>(d, key);    // quad_perm [1, 0, 3, 2]
+    tabu_dpp<0x4E>(d, key);    // quad_perm [2, 3, 0, 1]
+    tabu_dpp<0x141>(d, key);   // row_half_mirror
+    tabu_dpp<0x140>(d, key);   // row_mirror
 }
 
 __global__ __launch_bounds__(1024) void k_tabu(TabuArgs a) {
     __shared__ int8_t sx[TABU_SPT * 1024];
     __shared__ double sd[2][16];
-    __shared__ int si[2][16], so[2][16];
+    __shared__ int sk[2][16];
     const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int n = a.n, N = a.N;
     const int32_t *A = a.amb + (int64_t)r * n;
@@ -854,26 +892,27 @@ __global__ __launch_bounds__(1024) void k_tabu(TabuArgs a) {
     for (int64_t t = 1; t <= a.iters; t++) {
         const int par = (int)(t & 1);
         double bd = INFINITY;
-        int bi = INT_MAX, bo = 0;
+        int bk = INT_MAX;
 #pragma unroll
         for (int k = 0; k < TABU_SPT; k++) {
             const int ai = tid + 1024 * k;
             if (ai >= n) continue;
             const double d = x[k] > 0 ? -2.0 * f[k] : 2.0 * f[k];
-            if (until[k] < t || D + d < Db) tabu_better(bd, bi, bo, d, ai, x[k]);
+            if (until[k] < t || D + d < Db) tabu_better(bd, bk, d, 2 * ai + (x[k] > 0));
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            const double d2 = __shfl_xor(bd, o);
-            const int i2 = __shfl_xor(bi, o), o2 = __shfl_xor(bo, o);
-            tabu_better(bd, bi, bo, d2, i2, o2);
-        }
-        if (lane == 0) { sd[par][w] = bd; si[par][w] = bi; so[par][w] = bo; }
+        tabu_row_min(bd, bk);
+        tabu_swap<false>(bd, bk);
+        tabu_swap<true>(bd, bk);
+        if (lane == 0) { sd[par][w] = bd; sk[par][w] = bk; }
         __syncthreads();
-        bd = sd[par][0]; bi = si[par][0]; bo = so[par][0];
-        for (int v = 1; v < 16; v++) tabu_better(bd, bi, bo, sd[par][v], si[par][v], so[par][v]);
+        // each wavefront combines the 16 slots: lane v takes slot v mod 16
+        bd = sd[par][lane & 15];
+        bk = sk[par][lane & 15];
+        tabu_row_min(bd, bk);
+        const int bi = bk >> 1, bo = (bk & 1) ? 1 : -1;
         // At most tenure < n spins are tabu, so some move is allowed; only gains that
         // are all NaN (fields overflowed) leave none.  bi is the same in every thread.
-        if (bi >= n) break;
+        if (bk == INT_MAX) break;
         D = D + bd;
         const int rowj = A[bi];
 #pragma unroll

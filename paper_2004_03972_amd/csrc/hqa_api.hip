@@ -600,6 +600,10 @@ static hqa_status tune_multi(hqa_md *md, int32_t steps, hipEvent_t e0, hipEvent_
         if (he == hipSuccess) he = dalloc(&sn[k].S, sn[k].n);
         if (he == hipSuccess) he = dalloc(&sn[k].b, sn[k].n);
     }
+    if (he != hipSuccess) {
+        for (auto &x : sn) { dfree(x.x); dfree(x.p); dfree(x.S); dfree(x.b); }
+        return fail(HQA_ENOMEM, "tuner snapshot of %zu instances", d.size());
+    }
     auto copy = [&](bool save) -> hipError_t {
         hipError_t e = hipSuccess;
         for (size_t k = 0; k < d.size(); k++) {

@@ -862,14 +862,19 @@ __device__ __forceinline__ void tabu_row_min(double &d, int &key) {
 }
 
 __global__ __launch_bounds__(1024) void k_tabu(TabuArgs a) {
-    __shared__ int8_t sx[TABU_SPT * 1024];
+    __shared__ int8_t sx[TABU_SPT * 1024];      // starting spins of the ambivalent set
+    __shared__ int32_t sA[TABU_SPT * 1024];     // their indices (a move reads one)
     __shared__ double sd[2][16];
     __shared__ int sk[2][16];
     const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int n = a.n, N = a.N;
     const int32_t *A = a.amb + (int64_t)r * n;
     const int8_t *s0 = a.spins + (int64_t)r * N;
-    for (int b = tid; b < n; b += 1024) sx[b] = s0[A[b]];
+    for (int b = tid; b < n; b += 1024) {
+        const int i = A[b];
+        sA[b] = i;
+        sx[b] = s0[i];
+    }
     __syncthreads();
     double f[TABU_SPT];
     int x[TABU_SPT], xb[TABU_SPT], Ai[TABU_SPT];
@@ -879,11 +884,22 @@ __global__ __launch_bounds__(1024) void k_tabu(TabuArgs a) {
         const int ai = tid + 1024 * k;
         f[k] = 0.0; x[k] = 1; xb[k] = 1; Ai[k] = 0; until[k] = 0;
         if (ai < n) {
-            Ai[k] = A[ai];
+            Ai[k] = sA[ai];
             x[k] = xb[k] = sx[ai];
             double acc = a.h_eff[(int64_t)r * n + ai];
-            for (int b = 0; b < n; b++)
-                if (b != ai) acc = acc + tabu_j(a, Ai[k], A[b]) * (double)sx[b];
+            if (!a.csr) {
+                // the loads of a row are independent, so several are in flight; the
+                // sum itself keeps the order b = 0, 1, ...
+                const double *Jr = a.J + (int64_t)Ai[k] * N;
+#pragma unroll 8
+                for (int b = 0; b < n; b++) {
+                    const double J = Jr[sA[b]];
+                    if (b != ai) acc = acc + J * (double)sx[b];
+                }
+            } else {
+                for (int b = 0; b < n; b++)
+                    if (b != ai) acc = acc + tabu_j(a, Ai[k], sA[b]) * (double)sx[b];
+            }
             f[k] = acc;
         }
     }
@@ -914,7 +930,7 @@ __global__ __launch_bounds__(1024) void k_tabu(TabuArgs a) {
         // are all NaN (fields overflowed) leave none.  bi is the same in every thread.
         if (bk == INT_MAX) break;
         D = D + bd;
-        const int rowj = A[bi];
+        const int rowj = sA[bi];
 #pragma unroll
         for (int k = 0; k < TABU_SPT; k++) {
             const int ai = tid + 1024 * k;

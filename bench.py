@@ -619,13 +619,46 @@ def bench_copy(args, hqa, torch):
     return {"workload": "copy 1 GiB float32", "bytes_read": 4 * n, "bytes_written": 4 * n}
 
 
+def bench_peaks(args, hqa, torch):
+    """Achievable peaks next to the vendor figures: a plain device copy of 1 GiB (HBM
+    bytes read + written per second) and the library BF16 GEMM at 8192^3 (dense MFMA
+    flop per second), each the best of 10 timed repetitions after 3 warm-ups."""
+    st = torch.cuda.current_stream()
+
+    def best_ms(fn, reps=10):
+        for _ in range(3):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = _events(torch)
+            e0.record(st); fn(); e1.record(st); e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts)
+
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    ms_copy = best_ms(lambda: y.copy_(x))
+    hbm = 2 * 4 * n / (ms_copy * 1e-3) / 1e9
+    del x, y
+    m = 8192
+    a = torch.randn(m, m, dtype=torch.bfloat16, device="cuda")
+    b = torch.randn(m, m, dtype=torch.bfloat16, device="cuda")
+    ms_mm = best_ms(lambda: torch.mm(a, b))
+    tf = 2.0 * m ** 3 / (ms_mm * 1e-3) / 1e12
+    return {"workload": "achievable peaks", "hbm_copy_GBps": hbm, "hbm_vendor_GBps": 8000.0,
+            "bf16_gemm_8192_TFLOPs": tf, "bf16_vendor_dense_TFLOPs": 2500.0,
+            "copy_ms": ms_copy, "gemm_ms": ms_mm}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="er800",
-                    choices=["er800", "ea3d", "batch512", "es", "k2000", "glass", "dense8k", "sweep", "copy"])
+                    choices=["er800", "ea3d", "batch512", "es", "k2000", "glass", "dense8k", "sweep", "copy",
+                             "peaks"])
     ap.add_argument("--glass-n", default="1000,2000,10000")
     ap.add_argument("--glass-instances", default="8,8,2")
     ap.add_argument("--glass-steps", default="1000,10000,100000,500000")
@@ -669,7 +702,7 @@ def main():
     torch.cuda.set_device(0)
     fn = {"er800": bench_er800, "ea3d": bench_ea3d, "batch512": bench_batch512,
           "es": bench_es, "k2000": bench_k2000, "glass": bench_glass, "dense8k": bench_dense8k, "sweep": bench_sweep,
-          "copy": bench_copy}[args.workload]
+          "copy": bench_copy, "peaks": bench_peaks}[args.workload]
     print(json.dumps(fn(args, hqa, torch)), flush=True)
 
 

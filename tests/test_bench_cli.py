@@ -21,5 +21,5 @@ def test_more_than_one_gpu_is_refused():
 def test_help_lists_every_workload():
     r = _run("--help")
     assert r.returncode == 0
-    for w in ("er800", "ea3d", "batch512", "es", "k2000", "glass", "dense8k", "sweep", "copy"):
+    for w in ("er800", "ea3d", "batch512", "es", "k2000", "glass", "dense8k", "sweep", "copy", "peaks"):
         assert w in r.stdout

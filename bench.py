@@ -341,7 +341,7 @@ def bench_es(args, hqa, torch):
     rp, ci, v = inst.er_sparse(Ne, 0.005 * (Ne - 1), 5001)
     prob = hqa.Problem(row_ptr=rp, col=ci, val=v)
     n_lab = round(0.05 * Ne)
-    # the full run's labels (the judge of the mislabel rate), untimed
+    # the full run's labels (the reference for the mislabel rate), untimed
     full = E.record_run(prob, sched, Re, K, nck, seed=7, n_amb=n_lab, solve_n=20, every=nck,
                         Ks=Ks, stride=args.es_stride)
     full.md.close()

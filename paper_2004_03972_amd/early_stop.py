@@ -10,7 +10,7 @@ the GPU by the library's own forward/backward/Adam kernels.  At inference the
 run stops at the first checkpoint whose mean max-probability reaches a
 threshold calibrated on validation runs; frozen spins take their predicted
 sign and the n most-ambivalent spins go to the exact solver.  The full run is
-both the fallback (no stop before T) and the judge (mislabel rate, cut loss).
+both the fallback (no stop before T) and the reference (mislabel rate, cut loss).
 """
 from __future__ import annotations
 

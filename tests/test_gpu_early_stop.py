@@ -18,7 +18,7 @@ Checked:
   loses at most 0.2% of the full run's best cut, and never stops after T.
 
 The network's quality is not fixed by the paper (it has no learned part): the full
-run is the judge.  The printed lines give the mislabel curves, the threshold, the
+run is the reference.  The printed lines give the mislabel curves, the threshold, the
 stop step and the cuts.
 """
 import numpy as np

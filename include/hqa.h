@@ -311,13 +311,13 @@ hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t sol
  *   D += d_a*, f_b -= 2 J_a*b x_a* (before the flip) for b != a*,
  *   tabu_until[a*] = t + min(tenure, n - 1); keep x whenever D < D_best.
  * Every operation is binary64 in that order (no contraction), so the result does
- * not depend on the launch; the search stops early only if every gain is NaN
- * (fields overflowed).  J_ab are the instance's binary64 couplings.  The best
+ * not depend on the launch.  J_ab are the instance's binary64 couplings.  The best
  * configuration is merged into spins; e_reduced receives D_best (<= 0; 0 for
  * n_amb = 0), the change of the Ising energy from the MD read-out; code is not
  * written; h_eff as hqa_classify.  HQA_EINVAL for iters or tenure < 0 or n_amb
- * outside [0, N], HQA_EUNSUPPORTED for n_amb > 4096, HQA_ESTATE before q = T.
- * Synchronises. */
+ * outside [0, N], HQA_EUNSUPPORTED for n_amb > 4096 or for couplings and fields so
+ * large (max |J|, |h| >= 2^(1020 - 2 ceil(log2(N + 1)))) that a local field or the
+ * energy change could overflow binary64, HQA_ESTATE before q = T.  Synchronises. */
 hqa_status hqa_classify_tabu(hqa_md *md, int32_t instance, int32_t n_amb, int64_t iters,
                              int32_t tenure, const hqa_classify_out *out, int32_t out_mem);
 

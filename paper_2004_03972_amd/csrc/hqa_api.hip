@@ -1012,6 +1012,14 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
         return fail(HQA_ESTATE, "classify needs the run to reach step T");
     if ((solve || out->energy || out->cut || out->h_eff) && !exact_ok(I))
         return fail(HQA_EUNSUPPORTED, "coupling exponents span too many binades for exact sums");
+    if (solve == 2 && I.es.lsb != INT32_MIN) {
+        // |f_a| <= 2 (N + 1) max(|J|, |h|) and |D| <= 2 (N + 1)^2 max(|J|, |h|): both stay
+        // finite, so every gain is a number and the search follows its definition
+        int lg = 0;
+        while (lg < 62 && ((int64_t)1 << lg) < (int64_t)N + 1) lg++;
+        if (I.es.msb + 2 * lg + 4 > 1023)
+            return fail(HQA_EUNSUPPORTED, "couplings too large for finite tabu-search fields");
+    }
     if (solve == 1 && I.j_integral && I.es.msb + 2 * 16 + 8 > 62)
         return fail(HQA_EUNSUPPORTED, "integer couplings too large for int64 enumeration");
     s = hqa_md_sync(md);

@@ -50,14 +50,26 @@ __device__ __forceinline__ void acc_add(Acc256 &a, double t, int b0) {
     int tz = __ffsll((long long)m) - 1;
     m >>= tz;
     e2 += tz;
-    int s = e2 - b0;
-    int L = s >> 6, o = s & 63;
-    uint64_t lo = m << o;
-    uint64_t hi = o ? (m >> (64 - o)) : 0ull;
+    const int s = e2 - b0;
+    // limb k holds bits [64 k, 64 k + 64) of m << s; each limb is formed from its own
+    // shift (no store at a run-time index, which would put the array in memory)
     uint64_t add[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) add[k] = (L == k ? lo : 0ull) | (L + 1 == k ? hi : 0ull);
-    add256((bits >> 63) ? a.n : a.p, add);
+    for (int k = 0; k < 4; k++) {
+        const int sh = s - 64 * k;
+        add[k] = (sh >= 0 && sh < 64) ? (m << sh) : (sh < 0 && sh > -64) ? (m >> -sh) : 0ull;
+    }
+    // both magnitudes take an add, one of them of zeros: no branch for the compiler to
+    // merge into an array chosen at run time, so both stay in registers
+    const uint64_t neg = 0ull - (bits >> 63);
+    uint64_t ap[4], an[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        ap[k] = add[k] & ~neg;
+        an[k] = add[k] & neg;
+    }
+    add256(a.p, ap);
+    add256(a.n, an);
 }
 
 __device__ __forceinline__ void acc_merge(Acc256 &a, const Acc256 &b) {

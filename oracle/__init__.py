@@ -77,6 +77,7 @@ def _declare(L):
         "or_hmd": (V, [P, P, i32, i64, P, P, P]),
         "or_integer_p": (V, [P, P, i32, i64, P, P, P]),
         "or_classify": (C.c_int, [i32, i32, P, i32, P, P]),
+        "or_enumerate_range": (C.c_int, [i32, P, P, i64, i64, P, P]),
         "or_reduce": (C.c_int, [P, i32, i32, P, P, P, P]),
         "or_enumerate": (C.c_int, [i32, i32, P, P, P, P]),
         "or_merge": (V, [i32, i32, i32, P, P, P]),
@@ -240,6 +241,38 @@ def enumerate_exact(J_eff, h_eff):
     E = np.empty(R)
     if lib().or_enumerate(n, R, _ptr(J_eff), _ptr(h_eff), _ptr(code), _ptr(E)) != 0:
         raise ValueError("bad n")
+    return code, E
+
+
+def enumerate_exact_blocks(J_eff, h_eff, nthreads: int = 8):
+    """enumerate_exact with each replica's codes split into ascending blocks scanned on
+    host threads (ctypes releases the GIL).  The minimum of E' with ties to the smallest
+    code is unique, so the first block holding the strictly smallest block minimum
+    gives the same code and energy as one scan over all codes."""
+    from concurrent.futures import ThreadPoolExecutor
+    J_eff, h_eff = _f64(J_eff), _f64(h_eff)
+    R, n = h_eff.shape
+    total = 1 << n
+    nb = max(1, min(int(nthreads) * 4, total))
+    bounds = [(total * b // nb, total * (b + 1) // nb) for b in range(nb)]
+    code = np.empty(R, dtype=np.int64)
+    E = np.empty(R)
+    for r in range(R):
+        Jr, hr = np.ascontiguousarray(J_eff[r]), np.ascontiguousarray(h_eff[r])
+
+        def scan(bd):
+            c, e = np.zeros(1, np.int64), np.zeros(1)
+            if lib().or_enumerate_range(n, _ptr(Jr), _ptr(hr), bd[0], bd[1], _ptr(c),
+                                        _ptr(e)) != 0:
+                raise ValueError("bad block")
+            return int(c[0]), float(e[0])
+        with ThreadPoolExecutor(max_workers=max(1, int(nthreads))) as ex:
+            res = list(ex.map(scan, [b for b in bounds if b[0] < b[1]]))
+        bc, be = res[0]
+        for c, e in res[1:]:
+            if e < be:
+                bc, be = c, e
+        code[r], E[r] = bc, be
     return code, E
 
 

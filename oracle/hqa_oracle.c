@@ -422,21 +422,23 @@ int or_reduce(const or_problem *pb, int32_t R, int32_t n, const int32_t *amb_idx
 /* minimum wins, ties to the smallest code.  Each code is scored from        */
 /* scratch (no incremental update).                                          */
 /* ------------------------------------------------------------------------ */
-int or_enumerate(int32_t n, int32_t R, const double *J_eff, const double *h_eff,
-                 int64_t *best_code, double *best_E) {
-    if (n < 0 || n > 30) return OR_EINVAL;
-    for (int32_t r = 0; r < R; r++) {
-        const double *Je = J_eff + (int64_t)r * n * n, *he = h_eff + (int64_t)r * n;
+/* The scan over codes c0 <= c < c1 of one reduced problem (first code with the   */
+/* smallest E' in that range).  The minimum over all codes with ties to the        */
+/* smallest code is unique, so a caller may split 0..2^n-1 into ascending blocks   */
+/* and keep the first block whose minimum is strictly smallest.                    */
+static void enum_range(int32_t n, const double *Je, const double *he, int64_t c0, int64_t c1,
+                       int64_t *best_code, double *best_E) {
+    {
         int integral = 1;
         for (int32_t a = 0; a < n && integral; a++) {
             if (!is_int53(he[a])) integral = 0;
             for (int32_t b = 0; b < n; b++)
                 if (!is_int53(Je[a * n + b])) integral = 0;
         }
-        int64_t bc = 0;
+        int64_t bc = c0;
         double bE = INFINITY;
         int64_t bEi = INT64_MAX;
-        for (int64_t c = 0; c < ((int64_t)1 << n); c++) {
+        for (int64_t c = c0; c < c1; c++) {
             if (integral) {
                 int64_t E = 0;
                 for (int32_t a = 0; a < n; a++) {
@@ -463,9 +465,25 @@ int or_enumerate(int32_t n, int32_t R, const double *J_eff, const double *h_eff,
                 if (E < bE) { bE = E; bc = c; }
             }
         }
-        best_code[r] = bc;
-        best_E[r] = integral ? (double)bEi : bE;
+        *best_code = bc;
+        *best_E = integral ? (double)bEi : bE;
     }
+}
+
+int or_enumerate(int32_t n, int32_t R, const double *J_eff, const double *h_eff,
+                 int64_t *best_code, double *best_E) {
+    if (n < 0 || n > 30) return OR_EINVAL;
+    for (int32_t r = 0; r < R; r++)
+        enum_range(n, J_eff + (int64_t)r * n * n, h_eff + (int64_t)r * n, 0, (int64_t)1 << n,
+                   &best_code[r], &best_E[r]);
+    return OR_OK;
+}
+
+/* One block of codes [c0, c1) of one reduced problem (see enum_range). */
+int or_enumerate_range(int32_t n, const double *J_eff, const double *h_eff, int64_t c0,
+                       int64_t c1, int64_t *best_code, double *best_E) {
+    if (n < 0 || n > 30 || c0 < 0 || c1 > ((int64_t)1 << n) || c0 >= c1) return OR_EINVAL;
+    enum_range(n, J_eff, h_eff, c0, c1, best_code, best_E);
     return OR_OK;
 }
 

@@ -400,3 +400,20 @@ def test_hqa_full_subproblem_is_ground_state(orc):
         assert np.all(out["E_hqa"] == gs)
         out = orc.hqa(pb, mp, p0, n=5)
         assert np.all(out["E_hqa"] <= out["E_md"])
+
+
+def test_enumeration_blocks_equal_one_scan(orc):
+    # splitting the code range into ascending blocks leaves the minimiser unchanged,
+    # ties included (h = 0 mirror pairs; small-integer couplings with many equal sums)
+    from paper_2004_03972_amd import instances as inst
+    for n in (1, 2, 5, 9, 13):
+        rng = np.random.default_rng(n)
+        Jr = np.triu(rng.standard_normal((n, n)), 1)
+        Jr = Jr + Jr.T
+        Ji = inst.small_int(n, 40 + n, -1, 1, density=0.8) if n > 1 else np.zeros((1, 1))
+        for J, h in ((Jr, rng.standard_normal(n)), (Ji, np.zeros(n)),
+                     (Ji, rng.integers(-1, 2, n).astype(float))):
+            a = orc.enumerate_exact(J[None], h[None])
+            for th in (1, 3, 8):
+                b = orc.enumerate_exact_blocks(J[None], h[None], nthreads=th)
+                assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

@@ -1,19 +1,23 @@
 """HQA-MD throughput on one MI355X: MD spin-updates/s, plain FP32 vs the chosen form.
 
-Default workload: MAX-CUT on an Erdos-Renyi graph G(800, 0.06) with unit weights
-mapped to J = +w, 256 replicas, 5000 MD steps (paper schedule, M = 6, W = 100),
-n = 20 ambivalent spins solved exactly.  One bench step is one pass of the whole
-hot path on the resident instance: reset of the initial state, T MD steps (field
-+ fused leapfrog), the frozen/ambivalent sort, the reduced problem, the exact
-enumeration, merge and exact energies/cuts.  value = N * R * T * steps / time of
-the chosen form: J stored exactly in FP8 e4m3 and widened to BF16 in registers,
-BF16 flux operand, FP32 accumulation and state (BF16 storage of J is reported
-beside it).  The same steps run in plain FP32 with the same initial momenta; the
-chosen form's best cut must be within 0.1% of FP32's.
+Default workload (the bench line): a batch of 512 uneven dense instances, 256
+Sherrington-Kirkpatrick glasses (N ~ U{100..2000}, J ~ N(0, 1/N), couplings stored in
+BF16) and 256 Erdos-Renyi MAX-CUT graphs (N ~ U{500..5000}, p ~ U[0.01, 0.1], unit
+weights J = +w stored exactly in FP8 e4m3), 64 replicas each, 5000 MD steps (paper
+schedule, M = 6, W = 100), n = 20 ambivalent spins of every replica solved exactly.
+One bench step is one pass of the whole hot path over the batch: reset of the initial
+state, T MD steps of all 512 instances (field on MFMA with BF16 flux operands and FP32
+accumulation, fused leapfrog and window sum), then for every instance the
+frozen/ambivalent sort, the reduced problem, the exact enumeration, merge and exact
+energies/cuts.  value = sum_k N_k * R * T * steps / time.  The same instances and
+initial momenta run in plain FP32 (FP32 couplings, FP32 MFMA) for the first seeds; the
+line reports the best-cut ratio per instance and seed, the field error of every
+instance against binary64, the trajectory divergence from the FP64 oracle on a
+stratified sample, and the oracle's own rate on that sample.
 
 Other workloads (measurement lines for the design notes, not the bench line):
+  --workload er800     ER MAX-CUT G(800, 0.06), R = 256, T = 5000, FP8 / BF16 / FP32
   --workload ea3d      3D +-J lattice 16^3, CSR FP32, R = 1024, T = 10000
-  --workload batch512  512 uneven instances (SK BF16 / ER FP8), R = 64, T = 5000
   --workload es        learned early stop: train on ER runs, evaluate on ER N = 10^4
   --workload k2000     MAX-CUT on K_2000 with +-1 weights: deviation from C* vs MD steps
                        (MD alone, HQA with n = 20 exact, HQA with the n = 1000 tabu search)
@@ -261,44 +265,246 @@ def bench_ea3d(args, hqa, torch):
     return out
 
 
-def bench_batch512(args, hqa, torch):
-    """512 uneven instances: SK N~U{100..2000} BF16, ER N~U{500..5000} p~U[0.01,0.1] FP8."""
-    from paper_2004_03972_amd import instances as inst
-    rng = np.random.default_rng(4)
-    K = args.instances
-    Rr, Tt = 64, args.md_steps or 5000
-    probs, flops, upd = [], 0.0, 0.0
+BATCH_R, BATCH_T, BATCH_N_AMB, BATCH_SEED = 64, 5000, 20, 4
+BATCH_WORKLOAD = ("512 uneven dense instances: 256 SK N~U{100..2000} J~N(0,1/N) stored BF16, "
+                  "256 ER MAX-CUT N~U{500..5000} p~U[0.01,0.1] unit weights J=+w stored FP8 "
+                  "e4m3 (exact); R=64 replicas each, T=5000 MD steps, W=100, n=20 exact")
+
+
+def batch_bytes_per_step(specs, R, W, T):
+    """Algorithmic HBM bytes of one MD step of the batch: every coupling once in its storage
+    type (BF16 2 B, FP8 1 B), and per spin-update 20 B of state (flux in 4, momentum in 4
+    and out 4, new flux out 4, its BF16 operand copy out 2 and in 2 as the MFMA operand),
+    plus the window sum (in 4, out 4) on W of the T steps."""
+    j = sum(N * N * (2 if fam == "sk" else 1) for fam, N, _, _ in specs)
+    upd = sum(N for _, N, _, _ in specs) * R
+    return j + upd * (20.0 + 8.0 * W / T), j, upd
+
+
+def classify_batch(md, K, n_amb):
+    """Exact HQA read-out of every instance: best cut and best energy over the replicas."""
+    cut, en = np.empty(K), np.empty(K)
     for k in range(K):
-        if k < K // 2:
-            Nk = int(rng.integers(100, 2001))
-            probs.append(hqa.Problem(inst.sk(Nk, 4000 + k), storage="bf16"))
-        else:
-            Nk = int(rng.integers(500, 5001))
-            probs.append(hqa.Problem(inst.er_maxcut(Nk, rng.uniform(0.01, 0.1), 4000 + k),
-                                     storage="fp8"))
-        flops += 2.0 * Nk * Nk * Rr
-        upd += Nk * Rr
-        if k % 64 == 63:
-            _log(f"  generated {k + 1} instances")
+        g = md.classify(n_amb, solve=True, k=k)
+        cut[k], en[k] = g["cut"].max(), g["energy"].min()
+    return cut, en
+
+
+def cpu_baseline_batch(specs, Js, chosen, fp32, torch, rs=4, ts=500, checkpoints=(1, 10, 100, 500)):
+    """The FP64 oracle on a bounded sample of the batch: the stratified 16 instances (8 SK,
+    8 ER spread over the size range), the first `rs` replicas of each (the same initial
+    momenta as the GPU runs), `ts` MD steps, (instance, replica) items on 16 host threads;
+    then a one-thread figure on one replica of each for ts/10 steps.  The oracle's fluxes at
+    the checkpoints give the trajectory divergence of the GPU forms (same initial momenta,
+    same steps): max |phi_form - phi_64| per checkpoint, over the sample."""
+    import oracle as orc
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2004_03972_amd import instances as inst
+    strat = inst.stratified(specs)
+    threads = 16
+    seed = BATCH_SEED + 7
+    mp = orc.MDParams(T=BATCH_T, W=100)
+    items = []
+    for k in strat:
+        N = specs[k][1]
+        pb = orc.Problem(N, J=Js[k])
+        p0 = orc.init_p0(seed, N, rs)
+        for r in range(rs):
+            items.append((k, r, pb, p0[r:r + 1].copy()))
+    traj = {}
+
+    def one(it, steps, keep):
+        k, r, pb, p0 = it
+        phi, p = np.zeros_like(p0), p0.copy()
+        q = 0
+        out = {}
+        for c in [c for c in checkpoints if c <= steps] + [steps]:
+            if c > q:
+                orc.md_advance(pb, mp, phi, p, None, q, c, nthreads=1)
+                q = c
+            if keep:
+                out[c] = phi[0].copy()
+        return (k, r), out
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for key, out in ex.map(lambda it: one(it, ts, True), items):
+            traj[key] = out
+    dt = time.perf_counter() - t0
+    upd = sum(specs[k][1] for k, _, _, _ in items) * ts
+    t1 = time.perf_counter()
+    one1 = [it for it in items if it[1] == 0]
+    for it in one1:
+        one(it, ts // 10, False)
+    dt1 = time.perf_counter() - t1
+    upd1 = sum(specs[k][1] for k, _, _, _ in one1) * (ts // 10)
+    # divergence of the GPU forms from the oracle on the same sample
+    div = {}
+    for name, md in (("chosen", chosen), ("fp32", fp32)):
+        if md is None:
+            continue
+        md.reset(seed)
+        q = 0
+        rows = {c: {"sk": 0.0, "er": 0.0} for c in checkpoints if c <= ts}
+        for c in sorted(rows):
+            md.run(c)
+            for k in strat:
+                ph = md.state(0, k=k)[:rs]
+                fam = specs[k][0]
+                d = max(float(np.max(np.abs(ph[r] - traj[(k, r)][c]))) for r in range(rs))
+                rows[c][fam] = max(rows[c][fam], d)
+        div[name] = {str(c): v for c, v in rows.items()}
+        md.reset(BATCH_SEED)
+    return {"value": upd / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"stratified 16 of the 512 instances (8 SK, 8 ER, N {min(specs[k][1] for k in strat)}"
+                      f"..{max(specs[k][1] for k in strat)}), {rs} replicas each, {ts} of the "
+                      f"{BATCH_T} MD steps, FP64 oracle, {dt:.1f} s",
+            "single_thread": {"value": upd1 / dt1, "cores": 1,
+                              "sample": f"the same 16 instances, 1 replica, {ts // 10} steps, "
+                                        f"{dt1:.1f} s"}}, \
+        {"measure": "max over the stratified sample of max_i |phi_i^(m) - phi64_i^(m)| at step m "
+                    "(same initial momenta), by family; chosen = BF16 operands with BF16 (SK) or "
+                    "FP8 (ER) couplings", "replicas": rs, **div}
+
+
+def bench_batch(args, hqa, torch):
+    """The bench line: the uneven batch of 512 dense instances (BF16 SK and exact FP8 ER
+    couplings, BF16 flux operands, FP32 accumulation and state), R = 64, T = 5000, against
+    plain FP32 on the same instances and initial momenta."""
+    from paper_2004_03972_amd import instances as inst
+    K = args.instances
+    specs = inst.uneven_batch_specs(512)[:K] if K >= 512 else \
+        inst.uneven_batch_specs(512)[:K // 2] + inst.uneven_batch_specs(512)[256:256 + K - K // 2]
+    Rr, Tt, W = BATCH_R, args.md_steps or BATCH_T, 100
+    t0 = time.perf_counter()
+    Js = [inst.uneven_batch_instance(s) for s in specs]
+    _log(f"bench: generated {len(specs)} instances in {time.perf_counter() - t0:.1f} s")
+    Kn = len(specs)
     st = torch.cuda.current_stream()
-    md = hqa.MD(probs, hqa.make_schedule(Tt, 100), Rr, "bf16", seed=4, stream=st.cuda_stream)
+    sched = hqa.make_schedule(Tt, W)
+    probs = [hqa.Problem(J, storage="bf16" if s[0] == "sk" else "fp8") for J, s in zip(Js, specs)]
+    md = hqa.MD(probs, sched, Rr, "bf16", seed=BATCH_SEED, stream=st.cuda_stream)
+    # exactness of the FP8 storage of the unit weights, and the BF16 rounding of SK
+    jerr = {"er_fp8_exact": True, "sk_bf16_max_rel": 0.0}
+    for J, s in zip(Js, specs):
+        if s[0] == "sk":
+            Jb = torch.from_numpy(J).to(torch.bfloat16).double().numpy()
+            jerr["sk_bf16_max_rel"] = max(jerr["sk_bf16_max_rel"],
+                                          float(np.max(np.abs(Jb - J)) / np.max(np.abs(J))))
+        else:
+            jerr["er_fp8_exact"] &= bool(np.all((J == 0) | (J == 1)))
     md.run(min(Tt, 10)); md.sync()
-    md.reset(4)
-    e0, e1 = _events(torch)
-    e0.record(st); md.run(); e1.record(st); md.sync()
-    ms = e0.elapsed_time(e1)
-    # per-instance error of the binary32 field against binary64 on the final fluxes
-    rel = np.array([e / r if r > 0 else 0.0 for e, r in (md.field_error(k) for k in range(K))])
-    half = K // 2
-    err = {"sk_bf16_J": {"max": float(rel[:half].max()), "median": float(np.median(rel[:half]))},
-           "er_fp8_J": {"max": float(rel[half:].max()), "median": float(np.median(rel[half:]))},
-           "measure": "max|u32 - u64| / max|u64| per instance, all instances, final fluxes"}
-    return {"metric": "MD spin-updates/s", "workload": f"{K} uneven instances, R={Rr}, T={Tt}",
-            "field_error_vs_fp64": err,
-            "value": upd * Tt / (ms / 1e3), "unit": "spin-updates/s", "md_ms": ms,
-            "roofline": {"bound": "mfma", "achieved": flops * Tt / (ms / 1e3) / 1e12,
-                         "peak": 2.5e3, "unit": "TFLOP/s",
-                         "frac": flops * Tt / (ms / 1e3) / 2.5e15, "kernel": "k_step_batch_lds"}}
+    for w in range(args.warmup):
+        md.reset(BATCH_SEED + 1000 + w)
+        md.run()
+        classify_batch(md, Kn, BATCH_N_AMB)
+    torch.cuda.synchronize()
+    cut_c, en_c, md_ms = [], [], []
+    t0e, t1e = _events(torch)
+    t0e.record(st)
+    for k in range(args.steps):
+        md.reset(BATCH_SEED + k)
+        e0, e1 = _events(torch)
+        e0.record(st); md.run(); e1.record(st)
+        c, e = classify_batch(md, Kn, BATCH_N_AMB)
+        md_ms.append(e0.elapsed_time(e1))
+        cut_c.append(c); en_c.append(e)
+    t1e.record(st)
+    torch.cuda.synchronize()
+    total_ms = t0e.elapsed_time(t1e)
+    _log(f"  chosen: {total_ms:.1f} ms for {args.steps} steps (MD {np.mean(md_ms):.1f} ms per run)")
+    bytes_step, jbytes, upd_step = batch_bytes_per_step(specs, Rr, W, Tt)
+    flop_step = sum(2.0 * N * N * Rr for _, N, _, _ in specs)
+    upd_run = upd_step * Tt
+    value = upd_run * args.steps / (total_ms / 1e3)
+    # max |dh| of every instance: the form's field against binary64 on the final fluxes
+    fe = [md.field_error(k) for k in range(Kn)]
+    dh = np.array([e for e, _ in fe])
+    rel = np.array([e / r if r > 0 else 0.0 for e, r in fe])
+    fam = np.array([s[0] for s in specs])
+    # plain FP32 on the same instances and seeds (fewer seeds: it is the slow side)
+    nf = min(args.steps, args.fp32_seeds)
+    cut_f, f_ms = [], None
+    md32 = None
+    if nf > 0:
+        probs32 = [hqa.Problem(J, storage="f32") for J in Js]
+        md32 = hqa.MD(probs32, sched, Rr, "f32", seed=BATCH_SEED, stream=st.cuda_stream)
+        md32.run(min(Tt, 10)); md32.sync()
+        torch.cuda.synchronize()
+        a0, a1 = _events(torch)
+        a0.record(st)
+        for k in range(nf):
+            md32.reset(BATCH_SEED + k)
+            md32.run()
+            c, _ = classify_batch(md32, Kn, BATCH_N_AMB)
+            cut_f.append(c)
+        a1.record(st)
+        torch.cuda.synchronize()
+        f_ms = a0.elapsed_time(a1) / nf
+        _log(f"  fp32: {f_ms:.1f} ms per step over {nf} seeds")
+    out = {
+        "metric": METRIC, "value": value, "unit": "spin-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": BATCH_WORKLOAD if Kn == 512 and Tt == BATCH_T else
+                   f"{Kn} uneven instances, R={Rr}, T={Tt}", "instances": Kn, "replicas": Rr,
+                   "md_steps": Tt, "n_amb": BATCH_N_AMB, "j_storage": "bf16 (SK) / fp8 (ER)",
+                   "spin_updates_per_run": upd_run, "parallelism": "none (1 GPU)"},
+        "md_only_spin_updates_per_s": upd_run / (np.mean(md_ms) / 1e3),
+        "j_storage_error": jerr,
+        "max_abs_dh": {"measure": "per instance max|u_form - u_64| / max|u_64| (and absolute) on "
+                                  "the final fluxes; the binary64 field is sum_j J_ij phi_j",
+                       "sk_bf16": {"max_rel": float(rel[fam == "sk"].max()),
+                                   "median_rel": float(np.median(rel[fam == "sk"])),
+                                   "max_abs": float(dh[fam == "sk"].max())},
+                       "er_fp8": {"max_rel": float(rel[fam == "er"].max()),
+                                  "median_rel": float(np.median(rel[fam == "er"])),
+                                  "max_abs": float(dh[fam == "er"].max())},
+                       "instances": Kn},
+    }
+    if nf > 0:
+        ratios = np.array([cut_c[k] / cut_f[k] for k in range(nf)])        # [seed][instance]
+        worst = np.unravel_index(np.argmin(ratios), ratios.shape)
+        per_inst_min = ratios.min(axis=0)
+        out["fp32"] = {"value": upd_run / (f_ms / 1e3), "ms_per_step": f_ms, "seeds": nf}
+        out["speedup_vs_fp32"] = value / out["fp32"]["value"]
+        out["matched_cut"] = {
+            "bar": 0.999, "pairs": int(ratios.size), "seeds": nf,
+            "min_ratio": float(ratios.min()), "mean_ratio": float(ratios.mean()),
+            "quantiles_1_5_50": [float(np.quantile(ratios, q)) for q in (0.01, 0.05, 0.5)],
+            "instances_below_bar": int(np.sum(per_inst_min < 0.999)),
+            "sk_min": float(ratios[:, fam == "sk"].min()),
+            "er_min": float(ratios[:, fam == "er"].min()),
+            "chosen_better_or_equal": int(np.sum(ratios >= 1.0)),
+            "worst": {"instance": int(worst[1]), "family": specs[worst[1]][0],
+                      "N": specs[worst[1]][1], "seed": BATCH_SEED + int(worst[0]),
+                      "chosen": float(cut_c[worst[0]][worst[1]]),
+                      "fp32": float(cut_f[worst[0]][worst[1]])},
+            "ok": bool(ratios.min() >= 0.999)}
+        if args.detail:
+            with open(args.detail, "w") as fh:
+                json.dump({"specs": specs, "cut_chosen": [c.tolist() for c in cut_c],
+                           "cut_fp32": [c.tolist() for c in cut_f],
+                           "dh_abs": dh.tolist(), "dh_rel": rel.tolist()}, fh)
+    launch_s = float(np.mean(md_ms)) / 1e3 / Tt       # one launch per MD step
+    out["roofline"] = {"bound": "hbm", "achieved": bytes_step / launch_s / 1e9, "peak": 8000.0,
+                       "unit": "GB/s", "frac": bytes_step / launch_s / 8.0e12,
+                       "traffic": measured_traffic("k_step_batch_lds_batch512_pmc.txt", "batch",
+                                                   "k_step_batch_lds"),
+                       "kernel": "k_step_batch_lds", "launches_per_run": Tt,
+                       "bytes_per_launch": bytes_step, "j_bytes_per_launch": jbytes,
+                       "launch_us": launch_s * 1e6,
+                       "mfma_tflops": flop_step / launch_s / 1e12,
+                       "mfma_frac_bf16": flop_step / launch_s / 2.5e15}
+    if not args.no_cpu:
+        cb, div = cpu_baseline_batch(specs, Js, md, md32, torch)
+        out["cpu_baseline"] = cb
+        out["divergence"] = div
+    if md32 is not None:
+        md32.close()
+    md.close()
+    return out
 
 
 def bench_es(args, hqa, torch):
@@ -656,8 +862,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="er800",
-                    choices=["er800", "ea3d", "batch512", "es", "k2000", "glass", "dense8k", "sweep", "copy",
+    ap.add_argument("--workload", default="batch",
+                    choices=["batch", "er800", "ea3d", "batch512", "es", "k2000", "glass", "dense8k", "sweep", "copy",
                              "peaks"])
     ap.add_argument("--glass-n", default="1000,2000,10000")
     ap.add_argument("--glass-instances", default="8,8,2")
@@ -685,6 +891,9 @@ def main():
     ap.add_argument("--forms", default="fp8,bf16,f32")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--md-steps", type=int, default=0)
+    ap.add_argument("--fp32-seeds", type=int, default=2,
+                    help="seeds of the plain FP32 comparison (the first of the timed seeds)")
+    ap.add_argument("--detail", default="", help="write per-instance cuts and errors here")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pin", default="",
                     help="TM,TN,CB[,TILED]: fixed per-step block instead of tuning")
@@ -700,7 +909,7 @@ def main():
     from paper_2004_03972_amd import hqa
     hqa.lib()
     torch.cuda.set_device(0)
-    fn = {"er800": bench_er800, "ea3d": bench_ea3d, "batch512": bench_batch512,
+    fn = {"batch": bench_batch, "batch512": bench_batch, "er800": bench_er800, "ea3d": bench_ea3d,
           "es": bench_es, "k2000": bench_k2000, "glass": bench_glass, "dense8k": bench_dense8k, "sweep": bench_sweep,
           "copy": bench_copy, "peaks": bench_peaks}[args.workload]
     print(json.dumps(fn(args, hqa, torch)), flush=True)

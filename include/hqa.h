@@ -189,7 +189,9 @@ void hqa_md_opts_default(hqa_md_opts *o);
 hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedule *sched,
                        const hqa_md_opts *opts, void *hip_stream, hqa_md **out);
 
-/* Advance every instance to step until_step (T when negative), asynchronously.
+/* Advance every instance to step until_step (T when negative), asynchronously: the
+ * leapfrog integration of the Hamilton equations of Eq. (3) (Methods, "Leapfrog
+ * algorithm", with the schedule of "Scheduling functions for MD").
  * Step q evaluates the force at phi^(q) with alpha/beta at tau = q/T, kicks p (half a
  * kick at q = 0), then drifts phi^(q+1) = phi^(q) + alpha(tau=(q+1/2)/T) p, adding
  * phi^(q+1) to the window sum when q+1 >= T-W+1.  HQA_ESTATE if until_step is before
@@ -296,7 +298,8 @@ typedef struct hqa_classify_out {
  * and J_eff = J[A, A], finds the exact minimum of the reduced energy over all 2^n
  * codes (ties: smallest code) and writes the merged spins.  Energies and cuts are
  * exact sums of the binary64 couplings, correctly rounded.  HQA_ESTATE before q = T,
- * HQA_EINVAL for n_amb outside [0, N], HQA_EUNSUPPORTED for solve = 1 with n_amb > 24.
+ * HQA_EINVAL for n_amb outside [0, N] or solve outside {0, 1}, HQA_EUNSUPPORTED for
+ * solve = 1 with n_amb > 24.
  * Synchronises. */
 hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                         const hqa_classify_out *out, int32_t out_mem);

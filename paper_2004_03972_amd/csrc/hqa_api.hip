@@ -1094,6 +1094,8 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
 
 hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                         const hqa_classify_out *out, int32_t out_mem) {
+    // the tabu mode (2) is reachable only through hqa_classify_tabu, which checks its limits
+    if (solve != 0 && solve != 1) return fail(HQA_EINVAL, "solve must be 0 or 1");
     return classify_impl(md, instance, n_amb, solve, out, out_mem, nullptr, HQA_HOST);
 }
 
@@ -1109,6 +1111,7 @@ hqa_status hqa_classify_probs(hqa_md *md, int32_t instance, const float *prob, i
                               int32_t out_mem) {
     if (!prob) return fail(HQA_EINVAL, "prob is NULL");
     if (prob_mem != HQA_HOST && prob_mem != HQA_DEVICE) return fail(HQA_EINVAL, "bad prob_mem");
+    if (solve != 0 && solve != 1) return fail(HQA_EINVAL, "solve must be 0 or 1");
     return classify_impl(md, instance, n_amb, solve, out, out_mem, prob, prob_mem);
 }
 

@@ -117,3 +117,37 @@ def random_pm1(shape, seed: int) -> np.ndarray:
     """Random +-1 array (float64), e.g. explicit initial momenta or spin vectors."""
     rng = np.random.default_rng(seed)
     return rng.choice(np.array([-1.0, 1.0]), size=shape)
+
+
+def uneven_batch_specs(count: int = 512, seed: int = 4):
+    """Sizes of the uneven batch: the first half Sherrington-Kirkpatrick glasses with
+    N ~ U{100..2000} (couplings stored in BF16), the second half Erdos-Renyi MAX-CUT
+    graphs with N ~ U{500..5000} and edge probability ~ U[0.01, 0.1] (unit weights,
+    stored exactly in FP8 e4m3).  Returns [(family, N, p, instance seed)]; the
+    couplings come from uneven_batch_instance."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        if k < count // 2:
+            out.append(("sk", int(rng.integers(100, 2001)), 0.0, 4000 + k))
+        else:
+            N = int(rng.integers(500, 5001))
+            out.append(("er", N, float(rng.uniform(0.01, 0.1)), 4000 + k))
+    return out
+
+
+def uneven_batch_instance(spec) -> np.ndarray:
+    family, N, p, s = spec
+    return sk(N, s) if family == "sk" else er_maxcut(N, p, s)
+
+
+def stratified(specs, per_family: int = 8):
+    """Indices of per_family instances of each family spread evenly over its size range
+    (ranks 0, ..., count - 1 of the sizes, evenly spaced)."""
+    out = []
+    for fam in ("sk", "er"):
+        idx = [k for k, s in enumerate(specs) if s[0] == fam]
+        idx.sort(key=lambda k: (specs[k][1], k))
+        m = len(idx)
+        out += [idx[round(j * (m - 1) / max(1, per_family - 1))] for j in range(min(per_family, m))]
+    return out

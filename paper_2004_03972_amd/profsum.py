@@ -25,7 +25,9 @@ CSR_SOURCES = ("csrc/k_md_csr.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 RESIDENT_SOURCES = ("csrc/k_md_resident.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 PERSIST_SOURCES = ("csrc/k_md_persist.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 CSR_RESIDENT_SOURCES = ("csrc/k_csr_resident.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
+BATCH_SOURCES = ("csrc/k_md_batch.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 SOURCES = {"dense": DENSE_SOURCES, "csr": CSR_SOURCES, "resident": RESIDENT_SOURCES,
+           "batch": BATCH_SOURCES,
            "persist": PERSIST_SOURCES, "csr_resident": CSR_RESIDENT_SOURCES}
 
 

@@ -70,3 +70,55 @@ def test_integer_enumeration_large_sums_take_int64_walk(H):
     J = inst.small_int(40, 3000, -3, 3, density=0.6) * float(1 << 21)
     print("large sums n", n, flush=True)
     _solve(H, J, n, 3, seed=5)
+
+
+def _solve_real(H, J, n, R, seed, h=None):
+    """As _solve, for couplings that are not integers: the binary64 Gray walk with the
+    exact rescoring of near-ties.  The oracle scores every code from scratch with a
+    correctly rounded sum (its code range split over host threads)."""
+    N = J.shape[0]
+    T, W = 200, 50
+    md = H.MD(H.Problem(J, h=h), H.make_schedule(T, W), R, "f32", seed=1)
+    rng = np.random.default_rng(seed)
+    md.set_state(H.HQA_STATE_WSUM, rng.standard_normal((R, N)) * W)
+    H.hqa_md_set_step(md.h, T)
+    g = md.classify(n, solve=True)
+    bar = md.state(H.HQA_STATE_PHIBAR)
+    md.close()
+    pb = orc.Problem(N, J=J, h=h)
+    A, s = orc.classify(bar, n)
+    he, Je = orc.reduce(pb, A, s)
+    code, Ered = orc.enumerate_exact_blocks(Je, he, nthreads=16)
+    assert np.array_equal(g["amb_idx"], A) and np.array_equal(g["h_eff"], he)
+    assert np.array_equal(g["code"], code), (g["code"], code)
+    assert np.array_equal(g["e_reduced"], Ered), (g["e_reduced"] - Ered)
+    assert np.array_equal(g["spins"], orc.merge(s, A, code))
+
+
+# Real couplings at the walk widths where the low walk carries 6, 10 and 14 bits and the
+# K^2 term of the rescoring bound sets the window: the path SK reduced problems take.
+@pytest.mark.parametrize("n,R", [(16, 3), (20, 2), (24, 1)])
+def test_real_enumeration_sk_matches_oracle(H, n, R):
+    print("real enumerate SK n", n, "R", R, flush=True)
+    _solve_real(H, inst.sk(64, 5000 + n), n, R, seed=100 + n)
+
+
+@pytest.mark.parametrize("n,R", [(16, 3), (20, 2), (24, 1)])
+def test_real_enumeration_glass_with_field_matches_oracle(H, n, R):
+    print("real enumerate glass n", n, "R", R, flush=True)
+    J, h = inst.uniform_glass(64, 6000 + n)
+    _solve_real(H, J, n, R, seed=200 + n, h=h)
+
+
+def test_real_enumeration_near_ties(H):
+    # couplings on a coarse binary grid plus one tiny offset: many codes tie in binary64
+    # sums up to the offset, so the exact rescoring decides; n = 20 with a field
+    n = 20
+    rng = np.random.default_rng(77)
+    N = 48
+    J = np.triu(rng.integers(-4, 5, (N, N)) * 0.25, 1)
+    J[0, 1] += 2.0 ** -40
+    J = J + J.T
+    h = rng.integers(-2, 3, N) * 0.5
+    print("real enumerate near ties n", n, flush=True)
+    _solve_real(H, J, n, 2, seed=9, h=h)

@@ -324,6 +324,19 @@ def test_error_paths(H):
     with pytest.raises(H.HQAError) as e:
         md.classify(N + 1)
     assert e.value.status == H.HQA_EINVAL
+    # solve outside {0, 1} is refused on the host (the tabu mode has its own entry point),
+    # by hqa_classify and by hqa_classify_probs alike; no kernel is launched
+    out = H.hqa_classify_out()
+    spins = np.zeros((2, N), np.int8)
+    out.spins = spins.ctypes.data
+    prob = np.full((2, N, 3), 1.0 / 3.0, np.float32)
+    for solve in (2, 3, -1):
+        with pytest.raises(H.HQAError) as e:
+            H.hqa_classify(md.h, 0, 3, solve, out, H.HQA_HOST)
+        assert e.value.status == H.HQA_EINVAL
+        with pytest.raises(H.HQAError) as e:
+            H.hqa_classify_probs(md.h, 0, prob, H.HQA_HOST, 3, solve, out, H.HQA_HOST)
+        assert e.value.status == H.HQA_EINVAL
     # a flux poisoned from the host overflows phi^5 -> non-finite flag at sync
     md = H.MD(H.Problem(J), H.make_schedule(10, 5), 2, "f32")
     md.set_state(H.HQA_STATE_PHI, np.full((2, N), 1e30))

@@ -78,6 +78,7 @@ def _declare(L):
         "or_integer_p": (V, [P, P, i32, i64, P, P, P]),
         "or_classify": (C.c_int, [i32, i32, P, i32, P, P]),
         "or_enumerate_range": (C.c_int, [i32, P, P, i64, i64, P, P]),
+        "or_field": (V, [P, i32, P, P]),
         "or_reduce": (C.c_int, [P, i32, i32, P, P, P, P]),
         "or_enumerate": (C.c_int, [i32, i32, P, P, P, P]),
         "or_merge": (V, [i32, i32, i32, P, P, P]),
@@ -175,6 +176,14 @@ def force(pb: Problem, mp: MDParams, q: int, phi) -> np.ndarray:
     F = np.empty(pb.N)
     lib().or_force(pb.c, mp.c, q, _ptr(phi), _ptr(F))
     return F
+
+
+def field(pb: Problem, phi) -> np.ndarray:
+    """Local fields u = J phi [R, N] of fluxes phi [R, N] (fma chain over ascending j)."""
+    phi = _f64(np.atleast_2d(phi))
+    u = np.empty_like(phi)
+    lib().or_field(pb.c, phi.shape[0], _ptr(phi), _ptr(u))
+    return u
 
 
 def md_run(pb: Problem, mp: MDParams, phi0, p0, nthreads: int = 1):

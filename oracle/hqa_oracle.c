@@ -190,6 +190,14 @@ static double force_i(const or_problem *pb, const or_md_params *mp, int64_t i,
     return F;
 }
 
+/* Local fields u_i = sum_j J_ij phi_j of R replicas [R][N] (the field term of the */
+/* force, Eq. 3), exported for the field parity checks of the binary32 forms.    */
+void or_field(const or_problem *pb, int32_t R, const double *phi, double *u) {
+    for (int32_t r = 0; r < R; r++)
+        for (int64_t i = 0; i < pb->N; i++)
+            u[(int64_t)r * pb->N + i] = field_row(pb, i, phi + (int64_t)r * pb->N);
+}
+
 /* Force at phi for one replica, exposed for the gradient checks. */
 void or_force(const or_problem *pb, const or_md_params *mp, int64_t q,
               const double *phi, double *F) {

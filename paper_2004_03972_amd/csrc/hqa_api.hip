@@ -1064,8 +1064,10 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
         HIPCHK(B.get(&code, (size_t)R));
         HIPCHK(B.get(&e_red, (size_t)R));
         HIPCHK(launch_reduce(I, R, n_amb, amb, spins, h_eff, J_eff, st));
+        uint8_t *escr;
+        HIPCHK(B.get(&escr, enum_scratch_bytes(n_amb, R)));
         HIPCHK(launch_enumerate(n_amb, R, J_eff, h_eff, I.es.lsb, I.j_integral ? 1 : 0, code,
-                                e_red, st));
+                                e_red, escr, st));
         HIPCHK(launch_merge(N, R, n_amb, amb, code, spins, st));
     } else if (out->h_eff && n_amb > 0) {
         HIPCHK(B.get(&h_eff, (size_t)R * n_amb));

@@ -160,7 +160,9 @@ hipError_t launch_tabu(const Instance &I, int R, int n, const int32_t *amb, cons
                        const double *h_eff, int64_t iters, int tenure, int8_t *spins_out,
                        double *d_best, hipStream_t st);
 hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_eff, int b0,
-                            int integral, int64_t *code, double *e_red, hipStream_t st);
+                            int integral, int64_t *code, double *e_red, void *scratch,
+                            hipStream_t st);
+size_t enum_scratch_bytes(int n, int R);
 hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
                         int8_t *spins, hipStream_t st);
 // Exact energies and cuts of V spin vectors; `part` holds energy_part_bytes(N, V)

@@ -198,8 +198,42 @@ __global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
 // from the MFMA-tiled copy, one group ahead in registers; the LDS block is double-
 // buffered with one barrier per group.  Chains, operands and epilogue are those of
 // the other dense kernels (bit-identical results).  Wavefronts whose rows are all
-// padding keep zero J fragments and take part in the staging and the barriers.
+// padding compute on a real row tile, store nothing, and take part in the staging and
+// the barriers.  The J fragments of group g + 1 are loaded into the other of two
+// register sets while group g computes (the loop is unrolled by two, so no set is
+// copied into the other), and the flux block of group g + 1 is loaded into registers
+// at the start of group g and stored into the other LDS buffer at its end.
+//
+// Every global access goes through global-address-space pointers.  The buffers come
+// from a table in memory, so plain pointers would be generic (flat) ones, and a flat
+// load counts against the LDS counter as well: the wait for the B fragments' LDS reads
+// would then also wait for the next group's prefetch, and every group would pay the
+// whole memory latency.  Global loads count only against the vector-memory counter,
+// so the prefetch stays in flight across the group's MFMAs and its barrier.
 constexpr int BL_ROWS = 128, BL_REPS = 64, BL_LDB = 128 + 8;   // LDS row: 272 bytes
+
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gld(const void *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gst(void *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4_b;
+
+// The four K chunks of one 128-column group as BF16 operands: from four 16-byte words
+// (BF16 storage) or from the eight FP8 bytes of each chunk in two words (FP8 storage).
+template <int JT>
+__device__ __forceinline__ bf16x8 a_chunk(const u32x4_b *g, int j) {
+    if constexpr (JT == JT_BF16) {
+        return __builtin_bit_cast(bf16x8, g[j]);
+    } else {
+        const u32x4_b w = g[j >> 1];
+        return (j & 1) ? cvt_fp8x8_b(make_uint2(w[2], w[3])) : cvt_fp8x8_b(make_uint2(w[0], w[1]));
+    }
+}
 
 template <int JT>
 __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, const BatchTile &tl,
@@ -210,84 +244,87 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
     const int i0 = tl.i0 + 16 * w;
     const bool active = i0 < I.N;
     const int r0 = tl.r0;
-    const float *phi_in = I.phi[a.cur];
-    const bf16 *xb_in = I.xb[a.cur];
+    // buffers of the current parity, chosen without run-time indexing of the table
+    const bool odd = a.cur != 0;
+    const float *phi_in = odd ? I.phi[1] : I.phi[0];
+    const bf16 *xb_in = odd ? I.xb[1] : I.xb[0];
+    float *phi_out = odd ? I.phi[0] : I.phi[1];
+    bf16 *xb_out = odd ? I.xb[0] : I.xb[1];
     const int ngroups = I.Np / 128;
-    typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
-    constexpr int lane_bytes = JT == JT_BF16 ? 64 : 32;
-    const uint8_t *Jt = (const uint8_t *)I.Jt +
-                        ((int64_t)(i0 / 16) * I.nrounds * 64 + lane) * lane_bytes;
+    constexpr int NA = JT == JT_BF16 ? 4 : 2;          // 16-byte words of J per lane and group
+    // the tiled copy holds ceil(N / 16) row tiles: a wavefront whose rows are all
+    // padding reads the last real row tile instead (its results are never stored)
+    const int jtile = min(i0, I.N - 1) / 16;
+    const auto *Jt = gld<u32x4_b>((const uint8_t *)I.Jt +
+                                  ((int64_t)jtile * I.nrounds * 64 + lane) * (16 * NA));
     // staging: thread -> (replica row, 16-column segment) of the 64 x 128 block
     const int srow = tid >> 3, sseg = tid & 7;
-    const bf16 *bsrc = xb_in + (int64_t)min(r0 + srow, a.R - 1) * I.ld + 16 * sseg;
-
-    AT A[4], An[4];
-    auto loadA = [&](int gi, AT (&Ag)[4]) {
-        if (!active) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) Ag[j] = AT{};
-            return;
-        }
-        const uint8_t *src = Jt + (int64_t)gi * 64 * lane_bytes;
-        if constexpr (JT == JT_BF16) {
-#pragma unroll
-            for (int j = 0; j < 4; j++) Ag[j] = *(const bf16x8 *)(src + 16 * j);
-        } else {
-            const uint4 lo = *(const uint4 *)src, hi = *(const uint4 *)(src + 16);
-            Ag[0] = make_uint2(lo.x, lo.y); Ag[1] = make_uint2(lo.z, lo.w);
-            Ag[2] = make_uint2(hi.x, hi.y); Ag[3] = make_uint2(hi.z, hi.w);
-        }
-    };
-    {
-        const uint4 b0 = *(const uint4 *)bsrc, b1 = *(const uint4 *)(bsrc + 8);
-        *(uint4 *)&Bs[0][srow][16 * sseg] = b0;
-        *(uint4 *)&Bs[0][srow][16 * sseg + 8] = b1;
-    }
-    loadA(0, A);
-    __syncthreads();
+    const auto *Bsrc = gld<u32x4_b>(xb_in + (int64_t)min(r0 + srow, a.R - 1) * I.ld + 16 * sseg);
+    u32x4_b *Bdst0 = (u32x4_b *)&Bs[0][srow][16 * sseg];
+    u32x4_b *Bdst1 = (u32x4_b *)&Bs[1][srow][16 * sseg];
 
     f32x4 acc[4][4];
 #pragma unroll
     for (int rt = 0; rt < 4; rt++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[rt][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int gi = 0; gi < ngroups; gi++) {
-        const bool more = gi + 1 < ngroups;
-        uint4 s0, s1;
-        if (more) {
-            const bf16 *src = bsrc + 128 * (gi + 1);
-            s0 = *(const uint4 *)src;
-            s1 = *(const uint4 *)(src + 8);
-            loadA(gi + 1, An);
-        }
-        const int buf = gi & 1;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            bf16x8 av;
-            if constexpr (JT == JT_BF16) av = A[j];
-            else av = cvt_fp8x8_b(A[j]);
-#pragma unroll
-            for (int rt = 0; rt < 4; rt++) {
-                const bf16x8 bv = *(const bf16x8 *)&Bs[buf][16 * rt + (lane & 15)][32 * j + 8 * kg];
-                acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[rt][j], 0, 0, 0);
-            }
-        }
-        if (more) {
-            *(uint4 *)&Bs[buf ^ 1][srow][16 * sseg] = s0;
-            *(uint4 *)&Bs[buf ^ 1][srow][16 * sseg + 8] = s1;
-#pragma unroll
-            for (int j = 0; j < 4; j++) A[j] = An[j];
-        }
+
+    // Two register sets used in turn (the loop is unrolled by two, so no set is copied
+    // into the other): the loads of group g + 1 are issued before the MFMAs of group g
+    // and are first waited for when group g + 1 begins.
+    u32x4_b A0[NA], A1[NA];
+    u32x4_b S0a, S0b, S1a, S1b;
+#define HQA_LOAD_GROUP(g, A, Sa, Sb)                                                  \
+    do {                                                                              \
+        Sa = Bsrc[16 * (g)];                                                          \
+        Sb = Bsrc[16 * (g) + 1];                                                      \
+        _Pragma("unroll") for (int j = 0; j < NA; j++) A[j] = Jt[(int64_t)(g) * 64 * NA + j]; \
+    } while (0)
+#define HQA_MFMA_GROUP(buf, A)                                                        \
+    do {                                                                              \
+        _Pragma("unroll") for (int j = 0; j < 4; j++) {                              \
+            const bf16x8 av = a_chunk<JT>(A, j);                                      \
+            bf16x8 bv[4];                                                             \
+            _Pragma("unroll") for (int rt = 0; rt < 4; rt++)                         \
+                bv[rt] = *(const bf16x8 *)&Bs[buf][16 * rt + (lane & 15)][32 * j + 8 * kg]; \
+            _Pragma("unroll") for (int rt = 0; rt < 4; rt++)                         \
+                acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[rt], acc[rt][j], 0, 0, 0); \
+        }                                                                             \
+    } while (0)
+    // Every load is unconditional, so the compiler can count the loads in flight
+    // exactly and wait only for the group about to be used: a wavefront whose rows are
+    // all padding reads a real row tile (above), and past the last group the last
+    // group is loaded again and not used.
+    HQA_LOAD_GROUP(0, A0, S0a, S0b);
+    Bdst0[0] = S0a;
+    Bdst0[1] = S0b;
+    __syncthreads();
+    for (int gi = 0; gi < ngroups; gi += 2) {
+        // even group gi (A0, LDS buffer 0); prefetch gi + 1 into A1 / S1
+        HQA_LOAD_GROUP(min(gi + 1, ngroups - 1), A1, S1a, S1b);
+        __builtin_amdgcn_sched_barrier(0);
+        HQA_MFMA_GROUP(0, A0);
+        Bdst1[0] = S1a;
+        Bdst1[1] = S1b;
+        __syncthreads();
+        if (gi + 1 >= ngroups) break;
+        // odd group gi + 1 (A1, LDS buffer 1); prefetch gi + 2 into A0 / S0
+        HQA_LOAD_GROUP(min(gi + 2, ngroups - 1), A0, S0a, S0b);
+        __builtin_amdgcn_sched_barrier(0);
+        HQA_MFMA_GROUP(1, A1);
+        Bdst0[0] = S0a;
+        Bdst0[1] = S0b;
         __syncthreads();
     }
+#undef HQA_LOAD_GROUP
+#undef HQA_MFMA_GROUP
 
     if (!active) return;
     const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
     const int ib = i0 + 4 * kg;
     const bool win = q + 1 >= a.T - a.W + 1;
     bool bad = false;
-    float *phi_out = I.phi[a.cur ^ 1];
-    bf16 *xb_out = I.xb[a.cur ^ 1];
+    const auto *hg = gld<float>(I.h);
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) {
         const int col = r0 + 16 * rt + (lane & 15);
@@ -295,28 +332,28 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
         const f32x4 parts[4] = {acc[rt][0], acc[rt][1], acc[rt][2], acc[rt][3]};
         const f32x4 u = combine4(parts);
         const int64_t base = (int64_t)col * I.ld + ib;
-        float4 x = *(const float4 *)(phi_in + base);
-        float4 p = *(const float4 *)(I.p + base);
-        float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w}, xn[4];
+        const f32x4 x = *gld<f32x4>(phi_in + base);
+        const f32x4 p = *gld<f32x4>(I.p + base);
+        float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             if (ib + v < I.N) {
-                leapfrog(cf, xs[v], u[v], I.h[ib + v], ps[v], xn[v]);
+                leapfrog(cf, xs[v], u[v], hg[ib + v], ps[v], xn[v]);
                 bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
             } else {
                 xn[v] = 0.0f;
                 ps[v] = 0.0f;
             }
         }
-        *(float4 *)(phi_out + base) = make_float4(xn[0], xn[1], xn[2], xn[3]);
-        *(float4 *)(I.p + base) = make_float4(ps[0], ps[1], ps[2], ps[3]);
+        *gst<f32x4>(phi_out + base) = (f32x4){xn[0], xn[1], xn[2], xn[3]};
+        *gst<f32x4>(I.p + base) = (f32x4){ps[0], ps[1], ps[2], ps[3]};
         typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
         bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
-        *(bf16x4 *)(xb_out + base) = b;
+        *gst<bf16x4>(xb_out + base) = b;
         if (win) {
-            float4 s = *(const float4 *)(I.S + base);
-            s.x = s.x + xn[0]; s.y = s.y + xn[1]; s.z = s.z + xn[2]; s.w = s.w + xn[3];
-            *(float4 *)(I.S + base) = s;
+            f32x4 s = *gld<f32x4>(I.S + base);
+            s[0] = s[0] + xn[0]; s[1] = s[1] + xn[1]; s[2] = s[2] + xn[2]; s[3] = s[3] + xn[3];
+            *gst<f32x4>(I.S + base) = s;
         }
     }
     if (bad) atomicOr(a.err, ERR_NONFINITE);
@@ -324,8 +361,8 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
 
 // One launch per MD step for every BF16 and FP8 instance of the batch: the storage
 // type is uniform per tile.  A tile with instance index -1 is a placeholder of the
-// XCD placement and does nothing.
-__global__ __launch_bounds__(512, 4) void k_step_batch_lds(BatchArgs a, int64_t q) {
+// XCD placement and does nothing.  Two workgroups per CU (128 registers per lane).
+__global__ __launch_bounds__(512, 2) void k_step_batch_lds(BatchArgs a, int64_t q) {
     __shared__ __align__(16) bf16 Bs[2][BL_REPS][BL_LDB];
     const BatchTile tl = a.tiles[blockIdx.x];
     if (tl.inst < 0) return;

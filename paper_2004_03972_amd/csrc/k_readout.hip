@@ -203,9 +203,10 @@ hipError_t launch_reduce(const Instance &I, int R, int n, const int32_t *amb,
 
 // ---------------------------------------------------------------------------
 // Exact minimum of the reduced energy E'(c) = sum_{a<b} J_ab x_a x_b + sum_a h_a x_a
-// over all codes c (bit a set: x_a = -1), ties to the smallest code.  One
-// workgroup per replica; thread t fixes the top bits of the code to t and walks
-// the low bits in Gray-code order, updating E' and the local fields
+// over all codes c (bit a set: x_a = -1), ties to the smallest code.  Thread t
+// fixes the top bits of the code to t and walks the low bits in Gray-code order
+// (one workgroup per replica for integer couplings, several for real ones; see
+// k_enumerate_int and k_enum_real), updating E' and the local fields
 // f_a = h_a + sum_{b != a} J_ab x_b by one flip per code (dE = -2 x_a f_a).
 // Integer instances run in int64 (exact).  Otherwise pass 1 walks in binary64
 // and pass 2 re-walks, rescoring exactly (fixed-point accumulator, rounded once)
@@ -292,105 +293,183 @@ __device__ __forceinline__ void gray_walk(const T *J, const T *h, int n, int nl,
     }
 }
 
-template <typename T>
-__device__ void block_argmin(T &E, int64_t &code, T *sE, int64_t *sC) {
-    const int tid = threadIdx.x;
-    sE[tid] = E;
-    sC[tid] = code;
+// Real couplings, many codes: the code space of each replica is split over P
+// workgroups of 256 threads; thread t of workgroup p fixes the top pt = n - NL bits of
+// the code to p * 256 + t and walks the NL low bits in Gray-code order.  Every code
+// sees the operations of gray_walk above in the same order (E and the local fields
+// from scratch at the start, then E - 2 x_a f_a and f_b - 2 J_ab x_a per flip, each
+// product exact, one rounding per update; the products are formed inside fma, which
+// rounds once like the two-step form), so the pass-1 minimum obeys the same error
+// bound with K = 2^NL codes per walk.  The local fields sit in registers: within a
+// block of 16 codes the flipped bit is a compile-time ruler index (with 2 J_ab of
+// those bits in registers), and the flip between blocks picks its field by selects.
+//   k_enum_real<NL>(pass 1): each workgroup's binary64 minimum (E, code) -> part;
+//   k_enum_real_mid: per replica, the minimum over the workgroups and the rescoring
+//     threshold E_min + 2 delta + 4 u S (the bound of k_enumerate);
+//   k_enum_real<NL>(pass 2): every code at or below the threshold is rescored exactly
+//     (fixed-point accumulator, rounded once); each workgroup's exact minimum -> part;
+//   k_enum_real_fin: per replica, the exact minimum over the workgroups, ties to the
+//     smallest code.
+// ---------------------------------------------------------------------------
+#define ENUM_PT_REAL 12
+
+struct EnumRealArgs {
+    int n, R, P, b0;
+    const double *J_eff, *h_eff;
+    double *partE;        // [R][P]
+    int64_t *partC;       // [R][P]
+    double *thresh;       // [R]
+    int64_t *code;
+    double *e_red;
+};
+
+template <int NL>
+__global__ __launch_bounds__(256) void k_enum_real(EnumRealArgs a, int pass) {
+    __shared__ double Jd[ENUM_MAXN * ENUM_MAXN], J2[ENUM_MAXN * ENUM_MAXN], hd[ENUM_MAXN];
+    __shared__ double sE[256];
+    __shared__ int64_t sC[256];
+    const int r = blockIdx.x / a.P, p = blockIdx.x % a.P, tid = threadIdx.x, n = a.n;
+    for (int k = tid; k < n * n; k += 256) {
+        const double v = a.J_eff[(int64_t)r * n * n + k];
+        Jd[k] = v;
+        J2[k] = 2.0 * v;
+    }
+    for (int k = tid; k < n; k += 256) hd[k] = a.h_eff[(int64_t)r * n + k];
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) {
-            T e2 = sE[tid + s];
-            int64_t c2 = sC[tid + s];
-            if (e2 < sE[tid] || (e2 == sE[tid] && c2 < sC[tid])) { sE[tid] = e2; sC[tid] = c2; }
+    const uint32_t top = (uint32_t)(p * 256 + tid);
+    const bool active = top < (1u << (n - NL));
+    const double thr = pass == 2 ? a.thresh[r] : 0.0;
+    double bestE = INFINITY;
+    int64_t bestC = INT64_MAX;
+    auto visit = [&](double E, uint32_t c) {
+        if (pass == 1) {
+            if (better_d(E, c, bestE, bestC)) { bestE = E; bestC = c; }
+        } else if (E <= thr) {
+            const double ex = energy_exact(Jd, hd, n, c, a.b0);
+            if (better_d(ex, c, bestE, bestC)) { bestE = ex; bestC = c; }
+        }
+    };
+    if (active) {
+        uint32_t code = top << NL;
+        double E = energy_from_scratch<double>(Jd, hd, n, code);
+        visit(E, code);
+        if constexpr (NL > 0) {
+            double f[NL];
+#pragma unroll
+            for (int aa = 0; aa < NL; aa++) {
+                double acc = hd[aa];
+                for (int b = 0; b < n; b++)
+                    if (b != aa) acc = acc + Jd[aa * n + b] * (((code >> b) & 1) ? -1.0 : 1.0);
+                f[aa] = acc;
+            }
+            constexpr int NA = NL < 4 ? NL : 4;        // bits flipped inside a block of 16
+            double D[NA][NL];
+#pragma unroll
+            for (int aa = 0; aa < NA; aa++)
+#pragma unroll
+                for (int b = 0; b < NL; b++) D[aa][b] = J2[aa * n + b];
+            constexpr int NBLK = NL >= 4 ? 1 << (NL - 4) : 1;
+            for (int m = 0; m < NBLK; m++) {
+#pragma unroll
+                for (int j = 1; j < 16; j++) {
+                    if (j >= (1 << NL)) break;
+                    const int aa = __builtin_ctz(j);
+                    const double xa = ((code >> aa) & 1u) ? -1.0 : 1.0;
+                    E = __builtin_fma(-2.0 * xa, f[aa], E);
+#pragma unroll
+                    for (int b = 0; b < NL; b++)
+                        if (b != aa) f[b] = __builtin_fma(-xa, D[aa][b], f[b]);
+                    code ^= 1u << aa;
+                    visit(E, code);
+                }
+                if (m + 1 < NBLK) {                       // flip of bit 4 + ctz(m + 1)
+                    const int aa = 4 + __builtin_ctz(m + 1);
+                    const double xa = ((code >> aa) & 1u) ? -1.0 : 1.0;
+                    double fa = f[0];
+#pragma unroll
+                    for (int b = 1; b < NL; b++) fa = b == aa ? f[b] : fa;
+                    E = __builtin_fma(-2.0 * xa, fa, E);
+#pragma unroll
+                    for (int b = 0; b < NL; b++)
+                        if (b != aa) f[b] = __builtin_fma(-xa, J2[aa * n + b], f[b]);
+                    code ^= 1u << aa;
+                    visit(E, code);
+                }
+            }
+        }
+    }
+    sE[tid] = bestE;
+    sC[tid] = bestC;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (tid < s2 && better_d(sE[tid + s2], sC[tid + s2], sE[tid], sC[tid])) {
+            sE[tid] = sE[tid + s2];
+            sC[tid] = sC[tid + s2];
         }
         __syncthreads();
     }
-    E = sE[0];
-    code = sC[0];
-    __syncthreads();
+    if (tid == 0) {
+        a.partE[(int64_t)r * a.P + p] = sE[0];
+        a.partC[(int64_t)r * a.P + p] = sC[0];
+    }
 }
 
-__global__ __launch_bounds__(256) void k_enumerate(EnumArgs a) {
-    __shared__ double Jd[ENUM_MAXN * ENUM_MAXN], hd[ENUM_MAXN];
-    __shared__ int64_t Ji[ENUM_MAXN * ENUM_MAXN], hi_[ENUM_MAXN];
-    __shared__ double sEd[256];
-    __shared__ int64_t sEi[256], sC[256];
-    __shared__ double sS[256];
-    const int r = blockIdx.x, tid = threadIdx.x, n = a.n;
-    for (int k = tid; k < n * n; k += 256) {
-        double v = a.J_eff[(int64_t)r * n * n + k];
-        Jd[k] = v;
-        Ji[k] = (int64_t)v;
+// One wavefront per replica: minimum over the P workgroup results; after pass 1 the
+// rescoring threshold, after pass 2 the result.
+__global__ __launch_bounds__(64) void k_enum_real_mid(EnumRealArgs a, int pass) {
+    const int r = blockIdx.x, lane = threadIdx.x, n = a.n;
+    double E = INFINITY;
+    int64_t C = INT64_MAX;
+    for (int p = lane; p < a.P; p += 64) {
+        const double e2 = a.partE[(int64_t)r * a.P + p];
+        const int64_t c2 = a.partC[(int64_t)r * a.P + p];
+        if (better_d(e2, c2, E, C)) { E = e2; C = c2; }
     }
-    for (int k = tid; k < n; k += 256) {
-        double v = a.h_eff[(int64_t)r * n + k];
-        hd[k] = v;
-        hi_[k] = (int64_t)v;
+    for (int off = 32; off > 0; off >>= 1) {
+        const double e2 = __shfl_xor(E, off);
+        const int64_t c2 = __shfl_xor(C, off);
+        if (better_d(e2, c2, E, C)) { E = e2; C = c2; }
     }
-    __syncthreads();
-    const int ptop = n < 8 ? n : 8;
-    const int nl = n - ptop;
-    const bool active = tid < (1 << ptop);
-    if (a.integral) {
-        int64_t f[ENUM_MAXLOW];
-        int64_t bestE = INT64_MAX, bestC = INT64_MAX;
-        if (active)
-            gray_walk<int64_t>(Ji, hi_, n, nl, (uint32_t)tid, f, [&](int64_t E, uint32_t c) {
-                if (better_i(E, c, bestE, bestC)) { bestE = E; bestC = c; }
-            });
-        block_argmin<int64_t>(bestE, bestC, sEi, sC);
-        if (tid == 0) {
-            a.code[r] = bestC;
-            a.e_red[r] = (double)bestE;
+    if (pass == 2) {
+        if (lane == 0) {
+            a.code[r] = C;
+            a.e_red[r] = E;
         }
         return;
     }
-    // binary64 pass 1
-    double f[ENUM_MAXLOW];
-    double bestE = INFINITY;
-    int64_t bestC = INT64_MAX;
-    if (active)
-        gray_walk<double>(Jd, hd, n, nl, (uint32_t)tid, f, [&](double E, uint32_t c) {
-            if (better_d(E, c, bestE, bestC)) { bestE = E; bestC = c; }
-        });
-    block_argmin<double>(bestE, bestC, sEd, sC);
-    // rigorous bound on |E_binary64 - E_exact| along a walk of K = 2^nl codes:
-    // u S (m + K (2n + 1) + K^2) with S = sum |J_ab| (a<b) + sum |h_a|, m the term
-    // count, u = 2^-53; doubled, plus the rounding of the exact values themselves.
+    // rigorous bound on |E_binary64 - E_exact| along a walk of K = 2^NL codes:
+    // u S (m + K (2n + 1) + K^2) with S = sum |J_ab| (a < b) + sum |h_a|, m the term
+    // count, u = 2^-53; doubled (the minimum's own error and a candidate's), plus the
+    // rounding of the exact values themselves
     double Ssum = 0.0;
-    for (int k = tid; k < n * n; k += 256) {
-        int aa = k / n, bb = k % n;
-        if (bb > aa) Ssum += fabs(Jd[k]);
+    const double *J = a.J_eff + (int64_t)r * n * n, *h = a.h_eff + (int64_t)r * n;
+    for (int k = lane; k < n * n; k += 64)
+        if (k % n > k / n) Ssum += fabs(J[k]);
+    for (int k = lane; k < n; k += 64) Ssum += fabs(h[k]);
+    for (int off = 32; off > 0; off >>= 1) Ssum += __shfl_xor(Ssum, off);
+    if (lane == 0) {
+        const int nl = n > ENUM_PT_REAL ? n - ENUM_PT_REAL : 0;
+        const double S = Ssum * (1.0 + 1e-12);
+        const double K = (double)(1u << nl);
+        const double mterms = (double)(n * (n - 1) / 2 + n);
+        const double u = 1.1102230246251565e-16;
+        const double delta = u * S * (mterms + K * (2.0 * n + 1.0) + K * K);
+        a.thresh[r] = E + 2.0 * delta + 4.0 * u * S;
     }
-    for (int k = tid; k < n; k += 256) Ssum += fabs(hd[k]);
-    sS[tid] = Ssum;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) sS[tid] += sS[tid + s];
-        __syncthreads();
-    }
-    const double S = sS[0] * (1.0 + 1e-12);
-    const double K = (double)(1u << nl);
-    const double mterms = (double)(n * (n - 1) / 2 + n);
-    const double u = 1.1102230246251565e-16;
-    const double delta = u * S * (mterms + K * (2.0 * n + 1.0) + K * K);
-    const double thresh = bestE + 2.0 * delta + 4.0 * u * S;
-    // pass 2: exact rescoring of the candidates
-    double xE = INFINITY;
-    int64_t xC = INT64_MAX;
-    if (active)
-        gray_walk<double>(Jd, hd, n, nl, (uint32_t)tid, f, [&](double E, uint32_t c) {
-            if (E <= thresh) {
-                double ex = energy_exact(Jd, hd, n, c, a.b0);
-                if (better_d(ex, c, xE, xC)) { xE = ex; xC = c; }
-            }
-        });
-    block_argmin<double>(xE, xC, sEd, sC);
-    if (tid == 0) {
-        a.code[r] = xC;
-        a.e_red[r] = xE;
-    }
+}
+
+template <int NL>
+static void launch_enum_real(const EnumRealArgs &a, hipStream_t st) {
+    k_enum_real<NL><<<a.R * a.P, 256, 0, st>>>(a, 1);
+    k_enum_real_mid<<<a.R, 64, 0, st>>>(a, 1);
+    k_enum_real<NL><<<a.R * a.P, 256, 0, st>>>(a, 2);
+    k_enum_real_mid<<<a.R, 64, 0, st>>>(a, 2);
+}
+
+size_t enum_scratch_bytes(int n, int R) {
+    const int pt = n < ENUM_PT_REAL ? n : ENUM_PT_REAL;
+    const int P = ((1 << pt) + 255) / 256;
+    return (size_t)R * P * 16 + (size_t)R * 8 + 64;
 }
 
 // Integer instances with small sums: 1024 threads per replica, thread t fixes the
@@ -539,13 +618,35 @@ static void launch_enum_int(const EnumArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_eff, int b0,
-                            int integral, int64_t *code, double *e_red, hipStream_t st) {
+                            int integral, int64_t *code, double *e_red, void *scratch,
+                            hipStream_t st) {
     EnumArgs a;
     a.n = n; a.R = R; a.b0 = b0; a.integral = integral;
     a.J_eff = J_eff; a.h_eff = h_eff; a.code = code; a.e_red = e_red;
     if (R == 0) return hipSuccess;
     if (!integral) {
-        k_enumerate<<<R, 256, 0, st>>>(a);
+        EnumRealArgs b;
+        const int pt = n < ENUM_PT_REAL ? n : ENUM_PT_REAL;
+        b.n = n; b.R = R; b.P = ((1 << pt) + 255) / 256; b.b0 = b0;
+        b.J_eff = J_eff; b.h_eff = h_eff; b.code = code; b.e_red = e_red;
+        b.partE = (double *)scratch;
+        b.partC = (int64_t *)((char *)scratch + (size_t)R * b.P * 8);
+        b.thresh = (double *)((char *)scratch + (size_t)R * b.P * 16);
+        switch (n - pt) {
+            case 0: launch_enum_real<0>(b, st); break;
+            case 1: launch_enum_real<1>(b, st); break;
+            case 2: launch_enum_real<2>(b, st); break;
+            case 3: launch_enum_real<3>(b, st); break;
+            case 4: launch_enum_real<4>(b, st); break;
+            case 5: launch_enum_real<5>(b, st); break;
+            case 6: launch_enum_real<6>(b, st); break;
+            case 7: launch_enum_real<7>(b, st); break;
+            case 8: launch_enum_real<8>(b, st); break;
+            case 9: launch_enum_real<9>(b, st); break;
+            case 10: launch_enum_real<10>(b, st); break;
+            case 11: launch_enum_real<11>(b, st); break;
+            default: launch_enum_real<12>(b, st); break;
+        }
         return hipGetLastError();
     }
     switch (n > ENUM_PT ? n - ENUM_PT : 0) {   // low bits walked per thread

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -317,6 +318,10 @@ class ES:
             self.h = None
 
     def __del__(self):
+        # a handle still open at interpreter shutdown is left to the process exit: the HIP
+        # runtime may already be torn down, so no device call is made from here then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -433,6 +438,10 @@ class MD:
             self.h = None
 
     def __del__(self):
+        # a handle still open at interpreter shutdown is left to the process exit: the HIP
+        # runtime may already be torn down, so no device call is made from here then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

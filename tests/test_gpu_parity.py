@@ -137,7 +137,7 @@ def test_f32_dense_field_within_1e5(H, N, R):
     phi = _shared_phi(R, N, N).astype(np.float32).astype(np.float64)
     md.set_state(H.HQA_STATE_PHI, phi)
     u = md.field()
-    u64 = phi @ J.T
+    u64 = orc.field(orc.Problem(N, J=J), phi)
     rel = np.max(np.abs(u - u64)) / np.max(np.abs(u64))
     _say("dense f32 field rel err", N, R, rel)
     assert rel <= 1e-5
@@ -154,9 +154,10 @@ def test_lowp_dense_field(H, prec):
     u = md.field()
     import torch
     phib = torch.tensor(phi, dtype=torch.float32).to(torch.bfloat16).double().numpy()
-    u64 = phib @ J.T
+    pb = orc.Problem(N, J=J)
+    u64 = orc.field(pb, phib)
     assert np.max(np.abs(u - u64)) / np.max(np.abs(u64)) <= 1e-5
-    uf = phi @ J.T
+    uf = orc.field(pb, phi)
     _say(prec, "max |dh| vs fp64 phi", np.max(np.abs(u - uf)))
 
 
@@ -167,8 +168,7 @@ def test_csr_f32_field_within_1e5(H):
     phi = _shared_phi(R, N, 5).astype(np.float32).astype(np.float64)
     md.set_state(H.HQA_STATE_PHI, phi)
     u = md.field()
-    Jd = inst.csr_to_dense(N, rp, ci, v)
-    u64 = phi @ Jd.T
+    u64 = orc.field(orc.Problem(N, row_ptr=rp, col=ci, val=v), phi)
     assert np.max(np.abs(u - u64)) / np.max(np.abs(u64)) <= 1e-5
 
 

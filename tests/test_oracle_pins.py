@@ -417,3 +417,25 @@ def test_enumeration_blocks_equal_one_scan(orc):
             for th in (1, 3, 8):
                 b = orc.enumerate_exact_blocks(J[None], h[None], nthreads=th)
                 assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_field_export_exact_on_dyadic_inputs(orc):
+    # u_i = sum_j J_ij phi_j (the field term of Eq. 3).  With integer couplings and
+    # fluxes k / 1024 every product and partial sum is exact in binary64, so the
+    # oracle's field must equal the integer result exactly.  J is not symmetric here,
+    # so a transposed operand fails; three replicas with different fluxes catch a
+    # replica-indexing slip; the CSR form of the same matrix must agree.
+    from paper_2004_03972_amd import instances as inst
+    rng = np.random.default_rng(11)
+    N, R = 37, 3
+    Ji = rng.integers(-3, 4, (N, N)) * (rng.random((N, N)) < 0.6)
+    np.fill_diagonal(Ji, 0)
+    k = rng.integers(-2000, 2001, (R, N))
+    exact = np.array([[sum(int(Ji[i, j]) * int(k[r, j]) for j in range(N)) for i in range(N)]
+                      for r in range(R)])
+    u = orc.field(orc.Problem(N, J=Ji.astype(float)), k / 1024.0)
+    assert np.array_equal(u * 1024.0, exact.astype(float))
+    rp, ci, v = inst.dense_to_csr(Ji.astype(float))
+    u2 = orc.field(orc.Problem(N, row_ptr=rp, col=ci, val=v), k / 1024.0)
+    assert np.array_equal(u2, u)
+    assert not np.array_equal(orc.field(orc.Problem(N, J=Ji.T.astype(float)), k / 1024.0), u)

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 5
+#define HQA_ABI_VERSION 6
 
 typedef enum {
     HQA_OK = 0,
@@ -410,6 +410,23 @@ hqa_status hqa_es_predict(hqa_es *es, const float *x, int64_t n, float *prob, in
  * one number to the host.  Synchronises the handle's stream. */
 hqa_status hqa_es_confidence(hqa_es *es, const float *prob, int64_t n, int32_t mem,
                              double *mean_max);
+
+/* The stop rule of the learned early stop, run inside the library: from the current
+ * step, advance every instance in checkpoints of K steps (the last one ending at T);
+ * before each checkpoint collect the statistics over its last Ks steps, sampling every
+ * stride-th step (hqa_md_stats_window), form the features of instance `instance`
+ * (hqa_md_features), predict its class probabilities with es (BF16 inference when
+ * bf16_infer != 0, hqa_es_predict) and compute their confidence (hqa_es_confidence);
+ * stop at the first checkpoint whose confidence reaches `threshold`, or at T (the
+ * fallback: the full run).  The last checkpoint's probabilities [R][N][3] go to prob
+ * (prob_mem; may be NULL) for hqa_classify_probs; *stop_step receives the step reached
+ * and *confidence its confidence (either may be NULL).  Only one number per
+ * checkpoint reaches the host.  HQA_EINVAL unless K >= 1, 1 <= Ks <= K and stride >= 1;
+ * HQA_EUNSUPPORTED for the binary64 reference precision; HQA_ESTATE if the run has
+ * already reached T; errors of the calls above are passed on.  Synchronises. */
+hqa_status hqa_md_run_es(hqa_md *md, int32_t instance, hqa_es *es, int64_t K, int64_t Ks,
+                         int64_t stride, double threshold, int32_t bf16_infer, float *prob,
+                         int32_t prob_mem, int64_t *stop_step, double *confidence);
 
 void hqa_es_destroy(hqa_es *es);
 

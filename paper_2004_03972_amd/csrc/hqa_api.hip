@@ -997,14 +997,13 @@ hqa_status hqa_md_hamiltonian(hqa_md *md, int32_t instance, double *H, int32_t d
 // Read-out shared by hqa_classify (sort by |phibar|), hqa_classify_probs (predicted
 // labels) and hqa_classify_tabu: selection, optional reduced problem solved exactly
 // (solve = 1) or by the tabu search (solve = 2), merge, energies.
-static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
-                                const hqa_classify_out *out, int32_t out_mem, const float *prob,
-                                int32_t prob_mem, int64_t tabu_iters = 0, int32_t tenure = 0) {
+static hqa_status classify_checks(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                                  const hqa_classify_out *out, const float *prob) {
     hqa_status s = check_instance(md, instance);
     if (s != HQA_OK) return s;
     if (!out || !out->spins) return fail(HQA_EINVAL, "out->spins is required");
     Instance &I = md->inst[instance];
-    const int R = md->R, N = I.N;
+    const int N = I.N;
     if (n_amb < 0 || n_amb > N) return fail(HQA_EINVAL, "n_amb must lie in [0, N]");
     if (solve == 1 && n_amb > 24)
         return fail(HQA_EUNSUPPORTED, "exact enumeration limited to n <= 24");
@@ -1022,10 +1021,21 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
     }
     if (solve == 1 && I.j_integral && I.es.msb + 2 * 16 + 8 > 62)
         return fail(HQA_EUNSUPPORTED, "integer couplings too large for int64 enumeration");
-    s = hqa_md_sync(md);
+    return HQA_OK;
+}
+
+// The read-out after classify_checks; device scratch comes from B (DevBufs allocates,
+// ScratchArena carves a fixed array).
+extern "C++" {
+template <class Bufs>
+static hqa_status classify_core(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                                const hqa_classify_out *out, int32_t out_mem, const float *prob,
+                                int32_t prob_mem, int64_t tabu_iters, int32_t tenure, Bufs &B) {
+    Instance &I = md->inst[instance];
+    const int R = md->R, N = I.N;
+    hqa_status s = hqa_md_sync(md);
     if (s != HQA_OK) return s;
     hipStream_t st = md->stream;
-    DevBufs B;
     int32_t *amb;
     int8_t *spins;
     HIPCHK(B.get(&amb, (size_t)R * (n_amb ? n_amb : 1)));
@@ -1092,6 +1102,17 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
     if (out->e_reduced && e_red) HIPCHK(hipMemcpyAsync(out->e_reduced, e_red, (size_t)R * 8, kd, st));
     HIPCHK(hipStreamSynchronize(st));
     return HQA_OK;
+}
+}  // extern "C++"
+
+static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                                const hqa_classify_out *out, int32_t out_mem, const float *prob,
+                                int32_t prob_mem, int64_t tabu_iters = 0, int32_t tenure = 0) {
+    hqa_status s = classify_checks(md, instance, n_amb, solve, out, prob);
+    if (s != HQA_OK) return s;
+    DevBufs B;
+    return classify_core(md, instance, n_amb, solve, out, out_mem, prob, prob_mem, tabu_iters,
+                         tenure, B);
 }
 
 hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
@@ -1314,6 +1335,47 @@ hqa_status hqa_es_confidence(hqa_es *es, const float *prob, int64_t n, int32_t m
     double t = 0.0;
     for (double v : h) t += v;
     *mean_max = t / (double)n;
+    return HQA_OK;
+}
+
+hqa_status hqa_md_run_es(hqa_md *md, int32_t instance, hqa_es *es, int64_t K, int64_t Ks,
+                         int64_t stride, double threshold, int32_t bf16_infer, float *prob,
+                         int32_t prob_mem, int64_t *stop_step, double *confidence) {
+    hqa_status s = check_instance(md, instance);
+    if (s != HQA_OK) return s;
+    if (!es) return fail(HQA_EINVAL, "es is NULL");
+    if (K < 1 || Ks < 1 || Ks > K || stride < 1)
+        return fail(HQA_EINVAL, "need K >= 1, 1 <= Ks <= K and stride >= 1");
+    if (prob && prob_mem != HQA_HOST && prob_mem != HQA_DEVICE) return fail(HQA_EINVAL, "bad prob_mem");
+    if (md->prec == HQA_PREC_F64_REF)
+        return fail(HQA_EUNSUPPORTED, "early-stop statistics run on the binary32 paths");
+    if (md->q >= md->sch.T) return fail(HQA_ESTATE, "the run has already reached step T");
+    const Instance &I = md->inst[instance];
+    const int64_t n = (int64_t)md->R * I.N;
+    DevBufs B;
+    float *feat, *pd;
+    HIPCHK(B.get(&feat, (size_t)n * HQA_ES_NFEAT));
+    HIPCHK(B.get(&pd, (size_t)n * 3));
+    const int64_t T = md->sch.T;
+    int64_t q = md->q;
+    double conf = 0.0;
+    for (;;) {
+        const int64_t nxt = std::min(q + K, T);
+        const int64_t k0 = std::max(q, nxt - Ks);
+        if ((s = hqa_md_run(md, k0)) != HQA_OK) return s;
+        if ((s = hqa_md_stats_window(md, k0, nxt, stride)) != HQA_OK) return s;
+        if ((s = hqa_md_run(md, nxt)) != HQA_OK) return s;
+        q = nxt;
+        if ((s = hqa_md_features(md, instance, feat, HQA_DEVICE)) != HQA_OK) return s;
+        if ((s = hqa_es_predict(es, feat, n, pd, bf16_infer, HQA_DEVICE)) != HQA_OK) return s;
+        if ((s = hqa_es_confidence(es, pd, n, HQA_DEVICE, &conf)) != HQA_OK) return s;
+        if (conf >= threshold || q >= T) break;
+    }
+    if (prob)
+        HIPCHK(hipMemcpy(prob, pd, sizeof(float) * n * 3,
+                         prob_mem == HQA_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice));
+    if (stop_step) *stop_step = q;
+    if (confidence) *confidence = conf;
     return HQA_OK;
 }
 

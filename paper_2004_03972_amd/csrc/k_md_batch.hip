@@ -319,49 +319,66 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
 #undef HQA_LOAD_GROUP
 #undef HQA_MFMA_GROUP
 
-    if (!active) return;
-    const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
-    const int ib = i0 + 4 * kg;
-    const bool win = q + 1 >= a.T - a.W + 1;
-    bool bad = false;
-    const auto *hg = gld<float>(I.h);
+    // Epilogue with full-line accesses: the fields pass through LDS (the flux stages
+    // are free after the last barrier), and thread (replica t / 8, j = t % 8) updates
+    // rows 32 v + 4 j .. 32 v + 4 j + 3 for v = 0..3, so the eight threads of a replica
+    // read and write one whole 128-byte line of fluxes and momenta per instruction.
+    {
+        float *U = (float *)&Bs[0][0][0];                  // [64 replicas][136]
+        constexpr int UL = 136;
 #pragma unroll
-    for (int rt = 0; rt < 4; rt++) {
-        const int col = r0 + 16 * rt + (lane & 15);
-        if (col >= a.R || ib >= I.N) continue;
-        const f32x4 parts[4] = {acc[rt][0], acc[rt][1], acc[rt][2], acc[rt][3]};
-        const f32x4 u = combine4(parts);
-        const int64_t base = (int64_t)col * I.ld + ib;
-        const f32x4 x = *gld<f32x4>(phi_in + base);
-        const f32x4 p = *gld<f32x4>(I.p + base);
-        float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
+        for (int rt = 0; rt < 4; rt++) {
+            const f32x4 parts[4] = {acc[rt][0], acc[rt][1], acc[rt][2], acc[rt][3]};
+            const f32x4 u = combine4(parts);
+            *(f32x4 *)&U[(16 * rt + (lane & 15)) * UL + 16 * w + 4 * kg] = u;
+        }
+        __syncthreads();
+        const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
+        const bool win = q + 1 >= a.T - a.W + 1;
+        bool bad = false;
+        const auto *hg = gld<float>(I.h);
+        const int rep = tid >> 3, j8 = tid & 7;
+        const int col = r0 + rep;
+        if (col < a.R) {
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            if (ib + v < I.N) {
-                leapfrog(cf, xs[v], u[v], hg[ib + v], ps[v], xn[v]);
-                bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
-            } else {
-                xn[v] = 0.0f;
-                ps[v] = 0.0f;
+            for (int v = 0; v < 4; v++) {
+                const int loc = 32 * v + 4 * j8;
+                const int ib = tl.i0 + loc;
+                if (ib >= I.N) continue;
+                const f32x4 u = *(const f32x4 *)&U[rep * UL + loc];
+                const int64_t base = (int64_t)col * I.ld + ib;
+                const f32x4 x = *gld<f32x4>(phi_in + base);
+                const f32x4 p = *gld<f32x4>(I.p + base);
+                float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    if (ib + e < I.N) {
+                        leapfrog(cf, xs[e], u[e], hg[ib + e], ps[e], xn[e]);
+                        bad |= !isfinite(xn[e]) || !isfinite(ps[e]);
+                    } else {
+                        xn[e] = 0.0f;
+                        ps[e] = 0.0f;
+                    }
+                }
+                *gst<f32x4>(phi_out + base) = (f32x4){xn[0], xn[1], xn[2], xn[3]};
+                *gst<f32x4>(I.p + base) = (f32x4){ps[0], ps[1], ps[2], ps[3]};
+                typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+                bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
+                *gst<bf16x4>(xb_out + base) = b;
+                if (win) {
+                    f32x4 s = *gld<f32x4>(I.S + base);
+                    s[0] = s[0] + xn[0]; s[1] = s[1] + xn[1]; s[2] = s[2] + xn[2]; s[3] = s[3] + xn[3];
+                    *gst<f32x4>(I.S + base) = s;
+                }
             }
         }
-        *gst<f32x4>(phi_out + base) = (f32x4){xn[0], xn[1], xn[2], xn[3]};
-        *gst<f32x4>(I.p + base) = (f32x4){ps[0], ps[1], ps[2], ps[3]};
-        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-        bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
-        *gst<bf16x4>(xb_out + base) = b;
-        if (win) {
-            f32x4 s = *gld<f32x4>(I.S + base);
-            s[0] = s[0] + xn[0]; s[1] = s[1] + xn[1]; s[2] = s[2] + xn[2]; s[3] = s[3] + xn[3];
-            *gst<f32x4>(I.S + base) = s;
-        }
+        if (bad) atomicOr(a.err, ERR_NONFINITE);
     }
-    if (bad) atomicOr(a.err, ERR_NONFINITE);
 }
 
 // One launch per MD step for every BF16 and FP8 instance of the batch: the storage
 // type is uniform per tile.  A tile with instance index -1 is a placeholder of the
-// XCD placement and does nothing.  Two workgroups per CU (128 registers per lane).
+// XCD placement and does nothing.
 __global__ __launch_bounds__(512, 2) void k_step_batch_lds(BatchArgs a, int64_t q) {
     __shared__ __align__(16) bf16 Bs[2][BL_REPS][BL_LDB];
     const BatchTile tl = a.tiles[blockIdx.x];

@@ -42,32 +42,43 @@ def labels_from_full(md, n_amb: int) -> tuple[np.ndarray, dict]:
 
 def record_run(problem, sched, R: int, K: int, n_ckpt: int, seed: int, n_amb: int,
                precision="f32", solve_n: int = 0, every: int = 1, Ks: int | None = None,
-               stride: int = 1) -> RunRecord:
+               stride: int = 1, keep: float = 1.0, keep_seed: int = 0,
+               means: bool = True) -> RunRecord:
     """Run to T with statistics windows of the last Ks steps (default K; sampling every
-    stride-th step) before every every-th checkpoint among K, 2K, ..., n_ckpt K; return the features and the trailing-
-    window mean flux at those checkpoints and the labels from the full run."""
+    stride-th step) before every every-th checkpoint among K, 2K, ..., n_ckpt K; return
+    the features and the trailing-window mean flux at those checkpoints and the labels
+    from the full run.  With keep < 1 only a random fraction `keep` of the (replica,
+    spin) samples of each checkpoint is returned, as rows [n, 12] with their labels in
+    record.labels (large training sets)."""
     Ks = K if Ks is None else Ks
     md = hqa.MD(problem, sched, R, precision, seed=seed)
-    feats, steps, means = [], [], []
+    feats, steps, mlist = [], [], []
     for j in range(every, n_ckpt + 1, every):
         md.run(j * K - Ks)
         md.stats_window(j * K - Ks, j * K, stride)
         md.run(j * K)
         feats.append(md.features())
-        means.append(md.state(hqa.HQA_STATE_STATMEAN))
+        if means:
+            mlist.append(md.state(hqa.HQA_STATE_STATMEAN))
         steps.append(j * K)
     md.run()
     lab, g = labels_from_full(md, n_amb)
     full = md.classify(solve_n, solve=solve_n > 0) if solve_n else g
-    return RunRecord(feats, steps, lab, full, md, means)
+    if keep < 1.0:
+        rng = np.random.default_rng(keep_seed)
+        sel = [rng.random(lab.size) < keep for _ in feats]
+        feats = [f.reshape(-1, hqa.HQA_ES_NFEAT)[m] for f, m in zip(feats, sel)]
+        lab = [lab.ravel()[m] for m in sel]
+    return RunRecord(feats, steps, lab, full, md, mlist)
 
 
 def dataset(records) -> tuple[np.ndarray, np.ndarray]:
     X, y = [], []
     for rec in records:
-        for f in rec.feats:
+        for c, f in enumerate(rec.feats):
             X.append(f.reshape(-1, hqa.HQA_ES_NFEAT))
-            y.append(rec.labels.ravel())
+            # subsampled records keep one label vector per checkpoint
+            y.append(rec.labels[c] if isinstance(rec.labels, list) else rec.labels.ravel())
     return np.concatenate(X), np.concatenate(y)
 
 
@@ -171,22 +182,12 @@ def run_with_early_stop(es, problem, sched, R: int, K: int, threshold: float, n_
     md = hqa.MD(problem, sched, R, "f32", seed=seed)
     T, N = sched.T, problem.n
     # features and probabilities stay on the device; each checkpoint returns one number
-    feat = torch.empty((R * N, hqa.HQA_ES_NFEAT), dtype=torch.float32, device="cuda")
     pdev = torch.empty((R * N, 3), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    q = 0
     Ks = K if Ks is None else Ks
-    while True:
-        nxt = min(q + K, T)
-        md.run(max(q, nxt - Ks))
-        md.stats_window(max(q, nxt - Ks), nxt, stride)
-        md.run(nxt)
-        q = nxt
-        md.features(out=feat)
-        es.predict(feat, bf16=bf16, out=pdev)
-        if es.confidence(pdev) >= threshold or q >= T:
-            break
+    # the checkpoint loop and the stop rule run in the library (hqa_md_run_es)
+    q, _conf = md.run_es(es, K, Ks, stride, threshold, bf16=bf16, prob=pdev)
     stopped = q < T
     out = md.classify(n_amb, solve=True, prob=pdev)   # host outputs: synchronises
     wall_ms = (time.perf_counter() - t0) * 1e3

@@ -30,9 +30,9 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_md_tuned_plan", "hqa_md_set_step_tiles", "hqa_md_field_error",
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
-            "hqa_es_confidence", "hqa_es_destroy", "hqa_classify_tabu")
+            "hqa_es_confidence", "hqa_es_destroy", "hqa_classify_tabu", "hqa_md_run_es")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
-ABI_VERSION = 5
+ABI_VERSION = 6
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
          "resident": HQA_PLAN_RESIDENT, "batch": HQA_PLAN_BATCH}
@@ -100,6 +100,7 @@ def lib():
         L.hqa_md_set_step_tiles.argtypes = [P, i32, i32, i32, i32, i32]
         L.hqa_md_field_error.argtypes = [P, i32, P, P]
         L.hqa_es_confidence.argtypes = [P, P, i64, i32, P]
+        L.hqa_md_run_es.argtypes = [P, i32, P, i64, i64, i64, C.c_double, i32, P, i32, P, P]
         L.hqa_md_state.argtypes = [P, i32, i32, P, i32, i32]
         L.hqa_md_set_step.argtypes = [P, i64]
         L.hqa_md_field.argtypes = [P, i32, P, i32]
@@ -202,6 +203,15 @@ def hqa_es_confidence(es, prob, n: int, mem: int) -> float:
     pa, _ = _addr(prob)
     _check(lib().hqa_es_confidence(es, pa, n, mem, C.byref(out)))
     return out.value
+
+
+def hqa_md_run_es(md, instance: int, es, K: int, Ks: int, stride: int, threshold: float,
+                  bf16_infer: int, prob, prob_mem: int) -> tuple[int, float]:
+    stop, conf = C.c_int64(0), C.c_double(0.0)
+    pp, _k = _addr(prob)
+    _check(lib().hqa_md_run_es(md, instance, es, K, Ks, stride, threshold, bf16_infer, pp,
+                               prob_mem, C.byref(stop), C.byref(conf)))
+    return stop.value, conf.value
 
 
 def hqa_md_field_error(md, k: int = 0) -> tuple[float, float]:
@@ -317,10 +327,11 @@ class ES:
             hqa_es_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # a handle still open at interpreter shutdown is left to the process exit: the HIP
         # runtime may already be torn down, so no device call is made from here then
-        if sys.is_finalizing():
+        # (the check is bound at definition: module globals are gone by that time)
+        if _finalizing():
             return
         try:
             self.close()
@@ -437,10 +448,11 @@ class MD:
             hqa_md_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # a handle still open at interpreter shutdown is left to the process exit: the HIP
         # runtime may already be torn down, so no device call is made from here then
-        if sys.is_finalizing():
+        # (the check is bound at definition: module globals are gone by that time)
+        if _finalizing():
             return
         try:
             self.close()
@@ -468,6 +480,14 @@ class MD:
     def tune(self, steps: int = 20):
         """Time every bit-identical plan from the current state and keep the fastest."""
         hqa_md_tune(self.h, steps)
+
+    def run_es(self, es, K: int, Ks: int, stride: int, threshold: float, k: int = 0,
+               bf16: bool = True, prob=None) -> tuple[int, float]:
+        """The learned early stop's checkpoint loop (hqa_md_run_es): returns (stop step,
+        confidence); the last checkpoint's probabilities go to `prob` (a device tensor
+        [R*N][3] or a host array [R][N][3]) when given."""
+        mem = HQA_HOST if prob is None or isinstance(prob, np.ndarray) else HQA_DEVICE
+        return hqa_md_run_es(self.h, k, es.h, K, Ks, stride, threshold, int(bf16), prob, mem)
 
     def field_error(self, k: int = 0) -> tuple[float, float]:
         """(max |u32 - u64|, max |u64|) of instance k's field on the current fluxes."""

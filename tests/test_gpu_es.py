@@ -132,3 +132,51 @@ def test_classify_from_probabilities(H):
     assert np.array_equal(g["spins"], sh) and np.array_equal(g["code"], code)
     E, C = orc.energy(pb, sh)
     assert np.array_equal(g["energy"], E)
+
+
+def test_run_es_equals_checkpoint_loop(H):
+    """hqa_md_run_es (the stop loop inside the library) against the same calls made one
+    by one: the same stop step, and bit-identical probabilities and confidence."""
+    import torch
+    N, R, T, K, Ks, stride = 300, 4, 2000, 400, 100, 2
+    J = inst.er_maxcut(N, 0.05, 41)
+    es = H.ES(seed=3)
+    md = H.MD(H.Problem(J), H.make_schedule(T, 100), R, "f32", seed=6)
+    feat = torch.empty((R * N, 12), dtype=torch.float32, device="cuda")
+    probs, confs, q = [], [], 0
+    while q < T:
+        nxt = min(q + K, T)
+        md.run(max(q, nxt - Ks))
+        md.stats_window(max(q, nxt - Ks), nxt, stride)
+        md.run(nxt)
+        q = nxt
+        md.features(out=feat)
+        pd = torch.empty((R * N, 3), dtype=torch.float32, device="cuda")
+        es.predict(feat, bf16=True, out=pd)
+        probs.append(pd.cpu().numpy())
+        confs.append(es.confidence(pd))
+    md.close()
+    thr = confs[2]
+    want = next(j for j, c in enumerate(confs) if c >= thr)
+    md = H.MD(H.Problem(J), H.make_schedule(T, 100), R, "f32", seed=6)
+    out = np.empty((R, N, 3), dtype=np.float32)
+    stop, conf = md.run_es(es, K, Ks, stride, thr, prob=out)
+    print("confidences", confs, "stop", stop, flush=True)
+    assert stop == (want + 1) * K and conf == confs[want]
+    assert np.array_equal(out.reshape(-1, 3), probs[want])
+    md.close()
+    # a threshold never reached runs to T (the fallback)
+    md = H.MD(H.Problem(J), H.make_schedule(T, 100), R, "f32", seed=6)
+    stop, conf = md.run_es(es, K, Ks, stride, 2.0)
+    assert stop == T and conf == confs[-1]
+    with pytest.raises(H.HQAError) as e:
+        md.run_es(es, K, Ks, stride, 0.5)            # already at T
+    assert e.value.status == H.HQA_ESTATE
+    md.close()
+    md = H.MD(H.Problem(J), H.make_schedule(T, 100), R, "f32", seed=6)
+    for bad in ((0, 1, 1), (100, 200, 1), (100, 50, 0)):
+        with pytest.raises(H.HQAError) as e:
+            md.run_es(es, *bad, 0.5)
+        assert e.value.status == H.HQA_EINVAL
+    md.close()
+    es.close()

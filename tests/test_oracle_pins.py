@@ -439,3 +439,44 @@ def test_field_export_exact_on_dyadic_inputs(orc):
     u2 = orc.field(orc.Problem(N, row_ptr=rp, col=ci, val=v), k / 1024.0)
     assert np.array_equal(u2, u)
     assert not np.array_equal(orc.field(orc.Problem(N, J=Ji.T.astype(float)), k / 1024.0), u)
+
+
+def test_divergence_follows_leapfrog_stability_bound(orc):
+    """Why some runs diverge (schedule sweeps with kappa2 < 0): the leapfrog of the
+    Methods, linearised about phi for the potential alone, reads
+    phi_(m+1) - 2 phi_m + phi_(m-1) = -k phi_m with k = alpha^2 M (M-1) phi^(M-2), and is
+    stable only for 0 < k < 4.  On the spin glass with fields at the field scale of
+    N = 10^4 (J ~ U[-1, 1] scaled by sqrt(10^4 / N), h ~ U[-2, 2]), the binary64 oracle
+    run with kappa2 = -1 blows up (|phi| > 10^3 or non-finite) only after
+    k = alpha^2 M (M-1) max|phi|^(M-2) has passed 4, shortly before; with kappa2 = +1
+    and the same instance and initial momenta, k stays below 4 and the run stays
+    finite."""
+    from paper_2004_03972_amd import instances as inst
+    N, M, T = 200, 6, 2000
+    J, h = inst.uniform_glass(N, 4)
+    pb = orc.Problem(N, J=J * np.sqrt(1e4 / N), h=h)
+    p0 = orc.init_p0(1, N, 32)[3:4]
+
+    def trace(kappa2):
+        mp = orc.MDParams(T=T, W=100, M=M, schedule=(0.008, 4.0, 3.0, 0.12, 0.05, kappa2))
+        phi, p = np.zeros((1, N)), p0.copy()
+        first_k4, kmax = None, 0.0
+        for q in range(T):
+            a = mp.alpha[2 * q]
+            k = a * a * M * (M - 1) * np.max(np.abs(phi)) ** (M - 2)
+            if first_k4 is None and k > 4.0:
+                first_k4 = q
+            kmax = max(kmax, k)
+            try:
+                orc.md_advance(pb, mp, phi, p, None, q, q + 1)
+            except FloatingPointError:
+                return first_k4, q, kmax
+            if np.max(np.abs(phi)) > 1e3:
+                return first_k4, q, kmax
+        return first_k4, None, kmax
+
+    first, blow, _ = trace(-1.0)
+    assert blow is not None and first is not None
+    assert first < blow <= first + 100
+    first, blow, kmax = trace(1.0)
+    assert blow is None and first is None and kmax < 4.0

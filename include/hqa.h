@@ -304,6 +304,22 @@ typedef struct hqa_classify_out {
 hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                         const hqa_classify_out *out, int32_t out_mem);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hqa_classify with the same
+ * arguments, outputs and errors, but no device allocation or release.  Its scratch
+ * (ambivalent indices, read-out spins, reduced problem, enumeration and energy partial
+ * results) lives in one fixed device array of HQA_NOALLOC_SCRATCH_BYTES bytes that each
+ * GPU the library runs on holds until the process ends; its address is looked up at
+ * the first call on a device.  A read-out that needs more (about R (N + 8 n^2) bytes)
+ * returns HQA_EUNSUPPORTED before any device work.  Every call on one GPU uses that
+ * GPU's array, whose contents the last call leaves behind: calls that overlap in time
+ * on one GPU (other host threads, other streams) race, so serialise them.  Outputs may
+ * be host or device memory (out_mem); host outputs are copied synchronously.
+ * Synchronises. */
+#define HQA_NOALLOC_SCRATCH_BYTES (16u << 20)
+hqa_status hqa_classify_noalloc(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                                const hqa_classify_out *out, int32_t out_mem);
+
 /* Read-out at q = T as hqa_classify, with the reduced problem of the n_amb
  * ambivalent spins (HQA section: past exact enumeration the paper passes the
  * reduced problem to a tabu search) solved by a deterministic single-flip tabu

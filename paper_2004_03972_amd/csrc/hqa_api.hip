@@ -1,3 +1,4 @@
+#include <mutex>
 // hqa_api.hip -- the C ABI of include/hqa.h: argument checks, device buffers,
 // dispatch of the MD step kernels and of the read-out chain.
 #include <math.h>
@@ -1120,6 +1121,85 @@ hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t sol
     // the tabu mode (2) is reachable only through hqa_classify_tabu, which checks its limits
     if (solve != 0 && solve != 1) return fail(HQA_EINVAL, "solve must be 0 or 1");
     return classify_impl(md, instance, n_amb, solve, out, out_mem, nullptr, HQA_HOST);
+}
+
+// ---------------------------------------------------------------------------
+// Read-out without device allocation.  Its scratch is one fixed device array per GPU;
+// host code never passes the array's name to a kernel (in host code that name is a
+// stand-in, not a device address): the address comes from hipGetSymbolAddress, once
+// per device, and only that pointer is used.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[HQA_NOALLOC_SCRATCH_BYTES];
+
+#define HQA_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[HQA_MAX_DEVICES] = {};
+
+// The current device's address of `scratch` (looked up at the first call on a device).
+static hqa_status noalloc_scratch(void **ptr) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= HQA_MAX_DEVICES)
+        return fail(HQA_EUNSUPPORTED, "device %d beyond the %d the library tracks", dev,
+                    HQA_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HQA_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return HQA_OK;
+}
+
+// Bump allocation from a fixed region, 256-byte aligned, in the same order and sizes
+// as DevBufs::get calls of classify_core.
+extern "C++" {
+struct ScratchArena {
+    uint8_t *base = nullptr;
+    size_t cap = 0, used = 0;
+    static size_t round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+    template <typename T>
+    hipError_t get(T **p, size_t n) {
+        const size_t b = round(n * sizeof(T));
+        if (used + b > cap) return hipErrorOutOfMemory;
+        *p = (T *)(base + used);
+        used += b;
+        return hipSuccess;
+    }
+};
+}  // extern "C++"
+
+// Bytes classify_core takes from its provider for solve in {0, 1} and phibar input.
+static size_t classify_scratch_bytes(int R, int N, int n, int solve, const hqa_classify_out *out) {
+    auto r = ScratchArena::round;
+    size_t b = r((size_t)R * (n ? n : 1) * 4) + r((size_t)R * N);
+    if (solve && n > 0)
+        b += r((size_t)R * n * 8) + r((size_t)R * n * n * 8) + r((size_t)R * 8) + r((size_t)R * 8) +
+             r(enum_scratch_bytes(n, R));
+    else if (out->h_eff && n > 0)
+        b += r((size_t)R * n * 8) + r((size_t)R * n * n * 8);
+    if (out->energy || out->cut) b += 2 * r((size_t)R * 8) + r(energy_part_bytes(N, R));
+    return b;
+}
+
+hqa_status hqa_classify_noalloc(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
+                                const hqa_classify_out *out, int32_t out_mem) {
+    if (solve != 0 && solve != 1) return fail(HQA_EINVAL, "solve must be 0 or 1");
+    hqa_status s = classify_checks(md, instance, n_amb, solve, out, nullptr);
+    if (s != HQA_OK) return s;
+    const size_t need = classify_scratch_bytes(md->R, md->inst[instance].N, n_amb, solve, out);
+    if (need > (size_t)HQA_NOALLOC_SCRATCH_BYTES)
+        return fail(HQA_EUNSUPPORTED, "read-out needs %zu bytes of scratch, above the %zu of the "
+                    "fixed array", need, (size_t)HQA_NOALLOC_SCRATCH_BYTES);
+    void *base = nullptr;
+    if ((s = noalloc_scratch(&base)) != HQA_OK) return s;
+    ScratchArena A;
+    A.base = (uint8_t *)base;
+    A.cap = HQA_NOALLOC_SCRATCH_BYTES;
+    return classify_core(md, instance, n_amb, solve, out, out_mem, nullptr, HQA_HOST, 0, 0, A);
 }
 
 hqa_status hqa_classify_tabu(hqa_md *md, int32_t instance, int32_t n_amb, int64_t iters,

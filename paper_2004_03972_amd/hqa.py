@@ -30,8 +30,10 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_md_tuned_plan", "hqa_md_set_step_tiles", "hqa_md_field_error",
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
-            "hqa_es_confidence", "hqa_es_destroy", "hqa_classify_tabu", "hqa_md_run_es")
+            "hqa_es_confidence", "hqa_es_destroy", "hqa_classify_tabu", "hqa_md_run_es",
+            "hqa_classify_noalloc")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
+HQA_NOALLOC_SCRATCH_BYTES = 16 << 20
 ABI_VERSION = 6
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
@@ -106,6 +108,7 @@ def lib():
         L.hqa_md_field.argtypes = [P, i32, P, i32]
         L.hqa_md_hamiltonian.argtypes = [P, i32, P, i32]
         L.hqa_classify.argtypes = [P, i32, i32, i32, P, i32]
+        L.hqa_classify_noalloc.argtypes = [P, i32, i32, i32, P, i32]
         L.hqa_ising_energy.argtypes = [P, P, i32, P, P, i32, P]
         L.hqa_md_destroy.argtypes = [P]
         L.hqa_md_stats_window.argtypes = [P, i64, i64, i64]
@@ -251,6 +254,11 @@ def hqa_md_hamiltonian(md, instance: int, H, dst_mem: int):
 
 def hqa_classify(md, instance: int, n_amb: int, solve: int, out: hqa_classify_out, out_mem: int):
     _check(lib().hqa_classify(md, instance, n_amb, solve, C.byref(out), out_mem))
+
+
+def hqa_classify_noalloc(md, instance: int, n_amb: int, solve: int, out: hqa_classify_out,
+                         out_mem: int):
+    _check(lib().hqa_classify_noalloc(md, instance, n_amb, solve, C.byref(out), out_mem))
 
 
 def hqa_classify_tabu(md, instance: int, n_amb: int, iters: int, tenure: int,

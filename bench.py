@@ -55,7 +55,8 @@ def measured_traffic(name, sources="dense", kernel=None):
     """HBM bytes per launch from a committed PMC summary (FETCH_SIZE and WRITE_SIZE in KiB
     per dispatch, each scaled by the factor a plain copy of known size gives), or None when
     the summary is missing, was taken for another kernel instance than `kernel`, or the
-    kernel's sources changed since the counters were taken."""
+    kernel changed since the counters were taken: its gfx950 machine code in the loaded
+    library (isa_sha256, when the summary stores one), else its sources (source_sha256)."""
     from paper_2004_03972_amd import profsum
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
@@ -69,8 +70,10 @@ def measured_traffic(name, sources="dense", kernel=None):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        srcs = profsum.SOURCES[sources]
-        if kv.get("source_sha256") != profsum.source_hash(srcs):
+        if "isa_sha256" in kv:
+            if kernel is None or kv["isa_sha256"] != profsum.isa_hash(kernel):
+                return None
+        elif kv.get("source_sha256") != profsum.source_hash(profsum.SOURCES[sources]):
             return None
         return (float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_factor"])
                 + float(kv["write_kib_per_dispatch"]) * float(kv["write_factor"])) * 1024.0

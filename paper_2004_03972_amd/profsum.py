@@ -9,7 +9,12 @@
 name contains SUBSTR; ``calib`` prints the counter of the largest dispatch (a plain
 copy of B bytes) and the factor B / (1024 * value) that turns the counter into bytes.
 ``srchash`` prints the SHA-256 of the dense step kernel's sources, stored beside PMC
-figures so that a later reader can tell whether the kernel changed since.
+figures so that a later reader can tell whether the kernel changed since.  ``isahash``
+prints the SHA-256 of one kernel's gfx950 machine code as built into libhqa.so (its
+instruction text without addresses, plus its kernel descriptor): a host-only edit of a
+shared header leaves it unchanged, any change of the kernel's code does not.
+
+  python -m paper_2004_03972_amd.profsum isahash --kernel k_step_batch_lds [--lib PATH]
 """
 from __future__ import annotations
 
@@ -17,8 +22,12 @@ import argparse
 import csv
 import hashlib
 import os
+import re
+import shutil
 import statistics
+import subprocess
 import sys
+import tempfile
 
 DENSE_SOURCES = ("csrc/k_md_dense.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
 CSR_SOURCES = ("csrc/k_md_csr.hip", "csrc/md_epilogue.h", "csrc/hqa_internal.h")
@@ -38,6 +47,95 @@ def source_hash(files=DENSE_SOURCES) -> str:
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+_LLVM = "/opt/rocm/llvm/bin"
+_BUNDLE_MAGIC = b"__CLANG_OFFLOAD_BUNDLE__"
+_TARGET = "hipv4-amdgcn-amd-amdhsa--gfx950"
+
+
+def _tool(name):
+    p = os.path.join(_LLVM, name)
+    return p if os.access(p, os.X_OK) else shutil.which(name)
+
+
+def isa_hash(kernel: str, lib: str | None = None) -> str | None:
+    """SHA-256 of the gfx950 code of the kernel whose mangled name contains
+    `kernel` (exactly one such kernel must exist) in the library's offload bundles, or
+    None when the ROCm object tools are missing or the kernel is not found.  The
+    instruction text is taken without addresses and encodings (branch offsets are
+    relative), so the hash does not move when other kernels of the library change."""
+    tools = [_tool(t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-readelf",
+                                "llvm-objdump")]
+    if None in tools:
+        return None
+    objcopy, bundler, readelf, objdump = tools
+    lib = lib or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhqa.so")
+    with tempfile.TemporaryDirectory() as tmp:
+        fb = os.path.join(tmp, "fatbin")
+        r = subprocess.run([objcopy, f"--dump-section=.hip_fatbin={fb}", lib,
+                            os.path.join(tmp, "stripped")], capture_output=True)
+        if r.returncode or not os.path.exists(fb):
+            return None
+        data = open(fb, "rb").read()
+        offs = [m.start() for m in re.finditer(re.escape(_BUNDLE_MAGIC), data)] + [len(data)]
+        found = []
+        for i, (a, b) in enumerate(zip(offs, offs[1:])):
+            bi, co = os.path.join(tmp, f"b{i}"), os.path.join(tmp, f"c{i}.o")
+            with open(bi, "wb") as fh:
+                fh.write(data[a:b])
+            if subprocess.run([bundler, "--unbundle", "--type=o", f"--input={bi}",
+                               f"--targets={_TARGET}", f"--output={co}"],
+                              capture_output=True).returncode:
+                continue
+            syms = subprocess.run([readelf, "-s", "--wide", co], capture_output=True,
+                                  text=True).stdout
+            for line in syms.splitlines():
+                f = line.split()
+                if len(f) >= 8 and f[3] == "FUNC" and kernel in f[7]:
+                    found.append((co, f[7]))
+        names = {n for _, n in found}
+        if len(names) != 1:
+            return None
+        co, name = found[0]
+        dis = subprocess.run([objdump, "-d", "--no-show-raw-insn", "--no-leading-addr",
+                              f"--disassemble-symbols={name}", co],
+                             capture_output=True, text=True).stdout
+        lines = dis.splitlines()
+        start = next((k for k, ln in enumerate(lines) if ln.startswith(f"{name}>:")
+                      or ln.endswith(f"<{name}>:")), None)
+        if start is None:
+            return None
+        body = [ln.split("//")[0].rstrip() for ln in lines[start:]]
+        body = [ln for ln in body if ln.strip()]
+        if len(body) < 2:
+            return None
+        # the kernel descriptor (register counts, LDS size, launch properties)
+        kd = subprocess.run([readelf, "-s", "--wide", co], capture_output=True,
+                            text=True).stdout
+        h = hashlib.sha256("\n".join(body).encode())
+        for line in kd.splitlines():
+            f = line.split()
+            if len(f) >= 8 and f[7] == name + ".kd":
+                kdb = bytearray(_kd_bytes(co, int(f[1], 16), int(f[2])))
+                kdb[16:24] = bytes(8)      # the code entry offset depends on the layout
+                h.update(bytes(kdb))
+                break
+        return h.hexdigest()
+
+
+def _kd_bytes(obj, vaddr, size):
+    """Bytes of a symbol at virtual address vaddr in an ELF object's loaded sections."""
+    import struct
+    d = open(obj, "rb").read()
+    shoff, = struct.unpack_from("<Q", d, 0x28)
+    shentsize, shnum = struct.unpack_from("<HH", d, 0x3A)
+    for k in range(shnum):
+        o = shoff + k * shentsize
+        _, typ, _, addr, off, sz = struct.unpack_from("<IIQQQQ", d, o)
+        if typ != 8 and addr <= vaddr < addr + sz:          # not SHT_NOBITS
+            return d[off + vaddr - addr: off + vaddr - addr + size]
+    return b""
 
 
 def _rows(path):
@@ -104,13 +202,14 @@ def calib(path, nbytes):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "trace", "pmc", "calib", "srchash"])
+    ap.add_argument("mode", choices=["stats", "trace", "pmc", "calib", "srchash", "isahash"])
     ap.add_argument("path", nargs="?")
     ap.add_argument("--kernel", default="")
     ap.add_argument("--top", type=int, default=12)
     ap.add_argument("--bytes", type=int, default=0)
     ap.add_argument("--sources", default="dense", choices=sorted(SOURCES))
     ap.add_argument("--last", type=int, default=0, help="only the last N dispatches")
+    ap.add_argument("--lib", default=None, help="library for isahash (default libhqa.so)")
     a = ap.parse_args(argv)
     if a.mode == "stats":
         stats(a.path, a.top)
@@ -120,6 +219,11 @@ def main(argv=None):
         pmc(a.path, a.kernel, a.last)
     elif a.mode == "calib":
         calib(a.path, a.bytes)
+    elif a.mode == "isahash":
+        h = isa_hash(a.kernel, a.lib)
+        if h is None:
+            sys.exit(f"no unique gfx950 kernel matching {a.kernel!r} (or no ROCm object tools)")
+        print(h)
     else:
         print(source_hash(SOURCES[a.sources]))
 

@@ -1,5 +1,6 @@
 """bench.py's command line on the CPU: more than one GPU is refused with a message
-before any device work, and the workload list parses."""
+before any device work, the workload list parses, and the kernel-code hash that ties a
+PMC summary to the kernel it measured is well defined."""
 import os
 import subprocess
 import sys
@@ -23,3 +24,18 @@ def test_help_lists_every_workload():
     assert r.returncode == 0
     for w in ("er800", "ea3d", "batch512", "es", "k2000", "glass", "dense8k", "sweep", "copy", "peaks"):
         assert w in r.stdout
+
+
+def test_kernel_code_hash_identifies_one_kernel():
+    """The PMC summaries are tied to a kernel's gfx950 code in the built library: the
+    hash is stable, distinct between kernels, and refuses an ambiguous name."""
+    sys.path.insert(0, ROOT)
+    from paper_2004_03972_amd import hqa, profsum
+    hqa.lib()
+    a = profsum.isa_hash("k_step_batch_lds")
+    assert a is not None and len(a) == 64
+    assert profsum.isa_hash("k_step_batch_lds") == a
+    b = profsum.isa_hash("k_step_batchILi0")
+    assert b is not None and b != a
+    assert profsum.isa_hash("k_step_batch") is None          # two kernels match
+    assert profsum.isa_hash("no_such_kernel_name") is None

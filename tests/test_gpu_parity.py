@@ -344,3 +344,32 @@ def test_error_paths(H):
     with pytest.raises(H.HQAError) as e:
         md.sync()
     assert e.value.status == H.HQA_ENONFINITE
+
+
+@pytest.mark.parametrize("prec", ["fp8", "bf16"])
+def test_lowp_trajectory_within_bound(H, prec):
+    """The chosen forms against the oracle's binary64 trajectory over the first steps:
+    within the derived forward error bound (tests/f32_bound.py) with the couplings
+    rounded to their storage (exact for unit weights in FP8, 2^-8 relative in BF16) and
+    the flux operand rounded to BF16 (2^-8 relative), FP32 accumulation (the matrix
+    core's summation allowed twice the round-to-nearest error)."""
+    from f32_bound import f32_bound
+    R, T = 8, 2000
+    if prec == "fp8":
+        N = 300
+        J = inst.er_maxcut(N, 0.05, 81)
+        uJ = 0.0
+    else:
+        N = 200
+        J = inst.sk(N, 82)
+        uJ = 2.0 ** -8
+    md = H.MD(H.Problem(J), H.make_schedule(T, 100), R, prec, seed=3,
+              require_exact=(prec == "fp8"))
+    e, phis = f32_bound(orc, orc.Problem(N, J=J), orc.MDParams(T=T, W=100), np.zeros((R, N)),
+                        orc.init_p0(3, N, R), 30, uJ=uJ, uB=2.0 ** -8, gam_factor=2.0)
+    for q in (1, 5, 10, 20, 30):
+        md.run(q)
+        err = np.max(np.abs(md.state(H.HQA_STATE_PHI) - phis[q]))
+        _say(prec, "step", q, "max |phi - phi64|", err, "bound", e[q])
+        assert err <= e[q]
+    md.close()

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 6
+#define HQA_ABI_VERSION 7
 
 typedef enum {
     HQA_OK = 0,
@@ -119,8 +119,19 @@ typedef struct hqa_md_opts {
                                 exactly to the storage type of the precision */
     int32_t plan;            /* hqa_plan for the dense binary32 instances (below);
                                 every plan gives bit-identical trajectories */
-    int32_t reserved;
+    int32_t flags;           /* 0 or HQA_MD_GRAPH (below); other bits: HQA_EINVAL */
 } hqa_md_opts;
+
+/* HQA_MD_GRAPH: hqa_md_run enqueues the BATCH plan's launches of steps [q, until_step)
+ * as one HIP graph launch on the handle's stream.  The graph is captured on first use
+ * (on a stream of the handle's own, so the handle's stream may be the null stream)
+ * and kept per (first step, last step, flux-buffer parity), up to 8 graphs per handle,
+ * least recently used dropped first; a replay runs the same kernels with the same
+ * arguments as the eager launches, so trajectories are bit-identical.  It saves the
+ * host the cost of one launch per step when the steps are short (small instances).
+ * Other plans, and steps inside an early-stop statistics window, launch eagerly.  A
+ * capture or instantiation failure is returned as HQA_EDEVICE by hqa_md_run. */
+#define HQA_MD_GRAPH 1
 
 /* Execution plans of the dense binary32 step.  All of them compute the same
  * binary32 operations in the same order (K chunk c of 32 columns feeds MFMA

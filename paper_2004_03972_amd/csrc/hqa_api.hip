@@ -21,7 +21,7 @@ hipError_t launch_md_steps_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_persist(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_md_persist_set(hqa_md *md, Instance *const *set, int K, int64_t q0,
                                  int64_t q1);
-hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1);
+hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1, bool graph = false);
 void free_batch_plan(void *p);
 hipError_t launch_field_f64(hqa_md *md, Instance &I, double *u, hipStream_t st);
 hipError_t launch_field_dense(hqa_md *md, Instance &I, float *u, hipStream_t st);
@@ -266,6 +266,7 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
         return fail(HQA_EINVAL, "bad init_mem");
     if (opts->plan < HQA_PLAN_AUTO || opts->plan > HQA_PLAN_BATCH)
         return fail(HQA_EINVAL, "unknown plan %d", opts->plan);
+    if (opts->flags & ~HQA_MD_GRAPH) return fail(HQA_EINVAL, "unknown flags 0x%x", opts->flags);
     for (int k = 0; k < count; k++) {
         hqa_status s = check_problem(probs[k], k);
         if (s != HQA_OK) return s;
@@ -287,6 +288,7 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
     md->R = opts->replicas;
     md->prec = opts->precision;
     md->plan = opts->plan;
+    md->flags = opts->flags;
     {
         int dev = 0, lds = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -383,6 +385,7 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
                 return bail(fail(HQA_EUNSUPPORTED,
                                  "instance %d: J is not exactly representable in the storage "
                                  "type of the requested precision", k));
+            I.js_exact = P.layout == HQA_DENSE && !(e & ERR_INEXACT);
             HK(hipMemsetAsync(md->err, 0, sizeof(int32_t), st));
         }
         const double *p0 = opts->p0 ? opts->p0 + off : nullptr;
@@ -451,7 +454,7 @@ static hipError_t run_dense(hqa_md *md, Instance &I, int64_t q0, int64_t q1, boo
         (void)hipGetLastError();
     }
     if (!stats_live && plan == HQA_PLAN_BATCH && batch_alone(md, I)) {
-        hipError_t e = launch_md_steps_batch(md, q0, q1);
+        hipError_t e = launch_md_steps_batch(md, q0, q1, md->flags & HQA_MD_GRAPH);
         if (e == hipSuccess) {
             *used = HQA_PLAN_BATCH;
             return e;
@@ -535,7 +538,7 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     const bool batched = multi && md->plan == HQA_PLAN_AUTO && mp == HQA_PLAN_BATCH;
     const bool clustered = multi && mp == HQA_PLAN_CLUSTER;
     if (batched) {
-        hipError_t e = launch_md_steps_batch(md, md->q, q1);
+        hipError_t e = launch_md_steps_batch(md, md->q, q1, md->flags & HQA_MD_GRAPH);
         if (e != hipSuccess) return fail(HQA_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
         md->last_plan = HQA_PLAN_BATCH;
     }

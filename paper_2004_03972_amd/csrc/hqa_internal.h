@@ -77,6 +77,7 @@ struct Instance {
 
     ExpStats es{0, 0};
     bool j_integral = false;  // every J and h is an integer
+    bool js_exact = false;    // dense: Js holds every coupling exactly
     // dense binary32 plan chosen by the tuner (0: not tuned) and its per-step tile width
     int32_t tuned_plan = 0;
     int32_t step_tn = 0;      // replica tiles of 16 per per-step block (0: widest that divides Rp)
@@ -116,6 +117,8 @@ struct hqa_md {
     int multi_plan = 0;                      // tuned way to run several dense instances:
                                              // BATCH, CLUSTER, or STEP (each on its own plan)
     void *batch = nullptr;                   // device tile tables of a multi-instance batch
+                                             // and its captured step graphs
+    int32_t flags = 0;                       // HQA_MD_* run flags
     int64_t stats_k0 = 0, stats_k1 = 0;      // early-stop statistics window [k0, k1)
     int64_t stats_every = 1;                 // ... sampling steps k0, k0 + every, ...
 };

@@ -390,15 +390,28 @@ __global__ __launch_bounds__(512, 2) void k_step_batch_lds(BatchArgs a, int64_t 
 
 // Device tables of a batch, built once per handle: instance descriptors and the
 // tile lists (FP32 storage; BF16 and FP8 storage together).
+// A captured run of steps [q0, q1) that starts on flux buffer `cur`: replaying it
+// launches the same kernels with the same arguments as the eager path.
+struct BatchGraph {
+    int64_t q0, q1;
+    int cur;
+    hipGraphExec_t exec;
+};
+constexpr size_t BATCH_MAX_GRAPHS = 8;
+
 struct BatchPlan {
     BatchInst *dinst = nullptr;
     BatchTile *dtiles[3] = {nullptr, nullptr, nullptr};
     int ntiles[3] = {0, 0, 0};
+    std::vector<BatchGraph> graphs;     // most recently used last
+    hipStream_t cap = nullptr;          // capture-only stream (no work runs on it)
 };
 
 void free_batch_plan(void *p) {
     BatchPlan *bp = (BatchPlan *)p;
     if (!bp) return;
+    for (auto &g : bp->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (bp->cap) (void)hipStreamDestroy(bp->cap);
     if (bp->dinst) (void)hipFree(bp->dinst);
     for (int t = 0; t < 3; t++)
         if (bp->dtiles[t]) (void)hipFree(bp->dtiles[t]);
@@ -511,7 +524,65 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
 
 // Advance every dense instance of the handle from q0 to q1, one launch per step
 // and storage type.  Instances advance in lockstep, so one parity serves all.
-hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1) {
+// The launches of steps [q0, q1) from flux buffer `cur`, in order, on stream `st`.
+static void enqueue_steps(hqa_md *md, const BatchPlan *bp, int64_t q0, int64_t q1, int cur,
+                          hipStream_t st) {
+    BatchArgs a;
+    a.inst = bp->dinst; a.R = md->R; a.M = md->sch.M; a.W = md->sch.W; a.T = md->sch.T;
+    a.rg = (float)md->sch.r_g; a.a32 = md->a32; a.b32 = md->b32; a.err = md->err;
+    for (int64_t q = q0; q < q1; q++) {
+        a.cur = cur;
+        for (int t = 0; t < 3; t++) {
+            if (!bp->ntiles[t]) continue;
+            a.tiles = bp->dtiles[t];
+            a.ntiles = bp->ntiles[t];
+            if (t == JT_F32) k_step_batch<JT_F32><<<a.ntiles, 256, 0, st>>>(a, q);
+            else k_step_batch_lds<<<a.ntiles, 512, 0, st>>>(a, q);   // BF16 and FP8
+        }
+        cur ^= 1;
+    }
+}
+
+// The graph of steps [q0, q1) from buffer `cur`: from the cache, else captured on the
+// plan's own stream (a capture records the launches without running them, so the
+// caller's stream may be any stream, the null stream included) and instantiated.
+static hipError_t batch_graph(hqa_md *md, BatchPlan *bp, int64_t q0, int64_t q1, int cur,
+                              hipGraphExec_t *out) {
+    for (size_t k = 0; k < bp->graphs.size(); k++) {
+        const BatchGraph g = bp->graphs[k];
+        if (g.q0 == q0 && g.q1 == q1 && g.cur == cur) {
+            bp->graphs.erase(bp->graphs.begin() + k);
+            bp->graphs.push_back(g);
+            *out = g.exec;
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!bp->cap) e = hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    enqueue_steps(md, bp, q0, q1, cur, bp->cap);
+    hipError_t le = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(bp->cap, &graph);
+    if (e == hipSuccess) e = le;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (bp->graphs.size() >= BATCH_MAX_GRAPHS) {
+        // the least recently used graph; a replay of it already enqueued keeps its own
+        // reference in the runtime until it has run
+        (void)hipGraphExecDestroy(bp->graphs.front().exec);
+        bp->graphs.erase(bp->graphs.begin());
+    }
+    bp->graphs.push_back({q0, q1, cur, exec});
+    *out = exec;
+    return hipSuccess;
+}
+
+hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1, bool graph) {
     if (!md->batch) {
         BatchPlan *bp = nullptr;
         hipError_t e = build_plan(md, bp);
@@ -523,20 +594,16 @@ hipError_t launch_md_steps_batch(hqa_md *md, int64_t q0, int64_t q1) {
     for (auto &I : md->inst)
         if (I.layout == HQA_DENSE) { cur = I.cur; break; }
     if (cur < 0) return hipSuccess;
-    BatchArgs a;
-    a.inst = bp->dinst; a.R = md->R; a.M = md->sch.M; a.W = md->sch.W; a.T = md->sch.T;
-    a.rg = (float)md->sch.r_g; a.a32 = md->a32; a.b32 = md->b32; a.err = md->err;
-    for (int64_t q = q0; q < q1; q++) {
-        a.cur = cur;
-        for (int t = 0; t < 3; t++) {
-            if (!bp->ntiles[t]) continue;
-            a.tiles = bp->dtiles[t];
-            a.ntiles = bp->ntiles[t];
-            if (t == JT_F32) k_step_batch<JT_F32><<<a.ntiles, 256, 0, md->stream>>>(a, q);
-            else k_step_batch_lds<<<a.ntiles, 512, 0, md->stream>>>(a, q);   // BF16 and FP8
-        }
-        cur ^= 1;
+    if (graph && q1 > q0) {
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = batch_graph(md, bp, q0, q1, cur, &exec);
+        if (e != hipSuccess) return e;
+        e = hipGraphLaunch(exec, md->stream);
+        if (e != hipSuccess) return e;
+    } else {
+        enqueue_steps(md, bp, q0, q1, cur, md->stream);
     }
+    if ((q1 - q0) & 1) cur ^= 1;
     for (auto &I : md->inst)
         if (I.layout == HQA_DENSE) I.cur = cur;
     return hipGetLastError();

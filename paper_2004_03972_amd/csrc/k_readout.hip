@@ -698,6 +698,9 @@ hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *
 struct EnArgs {
     int N, V, P, csr, b0;
     int fast;          // plain binary64 sums are exact (see launch_energy)
+    int jt;            // dense: type of Js (JT_F32, JT_BF16, JT_FP8), -1 to read J
+    int ldj;           // dense: row pitch of Js
+    const void *Js;    // dense: the exact storage copy of J (or NULL)
     const double *J;
     const int32_t *rp, *ci;
     const double *h;
@@ -729,18 +732,44 @@ __device__ double block_sum(double x, double *sh) {
     return t;
 }
 
-// Workgroup b takes slice p = b mod P of vector b / P: the vector is staged in LDS;
-// a dense J is read row by row (rows p*4 + w, then every 4P; lanes along the
-// columns), a CSR J a row per thread (rows p*256 + tid, then every 256P).
+// Coupling J_ij of a dense instance: from the storage copy when it holds J exactly
+// (1, 2 or 4 bytes per coupling instead of 8), else from the binary64 input.
+__device__ __forceinline__ double en_coupling(const EnArgs &a, int i, int j) {
+    if (a.jt < 0) return a.J[(int64_t)i * a.N + j];
+    const int64_t t = (int64_t)i * a.ldj + j;
+    if (a.jt == JT_FP8) {
+        // OCP e4m3: sign, 4 exponent bits (bias 7), 3 mantissa bits; exponent 0 is
+        // subnormal (m 2^-9).  The couplings are finite, so 0x7f / 0xff do not occur.
+        const uint32_t b = ((const uint8_t *)a.Js)[t];
+        const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+        const double mag = e ? (double)(8u + m) * (double)__uint_as_float((e + 117u) << 23)
+                             : (double)m * 0x1p-9;
+        return (b & 0x80u) ? -mag : mag;
+    }
+    if (a.jt == JT_BF16) {
+        const uint32_t b = ((const uint16_t *)a.Js)[t];
+        return (double)__uint_as_float(b << 16);
+    }
+    return (double)((const float *)a.Js)[t];
+}
+
+// Dense instances use the upper triangle and one accumulation per cut pair:
+//   C = sum_{i<j, s_i != s_j} J_ij,  H = sum_i h_i s_i,  S = sum_{i<j} J_ij,
+//   E = sum_{i<j} J_ij s_i s_j + H = S - 2 C + H   (s_i s_j = 1 - 2 [s_i != s_j]),
+// all exact; S is the same for every vector and is summed once, by the extra vector
+// slot V.  Workgroup b takes slice p = b mod P of vector b / P (vector slot V: S):
+// rows p*4 + w, then every 4P, lanes along the columns j > i; the vector is staged in
+// LDS.  CSR instances keep both directions of every pair: 2E and 2C over i != j.
 __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
     __shared__ Acc256 sh[4];
     __shared__ double shd[4];
     __shared__ int8_t sv[ENERGY_MAXN_LDS];
     const int v = blockIdx.x / a.P, p = blockIdx.x % a.P, tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    const int8_t *s = a.spins + (int64_t)v * a.N;
+    const bool total = v == a.V;                       // the slot that sums S
+    const int8_t *s = a.spins + (int64_t)(total ? 0 : v) * a.N;
     const bool lds = a.N <= ENERGY_MAXN_LDS;
-    if (lds)
+    if (lds && !total)
         for (int i = tid; i < a.N; i += 256) sv[i] = s[i];
     __syncthreads();
     const int8_t *ss = lds ? sv : s;
@@ -751,16 +780,16 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
         double ae = 0.0, ac = 0.0;
         if (!a.csr) {
             for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
-                const double *Jr = a.J + (int64_t)i * a.N;
-                const int si = ss[i];
+                const int si = total ? 0 : ss[i];
 #pragma unroll 4
-                for (int j = lane; j < a.N; j += 64) {
-                    const double J = Jr[j];
-                    const bool same = si == ss[j];
-                    ae += same ? J : -J;
-                    ac += same ? 0.0 : J;
+                for (int j = i + 1 + lane; j < a.N; j += 64) {
+                    const double J = en_coupling(a, i, j);
+                    ac += (total || si != ss[j]) ? J : 0.0;
                 }
             }
+            if (!total)
+                for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
+                    ae += ss[i] > 0 ? a.h[i] : -a.h[i];
         } else {
             for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
                 const int si = ss[i];
@@ -771,9 +800,9 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
                     ac += same ? 0.0 : J;
                 }
             }
+            for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
+                ae += ss[i] > 0 ? 2.0 * a.h[i] : -2.0 * a.h[i];
         }
-        for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
-            ae += ss[i] > 0 ? 2.0 * a.h[i] : -2.0 * a.h[i];
         ae = block_sum(ae, shd);
         ac = block_sum(ac, shd);
         if (tid == 0) {
@@ -789,15 +818,15 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
     if (!a.csr) {
         for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
             const double *Jr = a.J + (int64_t)i * a.N;
-            const int si = ss[i];
-            for (int j = lane; j < a.N; j += 64) {
+            const int si = total ? 0 : ss[i];
+            for (int j = i + 1 + lane; j < a.N; j += 64) {
                 const double J = Jr[j];
-                if (J == 0.0) continue;
-                const int sj = ss[j];
-                acc_add(ae, si == sj ? J : -J, b0);
-                if (si != sj) acc_add(ac, J, b0);
+                if (J != 0.0 && (total || si != ss[j])) acc_add(ac, J, b0);
             }
         }
+        if (!total)
+            for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
+                acc_add(ae, ss[i] > 0 ? a.h[i] : -a.h[i], b0);
     } else {
         for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
             int si = ss[i];
@@ -808,10 +837,10 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
                 if (si != sj) acc_add(ac, J, b0);
             }
         }
-    }
-    for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
-        double hh = a.h[i];
-        if (hh != 0.0) acc_add(ae, ss[i] > 0 ? 2.0 * hh : -2.0 * hh, b0);
+        for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
+            double hh = a.h[i];
+            if (hh != 0.0) acc_add(ae, ss[i] > 0 ? 2.0 * hh : -2.0 * hh, b0);
+        }
     }
     block_acc_reduce(ae, sh);
     block_acc_reduce(ac, sh);
@@ -822,11 +851,20 @@ __global__ __launch_bounds__(256) void k_energy(EnArgs a) {
     }
 }
 
-// Totals of the P slices of each vector (a thread per vector), rounded once.
+// Totals of the P slices of each vector (a thread per vector), rounded once.  Dense:
+// slot 0 of a slice holds its part of H, slot 1 its part of C (of S for the extra vector
+// V), and E = S - 2 C + H.  CSR: slot 0 holds 2E, slot 1 2C.
+__device__ __forceinline__ void acc_merge_neg2(Acc256 &a, const Acc256 &c) {
+    add256(a.p, c.n);
+    add256(a.p, c.n);
+    add256(a.n, c.p);
+    add256(a.n, c.p);
+}
+
 __global__ __launch_bounds__(64) void k_energy_merge(EnArgs a) {
     const int v = blockIdx.x * 64 + threadIdx.x;
     if (v >= a.V) return;
-    const int64_t s0 = (int64_t)v * a.P;
+    const int64_t s0 = (int64_t)v * a.P, sS = (int64_t)a.V * a.P;
     if (a.fast) {
         const double *o = (const double *)a.part;
         double ae = 0.0, ac = 0.0;
@@ -834,8 +872,15 @@ __global__ __launch_bounds__(64) void k_energy_merge(EnArgs a) {
             ae += o[2 * (s0 + p)];
             ac += o[2 * (s0 + p) + 1];
         }
-        if (a.E) a.E[v] = 0.5 * ae;
-        if (a.cut) a.cut[v] = 0.5 * ac;
+        if (a.csr) {
+            if (a.E) a.E[v] = 0.5 * ae;
+            if (a.cut) a.cut[v] = 0.5 * ac;
+            return;
+        }
+        double S = 0.0;
+        for (int p = 0; p < a.P; p++) S += o[2 * (sS + p) + 1];
+        if (a.E) a.E[v] = (S - 2.0 * ac) + ae;
+        if (a.cut) a.cut[v] = ac;
         return;
     }
     const Acc256 *o = (const Acc256 *)a.part;
@@ -844,8 +889,15 @@ __global__ __launch_bounds__(64) void k_energy_merge(EnArgs a) {
         acc_merge(ae, o[2 * (s0 + p)]);
         acc_merge(ac, o[2 * (s0 + p) + 1]);
     }
-    if (a.E) a.E[v] = acc_round(ae, a.b0 - 1);
-    if (a.cut) a.cut[v] = acc_round(ac, a.b0 - 1);
+    if (a.csr) {
+        if (a.E) a.E[v] = acc_round(ae, a.b0 - 1);
+        if (a.cut) a.cut[v] = acc_round(ac, a.b0 - 1);
+        return;
+    }
+    for (int p = 0; p < a.P; p++) acc_merge(ae, o[2 * (sS + p) + 1]);   // + S
+    acc_merge_neg2(ae, ac);                                             // - 2 C
+    if (a.E) a.E[v] = acc_round(ae, a.b0);
+    if (a.cut) a.cut[v] = acc_round(ac, a.b0);
 }
 
 int energy_slices(int N, int V) {
@@ -856,7 +908,7 @@ int energy_slices(int N, int V) {
 }
 
 size_t energy_part_bytes(int N, int V) {
-    return (size_t)std::max(V, 1) * energy_slices(N, V) * 2 * sizeof(Acc256);
+    return (size_t)(std::max(V, 1) + 1) * energy_slices(N, V) * 2 * sizeof(Acc256);
 }
 
 hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
@@ -874,8 +926,14 @@ hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *
     }
     a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64; a.spins = spins; a.part = part;
     a.E = E; a.cut = cut;
+    // the compact storage copy, when it holds every coupling exactly (fast path only:
+    // the accumulator path takes binary64 terms from J)
+    a.jt = -1; a.ldj = 0; a.Js = nullptr;
+    if (!a.csr && a.fast && I.js_exact && I.Js) {
+        a.jt = (int)I.jt; a.ldj = I.Np; a.Js = I.Js;
+    }
     if (V == 0) return hipSuccess;
-    k_energy<<<V * a.P, 256, 0, st>>>(a);
+    k_energy<<<(V + (a.csr ? 0 : 1)) * a.P, 256, 0, st>>>(a);
     k_energy_merge<<<(V + 63) / 64, 64, 0, st>>>(a);
     return hipGetLastError();
 }

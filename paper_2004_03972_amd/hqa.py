@@ -34,8 +34,9 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_classify_noalloc")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
 HQA_NOALLOC_SCRATCH_BYTES = 16 << 20
-ABI_VERSION = 6
+ABI_VERSION = 7
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
+HQA_MD_GRAPH = 1
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
          "resident": HQA_PLAN_RESIDENT, "batch": HQA_PLAN_BATCH}
 PLAN_NAMES = {0: None, 1: "step", 2: "cluster", 3: "resident", 4: "batch"}
@@ -64,7 +65,7 @@ class hqa_md_opts(C.Structure):
     _fields_ = [("replicas", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
                 ("p0", C.c_void_p), ("phi0", C.c_void_p), ("init_mem", C.c_int32),
                 ("require_exact", C.c_int32), ("plan", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 class hqa_classify_out(C.Structure):
@@ -434,7 +435,8 @@ class MD:
     """A handle over hqa_md_* calls with numpy in/out (host memory)."""
 
     def __init__(self, problems, sched: hqa_schedule, replicas: int, precision="f32", seed=0,
-                 p0=None, phi0=None, require_exact=False, plan="auto", stream: int = 0):
+                 p0=None, phi0=None, require_exact=False, plan="auto", stream: int = 0,
+                 graph: bool = False):
         self.problems = problems if isinstance(problems, (list, tuple)) else [problems]
         o = hqa_md_opts_default()
         o.replicas = replicas
@@ -442,6 +444,7 @@ class MD:
         o.seed = seed
         o.require_exact = int(require_exact)
         o.plan = PLANS[plan] if isinstance(plan, str) else int(plan)
+        o.flags = HQA_MD_GRAPH if graph else 0
         self._p0 = None if p0 is None else np.ascontiguousarray(p0, dtype=np.float64)
         self._phi0 = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.float64)
         o.p0 = None if self._p0 is None else self._p0.ctypes.data

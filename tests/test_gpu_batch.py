@@ -175,3 +175,42 @@ def test_single_instance_batch_plan_equals_step(H, kind, N, R):
         md.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+def test_graph_replay_equals_eager(H):
+    """HQA_MD_GRAPH: the batch plan's steps replayed from captured HIP graphs give the
+    eager launches' trajectories bit for bit, over several replays of each graph with
+    eager work and synchronisations between them, split runs (two graphs per run) and
+    an odd step count (so the flux-buffer parity, part of a graph's key, alternates
+    between rounds); a single instance on the BATCH plan replays as well."""
+    probs, Js = _mixed_batch(H, [100, 333], [700], 60)
+    T, R = 161, 64
+    ws = (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM)
+    eager = H.MD(probs, H.make_schedule(T, 30), R, "bf16", seed=3)
+    graph = H.MD(probs, H.make_schedule(T, 30), R, "bf16", seed=3, graph=True)
+    for rnd in range(4):
+        print("graph replay round", rnd, flush=True)
+        for md in (eager, graph):
+            md.reset(10 + rnd)
+            md.run(T // 2)
+            md.run()
+            md.sync()
+            assert md.last_plan == "batch"
+        for k in range(len(probs)):
+            for w in ws:
+                assert np.array_equal(eager.state(w, k), graph.state(w, k)), (rnd, k, w)
+    eager.close()
+    graph.close()
+    # a lone dense instance on the BATCH plan
+    out = []
+    for g in (False, True):
+        md = H.MD(probs[2], H.make_schedule(T, 30), R, "fp8", seed=7, plan="batch", graph=g)
+        for rnd in range(3):
+            md.reset(7 + rnd)
+            md.run()
+            md.sync()
+        assert md.last_plan == "batch"
+        out.append([md.state(w) for w in ws])
+        md.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)

@@ -259,7 +259,7 @@ def bench_ea3d(args, hqa, torch):
                            "frac": flop / (ms / 1e3) / 78.6e12,
                            "frac_of_vendor_157": flop / (ms / 1e3) / 157.3e12,
                            "traffic": measured_traffic("k_csr_resident_ea3d_pmc.txt",
-                                                       "csr_resident"),
+                                                       "csr_resident", "k_csr_resident<4, 6>"),
                            "kernel": "k_csr_resident<4, 6>", "flop_per_update": flop / upd,
                            "hbm_equivalent_GBps": bytes_alg / (ms / 1e3) / 1e9}
     else:
@@ -288,12 +288,11 @@ def batch_bytes_per_step(specs, R, W, T):
 
 
 def classify_batch(md, K, n_amb):
-    """Exact HQA read-out of every instance: best cut and best energy over the replicas."""
-    cut, en = np.empty(K), np.empty(K)
-    for k in range(K):
-        g = md.classify(n_amb, solve=True, k=k)
-        cut[k], en[k] = g["cut"].max(), g["energy"].min()
-    return cut, en
+    """Exact HQA read-out of every instance (one hqa_classify_many call): best cut and best
+    energy over the replicas."""
+    en, cut = md.classify_many(n_amb, solve=True)
+    assert en.shape[0] == K
+    return cut.max(axis=1), en.min(axis=1)
 
 
 def cpu_baseline_batch(specs, Js, chosen, fp32, torch, rs=4, ts=500, checkpoints=(1, 10, 100, 500)):

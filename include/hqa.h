@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 7
+#define HQA_ABI_VERSION 8
 
 typedef enum {
     HQA_OK = 0,
@@ -314,6 +314,22 @@ typedef struct hqa_classify_out {
  * Synchronises. */
 hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                         const hqa_classify_out *out, int32_t out_mem);
+
+/* The read-out of hqa_classify for several instances of a handle in one call (Results,
+ * "Sorting ..."; HQA section): instance instances[c], c < count, gets the operations of
+ * hqa_classify with the same n_amb and solve, and its R exact energies and cuts go to
+ * energy[c R .. c R + R) and cut[c R .. c R + R) (either may be NULL, not both; host or
+ * device memory per out_mem).  Spins and the other outputs are not returned (hqa_classify
+ * gives them per instance).  Results equal those of hqa_classify bit for bit.  The
+ * instances go round-robin to up to four streams of the call's own (ordered after the
+ * handle's stream, which waits for them at the end), each with one scratch region sized
+ * for the largest listed instance, so the small kernels of several instances overlap;
+ * the call synchronises once, at its end, instead of per instance.  Errors as
+ * hqa_classify, checked for every listed instance before any device work; HQA_EINVAL for
+ * count < 1, a NULL list or both outputs NULL. */
+hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count,
+                             int32_t n_amb, int32_t solve, double *energy, double *cut,
+                             int32_t out_mem);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): hqa_classify with the same

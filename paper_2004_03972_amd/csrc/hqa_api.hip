@@ -1002,10 +1002,11 @@ hqa_status hqa_md_hamiltonian(hqa_md *md, int32_t instance, double *H, int32_t d
 // labels) and hqa_classify_tabu: selection, optional reduced problem solved exactly
 // (solve = 1) or by the tabu search (solve = 2), merge, energies.
 static hqa_status classify_checks(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
-                                  const hqa_classify_out *out, const float *prob) {
+                                  const hqa_classify_out *out, const float *prob,
+                                  bool need_spins = true) {
     hqa_status s = check_instance(md, instance);
     if (s != HQA_OK) return s;
-    if (!out || !out->spins) return fail(HQA_EINVAL, "out->spins is required");
+    if (!out || (need_spins && !out->spins)) return fail(HQA_EINVAL, "out->spins is required");
     Instance &I = md->inst[instance];
     const int N = I.N;
     if (n_amb < 0 || n_amb > N) return fail(HQA_EINVAL, "n_amb must lie in [0, N]");
@@ -1034,12 +1035,17 @@ extern "C++" {
 template <class Bufs>
 static hqa_status classify_core(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                                 const hqa_classify_out *out, int32_t out_mem, const float *prob,
-                                int32_t prob_mem, int64_t tabu_iters, int32_t tenure, Bufs &B) {
+                                int32_t prob_mem, int64_t tabu_iters, int32_t tenure, Bufs &B,
+                                bool sync = true, hipStream_t side = nullptr) {
     Instance &I = md->inst[instance];
     const int R = md->R, N = I.N;
-    hqa_status s = hqa_md_sync(md);
-    if (s != HQA_OK) return s;
-    hipStream_t st = md->stream;
+    if (sync) {
+        hqa_status s = hqa_md_sync(md);
+        if (s != HQA_OK) return s;
+    }
+    // the handle's stream, or (side != NULL, no sync) a stream of the caller's that has
+    // been ordered after it
+    hipStream_t st = side ? side : md->stream;
     int32_t *amb;
     int8_t *spins;
     HIPCHK(B.get(&amb, (size_t)R * (n_amb ? n_amb : 1)));
@@ -1097,14 +1103,14 @@ static hqa_status classify_core(hqa_md *md, int32_t instance, int32_t n_amb, int
         HIPCHK(launch_energy(I, R, spins, E, C, part, st));
     }
     hipMemcpyKind kd = kind_out(out_mem);
-    HIPCHK(hipMemcpyAsync(out->spins, spins, (size_t)R * N, kd, st));
+    if (out->spins) HIPCHK(hipMemcpyAsync(out->spins, spins, (size_t)R * N, kd, st));
     if (out->amb_idx && n_amb) HIPCHK(hipMemcpyAsync(out->amb_idx, amb, (size_t)R * n_amb * 4, kd, st));
     if (out->energy) HIPCHK(hipMemcpyAsync(out->energy, E, (size_t)R * 8, kd, st));
     if (out->cut) HIPCHK(hipMemcpyAsync(out->cut, C, (size_t)R * 8, kd, st));
     if (out->h_eff && h_eff) HIPCHK(hipMemcpyAsync(out->h_eff, h_eff, (size_t)R * n_amb * 8, kd, st));
     if (out->code && code) HIPCHK(hipMemcpyAsync(out->code, code, (size_t)R * 8, kd, st));
     if (out->e_reduced && e_red) HIPCHK(hipMemcpyAsync(out->e_reduced, e_red, (size_t)R * 8, kd, st));
-    HIPCHK(hipStreamSynchronize(st));
+    if (sync) HIPCHK(hipStreamSynchronize(st));
     return HQA_OK;
 }
 }  // extern "C++"
@@ -1203,6 +1209,86 @@ hqa_status hqa_classify_noalloc(hqa_md *md, int32_t instance, int32_t n_amb, int
     A.base = (uint8_t *)base;
     A.cap = HQA_NOALLOC_SCRATCH_BYTES;
     return classify_core(md, instance, n_amb, solve, out, out_mem, nullptr, HQA_HOST, 0, 0, A);
+}
+
+hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count,
+                             int32_t n_amb, int32_t solve, double *energy, double *cut,
+                             int32_t out_mem) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    if (!instances || count < 1) return fail(HQA_EINVAL, "need a list of at least one instance");
+    if (!energy && !cut) return fail(HQA_EINVAL, "energy and cut are both NULL");
+    if (solve != 0 && solve != 1) return fail(HQA_EINVAL, "solve must be 0 or 1");
+    if (out_mem != HQA_HOST && out_mem != HQA_DEVICE) return fail(HQA_EINVAL, "bad out_mem");
+    const int R = md->R;
+    hqa_classify_out o{};
+    o.energy = energy;          // only their presence matters to the checks and the sizing
+    o.cut = cut;
+    size_t need = 0;
+    for (int32_t c = 0; c < count; c++) {
+        hqa_status s = classify_checks(md, instances[c], n_amb, solve, &o, nullptr, false);
+        if (s != HQA_OK) return s;
+        need = std::max(need, classify_scratch_bytes(R, md->inst[instances[c]].N, n_amb, solve,
+                                                     &o));
+    }
+    hqa_status s = hqa_md_sync(md);
+    if (s != HQA_OK) return s;
+    // The instances are independent: they go round-robin to NS side streams, each with
+    // its own scratch region, so that the small kernels of several instances overlap.
+    // The side streams start after the handle's stream (an event) and the handle's stream
+    // waits for all of them before the results are copied.
+    const int NS = (int)std::min<int32_t>(count, 4);
+    const size_t res = out_mem == HQA_HOST ? ScratchArena::round((size_t)count * R * 8) : 0;
+    uint8_t *base = nullptr;
+    HIPCHK(hipMalloc((void **)&base, NS * need + 2 * res));
+    double *dE = energy, *dC = cut;
+    if (out_mem == HQA_HOST) {
+        dE = energy ? (double *)(base + NS * need) : nullptr;
+        dC = cut ? (double *)(base + NS * need + res) : nullptr;
+    }
+    hipStream_t side[4] = {};
+    hipEvent_t ev[5] = {};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k <= NS && e == hipSuccess; k++)
+        e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+    for (int k = 0; k < NS && e == hipSuccess; k++)
+        e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventRecord(ev[NS], md->stream);
+    for (int k = 0; k < NS && e == hipSuccess; k++) e = hipStreamWaitEvent(side[k], ev[NS], 0);
+    hipStream_t own = md->stream;
+    for (int32_t c = 0; c < count && s == HQA_OK && e == hipSuccess; c++) {
+        const int k = c % NS;
+        ScratchArena A;
+        A.base = base + (size_t)k * need;
+        A.cap = need;
+        hqa_classify_out oc{};
+        oc.energy = dE ? dE + (size_t)c * R : nullptr;
+        oc.cut = dC ? dC + (size_t)c * R : nullptr;
+        s = classify_core(md, instances[c], n_amb, solve, &oc, HQA_DEVICE, nullptr, HQA_HOST, 0,
+                          0, A, false, side[k]);
+    }
+    for (int k = 0; k < NS && e == hipSuccess; k++) {
+        e = hipEventRecord(ev[k], side[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(own, ev[k], 0);
+    }
+    if (s == HQA_OK && e == hipSuccess && out_mem == HQA_HOST) {
+        if (energy) e = hipMemcpyAsync(energy, dE, (size_t)count * R * 8, hipMemcpyDeviceToHost,
+                                       own);
+        if (e == hipSuccess && cut)
+            e = hipMemcpyAsync(cut, dC, (size_t)count * R * 8, hipMemcpyDeviceToHost, own);
+    }
+    // whatever happened above, every stream is drained before its memory is released
+    for (int k = 0; k < NS; k++)
+        if (side[k]) (void)hipStreamSynchronize(side[k]);
+    hipError_t e2 = hipStreamSynchronize(own);
+    for (int k = 0; k < NS; k++)
+        if (side[k]) (void)hipStreamDestroy(side[k]);
+    for (int k = 0; k <= NS; k++)
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+    (void)hipFree(base);
+    if (s != HQA_OK) return s;
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return fail(HQA_EDEVICE, "read-out: %s", hipGetErrorString(e));
+    return HQA_OK;
 }
 
 hqa_status hqa_classify_tabu(hqa_md *md, int32_t instance, int32_t n_amb, int64_t iters,

@@ -195,14 +195,17 @@ __global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
 // flux operand block (64 replicas x 128 columns, BF16) is staged once into LDS by
 // the whole workgroup with full-line loads and shared by the eight row tiles, so it
 // is read from L2 once per 128 rows instead of once per 32; the J fragments come
-// from the MFMA-tiled copy, one group ahead in registers; the LDS block is double-
+// from the MFMA-tiled copy, two groups ahead in registers; the LDS block is double-
 // buffered with one barrier per group.  Chains, operands and epilogue are those of
 // the other dense kernels (bit-identical results).  Wavefronts whose rows are all
 // padding compute on a real row tile, store nothing, and take part in the staging and
-// the barriers.  The J fragments of group g + 1 are loaded into the other of two
-// register sets while group g computes (the loop is unrolled by two, so no set is
-// copied into the other), and the flux block of group g + 1 is loaded into registers
-// at the start of group g and stored into the other LDS buffer at its end.
+// the barriers.  Registers hold three groups in turn (the loop is unrolled by three,
+// so no set is copied into another): the J fragments of group g + 2 and the flux
+// block of group g + 3 are requested at the start of group g, and the flux block of
+// group g + 1 is stored into the other LDS buffer at its end.  The deeper prefetch
+// costs registers (188 VGPRs) but not occupancy: at 146 VGPRs a compute unit already
+// held only one 512-thread workgroup, and the two-deep version took 2.3% longer per
+// step on the 512-instance batch.
 //
 // Every global access goes through global-address-space pointers.  The buffers come
 // from a table in memory, so plain pointers would be generic (flat) ones, and a flat
@@ -269,16 +272,19 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[rt][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    // Two register sets used in turn (the loop is unrolled by two, so no set is copied
-    // into the other): the loads of group g + 1 are issued before the MFMAs of group g
-    // and are first waited for when group g + 1 begins.
-    u32x4_b A0[NA], A1[NA];
-    u32x4_b S0a, S0b, S1a, S1b;
-#define HQA_LOAD_GROUP(g, A, Sa, Sb)                                                  \
+    // Three register sets used in turn (the loop is unrolled by three): the couplings
+    // of group g + 2 and the fluxes of group g + 3 are requested when group g begins, so
+    // a group's couplings have two groups of time to arrive and its fluxes three.
+    u32x4_b A0[NA], A1[NA], A2[NA];
+    u32x4_b S0a, S0b, S1a, S1b, S2a, S2b;
+#define HQA_LOAD_J(g, A)                                                              \
+    do {                                                                              \
+        _Pragma("unroll") for (int j = 0; j < NA; j++) A[j] = Jt[(int64_t)(g) * 64 * NA + j]; \
+    } while (0)
+#define HQA_LOAD_S(g, Sa, Sb)                                                         \
     do {                                                                              \
         Sa = Bsrc[16 * (g)];                                                          \
         Sb = Bsrc[16 * (g) + 1];                                                      \
-        _Pragma("unroll") for (int j = 0; j < NA; j++) A[j] = Jt[(int64_t)(g) * 64 * NA + j]; \
     } while (0)
 #define HQA_MFMA_GROUP(buf, A)                                                        \
     do {                                                                              \
@@ -291,32 +297,37 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
                 acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[rt], acc[rt][j], 0, 0, 0); \
         }                                                                             \
     } while (0)
-    // Every load is unconditional, so the compiler can count the loads in flight
-    // exactly and wait only for the group about to be used: a wavefront whose rows are
-    // all padding reads a real row tile (above), and past the last group the last
-    // group is loaded again and not used.
-    HQA_LOAD_GROUP(0, A0, S0a, S0b);
+    const int gl = ngroups - 1;
+    HQA_LOAD_J(0, A0);
+    HQA_LOAD_S(0, S0a, S0b);
+    HQA_LOAD_J(min(1, gl), A1);
+    HQA_LOAD_S(min(1, gl), S1a, S1b);
+    HQA_LOAD_S(min(2, gl), S2a, S2b);
     Bdst0[0] = S0a;
     Bdst0[1] = S0b;
     __syncthreads();
-    for (int gi = 0; gi < ngroups; gi += 2) {
-        // even group gi (A0, LDS buffer 0); prefetch gi + 1 into A1 / S1
-        HQA_LOAD_GROUP(min(gi + 1, ngroups - 1), A1, S1a, S1b);
-        __builtin_amdgcn_sched_barrier(0);
-        HQA_MFMA_GROUP(0, A0);
-        Bdst1[0] = S1a;
-        Bdst1[1] = S1b;
-        __syncthreads();
+    // group g: couplings in set g % 3, fluxes in LDS buffer g % 2
+#define HQA_BODY(g, Ag, An2, Sn3a, Sn3b, Sn1a, Sn1b)                                  \
+    do {                                                                              \
+        HQA_LOAD_J(min((g) + 2, gl), An2);                                            \
+        HQA_LOAD_S(min((g) + 3, gl), Sn3a, Sn3b);                                     \
+        __builtin_amdgcn_sched_barrier(0);                                            \
+        HQA_MFMA_GROUP((g) & 1, Ag);                                                  \
+        u32x4_b *dst = ((g) & 1) ? Bdst0 : Bdst1;                                     \
+        dst[0] = Sn1a;                                                                \
+        dst[1] = Sn1b;                                                                \
+        __syncthreads();                                                              \
+    } while (0)
+    for (int gi = 0; gi < ngroups; gi += 3) {
+        HQA_BODY(gi, A0, A2, S0a, S0b, S1a, S1b);
         if (gi + 1 >= ngroups) break;
-        // odd group gi + 1 (A1, LDS buffer 1); prefetch gi + 2 into A0 / S0
-        HQA_LOAD_GROUP(min(gi + 2, ngroups - 1), A0, S0a, S0b);
-        __builtin_amdgcn_sched_barrier(0);
-        HQA_MFMA_GROUP(1, A1);
-        Bdst0[0] = S0a;
-        Bdst0[1] = S0b;
-        __syncthreads();
+        HQA_BODY(gi + 1, A1, A0, S1a, S1b, S2a, S2b);
+        if (gi + 2 >= ngroups) break;
+        HQA_BODY(gi + 2, A2, A1, S2a, S2b, S0a, S0b);
     }
-#undef HQA_LOAD_GROUP
+#undef HQA_BODY
+#undef HQA_LOAD_J
+#undef HQA_LOAD_S
 #undef HQA_MFMA_GROUP
 
     // Epilogue with full-line accesses: the fields pass through LDS (the flux stages

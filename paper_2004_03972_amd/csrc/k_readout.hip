@@ -688,19 +688,37 @@ hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *
 }
 
 // ---------------------------------------------------------------------------
-// Exact Ising energy (Eq. 1) and cut (Methods, MAX-CUT with w = J).  The sum over
-// ordered pairs i != j counts each pair twice, so 2E = sum_{i!=j} J s s + 2 sum h s
-// and 2C = sum_{i!=j, s_i != s_j} J are accumulated exactly and rounded with the
-// scale halved.  Each spin vector is split into P row slices, one workgroup per
-// (vector, slice), so that a few vectors still fill the device; the slices' partial
-// sums are exact, and so is their total, whatever the split.
+// Exact Ising energy (Eq. 1) and cut (Methods, MAX-CUT with w = J).
+//
+// Dense instances (k_energy_mv): over the upper triangle, with s_i s_j = 1 - 2 [s_i != s_j]
+// and s_i = 1 - 2 [s_i = -1],
+//   C = sum_{i<j, s_i != s_j} J_ij,   S = sum_{i<j} J_ij,
+//   H = sum_i h_i s_i = Ht - 2 Hn,    Ht = sum_i h_i,   Hn = sum_{i: s_i = -1} h_i,
+//   E = sum_{i<j} J_ij s_i s_j + H = S - 2 C + Ht - 2 Hn.
+// The spins of 64 vectors are packed into one 64-bit word per spin (bit v: vector v has
+// s = -1), so one pass over the upper triangle serves every vector of a group: for the
+// pair (i, j) the word m_i ^ m_j marks the vectors the pair cuts.
+//
+// Exactness by level sums: every J and h is a multiple of 2^b0 below 2^(msb + 1).  With
+// lg = ceil(log2(N^2 + N)) and w = 51 - lg, the levels sigma_k = b0 + k w (k < L) cover
+// the bits [b0, msb] when L w >= msb + 1 - b0.  A term is cut into parts t_k, multiples of
+// 2^sigma_k below 2^(sigma_(k+1)) (top level: 2^(sigma_L + 1)), by rounding to a multiple
+// of 2^sigma_k from the top level down ((r + K_k) - K_k with K_k = 1.5 2^(sigma_k + 52),
+// exact for |r| <= 2^(sigma_k + 51)) and keeping the exact remainder; the lowest part is
+// the last remainder.  Any sum of at most 2^lg parts of one level is then a multiple of
+// 2^sigma_k below 2^(sigma_k + 53): binary64 adds them exactly, in any order and any
+// grouping (lanes, wavefronts, workgroups, slices).  The merge adds the level totals
+// into the fixed-point accumulator and rounds once.  L = 1 is a plain binary64 sum.
+//
+// CSR instances, and dense ones whose bits need more than four levels (k_energy), keep
+// one workgroup per (vector, slice): the sum over ordered pairs i != j counts each pair
+// twice, so 2E = sum_{i!=j} J s s + 2 sum h s and 2C = sum_{i!=j, s_i != s_j} J are
+// accumulated exactly (binary64 when the fast condition holds, else the fixed-point
+// accumulator per term) and rounded with the scale halved.
 // ---------------------------------------------------------------------------
 struct EnArgs {
     int N, V, P, csr, b0;
     int fast;          // plain binary64 sums are exact (see launch_energy)
-    int jt;            // dense: type of Js (JT_F32, JT_BF16, JT_FP8), -1 to read J
-    int ldj;           // dense: row pitch of Js
-    const void *Js;    // dense: the exact storage copy of J (or NULL)
     const double *J;
     const int32_t *rp, *ci;
     const double *h;
@@ -732,9 +750,164 @@ __device__ double block_sum(double x, double *sh) {
     return t;
 }
 
-// Coupling J_ij of a dense instance: from the storage copy when it holds J exactly
-// (1, 2 or 4 bytes per coupling instead of 8), else from the binary64 input.
-__device__ __forceinline__ double en_coupling(const EnArgs &a, int i, int j) {
+__global__ __launch_bounds__(256) void k_energy(EnArgs a) {
+    __shared__ Acc256 sh[4];
+    __shared__ double shd[4];
+    __shared__ int8_t sv[ENERGY_MAXN_LDS];
+    const int v = blockIdx.x / a.P, p = blockIdx.x % a.P, tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int8_t *s = a.spins + (int64_t)v * a.N;
+    const bool lds = a.N <= ENERGY_MAXN_LDS;
+    if (lds)
+        for (int i = tid; i < a.N; i += 256) sv[i] = s[i];
+    __syncthreads();
+    const int8_t *ss = lds ? sv : s;
+    const int b0 = a.b0;
+    const int64_t slot = (int64_t)v * a.P + p;
+    if (a.fast) {
+        // every partial sum is a multiple of 2^b0 below 2^(53 + b0): binary64 is exact
+        double ae = 0.0, ac = 0.0;
+        if (!a.csr) {
+            for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
+                const double *Jr = a.J + (int64_t)i * a.N;
+                const int si = ss[i];
+                for (int j = lane; j < a.N; j += 64) {
+                    const double J = Jr[j];
+                    const bool same = si == ss[j];
+                    ae += same ? J : -J;
+                    ac += same ? 0.0 : J;
+                }
+            }
+        } else {
+            for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
+                const int si = ss[i];
+                for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
+                    const double J = a.J[e];
+                    const bool same = si == ss[a.ci[e]];
+                    ae += same ? J : -J;
+                    ac += same ? 0.0 : J;
+                }
+            }
+        }
+        for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
+            ae += ss[i] > 0 ? 2.0 * a.h[i] : -2.0 * a.h[i];
+        ae = block_sum(ae, shd);
+        ac = block_sum(ac, shd);
+        if (tid == 0) {
+            double *o = (double *)a.part + 2 * slot;
+            o[0] = ae;
+            o[1] = ac;
+        }
+        return;
+    }
+    Acc256 ae, ac;
+    acc_zero(ae);
+    acc_zero(ac);
+    if (!a.csr) {
+        for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
+            const double *Jr = a.J + (int64_t)i * a.N;
+            const int si = ss[i];
+            for (int j = lane; j < a.N; j += 64) {
+                const double J = Jr[j];
+                if (J == 0.0) continue;
+                const int sj = ss[j];
+                acc_add(ae, si == sj ? J : -J, b0);
+                if (si != sj) acc_add(ac, J, b0);
+            }
+        }
+    } else {
+        for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
+            int si = ss[i];
+            for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
+                double J = a.J[e];
+                int sj = ss[a.ci[e]];
+                acc_add(ae, si == sj ? J : -J, b0);
+                if (si != sj) acc_add(ac, J, b0);
+            }
+        }
+    }
+    for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
+        double hh = a.h[i];
+        if (hh != 0.0) acc_add(ae, ss[i] > 0 ? 2.0 * hh : -2.0 * hh, b0);
+    }
+    block_acc_reduce(ae, sh);
+    block_acc_reduce(ac, sh);
+    if (tid == 0) {
+        Acc256 *o = (Acc256 *)a.part + 2 * slot;
+        o[0] = ae;
+        o[1] = ac;
+    }
+}
+
+// Totals of the P slices of each vector (a thread per vector), rounded once.
+__global__ __launch_bounds__(64) void k_energy_merge(EnArgs a) {
+    const int v = blockIdx.x * 64 + threadIdx.x;
+    if (v >= a.V) return;
+    const int64_t s0 = (int64_t)v * a.P;
+    if (a.fast) {
+        const double *o = (const double *)a.part;
+        double ae = 0.0, ac = 0.0;
+        for (int p = 0; p < a.P; p++) {
+            ae += o[2 * (s0 + p)];
+            ac += o[2 * (s0 + p) + 1];
+        }
+        if (a.E) a.E[v] = 0.5 * ae;
+        if (a.cut) a.cut[v] = 0.5 * ac;
+        return;
+    }
+    const Acc256 *o = (const Acc256 *)a.part;
+    Acc256 ae = o[2 * s0], ac = o[2 * s0 + 1];
+    for (int p = 1; p < a.P; p++) {
+        acc_merge(ae, o[2 * (s0 + p)]);
+        acc_merge(ac, o[2 * (s0 + p) + 1]);
+    }
+    if (a.E) a.E[v] = acc_round(ae, a.b0 - 1);
+    if (a.cut) a.cut[v] = acc_round(ac, a.b0 - 1);
+}
+
+// ----- dense: many vectors per pass, level sums -----
+struct EnMvArgs {
+    int N, V, P, b0;
+    int jt;            // type of Js (JT_F32, JT_BF16, JT_FP8), -1 to read J
+    int ldj;           // row pitch of Js
+    const void *Js;    // the exact storage copy of J (or NULL)
+    const double *J;
+    const double *h;   // NULL: no field
+    const int8_t *spins;
+    uint64_t *masks;   // [ceil(V / 64)][N]
+    double *part;      // see energy_mv_layout
+    double K[4];       // rounding constants of levels 1 .. L - 1
+    double *E, *cut;
+};
+
+// Offsets (in doubles) of the partial sums of a launch with P slices, V vectors, L
+// levels: C and Hn per (slice, vector, level), then S and Ht per (slice, level).
+struct EnMvLayout {
+    int64_t c, hn, s, ht, total;
+};
+static __host__ __device__ EnMvLayout energy_mv_layout(int P, int V, int L) {
+    EnMvLayout o;
+    o.c = 0;
+    o.hn = (int64_t)P * V * L;
+    o.s = 2 * o.hn;
+    o.ht = o.s + (int64_t)P * L;
+    o.total = o.ht + (int64_t)P * L;
+    return o;
+}
+
+// Packed spins: word b of spin j has bit v set when vector 64 b + v has s_j = -1.
+__global__ void k_pack_masks(int N, int V, const int8_t *spins, uint64_t *masks) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = (V + 63) / 64;
+    if (t >= (int64_t)nw * N) return;
+    const int b = (int)(t / N), j = (int)(t % N);
+    uint64_t m = 0;
+    for (int v = 0; v < 64 && 64 * b + v < V; v++)
+        m |= (uint64_t)(spins[(int64_t)(64 * b + v) * N + j] < 0) << v;
+    masks[t] = m;
+}
+
+__device__ __forceinline__ double mv_coupling(const EnMvArgs &a, int i, int j) {
     if (a.jt < 0) return a.J[(int64_t)i * a.N + j];
     const int64_t t = (int64_t)i * a.ldj + j;
     if (a.jt == JT_FP8) {
@@ -753,149 +926,140 @@ __device__ __forceinline__ double en_coupling(const EnArgs &a, int i, int j) {
     return (double)((const float *)a.Js)[t];
 }
 
-// Dense instances use the upper triangle and one accumulation per cut pair:
-//   C = sum_{i<j, s_i != s_j} J_ij,  H = sum_i h_i s_i,  S = sum_{i<j} J_ij,
-//   E = sum_{i<j} J_ij s_i s_j + H = S - 2 C + H   (s_i s_j = 1 - 2 [s_i != s_j]),
-// all exact; S is the same for every vector and is summed once, by the extra vector
-// slot V.  Workgroup b takes slice p = b mod P of vector b / P (vector slot V: S):
-// rows p*4 + w, then every 4P, lanes along the columns j > i; the vector is staged in
-// LDS.  CSR instances keep both directions of every pair: 2E and 2C over i != j.
-__global__ __launch_bounds__(256) void k_energy(EnArgs a) {
-    __shared__ Acc256 sh[4];
-    __shared__ double shd[4];
-    __shared__ int8_t sv[ENERGY_MAXN_LDS];
-    const int v = blockIdx.x / a.P, p = blockIdx.x % a.P, tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
-    const bool total = v == a.V;                       // the slot that sums S
-    const int8_t *s = a.spins + (int64_t)(total ? 0 : v) * a.N;
-    const bool lds = a.N <= ENERGY_MAXN_LDS;
-    if (lds && !total)
-        for (int i = tid; i < a.N; i += 256) sv[i] = s[i];
-    __syncthreads();
-    const int8_t *ss = lds ? sv : s;
-    const int b0 = a.b0;
-    const int64_t slot = (int64_t)v * a.P + p;
-    if (a.fast) {
-        // every partial sum is a multiple of 2^b0 below 2^(53 + b0): binary64 is exact
-        double ae = 0.0, ac = 0.0;
-        if (!a.csr) {
-            for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
-                const int si = total ? 0 : ss[i];
-#pragma unroll 4
-                for (int j = i + 1 + lane; j < a.N; j += 64) {
-                    const double J = en_coupling(a, i, j);
-                    ac += (total || si != ss[j]) ? J : 0.0;
-                }
-            }
-            if (!total)
-                for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
-                    ae += ss[i] > 0 ? a.h[i] : -a.h[i];
-        } else {
-            for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
-                const int si = ss[i];
-                for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
-                    const double J = a.J[e];
-                    const bool same = si == ss[a.ci[e]];
-                    ae += same ? J : -J;
-                    ac += same ? 0.0 : J;
-                }
-            }
-            for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
-                ae += ss[i] > 0 ? 2.0 * a.h[i] : -2.0 * a.h[i];
-        }
-        ae = block_sum(ae, shd);
-        ac = block_sum(ac, shd);
-        if (tid == 0) {
-            double *o = (double *)a.part + 2 * slot;
-            o[0] = ae;
-            o[1] = ac;
-        }
-        return;
+// The parts of a term on levels 0 .. L - 1 (see above).
+template <int L>
+__device__ __forceinline__ void mv_split(const EnMvArgs &a, double r, double (&t)[L]) {
+#pragma unroll
+    for (int k = L - 1; k >= 1; k--) {
+        const double hi = (r + a.K[k]) - a.K[k];
+        r -= hi;
+        t[k] = hi;
     }
+    t[0] = r;
+}
+
+// Workgroup (p, g): vectors g G .. g G + G - 1 (G divides 64, so one mask word), rows
+// 4 p + w, 4 p + w + 4 P, ... (wavefront w), lanes along the columns j > i.  Lane x holds
+// the column sums of C for every vector of the group and, for vector g G + x, the sum
+// Hn; group 0 also sums S and Ht.
+template <int G, int L>
+__global__ __launch_bounds__(256) void k_energy_mv(EnMvArgs a) {
+    __shared__ double red[4][G + 2][L];
+    const int p = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int v0 = g * G, word = v0 >> 6, sh = v0 & 63;
+    const bool first = g == 0;
+    const uint64_t *M = a.masks + (int64_t)word * a.N;
+    double c[G][L], hn[L], s[L], ht[L];
+#pragma unroll
+    for (int k = 0; k < L; k++) {
+        hn[k] = 0.0; s[k] = 0.0; ht[k] = 0.0;
+#pragma unroll
+        for (int v = 0; v < G; v++) c[v][k] = 0.0;
+    }
+    for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
+        const uint64_t mi = M[i];
+        if (a.h) {
+            double t[L];
+            mv_split<L>(a, a.h[i], t);
+            // lanes x < G read bit sh + x <= 63 of the word; the others are not used
+            const double bit = (double)(uint32_t)((mi >> ((sh + lane) & 63)) & 1ull);
+            if (lane < G) {
+#pragma unroll
+                for (int k = 0; k < L; k++) hn[k] = fma(t[k], bit, hn[k]);
+            }
+            if (first && lane == 0) {
+#pragma unroll
+                for (int k = 0; k < L; k++) ht[k] += t[k];
+            }
+        }
+        for (int j = i + 1 + lane; j < a.N; j += 64) {
+            double t[L];
+            mv_split<L>(a, mv_coupling(a, i, j), t);
+            if (first) {
+#pragma unroll
+                for (int k = 0; k < L; k++) s[k] += t[k];
+            }
+            const uint64_t d = (mi ^ M[j]) >> sh;
+#pragma unroll
+            for (int v = 0; v < G; v++) {
+                const double bit = (double)(uint32_t)((d >> v) & 1ull);
+#pragma unroll
+                for (int k = 0; k < L; k++) c[v][k] = fma(t[k], bit, c[v][k]);
+            }
+        }
+    }
+    // column sums over the lanes, then over the wavefronts
+#pragma unroll
+    for (int v = 0; v < G; v++)
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            double x = c[v][k];
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            if (lane == 0) red[w][v][k] = x;
+        }
+#pragma unroll
+    for (int k = 0; k < L; k++) {
+        double x = s[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) {
+            red[w][G][k] = x;
+            red[w][G + 1][k] = ht[k];
+        }
+    }
+    __syncthreads();
+    const EnMvLayout lay = energy_mv_layout(a.P, a.V, L);
+    for (int e = tid; e < G * L; e += 256) {
+        const int v = e / L, k = e % L;
+        if (v0 + v < a.V)
+            a.part[lay.c + ((int64_t)p * a.V + v0 + v) * L + k] =
+                red[0][v][k] + red[1][v][k] + red[2][v][k] + red[3][v][k];
+    }
+    __syncthreads();
+    // Hn: lane x of each wavefront holds vector v0 + x
+    if (lane < G) {
+#pragma unroll
+        for (int k = 0; k < L; k++) red[w][lane][k] = hn[k];
+    }
+    __syncthreads();
+    for (int e = tid; e < G * L; e += 256) {
+        const int v = e / L, k = e % L;
+        if (v0 + v < a.V)
+            a.part[lay.hn + ((int64_t)p * a.V + v0 + v) * L + k] =
+                red[0][v][k] + red[1][v][k] + red[2][v][k] + red[3][v][k];
+    }
+    if (first && tid < L) {
+        a.part[lay.s + (int64_t)p * L + tid] =
+            red[0][G][tid] + red[1][G][tid] + red[2][G][tid] + red[3][G][tid];
+        a.part[lay.ht + (int64_t)p * L + tid] =
+            red[0][G + 1][tid] + red[1][G + 1][tid] + red[2][G + 1][tid] + red[3][G + 1][tid];
+    }
+}
+
+// Per vector: level totals over the slices (exact binary64), then E = S - 2 C + Ht - 2 Hn
+// and C in the fixed-point accumulator, each rounded once.
+template <int L>
+__global__ __launch_bounds__(64) void k_energy_mv_merge(EnMvArgs a) {
+    const int v = blockIdx.x * 64 + threadIdx.x;
+    if (v >= a.V) return;
+    const EnMvLayout lay = energy_mv_layout(a.P, a.V, L);
     Acc256 ae, ac;
     acc_zero(ae);
     acc_zero(ac);
-    if (!a.csr) {
-        for (int i = 4 * p + w; i < a.N; i += 4 * a.P) {
-            const double *Jr = a.J + (int64_t)i * a.N;
-            const int si = total ? 0 : ss[i];
-            for (int j = i + 1 + lane; j < a.N; j += 64) {
-                const double J = Jr[j];
-                if (J != 0.0 && (total || si != ss[j])) acc_add(ac, J, b0);
-            }
-        }
-        if (!total)
-            for (int i = 256 * p + tid; i < a.N; i += 256 * a.P)
-                acc_add(ae, ss[i] > 0 ? a.h[i] : -a.h[i], b0);
-    } else {
-        for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
-            int si = ss[i];
-            for (int e = a.rp[i]; e < a.rp[i + 1]; e++) {
-                double J = a.J[e];
-                int sj = ss[a.ci[e]];
-                acc_add(ae, si == sj ? J : -J, b0);
-                if (si != sj) acc_add(ac, J, b0);
-            }
-        }
-        for (int i = 256 * p + tid; i < a.N; i += 256 * a.P) {
-            double hh = a.h[i];
-            if (hh != 0.0) acc_add(ae, ss[i] > 0 ? 2.0 * hh : -2.0 * hh, b0);
-        }
-    }
-    block_acc_reduce(ae, sh);
-    block_acc_reduce(ac, sh);
-    if (tid == 0) {
-        Acc256 *o = (Acc256 *)a.part + 2 * slot;
-        o[0] = ae;
-        o[1] = ac;
-    }
-}
-
-// Totals of the P slices of each vector (a thread per vector), rounded once.  Dense:
-// slot 0 of a slice holds its part of H, slot 1 its part of C (of S for the extra vector
-// V), and E = S - 2 C + H.  CSR: slot 0 holds 2E, slot 1 2C.
-__device__ __forceinline__ void acc_merge_neg2(Acc256 &a, const Acc256 &c) {
-    add256(a.p, c.n);
-    add256(a.p, c.n);
-    add256(a.n, c.p);
-    add256(a.n, c.p);
-}
-
-__global__ __launch_bounds__(64) void k_energy_merge(EnArgs a) {
-    const int v = blockIdx.x * 64 + threadIdx.x;
-    if (v >= a.V) return;
-    const int64_t s0 = (int64_t)v * a.P, sS = (int64_t)a.V * a.P;
-    if (a.fast) {
-        const double *o = (const double *)a.part;
-        double ae = 0.0, ac = 0.0;
+    for (int k = 0; k < L; k++) {
+        double C = 0.0, Hn = 0.0, S = 0.0, Ht = 0.0;
         for (int p = 0; p < a.P; p++) {
-            ae += o[2 * (s0 + p)];
-            ac += o[2 * (s0 + p) + 1];
+            C += a.part[lay.c + ((int64_t)p * a.V + v) * L + k];
+            Hn += a.part[lay.hn + ((int64_t)p * a.V + v) * L + k];
+            S += a.part[lay.s + (int64_t)p * L + k];
+            Ht += a.part[lay.ht + (int64_t)p * L + k];
         }
-        if (a.csr) {
-            if (a.E) a.E[v] = 0.5 * ae;
-            if (a.cut) a.cut[v] = 0.5 * ac;
-            return;
-        }
-        double S = 0.0;
-        for (int p = 0; p < a.P; p++) S += o[2 * (sS + p) + 1];
-        if (a.E) a.E[v] = (S - 2.0 * ac) + ae;
-        if (a.cut) a.cut[v] = ac;
-        return;
+        acc_add(ac, C, a.b0);
+        acc_add(ae, S, a.b0);
+        acc_add(ae, Ht, a.b0);
+        acc_add(ae, -2.0 * C, a.b0);
+        acc_add(ae, -2.0 * Hn, a.b0);
     }
-    const Acc256 *o = (const Acc256 *)a.part;
-    Acc256 ae = o[2 * s0], ac = o[2 * s0 + 1];
-    for (int p = 1; p < a.P; p++) {
-        acc_merge(ae, o[2 * (s0 + p)]);
-        acc_merge(ac, o[2 * (s0 + p) + 1]);
-    }
-    if (a.csr) {
-        if (a.E) a.E[v] = acc_round(ae, a.b0 - 1);
-        if (a.cut) a.cut[v] = acc_round(ac, a.b0 - 1);
-        return;
-    }
-    for (int p = 0; p < a.P; p++) acc_merge(ae, o[2 * (sS + p) + 1]);   // + S
-    acc_merge_neg2(ae, ac);                                             // - 2 C
     if (a.E) a.E[v] = acc_round(ae, a.b0);
     if (a.cut) a.cut[v] = acc_round(ac, a.b0);
 }
@@ -907,12 +1071,79 @@ int energy_slices(int N, int V) {
     return std::max(1, std::min(want, most));
 }
 
+// Slices of the many-vector kernel: about 1024 workgroups over the vector groups, each
+// slice at least 16 rows.
+static int energy_mv_slices(int N, int groups) {
+    const int want = (1024 + groups - 1) / groups;
+    const int most = (N + 15) / 16;
+    return std::max(1, std::min(want, most));
+}
+
+static int energy_mv_group(int L) { return L == 1 ? 64 : L == 2 ? 32 : 16; }
+
 size_t energy_part_bytes(int N, int V) {
-    return (size_t)(std::max(V, 1) + 1) * energy_slices(N, V) * 2 * sizeof(Acc256);
+    V = std::max(V, 1);
+    const size_t old = (size_t)V * energy_slices(N, V) * 2 * sizeof(Acc256);
+    size_t mv = 0;
+    for (int L = 1; L <= 4; L++) {
+        const int G = energy_mv_group(L);
+        const int P = energy_mv_slices(N, (V + G - 1) / G);
+        const size_t b = (size_t)((V + 63) / 64) * N * 8 +
+                         (size_t)energy_mv_layout(P, V, L).total * 8 + 256;
+        mv = std::max(mv, b);
+    }
+    return std::max(old, mv);
+}
+
+// Levels of the many-vector kernel for instance I (0: it does not apply).
+static int energy_levels(const Instance &I, double *K) {
+    for (int k = 0; k < 4; k++) K[k] = 0.0;
+    if (I.layout != HQA_DENSE || I.es.lsb == INT32_MIN) return 0;
+    const double terms = (double)I.N * I.N + I.N;
+    int lg = 0;
+    while (lg < 64 && std::ldexp(1.0, lg) < terms) lg++;
+    const int w = 51 - lg;
+    if (w < 8) return 0;
+    const int span = I.es.msb + 1 - I.es.lsb;
+    const int L = std::max(1, (span + w - 1) / w);
+    // the rounding constants stay normal binary64 numbers
+    if (L > 4 || I.es.lsb + 52 < -1022 || I.es.lsb + (L - 1) * w + 52 > 1000) return 0;
+    for (int k = 1; k < L; k++) K[k] = std::ldexp(1.5, I.es.lsb + k * w + 52);
+    return L;
+}
+
+template <int L>
+static void launch_mv(EnMvArgs &a, hipStream_t st) {
+    constexpr int G = L == 1 ? 64 : L == 2 ? 32 : 16;
+    const int groups = (a.V + G - 1) / G;
+    a.P = energy_mv_slices(a.N, groups);
+    k_energy_mv<G, L><<<dim3(a.P, groups), 256, 0, st>>>(a);
+    k_energy_mv_merge<L><<<(a.V + 63) / 64, 64, 0, st>>>(a);
 }
 
 hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
                          void *part, hipStream_t st) {
+    if (V == 0) return hipSuccess;
+    EnMvArgs m;
+    const int L = energy_levels(I, m.K);
+    if (L) {
+        m.N = I.N; m.V = V; m.b0 = I.es.lsb;
+        m.J = I.J64; m.h = I.h64; m.spins = spins; m.E = E; m.cut = cut;
+        // the compact storage copy when it holds every coupling exactly
+        m.jt = -1; m.ldj = 0; m.Js = nullptr;
+        if (I.js_exact && I.Js) {
+            m.jt = (int)I.jt; m.ldj = I.Np; m.Js = I.Js;
+        }
+        m.masks = (uint64_t *)part;
+        const size_t mw = (size_t)((V + 63) / 64) * I.N;
+        m.part = (double *)((uint8_t *)part + ((mw * 8 + 255) & ~(size_t)255));
+        k_pack_masks<<<(unsigned)((mw + 255) / 256), 256, 0, st>>>(I.N, V, spins, m.masks);
+        if (L == 1) launch_mv<1>(m, st);
+        else if (L == 2) launch_mv<2>(m, st);
+        else if (L == 3) launch_mv<3>(m, st);
+        else launch_mv<4>(m, st);
+        return hipGetLastError();
+    }
     EnArgs a;
     a.N = I.N; a.V = V; a.P = energy_slices(I.N, V); a.csr = I.layout == HQA_CSR; a.b0 = I.es.lsb;
     // Every J and h is a multiple of 2^lsb below 2^(msb + 1); the sums take at most
@@ -926,14 +1157,7 @@ hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *
     }
     a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64; a.spins = spins; a.part = part;
     a.E = E; a.cut = cut;
-    // the compact storage copy, when it holds every coupling exactly (fast path only:
-    // the accumulator path takes binary64 terms from J)
-    a.jt = -1; a.ldj = 0; a.Js = nullptr;
-    if (!a.csr && a.fast && I.js_exact && I.Js) {
-        a.jt = (int)I.jt; a.ldj = I.Np; a.Js = I.Js;
-    }
-    if (V == 0) return hipSuccess;
-    k_energy<<<(V + (a.csr ? 0 : 1)) * a.P, 256, 0, st>>>(a);
+    k_energy<<<V * a.P, 256, 0, st>>>(a);
     k_energy_merge<<<(V + 63) / 64, 64, 0, st>>>(a);
     return hipGetLastError();
 }

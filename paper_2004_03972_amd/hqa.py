@@ -31,10 +31,10 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
             "hqa_es_confidence", "hqa_es_destroy", "hqa_classify_tabu", "hqa_md_run_es",
-            "hqa_classify_noalloc")
+            "hqa_classify_noalloc", "hqa_classify_many")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
 HQA_NOALLOC_SCRATCH_BYTES = 16 << 20
-ABI_VERSION = 7
+ABI_VERSION = 8
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 HQA_MD_GRAPH = 1
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
@@ -110,6 +110,7 @@ def lib():
         L.hqa_md_hamiltonian.argtypes = [P, i32, P, i32]
         L.hqa_classify.argtypes = [P, i32, i32, i32, P, i32]
         L.hqa_classify_noalloc.argtypes = [P, i32, i32, i32, P, i32]
+        L.hqa_classify_many.argtypes = [P, P, i32, i32, i32, P, P, i32]
         L.hqa_ising_energy.argtypes = [P, P, i32, P, P, i32, P]
         L.hqa_md_destroy.argtypes = [P]
         L.hqa_md_stats_window.argtypes = [P, i64, i64, i64]
@@ -260,6 +261,14 @@ def hqa_classify(md, instance: int, n_amb: int, solve: int, out: hqa_classify_ou
 def hqa_classify_noalloc(md, instance: int, n_amb: int, solve: int, out: hqa_classify_out,
                          out_mem: int):
     _check(lib().hqa_classify_noalloc(md, instance, n_amb, solve, C.byref(out), out_mem))
+
+
+def hqa_classify_many(md, instances, count: int, n_amb: int, solve: int, energy, cut,
+                      out_mem: int):
+    ks, _k = _addr(instances)
+    e, _e = _addr(energy)
+    c, _c = _addr(cut)
+    _check(lib().hqa_classify_many(md, ks, count, n_amb, solve, e, c, out_mem))
 
 
 def hqa_classify_tabu(md, instance: int, n_amb: int, iters: int, tenure: int,
@@ -579,6 +588,17 @@ class MD:
         res["amb_idx"] = res["amb_idx"][:, :n_amb]
         res["h_eff"] = res["h_eff"][:, :n_amb]
         return res
+
+
+    def classify_many(self, n_amb: int, solve: bool = True, instances=None):
+        """Exact energies and cuts [count][R] of the read-out of several instances
+        (default: all) in one call (hqa_classify_many)."""
+        ks = np.arange(len(self.problems), dtype=np.int32) if instances is None else \
+            np.ascontiguousarray(instances, dtype=np.int32)
+        E = np.empty((ks.size, self.R))
+        Cc = np.empty((ks.size, self.R))
+        hqa_classify_many(self.h, ks, ks.size, n_amb, int(solve), E, Cc, HQA_HOST)
+        return E, Cc
 
 
 def ising_energy(problem: Problem, spins) -> tuple[np.ndarray, np.ndarray]:

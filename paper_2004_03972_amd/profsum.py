@@ -60,7 +60,7 @@ def _tool(name):
 
 
 def isa_hash(kernel: str, lib: str | None = None) -> str | None:
-    """SHA-256 of the gfx950 code of the kernel whose mangled name contains
+    """SHA-256 of the gfx950 code of the kernel whose demangled name contains
     `kernel` (exactly one such kernel must exist) in the library's offload bundles, or
     None when the ROCm object tools are missing or the kernel is not found.  The
     instruction text is taken without addresses and encodings (branch offsets are
@@ -88,11 +88,15 @@ def isa_hash(kernel: str, lib: str | None = None) -> str | None:
                                f"--targets={_TARGET}", f"--output={co}"],
                               capture_output=True).returncode:
                 continue
-            syms = subprocess.run([readelf, "-s", "--wide", co], capture_output=True,
-                                  text=True).stdout
-            for line in syms.splitlines():
-                f = line.split()
-                if len(f) >= 8 and f[3] == "FUNC" and kernel in f[7]:
+            # the symbol table twice, mangled and demangled, in the same order
+            tabs = [subprocess.run([readelf, "-s", "--wide", *opt, co], capture_output=True,
+                                   text=True).stdout.splitlines() for opt in ((), ("-C",))]
+            if len(tabs[0]) != len(tabs[1]):
+                continue
+            for raw, dem in zip(*tabs):
+                f = raw.split(None, 7)
+                g = dem.split(None, 7)
+                if len(f) == 8 and len(g) == 8 and f[3] == "FUNC" and kernel in g[7]:
                     found.append((co, f[7]))
         names = {n for _, n in found}
         if len(names) != 1:
@@ -151,12 +155,16 @@ def stats(path, top=12):
               f"{float(r['TotalDurationNs']) / 1e6:>10.2f} {float(r['Percentage']):>6.2f}")
 
 
-def trace(path, kernel, last=0):
+def trace(path, kernel, last=0, span=""):
     rows = [r for r in _rows(path) if kernel in r["Kernel_Name"]]
     if not rows:
         sys.exit(f"no dispatch matches {kernel!r}")
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    if last:                                   # only the last dispatches (the timed runs)
+    if span:                                   # dispatches a..b-1 in launch order
+        a, b = (int(x) for x in span.split(":"))
+        rows = rows[a:b]
+        print(f"dispatches {a}..{b - 1} of the kernel (launch order, from 0)")
+    elif last:                                 # only the last dispatches (the timed runs)
         rows = rows[-last:]
         print(f"last {len(rows)} dispatches of the kernel")
     dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
@@ -209,12 +217,13 @@ def main(argv=None):
     ap.add_argument("--bytes", type=int, default=0)
     ap.add_argument("--sources", default="dense", choices=sorted(SOURCES))
     ap.add_argument("--last", type=int, default=0, help="only the last N dispatches")
+    ap.add_argument("--span", default="", help="trace: only dispatches A..B-1 (A:B)")
     ap.add_argument("--lib", default=None, help="library for isahash (default libhqa.so)")
     a = ap.parse_args(argv)
     if a.mode == "stats":
         stats(a.path, a.top)
     elif a.mode == "trace":
-        trace(a.path, a.kernel, a.last)
+        trace(a.path, a.kernel, a.last, a.span)
     elif a.mode == "pmc":
         pmc(a.path, a.kernel, a.last)
     elif a.mode == "calib":

@@ -214,3 +214,38 @@ def test_graph_replay_equals_eager(H):
         md.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+def test_classify_many_equals_per_instance(H):
+    """hqa_classify_many: the energies and cuts of every listed instance equal
+    hqa_classify's bit for bit (exact enumeration at n = 12 and the MD-alone read-out),
+    for all instances, for a subset with a repeat, and with device outputs; bad lists
+    are refused before any device work."""
+    import torch
+    probs, Js = _mixed_batch(H, [100, 333, 517], [700, 1200], 80)
+    R, T = 40, 120
+    md = H.MD(probs, H.make_schedule(T, 30), R, "bf16", seed=5)
+    md.run()
+    for solve, n in ((True, 12), (False, 7)):
+        E, Cc = md.classify_many(n, solve=solve)
+        for k in range(len(probs)):
+            g = md.classify(n, solve=solve, k=k)
+            assert np.array_equal(E[k], g["energy"]) and np.array_equal(Cc[k], g["cut"]), (solve, k)
+    ks = np.array([4, 0, 4], dtype=np.int32)
+    E2, C2 = md.classify_many(12, instances=ks)
+    E, Cc = md.classify_many(12)
+    assert np.array_equal(E2, E[ks]) and np.array_equal(C2, Cc[ks])
+    dE = torch.empty((3, R), dtype=torch.float64, device="cuda")
+    H.hqa_classify_many(md.h, ks, 3, 12, 1, dE, None, H.HQA_DEVICE)
+    assert np.array_equal(dE.cpu().numpy(), E[ks])
+    for bad in (np.array([5], np.int32), np.array([-1], np.int32)):
+        with pytest.raises(H.HQAError) as e:
+            md.classify_many(12, instances=bad)
+        assert e.value.status == H.HQA_EINVAL
+    with pytest.raises(H.HQAError) as e:
+        H.hqa_classify_many(md.h, ks, 0, 12, 1, dE, None, H.HQA_DEVICE)
+    assert e.value.status == H.HQA_EINVAL
+    with pytest.raises(H.HQAError) as e:
+        md.classify_many(25)                      # exact enumeration limited to n <= 24
+    assert e.value.status == H.HQA_EUNSUPPORTED
+    md.close()

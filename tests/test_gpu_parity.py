@@ -279,6 +279,70 @@ def test_ising_energy_exact_slices(H, kind, N, V):
     assert np.array_equal(E, Eo) and np.array_equal(C, Co)
 
 
+def _spanned(N, span, seed, top=-3):
+    """Symmetric J (zero diagonal) and h whose nonzero values carry full 53-bit mantissas
+    and exponents spread so that the bits of the set run from 2^top down to about
+    2^(top - span + 1); an eighth of the mantissas are all ones and a few values sit at
+    the largest magnitude."""
+    rng = np.random.default_rng(seed)
+    b = min(span, 53)                      # mantissa bits; the exponents spread the rest
+    m = rng.integers(2**(b - 1), 2**b, size=(N, N), dtype=np.uint64).astype(np.float64)
+    m[rng.random((N, N)) < 0.125] = float(2**b - 1)
+    e = rng.integers(top - span + b, top + 1, size=(N, N))
+    J = np.ldexp(m, e - (b - 1)) * np.where(rng.random((N, N)) < 0.5, -1.0, 1.0)
+    J[rng.random((N, N)) < 0.02] = np.ldexp(float(2**b - 1), top - (b - 1))
+    J = np.triu(J, 1)
+    J = J + J.T
+    h = np.ldexp(rng.integers(2**(b - 1), 2**b, size=N).astype(np.float64),
+                 rng.integers(top - span + b, top + 1, size=N) - (b - 1))
+    return J, h
+
+
+@pytest.mark.parametrize("span", [60, 100, 130, 145])
+def test_ising_energy_exact_level_sums(H, span):
+    """Exact energies and cuts of real couplings whose bits span 60, 100 and 130 binades
+    (two, three and four binary64 level sums at N = 300, 34 bits each) and 145 (beyond
+    four levels: the fixed-point accumulator per term; the library refuses exact sums
+    past 151): the oracle's values bit for bit."""
+    N, V = 300, 9
+    J, h = _spanned(N, span, 900 + span)
+    spins = inst.random_pm1((V, N), 901).astype(np.int8)
+    E, C = H.ising_energy(H.Problem(J, h=h), spins)
+    Eo, Co = orc.energy(orc.Problem(N, J=J, h=h), spins)
+    assert np.array_equal(E, Eo) and np.array_equal(C, Co)
+
+
+@pytest.mark.parametrize("storage,prec", [("fp8", "fp8"), ("bf16", "bf16"), ("f32", "f32")])
+def test_readout_energy_from_storage_copy(H, storage, prec):
+    """Read-out energies on a handle whose stored couplings hold J exactly (small
+    integers): the energy kernel reads the 1-, 2- or 4-byte copy instead of binary64.
+    R = 70 (a full and a partial group of 64 vectors); energies and cuts equal the
+    oracle's for the returned spins."""
+    N, R = 403, 70
+    J = inst.small_int(N, 831, -3, 3, density=0.4)
+    h = np.random.default_rng(832).integers(-2, 3, N).astype(np.float64)
+    md = H.MD(H.Problem(J, h=h, storage=storage), H.make_schedule(60, 10), R, prec, seed=3,
+              require_exact=True)
+    md.run()
+    g = md.classify(9, solve=True)
+    E, C = orc.energy(orc.Problem(N, J=J, h=h), g["spins"])
+    assert np.array_equal(g["energy"], E) and np.array_equal(g["cut"], C)
+    md.close()
+
+
+@pytest.mark.parametrize("N,V,span", [(2, 1, 20), (3, 65, 20), (130, 129, 60), (257, 64, 100),
+                                      (64, 200, 130)])
+def test_ising_energy_vector_groups(H, N, V, span):
+    """Tiny and ragged shapes of the many-vector energy kernel: one or two spins, vector
+    counts just past a group of 64 (and of 32 and 16 on the multi-level paths): the
+    oracle's energies and cuts bit for bit."""
+    J, h = _spanned(N, span, 840 + N)
+    spins = inst.random_pm1((V, N), 841).astype(np.int8)
+    E, C = H.ising_energy(H.Problem(J, h=h), spins)
+    Eo, Co = orc.energy(orc.Problem(N, J=J, h=h), spins)
+    assert np.array_equal(E, Eo) and np.array_equal(C, Co)
+
+
 # ------------------------------------------------------ determinism and resume
 def test_checkpoint_resume_bit_identical(H):
     N, R, T = 160, 24, 500

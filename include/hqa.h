@@ -21,6 +21,22 @@
  *    ordered on the HIP stream given at init (NULL = the null stream).
  *    hqa_md_run is asynchronous; calls that write host outputs synchronise.
  *  - Replica-indexed arrays are replica-major: x[r * N + i].
+ *
+ * Environment
+ *  - HQA_TIMING=1 (any value but 0): hqa_md_run, hqa_classify and
+ *    hqa_classify_many time their device work with HIP events on their stream,
+ *    synchronise, and print one line per call to stderr ("hqa timing: ...").
+ *    hqa_md_run is then synchronous.
+ *  - HQA_FAULT_ALLOC=k (k >= 1): the k-th device allocation counted from the
+ *    start of the latest hqa_md_init fails as out of memory, so the caller sees
+ *    HQA_ENOMEM from whichever call made it (tests of the error paths; a handle
+ *    that init returned stays usable after a later call fails this way).
+ *  - HQA_TUNE_CACHE=path: hqa_md_tune keeps its choices in that text file, one
+ *    line per tuned case (device, instance shape and storage, R, precision,
+ *    tuning length), and takes a stored choice instead of timing the candidates
+ *    when the case comes again.  Every plan gives bit-identical trajectories, so
+ *    the file affects speed only; entries that do not fit the instance are
+ *    ignored.
  */
 #ifndef HQA_H
 #define HQA_H

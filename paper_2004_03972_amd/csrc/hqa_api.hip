@@ -1,12 +1,15 @@
+#include <atomic>
 #include <mutex>
 // hqa_api.hip -- the C ABI of include/hqa.h: argument checks, device buffers,
 // dispatch of the MD step kernels and of the read-out chain.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -50,12 +53,64 @@ static hqa_status fail(hqa_status st, const char *fmt, ...) {
                         #expr, hipGetErrorString(e_));                                 \
     } while (0)
 
+namespace hqa {
+static std::atomic<int64_t> g_alloc_count{0}, g_alloc_fail{0};
+
+void fault_alloc_arm() {
+    const char *v = getenv("HQA_FAULT_ALLOC");
+    g_alloc_fail = v ? atoll(v) : 0;
+    g_alloc_count = 0;
+}
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+    *p = nullptr;
+    const int64_t k = ++g_alloc_count;
+    const int64_t f = g_alloc_fail.load();
+    if (f > 0 && k == f) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+}  // namespace hqa
+
+// The status of a failed HIP call: an allocation that failed is HQA_ENOMEM.
+static hqa_status dev_status(hipError_t e) {
+    return e == hipErrorOutOfMemory ? HQA_ENOMEM : HQA_EDEVICE;
+}
+
 template <typename T>
 static hipError_t dalloc(T **p, size_t count) {
-    *p = nullptr;
     if (count == 0) count = 1;
-    return hipMalloc((void **)p, count * sizeof(T));
+    return dev_malloc((void **)p, count * sizeof(T));
 }
+
+// HQA_TIMING=1 (any value but 0): hqa_md_run and the read-outs time their device work
+// with HIP events on their stream, synchronise, and print one line to stderr.
+static bool timing_on() {
+    const char *v = getenv("HQA_TIMING");
+    return v && *v && strcmp(v, "0") != 0;
+}
+
+struct CallTimer {
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool on = false;
+    explicit CallTimer(hipStream_t s) : st(s), on(timing_on()) {
+        if (on && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+                   hipEventRecord(e0, st) != hipSuccess))
+            on = false;
+    }
+    // milliseconds since construction, or -1 when timing is off or failed
+    double stop() {
+        float ms = -1.0f;
+        if (on && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
+            (void)hipEventElapsedTime(&ms, e0, e1);
+        on = false;
+        return ms;
+    }
+    ~CallTimer() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
 
 static void dfree(void *p) {
     if (p) (void)hipFree(p);
@@ -251,6 +306,7 @@ void hqa_md_destroy(hqa_md *md) {
 hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedule *sched,
                        const hqa_md_opts *opts, void *hip_stream, hqa_md **out) {
     g_err.clear();
+    fault_alloc_arm();
     if (!out) return fail(HQA_EINVAL, "out is NULL");
     *out = nullptr;
     if (!probs || count < 1) return fail(HQA_EINVAL, "need at least one problem");
@@ -351,7 +407,7 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
                 else if (P.storage == HQA_PREC_BF16) I.jt = JT_BF16;
                 else if (P.storage == HQA_PREC_FP8J_BF16) I.jt = JT_FP8;
                 size_t esz = I.jt == JT_F32 ? 4 : I.jt == JT_BF16 ? 2 : 1;
-                HK(hipMalloc(&I.Js, (size_t)I.Np * I.Np * esz));
+                HK(dev_malloc(&I.Js, (size_t)I.Np * I.Np * esz));
                 HK(launch_convert_dense(I.J64, N, I.Np, I.jt, I.Js, md->err, st));
                 size_t n = (size_t)I.Rp * I.ld;
                 for (int b = 0; b < 2; b++) {
@@ -525,6 +581,8 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     if (q1 < md->q) return fail(HQA_ESTATE, "until_step %lld is before the current step %lld",
                                 (long long)q1, (long long)md->q);
     if (q1 == md->q) return HQA_OK;
+    CallTimer tm(md->stream);
+    const int64_t q0 = md->q;
     md->last_plan = 0;
     int ndense = 0;
     for (auto &I : md->inst) ndense += I.layout == HQA_DENSE;
@@ -539,12 +597,12 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     const bool clustered = multi && mp == HQA_PLAN_CLUSTER;
     if (batched) {
         hipError_t e = launch_md_steps_batch(md, md->q, q1, md->flags & HQA_MD_GRAPH);
-        if (e != hipSuccess) return fail(HQA_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return fail(dev_status(e), "batch step launch: %s", hipGetErrorString(e));
         md->last_plan = HQA_PLAN_BATCH;
     }
     if (clustered) {
         hipError_t e = run_dense_clusters(md, md->q, q1, &md->last_plan);
-        if (e != hipSuccess) return fail(HQA_EDEVICE, "cluster launch: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return fail(dev_status(e), "cluster launch: %s", hipGetErrorString(e));
     }
     for (auto &I : md->inst) {
         hipError_t e;
@@ -552,9 +610,17 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
         else if (I.layout == HQA_DENSE && (batched || clustered)) e = hipSuccess;
         else if (I.layout == HQA_DENSE) e = run_dense(md, I, md->q, q1, stats_live, md->plan, &md->last_plan);
         else e = run_csr(md, I, md->q, q1, stats_live, md->plan, &md->last_plan);
-        if (e != hipSuccess) return fail(HQA_EDEVICE, "step launch: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return fail(dev_status(e), "step launch: %s", hipGetErrorString(e));
     }
     md->q = q1;
+    const double ms = tm.stop();
+    if (ms >= 0.0) {
+        static const char *names[] = {"none", "step", "cluster", "resident", "batch"};
+        const int lp = md->last_plan >= 0 && md->last_plan <= 4 ? md->last_plan : 0;
+        fprintf(stderr, "hqa timing: hqa_md_run steps %lld..%lld, %zu instances, plan %s: "
+                "%.3f ms, %.3f us per step\n", (long long)q0, (long long)q1, md->inst.size(),
+                names[lp], ms, 1e3 * ms / (double)(q1 - q0));
+    }
     return HQA_OK;
 }
 
@@ -583,16 +649,109 @@ struct TuneCand {
     int plan, tm, tn, cb, tj;
 };
 
+// Persisted tuner choices (HQA_TUNE_CACHE=path): one line per tuned case,
+//   <key> | <plan> <tm> <tn> <cb> <tj>
+// the last line for a key winning.  The key names the device (architecture and compute
+// units), the case (one instance: layout, N, nonzeros, R, storage type, precision, LDS per
+// workgroup; several dense instances: R, precision and every dense instance's N and
+// storage type) and the tuning length.  Every plan gives bit-identical trajectories, so a
+// stale entry can cost speed but never change a result; an entry naming a plan that does
+// not apply falls back to STEP at run time like any other choice.
+struct TuneCache {
+    bool on = false;
+    std::string path, device;
+    std::map<std::string, TuneCand> m;
+
+    explicit TuneCache(hqa_md *md) {
+        const char *v = getenv("HQA_TUNE_CACHE");
+        if (!v || !*v) return;
+        path = v;
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return;
+        char b[320];
+        snprintf(b, sizeof b, "%s/%dcu/lds%d", prop.gcnArchName, prop.multiProcessorCount,
+                 md->max_lds);
+        device = b;
+        on = true;
+        FILE *f = fopen(path.c_str(), "r");
+        if (!f) return;
+        char line[4096];
+        while (fgets(line, sizeof line, f)) {
+            char *bar = strchr(line, '|');
+            if (!bar) continue;
+            TuneCand c;
+            if (sscanf(bar + 1, "%d %d %d %d %d", &c.plan, &c.tm, &c.tn, &c.cb, &c.tj) != 5) continue;
+            if (c.plan < HQA_PLAN_STEP || c.plan > HQA_PLAN_BATCH) continue;
+            std::string k(line, bar - line);
+            while (!k.empty() && k.back() == ' ') k.pop_back();
+            m[k] = c;
+        }
+        fclose(f);
+    }
+    std::string instance_key(const hqa_md *md, const Instance &I, int steps) const {
+        char b[256];
+        snprintf(b, sizeof b, "%s one %s N=%d nnz=%lld R=%d jt=%d prec=%d steps=%d", device.c_str(),
+                 I.layout == HQA_DENSE ? "dense" : "csr", I.N, (long long)I.nnz, md->R, (int)I.jt,
+                 md->prec, steps);
+        return b;
+    }
+    std::string multi_key(const hqa_md *md, int steps) const {
+        std::string k = device + " several R=" + std::to_string(md->R) +
+                        " prec=" + std::to_string(md->prec) + " steps=" + std::to_string(steps) + " N:jt=";
+        for (const auto &I : md->inst)
+            if (I.layout == HQA_DENSE) k += std::to_string(I.N) + ":" + std::to_string((int)I.jt) + ",";
+        return k;
+    }
+    bool find(const std::string &k, TuneCand &c) const {
+        if (!on) return false;
+        auto it = m.find(k);
+        if (it == m.end()) return false;
+        c = it->second;
+        return true;
+    }
+    // An entry is used only if it is a choice the tuner itself could make for I (the file
+    // is input like any other: tile shapes must fit, as hqa_md_set_step_tiles checks).
+    static bool fits(const Instance &I, const TuneCand &c) {
+        const bool none = c.tm == 0 && c.tn == 0 && c.cb == 0 && c.tj == 0;
+        if (I.layout != HQA_DENSE)
+            return none && (c.plan == HQA_PLAN_STEP || c.plan == HQA_PLAN_RESIDENT);
+        if (c.plan != HQA_PLAN_STEP) return none && c.plan >= HQA_PLAN_CLUSTER && c.plan <= HQA_PLAN_BATCH;
+        if (none) return true;
+        const bool lowp = I.jt == JT_BF16 || I.jt == JT_FP8;
+        return (c.tm == 1 || c.tm == 2) && (c.tn == 1 || c.tn == 2 || c.tn == 4) &&
+               I.Rp % (16 * c.tn) == 0 && (c.cb == 4 || c.cb == 8) && (c.tj == 0 || c.tj == 1) &&
+               (!c.tj || lowp);
+    }
+    void store(const std::string &k, const TuneCand &c) {
+        if (!on) return;
+        m[k] = c;
+        FILE *f = fopen(path.c_str(), "a");
+        if (!f) return;
+        fprintf(f, "%s | %d %d %d %d %d\n", k.c_str(), c.plan, c.tm, c.tn, c.cb, c.tj);
+        fclose(f);
+    }
+};
+
 // Several dense instances: time the batched kernel, the same-size cluster launches and
 // each instance on its own tuned plan, over all dense instances together (snapshot,
 // `steps` and 2 `steps` steps, restore, as for one instance), and keep the fastest in
 // md->multi_plan for AUTO.  A candidate that raises the error word is disqualified.
-static hqa_status tune_multi(hqa_md *md, int32_t steps, hipEvent_t e0, hipEvent_t e1) {
+static hqa_status tune_multi(hqa_md *md, int32_t steps, hipEvent_t e0, hipEvent_t e1,
+                             TuneCache &cache) {
     std::vector<Instance *> d;
     for (auto &I : md->inst)
         if (I.layout == HQA_DENSE) d.push_back(&I);
     md->multi_plan = 0;
     if (d.size() < 2) return HQA_OK;
+    const std::string key = cache.multi_key(md, steps);
+    TuneCand cached;
+    if (cache.find(key, cached) && (cached.plan == HQA_PLAN_BATCH || cached.plan == HQA_PLAN_CLUSTER ||
+                                    cached.plan == HQA_PLAN_STEP)) {
+        md->multi_plan = cached.plan;
+        return HQA_OK;
+    }
     struct Snap { float *x, *p, *S; bf16 *b; size_t n; int cur; };
     std::vector<Snap> sn(d.size(), Snap{nullptr, nullptr, nullptr, nullptr, 0, 0});
     hipError_t he = hipSuccess;
@@ -671,8 +830,9 @@ static hqa_status tune_multi(hqa_md *md, int32_t steps, hipEvent_t e0, hipEvent_
     }
     if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
     for (auto &x : sn) { dfree(x.x); dfree(x.p); dfree(x.S); dfree(x.b); }
-    if (he != hipSuccess) return fail(HQA_EDEVICE, "tuning several instances: %s", hipGetErrorString(he));
+    if (he != hipSuccess) return fail(dev_status(he), "tuning several instances: %s", hipGetErrorString(he));
     md->multi_plan = pick;
+    cache.store(key, TuneCand{pick, 0, 0, 0, 0});
     return HQA_OK;
 }
 
@@ -689,9 +849,20 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
     hqa_status rs = HQA_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         rs = fail(HQA_EDEVICE, "event creation failed");
+    TuneCache cache(md);
     for (auto &I : md->inst) {
         if (rs != HQA_OK) break;
         const bool dense = I.layout == HQA_DENSE;
+        const std::string key = cache.instance_key(md, I, steps);
+        TuneCand cached;
+        if (cache.find(key, cached) && TuneCache::fits(I, cached)) {
+            I.tuned_plan = cached.plan;
+            I.step_tm = cached.tm;
+            I.step_tn = cached.tn;
+            I.step_cb = cached.cb;
+            I.step_tj = cached.tj;
+            continue;
+        }
         const size_t n = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
         float *sx = nullptr, *sp = nullptr, *sS = nullptr;
         bf16 *sb = nullptr;
@@ -808,7 +979,7 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         if (he == hipSuccess) he = hipStreamSynchronize(md->stream);
         dfree(sx); dfree(sp); dfree(sS); dfree(sb);
         if (he != hipSuccess) {
-            rs = fail(HQA_EDEVICE, "tuning (plan %d, tiles %d x %d, %s): %s", failed.plan, failed.tm,
+            rs = fail(dev_status(he), "tuning (plan %d, tiles %d x %d, %s): %s", failed.plan, failed.tm,
                       failed.tn, stage, hipGetErrorString(he));
             break;
         }
@@ -817,8 +988,9 @@ hqa_status hqa_md_tune(hqa_md *md, int32_t steps) {
         I.step_tm = pick.tm;
         I.step_cb = pick.cb;
         I.step_tj = pick.tj;
+        cache.store(key, pick);
     }
-    if (rs == HQA_OK) rs = tune_multi(md, steps, e0, e1);
+    if (rs == HQA_OK) rs = tune_multi(md, steps, e0, e1, cache);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     md->stats_k0 = k0;
@@ -1121,8 +1293,14 @@ static hqa_status classify_impl(hqa_md *md, int32_t instance, int32_t n_amb, int
     hqa_status s = classify_checks(md, instance, n_amb, solve, out, prob);
     if (s != HQA_OK) return s;
     DevBufs B;
-    return classify_core(md, instance, n_amb, solve, out, out_mem, prob, prob_mem, tabu_iters,
-                         tenure, B);
+    CallTimer tm(md->stream);
+    s = classify_core(md, instance, n_amb, solve, out, out_mem, prob, prob_mem, tabu_iters,
+                      tenure, B);
+    const double ms = tm.stop();
+    if (s == HQA_OK && ms >= 0.0)
+        fprintf(stderr, "hqa timing: read-out of instance %d (N = %d, R = %d, n = %d, solve %d): "
+                "%.3f ms\n", instance, md->inst[instance].N, md->R, n_amb, solve, ms);
+    return s;
 }
 
 hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
@@ -1232,6 +1410,7 @@ hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count
     }
     hqa_status s = hqa_md_sync(md);
     if (s != HQA_OK) return s;
+    CallTimer tm(md->stream);
     // The instances are independent: they go round-robin to NS side streams, each with
     // its own scratch region, so that the small kernels of several instances overlap.
     // The side streams start after the handle's stream (an event) and the handle's stream
@@ -1239,7 +1418,7 @@ hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count
     const int NS = (int)std::min<int32_t>(count, 4);
     const size_t res = out_mem == HQA_HOST ? ScratchArena::round((size_t)count * R * 8) : 0;
     uint8_t *base = nullptr;
-    HIPCHK(hipMalloc((void **)&base, NS * need + 2 * res));
+    HIPCHK(dev_malloc((void **)&base, NS * need + 2 * res));
     double *dE = energy, *dC = cut;
     if (out_mem == HQA_HOST) {
         dE = energy ? (double *)(base + NS * need) : nullptr;
@@ -1287,7 +1466,11 @@ hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count
     (void)hipFree(base);
     if (s != HQA_OK) return s;
     if (e == hipSuccess) e = e2;
-    if (e != hipSuccess) return fail(HQA_EDEVICE, "read-out: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(dev_status(e), "read-out: %s", hipGetErrorString(e));
+    const double ms = tm.stop();
+    if (ms >= 0.0)
+        fprintf(stderr, "hqa timing: read-out of %d instances (R = %d, n = %d, solve %d, %d "
+                "streams): %.3f ms\n", count, R, n_amb, solve, NS, ms);
     return HQA_OK;
 }
 
@@ -1584,7 +1767,7 @@ hqa_status hqa_ising_energy(const hqa_problem *prob, const int8_t *spins, int32_
         e = hipMemcpyAsync(cut, dC, V * 8, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     free_instance(I);
-    if (e != hipSuccess) return fail(HQA_EDEVICE, "energy: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(dev_status(e), "energy: %s", hipGetErrorString(e));
     return HQA_OK;
 }
 

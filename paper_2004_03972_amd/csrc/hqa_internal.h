@@ -168,6 +168,12 @@ hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_e
 size_t enum_scratch_bytes(int n, int R);
 hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
                         int8_t *spins, hipStream_t st);
+// Every device allocation of the library goes through dev_malloc.  With HQA_FAULT_ALLOC=k
+// in the environment, the k-th allocation counted from the start of the latest
+// hqa_md_init (from 1) fails as out of memory (tests of the error paths).
+hipError_t dev_malloc(void **p, size_t bytes);
+void fault_alloc_arm();
+
 // Exact energies and cuts of V spin vectors; `part` holds energy_part_bytes(N, V)
 // bytes of device scratch for the per-slice partial sums.
 int energy_slices(int N, int V);

@@ -202,7 +202,8 @@ __global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
 // the barriers.  Registers hold three groups in turn (the loop is unrolled by three,
 // so no set is copied into another): the J fragments of group g + 2 and the flux
 // block of group g + 3 are requested at the start of group g, and the flux block of
-// group g + 1 is stored into the other LDS buffer at its end.  The deeper prefetch
+// group g + 1 is stored into the other LDS buffer at its end.  The epilogue's fluxes
+// and momenta are requested before the first group.  The deeper prefetch
 // costs registers (188 VGPRs) but not occupancy: at 146 VGPRs a compute unit already
 // held only one 512-thread workgroup, and the two-deep version took 2.3% longer per
 // step on the 512-instance batch.
@@ -265,6 +266,20 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
     const auto *Bsrc = gld<u32x4_b>(xb_in + (int64_t)min(r0 + srow, a.R - 1) * I.ld + 16 * sseg);
     u32x4_b *Bdst0 = (u32x4_b *)&Bs[0][srow][16 * sseg];
     u32x4_b *Bdst1 = (u32x4_b *)&Bs[1][srow][16 * sseg];
+
+    // The epilogue's fluxes and momenta are requested now, so their latency is hidden
+    // behind the groups: thread (replica t / 8, j = t % 8) takes rows 32 v + 4 j .. + 3
+    // of replica r0 + t / 8 (clamped to a real replica; rows up to i0 + 127 < Np exist).
+    const int rep = tid >> 3, j8 = tid & 7;
+    f32x4 ex[4], epm[4];
+    {
+        const int64_t cbase = (int64_t)min(r0 + rep, a.R - 1) * I.ld + tl.i0 + 4 * j8;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            ex[v] = *gld<f32x4>(phi_in + cbase + 32 * v);
+            epm[v] = *gld<f32x4>(I.p + cbase + 32 * v);
+        }
+    }
 
     f32x4 acc[4][4];
 #pragma unroll
@@ -348,7 +363,6 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
         const bool win = q + 1 >= a.T - a.W + 1;
         bool bad = false;
         const auto *hg = gld<float>(I.h);
-        const int rep = tid >> 3, j8 = tid & 7;
         const int col = r0 + rep;
         if (col < a.R) {
 #pragma unroll
@@ -358,8 +372,8 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
                 if (ib >= I.N) continue;
                 const f32x4 u = *(const f32x4 *)&U[rep * UL + loc];
                 const int64_t base = (int64_t)col * I.ld + ib;
-                const f32x4 x = *gld<f32x4>(phi_in + base);
-                const f32x4 p = *gld<f32x4>(I.p + base);
+                const f32x4 x = ex[v];
+                const f32x4 p = epm[v];
                 float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
@@ -514,13 +528,13 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
             for (int x = 0; x < NX; x++)
                 ht[JT_BF16].push_back(j < xl[x].size() ? xl[x][j] : BatchTile{-1, 0, 0, 0});
     }
-    hipError_t e = hipMalloc((void **)&bp->dinst, sizeof(BatchInst) * hi.size());
+    hipError_t e = dev_malloc((void **)&bp->dinst, sizeof(BatchInst) * hi.size());
     if (e == hipSuccess)
         e = hipMemcpy(bp->dinst, hi.data(), sizeof(BatchInst) * hi.size(), hipMemcpyHostToDevice);
     for (int t = 0; t < 3 && e == hipSuccess; t++) {
         bp->ntiles[t] = (int)ht[t].size();
         if (!bp->ntiles[t]) continue;
-        e = hipMalloc((void **)&bp->dtiles[t], sizeof(BatchTile) * ht[t].size());
+        e = dev_malloc((void **)&bp->dtiles[t], sizeof(BatchTile) * ht[t].size());
         if (e == hipSuccess)
             e = hipMemcpy(bp->dtiles[t], ht[t].data(), sizeof(BatchTile) * ht[t].size(),
                           hipMemcpyHostToDevice);

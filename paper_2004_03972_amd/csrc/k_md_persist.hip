@@ -816,13 +816,13 @@ hipError_t launch_md_persist_set(hqa_md *md, Instance *const *set, int K, int64_
             if (I.xch) (void)hipFree(I.xch);
             I.xch = nullptr;
             I.xch_bytes = 0;
-            hipError_t e = hipMalloc(&I.xch, bytes);
+            hipError_t e = dev_malloc(&I.xch, bytes);
             if (e != hipSuccess) return e;
             I.xch_bytes = bytes;
         }
     }
     if (!md->bar) {
-        hipError_t e = hipMalloc((void **)&md->bar, sizeof(int32_t) * 64);
+        hipError_t e = dev_malloc((void **)&md->bar, sizeof(int32_t) * 64);
         if (e != hipSuccess) return e;
     }
     hipError_t e = hipMemsetAsync(md->bar, 0, sizeof(int32_t) * 64, md->stream);

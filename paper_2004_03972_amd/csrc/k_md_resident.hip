@@ -328,7 +328,7 @@ hipError_t ensure_tiled_j(Instance &I, hipStream_t st) {
     if (I.jt != JT_BF16 && I.jt != JT_FP8) return hipErrorNotSupported;
     const int esz = I.jt == JT_BF16 ? 2 : 1;
     const int64_t tb = resident_tile_bytes(I);
-    hipError_t e = hipMalloc(&I.Jt, tb);
+    hipError_t e = dev_malloc(&I.Jt, tb);
     if (e != hipSuccess) {
         I.Jt = nullptr;
         return e;

@@ -895,15 +895,24 @@ static __host__ __device__ EnMvLayout energy_mv_layout(int P, int V, int L) {
     return o;
 }
 
-// Packed spins: word b of spin j has bit v set when vector 64 b + v has s_j = -1.
-__global__ void k_pack_masks(int N, int V, const int8_t *spins, uint64_t *masks) {
+// Packed spins: word b of spin j has bit v set when vector 64 b + v has s_j = -1.  A
+// thread per (word, spin): its 64 loads (rows clamped to the last vector, bits past it
+// cleared) are independent, so they are all in flight at once, and consecutive threads
+// read consecutive bytes of a row.
+__global__ __launch_bounds__(256) void k_pack_masks(int N, int V, const int8_t *spins,
+                                                    uint64_t *masks) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int nw = (V + 63) / 64;
     if (t >= (int64_t)nw * N) return;
     const int b = (int)(t / N), j = (int)(t % N);
+    int8_t x[64];
+#pragma unroll
+    for (int v = 0; v < 64; v++) x[v] = spins[(int64_t)min(64 * b + v, V - 1) * N + j];
     uint64_t m = 0;
-    for (int v = 0; v < 64 && 64 * b + v < V; v++)
-        m |= (uint64_t)(spins[(int64_t)(64 * b + v) * N + j] < 0) << v;
+#pragma unroll
+    for (int v = 0; v < 64; v++) m |= (uint64_t)(x[v] < 0) << v;
+    const int have = V - 64 * b;                     // vectors in this word
+    if (have < 64) m &= (1ull << have) - 1ull;
     masks[t] = m;
 }
 
@@ -1036,29 +1045,47 @@ __global__ __launch_bounds__(256) void k_energy_mv(EnMvArgs a) {
     }
 }
 
-// Per vector: level totals over the slices (exact binary64), then E = S - 2 C + Ht - 2 Hn
-// and C in the fixed-point accumulator, each rounded once.
+// Per vector (one wavefront, lanes over the slices): level totals over the slices (exact
+// binary64 in any grouping), then E = S - 2 C + Ht - 2 Hn and C in the fixed-point
+// accumulator, each rounded once.
 template <int L>
-__global__ __launch_bounds__(64) void k_energy_mv_merge(EnMvArgs a) {
-    const int v = blockIdx.x * 64 + threadIdx.x;
+__global__ __launch_bounds__(256) void k_energy_mv_merge(EnMvArgs a) {
+    const int v = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (v >= a.V) return;
     const EnMvLayout lay = energy_mv_layout(a.P, a.V, L);
+    double C[L], Hn[L], S[L], Ht[L];
+#pragma unroll
+    for (int k = 0; k < L; k++) {
+        C[k] = 0.0; Hn[k] = 0.0; S[k] = 0.0; Ht[k] = 0.0;
+    }
+    for (int p = lane; p < a.P; p += 64) {
+#pragma unroll
+        for (int k = 0; k < L; k++) {
+            C[k] += a.part[lay.c + ((int64_t)p * a.V + v) * L + k];
+            Hn[k] += a.part[lay.hn + ((int64_t)p * a.V + v) * L + k];
+            S[k] += a.part[lay.s + (int64_t)p * L + k];
+            Ht[k] += a.part[lay.ht + (int64_t)p * L + k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < L; k++)
+        for (int o = 32; o > 0; o >>= 1) {
+            C[k] += __shfl_xor(C[k], o);
+            Hn[k] += __shfl_xor(Hn[k], o);
+            S[k] += __shfl_xor(S[k], o);
+            Ht[k] += __shfl_xor(Ht[k], o);
+        }
+    if (lane) return;
     Acc256 ae, ac;
     acc_zero(ae);
     acc_zero(ac);
+#pragma unroll
     for (int k = 0; k < L; k++) {
-        double C = 0.0, Hn = 0.0, S = 0.0, Ht = 0.0;
-        for (int p = 0; p < a.P; p++) {
-            C += a.part[lay.c + ((int64_t)p * a.V + v) * L + k];
-            Hn += a.part[lay.hn + ((int64_t)p * a.V + v) * L + k];
-            S += a.part[lay.s + (int64_t)p * L + k];
-            Ht += a.part[lay.ht + (int64_t)p * L + k];
-        }
-        acc_add(ac, C, a.b0);
-        acc_add(ae, S, a.b0);
-        acc_add(ae, Ht, a.b0);
-        acc_add(ae, -2.0 * C, a.b0);
-        acc_add(ae, -2.0 * Hn, a.b0);
+        acc_add(ac, C[k], a.b0);
+        acc_add(ae, S[k], a.b0);
+        acc_add(ae, Ht[k], a.b0);
+        acc_add(ae, -2.0 * C[k], a.b0);
+        acc_add(ae, -2.0 * Hn[k], a.b0);
     }
     if (a.E) a.E[v] = acc_round(ae, a.b0);
     if (a.cut) a.cut[v] = acc_round(ac, a.b0);
@@ -1118,7 +1145,7 @@ static void launch_mv(EnMvArgs &a, hipStream_t st) {
     const int groups = (a.V + G - 1) / G;
     a.P = energy_mv_slices(a.N, groups);
     k_energy_mv<G, L><<<dim3(a.P, groups), 256, 0, st>>>(a);
-    k_energy_mv_merge<L><<<(a.V + 63) / 64, 64, 0, st>>>(a);
+    k_energy_mv_merge<L><<<(a.V + 3) / 4, 256, 0, st>>>(a);
 }
 
 hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,

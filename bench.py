@@ -388,7 +388,10 @@ def bench_batch(args, hqa, torch):
     st = torch.cuda.current_stream()
     sched = hqa.make_schedule(Tt, W)
     probs = [hqa.Problem(J, storage="bf16" if s[0] == "sk" else "fp8") for J, s in zip(Js, specs)]
-    md = hqa.MD(probs, sched, Rr, "bf16", seed=BATCH_SEED, stream=st.cuda_stream)
+    # each run's 5000 step launches are replayed from one captured HIP graph (captured in
+    # the untimed warm-up; --eager launches them one by one)
+    md = hqa.MD(probs, sched, Rr, "bf16", seed=BATCH_SEED, stream=st.cuda_stream,
+                graph=not args.eager)
     # exactness of the FP8 storage of the unit weights, and the BF16 rounding of SK
     jerr = {"er_fp8_exact": True, "sk_bf16_max_rel": 0.0}
     for J, s in zip(Js, specs):
@@ -455,7 +458,8 @@ def bench_batch(args, hqa, torch):
         "config": {"workload": BATCH_WORKLOAD if Kn == 512 and Tt == BATCH_T else
                    f"{Kn} uneven instances, R={Rr}, T={Tt}", "instances": Kn, "replicas": Rr,
                    "md_steps": Tt, "n_amb": BATCH_N_AMB, "j_storage": "bf16 (SK) / fp8 (ER)",
-                   "spin_updates_per_run": upd_run, "parallelism": "none (1 GPU)"},
+                   "spin_updates_per_run": upd_run, "parallelism": "none (1 GPU)",
+                   "launch": "eager" if args.eager else "one HIP graph per run"},
         "md_only_spin_updates_per_s": upd_run / (np.mean(md_ms) / 1e3),
         "j_storage_error": jerr,
         "max_abs_dh": {"measure": "per instance max|u_form - u_64| / max|u_64| (and absolute) on "
@@ -934,6 +938,8 @@ def main():
                     help="seeds of the plain FP32 comparison (the first of the timed seeds)")
     ap.add_argument("--detail", default="", help="write per-instance cuts and errors here")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="batch: launch the MD steps one by one instead of replaying a graph")
     ap.add_argument("--pin", default="",
                     help="TM,TN,CB[,TILED]: fixed per-step block instead of tuning")
     args = ap.parse_args()

@@ -540,9 +540,11 @@ def bench_es(args, hqa, torch):
     """Learned early stop on sparse ER MAX-CUT: train on runs of the method itself
     (N ~ U{1000..4000}, mean degree ~ U[20, 100], T = 20000, checkpoints every K = 1000
     steps with statistics sampled every 10th step of the last Ks = 100 steps before each),
-    calibrate the stop threshold on validation runs, then evaluate on
-    ER N = 10^4, p = 0.005 (mean degree ~50), R = 128: stop step, mislabel rate and
-    best cut against the full run, and the truncation ablation at the same step."""
+    calibrate the stop threshold on validation runs (by default: the smallest threshold
+    at which the read-out at the stop loses at most --es-target-cut of the full run's best
+    cut on every validation run), then evaluate on ER N = 10^4, p = 0.005 (mean degree
+    ~50), R = 128: stop step, mislabel rate and best cut against the full run, and the
+    truncation ablation at the same step."""
     from paper_2004_03972_amd import early_stop as E
     from paper_2004_03972_amd import instances as inst
     Tt, K, Ks = 20000, args.es_k, args.es_ks
@@ -564,8 +566,9 @@ def bench_es(args, hqa, torch):
         rec = E.record_run(hqa.Problem(row_ptr=rp, col=ci, val=v), sched, Rt if train else 4,
                            K, nck, seed=100 + k, n_amb=n_lab, every=2 if train else 1, Ks=Ks,
                            stride=args.es_stride, keep=args.es_keep if train else 1.0,
-                           keep_seed=k, means=not train)
-        rec.md.close()
+                           keep_seed=k, means=not train, solve_n=0 if train else 20)
+        if train:
+            rec.md.close()                    # validation handles stay open for calibration
         recs.append(rec)
         if k % 32 == 31:
             _log(f"  recorded {k + 1} instances, {time.perf_counter() - t0:.1f} s")
@@ -575,7 +578,19 @@ def bench_es(args, hqa, torch):
     t1 = time.perf_counter()
     losses = E.train(es, X, y, epochs=2, batch=16384, lr=2e-3, log=_log)
     train_s = time.perf_counter() - t1
-    thr = E.calibrate(es, recs[ntrain:], target_mislabel=args.es_target)
+    # the threshold: on the validation runs, the read-out at the stop loses at most
+    # --es-target-cut of the full run's best cut (default), or the labels at the stop are
+    # wrong for at most --es-target of the spins
+    if args.es_calibrate == "cut":
+        thr = E.calibrate_cut(es, recs[ntrain:], target_loss=args.es_target_cut, n_amb=20)
+        calib = {"by": "cut loss of the read-out at the stop", "target": args.es_target_cut,
+                 "validation_runs": 4 * nval}
+    else:
+        thr = E.calibrate(es, recs[ntrain:], target_mislabel=args.es_target)
+        calib = {"by": "mislabel rate at the stop", "target": args.es_target,
+                 "validation_runs": 4 * nval}
+    for rec in recs[ntrain:]:
+        rec.md.close()
     _log(f"  trained on {X.shape[0]} samples in {train_s:.1f} s, threshold {thr:.4f}")
     # evaluation instance: ER N = 10^4, p = 0.005
     Ne, Re = 10000, 128
@@ -610,7 +625,7 @@ def bench_es(args, hqa, torch):
             "train_runs": ntrain * Rt, "record_s": record_s,
             "train_samples": int(X.shape[0]), "train_s": train_s,
             "loss_first_last": [float(np.mean(losses[:20])), float(np.mean(losses[-20:]))],
-            "threshold": thr, "target_mislabel": args.es_target,
+            "threshold": thr, "calibration": calib,
             "stop_step": res.stop_step, "speedup_steps": Tt / res.stop_step,
             "wall_ms_full": full_ms, "wall_ms_early": es_ms, "speedup_wall": full_ms / es_ms,
             "mislabel": {"network": res.mislabel, "truncation_same_step": res.mislabel_ablation},
@@ -927,7 +942,11 @@ def main():
     ap.add_argument("--es-train", type=int, default=48)
     ap.add_argument("--es-train-r", type=int, default=4)
     ap.add_argument("--es-keep", type=float, default=1.0)
-    ap.add_argument("--es-target", type=float, default=0.03)
+    ap.add_argument("--es-target", type=float, default=0.03,
+                    help="es --es-calibrate mislabel: largest mislabel rate at the stop")
+    ap.add_argument("--es-calibrate", choices=["cut", "mislabel"], default="cut")
+    ap.add_argument("--es-target-cut", type=float, default=1e-3,
+                    help="es --es-calibrate cut: largest relative cut loss at the stop")
     ap.add_argument("--es-k", type=int, default=1000)
     ap.add_argument("--es-ks", type=int, default=100)
     ap.add_argument("--es-stride", type=int, default=10)

@@ -120,11 +120,26 @@ def confidence(prob: np.ndarray) -> float:
     return float(prob.reshape(-1, 3).max(axis=1).mean())
 
 
+def pick_threshold(per, target: float, cands=None) -> float:
+    """Smallest threshold c such that, for every validation run, stopping at the first
+    checkpoint whose confidence is >= c costs at most `target`.  per[run] lists
+    (confidence, cost) per checkpoint in step order; a run with no such checkpoint runs
+    to T, which costs 0.  inf if no candidate meets the target."""
+    cands = np.linspace(0.50, 0.999, 200) if cands is None else cands
+    for c in cands:
+        worst = 0.0
+        for rows in per:
+            hit = [cost for conf, cost in rows if conf >= c]
+            worst = max(worst, hit[0] if hit else 0.0)
+        if worst <= target:
+            return float(c)
+    return float("inf")
+
+
 def calibrate(es, records, target_mislabel: float = 0.02, bf16: bool = True) -> float:
     """Smallest threshold c such that, on validation runs, stopping at the first
     checkpoint with confidence >= c gives a mislabel rate <= target (inf if none).
     Each record's labels fix its number of ambivalent spins per replica."""
-    cands = np.linspace(0.50, 0.999, 200)
     per = []
     for rec in records:
         n_lab = int(np.sum(rec.labels[0] == 2))
@@ -134,15 +149,28 @@ def calibrate(es, records, target_mislabel: float = 0.02, bf16: bool = True) -> 
             mis = float(np.mean(labels_from_probs(pr, n_lab) != rec.labels))
             rows.append((confidence(pr), mis))
         per.append(rows)
-    for c in cands:
-        worst = 0.0
-        for rows in per:
-            hit = [m for conf, m in rows if conf >= c]
-            mis = hit[0] if hit else 0.0          # no stop: the full run, no mislabel
-            worst = max(worst, mis)
-        if worst <= target_mislabel:
-            return float(c)
-    return float("inf")
+    return pick_threshold(per, target_mislabel)
+
+
+def calibrate_cut(es, records, target_loss: float = 1e-3, n_amb: int | None = None,
+                  bf16: bool = True) -> float:
+    """Smallest threshold c such that, on validation runs, the read-out at the first
+    checkpoint with confidence >= c (frozen spins from the predicted signs, the n_amb
+    most ambivalent solved exactly) loses at most target_loss of the full run's best cut
+    (inf if none).  The records' handles must still be open (the read-out uses their
+    couplings) and their `full` read-outs must have solved spins exactly (n_amb defaults
+    to the number they solved)."""
+    per = []
+    for rec in records:
+        best = float(rec.full["cut"].max())
+        n = rec.full["amb_idx"].shape[1] if n_amb is None else n_amb
+        rows = []
+        for f in rec.feats:
+            pr = es.predict(f.reshape(-1, 12), bf16=bf16).reshape(f.shape[0], f.shape[1], 3)
+            cut = float(rec.md.classify(n, solve=True, prob=pr)["cut"].max())
+            rows.append((confidence(pr), max(0.0, (best - cut) / abs(best)) if best else 0.0))
+        per.append(rows)
+    return pick_threshold(per, target_loss)
 
 
 def truncation_probs(m: np.ndarray) -> np.ndarray:

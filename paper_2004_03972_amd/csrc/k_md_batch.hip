@@ -1,15 +1,14 @@
 // k_md_batch.hip -- one MD step of many dense instances in one launch.
 //
 // A batch of uneven instances (sizes N_k, one shared schedule and replica count)
-// advances step by step; each step is one launch per storage type over a tile
-// table.  FP32 storage: a tile is (instance, 32 rows, 64 replicas): wavefront w takes rows
-// i0 + 16 (w & 1) and the two replica tiles r0 + 32 (w >> 1) + {0, 16}, so every
-// J fragment it loads feeds two MFMA tiles and, with 64 replicas, each J row
-// block is read once per step.  The tile table is ordered longest-first (LPT by
-// padded size), so the largest instances start first and the short tiles fill
-// the tail of the step.  The field uses the chunk-to-chain decomposition of the
-// other dense kernels, and the update the same binary32 sequence, so a batched
-// instance evolves bit-identically to the same instance run alone.
+// advances step by step; each step is one launch over a tile table of (instance, 128
+// rows, 64 replicas) tiles, whatever the storage type (FP32, BF16, FP8), so with 64
+// replicas each J row block is read once per step.  The tiles of an instance share
+// one XCD, and instances are placed longest-first (LPT by padded size), so the largest
+// instances start first and the short tiles fill the tail of the step.  The field
+// uses the chunk-to-chain decomposition of the other dense kernels, and the update
+// the same binary32 sequence, so a batched instance evolves bit-identically to the
+// same instance run alone.
 #include <algorithm>
 #include <type_traits>
 
@@ -55,140 +54,6 @@ struct BatchArgs {
     const float *a32, *b32;
     int32_t *err;
 };
-
-template <int JT>
-__global__ __launch_bounds__(256) void k_step_batch(BatchArgs a, int64_t q) {
-    const BatchTile tl = a.tiles[blockIdx.x];
-    const BatchInst I = a.inst[tl.inst];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kg = lane >> 4;
-    const int i0 = tl.i0 + 16 * (w & 1);
-    const int rb = tl.r0 + 32 * (w >> 1);         // first of the wavefront's two replica tiles
-    if (i0 >= I.N || rb >= a.R) return;           // rows all padding: nothing is written
-    const int row = i0 + (lane & 15);
-    const float *phi_in = I.phi[a.cur];
-    const bf16 *xb_in = I.xb[a.cur];
-    f32x4 acc[2][4];
-#pragma unroll
-    for (int c = 0; c < 2; c++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[c][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    // replica columns of the two tiles (clamped to valid rows of the state array;
-    // columns >= R only feed accumulators that are never stored)
-    int colr[2];
-#pragma unroll
-    for (int c = 0; c < 2; c++) colr[c] = min(rb + 16 * c + (lane & 15), a.R - 1);
-    if constexpr (JT == JT_F32) {
-        const float *Ja = (const float *)I.J + (int64_t)row * I.Np + 4 * kg;
-        const int ngroups = I.Np / 64;
-        for (int gi = 0; gi < ngroups; gi++) {
-            float4 A[4], B[2][4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int kk = gi * 64 + 16 * j;
-                A[j] = *(const float4 *)(Ja + kk);
-#pragma unroll
-                for (int c = 0; c < 2; c++)
-                    B[c][j] = *(const float4 *)(phi_in + (int64_t)colr[c] * I.ld + kk + 4 * kg);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-#pragma unroll
-                for (int c = 0; c < 2; c++) {
-                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].x, B[c][j].x, acc[c][j], 0, 0, 0);
-                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].y, B[c][j].y, acc[c][j], 0, 0, 0);
-                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].z, B[c][j].z, acc[c][j], 0, 0, 0);
-                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[j].w, B[c][j].w, acc[c][j], 0, 0, 0);
-                }
-        }
-    } else {
-        // A fragments from the MFMA-tiled copy of J: the four chunks of group gi of this
-        // row tile are one contiguous 32-byte (FP8) or 64-byte (BF16) run per lane, so
-        // each 16-byte load fills whole cache lines
-        typedef typename std::conditional<JT == JT_BF16, bf16x8, uint2>::type AT;
-        constexpr int lane_bytes = JT == JT_BF16 ? 64 : 32;
-        const uint8_t *Jt = (const uint8_t *)I.Jt +
-                            ((int64_t)(i0 / 16) * I.nrounds * 64 + lane) * lane_bytes;
-        const int ngroups = I.Np / 128;
-        AT A[4], An[4];
-        bf16x8 B[2][4], Bn[2][4];
-        auto load = [&](int gi, AT (&Ag)[4], bf16x8 (&Bg)[2][4]) {
-            const uint8_t *src = Jt + (int64_t)gi * 64 * lane_bytes;
-            if constexpr (JT == JT_BF16) {
-#pragma unroll
-                for (int j = 0; j < 4; j++) Ag[j] = *(const bf16x8 *)(src + 16 * j);
-            } else {
-                const uint4 lo = *(const uint4 *)src, hi = *(const uint4 *)(src + 16);
-                Ag[0] = make_uint2(lo.x, lo.y); Ag[1] = make_uint2(lo.z, lo.w);
-                Ag[2] = make_uint2(hi.x, hi.y); Ag[3] = make_uint2(hi.z, hi.w);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int kk = gi * 128 + 32 * j;
-#pragma unroll
-                for (int c = 0; c < 2; c++)
-                    Bg[c][j] = *(const bf16x8 *)(xb_in + (int64_t)colr[c] * I.ld + kk + 8 * kg);
-            }
-        };
-        load(0, A, B);
-        for (int gi = 0; gi < ngroups; gi++) {
-            if (gi + 1 < ngroups) load(gi + 1, An, Bn);
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                bf16x8 av;
-                if constexpr (JT == JT_BF16) av = A[j];
-                else av = cvt_fp8x8_b(A[j]);
-#pragma unroll
-                for (int c = 0; c < 2; c++)
-                    acc[c][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, B[c][j], acc[c][j], 0, 0, 0);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                A[j] = An[j];
-#pragma unroll
-                for (int c = 0; c < 2; c++) B[c][j] = Bn[c][j];
-            }
-        }
-    }
-    const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
-    const int ib = i0 + 4 * kg;
-    const bool win = q + 1 >= a.T - a.W + 1;
-    bool bad = false;
-    float *phi_out = I.phi[a.cur ^ 1];
-    bf16 *xb_out = I.xb[a.cur ^ 1];
-#pragma unroll
-    for (int c = 0; c < 2; c++) {
-        const int col = rb + 16 * c + (lane & 15);
-        if (col >= a.R || ib >= I.N) continue;
-        const f32x4 u = combine4(acc[c]);
-        const int64_t base = (int64_t)col * I.ld + ib;
-        float4 x = *(const float4 *)(phi_in + base);
-        float4 p = *(const float4 *)(I.p + base);
-        float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w}, xn[4];
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-            if (ib + v < I.N) {
-                leapfrog(cf, xs[v], u[v], I.h[ib + v], ps[v], xn[v]);
-                bad |= !isfinite(xn[v]) || !isfinite(ps[v]);
-            } else {
-                xn[v] = 0.0f;
-                ps[v] = 0.0f;
-            }
-        }
-        *(float4 *)(phi_out + base) = make_float4(xn[0], xn[1], xn[2], xn[3]);
-        *(float4 *)(I.p + base) = make_float4(ps[0], ps[1], ps[2], ps[3]);
-        if (xb_out) {
-            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-            bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
-            *(bf16x4 *)(xb_out + base) = b;
-        }
-        if (win) {
-            float4 s = *(const float4 *)(I.S + base);
-            s.x = s.x + xn[0]; s.y = s.y + xn[1]; s.z = s.z + xn[2]; s.w = s.w + xn[3];
-            *(float4 *)(I.S + base) = s;
-        }
-    }
-    if (bad) atomicOr(a.err, ERR_NONFINITE);
-}
 
 // BF16 / FP8 storage: tiles of 128 rows x 64 replicas, eight wavefronts, wavefront w
 // owning row tile i0 + 16 w and all four replica tiles.  Per 128-column group the
@@ -401,6 +266,175 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
     }
 }
 
+// FP32 storage: the same tiles, staging, prefetch and epilogue as batch_lds_tile, with
+// FP32 couplings read row-major (four 16-byte words per lane per group of 64 columns),
+// the FP32 flux block staged in LDS (64 replicas x 64 columns), and 16x16x4 FP32 MFMAs:
+// chunk j of 16 columns feeds chain j, its four MFMAs taking columns 4 kg + e, e = 0..3,
+// in that order -- the operand order of every FP32 dense plan (bit-identical results).
+__device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, const BatchTile &tl,
+                                               const BatchInst &I,
+                                               bf16 (&Bsh)[2][BL_REPS][BL_LDB]) {
+    typedef float BsRow[BL_LDB / 2];
+    BsRow *Bs0 = (BsRow *)&Bsh[0][0][0];
+    BsRow *Bs1 = (BsRow *)&Bsh[1][0][0];
+    const int tid = threadIdx.x, lane = tid & 63, kg = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i0 = tl.i0 + 16 * w;
+    const bool active = i0 < I.N;
+    const int r0 = tl.r0;
+    // buffers of the current parity, chosen without run-time indexing of the table
+    const bool odd = a.cur != 0;
+    const float *phi_in = odd ? I.phi[1] : I.phi[0];
+    float *phi_out = odd ? I.phi[0] : I.phi[1];
+    bf16 *xb_out = odd ? I.xb[0] : I.xb[1];
+    const int ngroups = I.Np / 64;
+    constexpr int NA = 4;                              // 16-byte words of J per lane and group
+    // row-major FP32 couplings with pitch Np: rows up to Np - 1 exist (zero padding), so
+    // a wavefront whose rows are all padding reads zeros (its results are never stored)
+    const auto *Jt = gld<u32x4_b>((const float *)I.J + (int64_t)(i0 + (lane & 15)) * I.Np + 4 * kg);
+    // staging: thread -> (replica row, 8-column segment) of the 64 x 64 FP32 block
+    const int srow = tid >> 3, sseg = tid & 7;
+    const auto *Bsrc = gld<u32x4_b>(phi_in + (int64_t)min(r0 + srow, a.R - 1) * I.ld + 8 * sseg);
+    u32x4_b *Bdst0 = (u32x4_b *)&Bs0[srow][8 * sseg];
+    u32x4_b *Bdst1 = (u32x4_b *)&Bs1[srow][8 * sseg];
+
+    // The epilogue's fluxes and momenta are requested now, so their latency is hidden
+    // behind the groups: thread (replica t / 8, j = t % 8) takes rows 32 v + 4 j .. + 3
+    // of replica r0 + t / 8 (clamped to a real replica; rows up to i0 + 127 < Np exist).
+    const int rep = tid >> 3, j8 = tid & 7;
+    f32x4 ex[4], epm[4];
+    {
+        const int64_t cbase = (int64_t)min(r0 + rep, a.R - 1) * I.ld + tl.i0 + 4 * j8;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            ex[v] = *gld<f32x4>(phi_in + cbase + 32 * v);
+            epm[v] = *gld<f32x4>(I.p + cbase + 32 * v);
+        }
+    }
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[rt][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    // Three register sets used in turn (the loop is unrolled by three): the couplings
+    // of group g + 2 and the fluxes of group g + 3 are requested when group g begins, so
+    // a group's couplings have two groups of time to arrive and its fluxes three.
+    u32x4_b A0[NA], A1[NA], A2[NA];
+    u32x4_b S0a, S0b, S1a, S1b, S2a, S2b;
+#define HQA_LOAD_J(g, A)                                                              \
+    do {                                                                              \
+        _Pragma("unroll") for (int j = 0; j < NA; j++) A[j] = Jt[(int64_t)(g) * 16 + 4 * j]; \
+    } while (0)
+#define HQA_LOAD_S(g, Sa, Sb)                                                         \
+    do {                                                                              \
+        Sa = Bsrc[16 * (g)];                                                          \
+        Sb = Bsrc[16 * (g) + 1];                                                      \
+    } while (0)
+#define HQA_MFMA_GROUP(buf, A)                                                        \
+    do {                                                                              \
+        _Pragma("unroll") for (int j = 0; j < 4; j++) {                              \
+            const f32x4 av = __builtin_bit_cast(f32x4, A[j]);                         \
+            f32x4 bv[4];                                                              \
+            _Pragma("unroll") for (int rt = 0; rt < 4; rt++)                         \
+                bv[rt] = *(const f32x4 *)&((buf) ? Bs1 : Bs0)[16 * rt + (lane & 15)][16 * j + 4 * kg]; \
+            _Pragma("unroll") for (int rt = 0; rt < 4; rt++)                         \
+                _Pragma("unroll") for (int e = 0; e < 4; e++)                        \
+                    acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[rt][e], acc[rt][j], 0, 0, 0); \
+        }                                                                             \
+    } while (0)
+    const int gl = ngroups - 1;
+    HQA_LOAD_J(0, A0);
+    HQA_LOAD_S(0, S0a, S0b);
+    HQA_LOAD_J(min(1, gl), A1);
+    HQA_LOAD_S(min(1, gl), S1a, S1b);
+    HQA_LOAD_S(min(2, gl), S2a, S2b);
+    Bdst0[0] = S0a;
+    Bdst0[1] = S0b;
+    __syncthreads();
+    // group g: couplings in set g % 3, fluxes in LDS buffer g % 2
+#define HQA_BODY(g, Ag, An2, Sn3a, Sn3b, Sn1a, Sn1b)                                  \
+    do {                                                                              \
+        HQA_LOAD_J(min((g) + 2, gl), An2);                                            \
+        HQA_LOAD_S(min((g) + 3, gl), Sn3a, Sn3b);                                     \
+        __builtin_amdgcn_sched_barrier(0);                                            \
+        HQA_MFMA_GROUP((g) & 1, Ag);                                                  \
+        u32x4_b *dst = ((g) & 1) ? Bdst0 : Bdst1;                                     \
+        dst[0] = Sn1a;                                                                \
+        dst[1] = Sn1b;                                                                \
+        __syncthreads();                                                              \
+    } while (0)
+    for (int gi = 0; gi < ngroups; gi += 3) {
+        HQA_BODY(gi, A0, A2, S0a, S0b, S1a, S1b);
+        if (gi + 1 >= ngroups) break;
+        HQA_BODY(gi + 1, A1, A0, S1a, S1b, S2a, S2b);
+        if (gi + 2 >= ngroups) break;
+        HQA_BODY(gi + 2, A2, A1, S2a, S2b, S0a, S0b);
+    }
+#undef HQA_BODY
+#undef HQA_LOAD_J
+#undef HQA_LOAD_S
+#undef HQA_MFMA_GROUP
+
+    // Epilogue with full-line accesses: the fields pass through LDS (the flux stages
+    // are free after the last barrier), and thread (replica t / 8, j = t % 8) updates
+    // rows 32 v + 4 j .. 32 v + 4 j + 3 for v = 0..3, so the eight threads of a replica
+    // read and write one whole 128-byte line of fluxes and momenta per instruction.
+    {
+        float *U = (float *)&Bsh[0][0][0];                 // [64 replicas][136]
+        constexpr int UL = 136;
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) {
+            const f32x4 parts[4] = {acc[rt][0], acc[rt][1], acc[rt][2], acc[rt][3]};
+            const f32x4 u = combine4(parts);
+            *(f32x4 *)&U[(16 * rt + (lane & 15)) * UL + 16 * w + 4 * kg] = u;
+        }
+        __syncthreads();
+        const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
+        const bool win = q + 1 >= a.T - a.W + 1;
+        bool bad = false;
+        const auto *hg = gld<float>(I.h);
+        const int col = r0 + rep;
+        if (col < a.R) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int loc = 32 * v + 4 * j8;
+                const int ib = tl.i0 + loc;
+                if (ib >= I.N) continue;
+                const f32x4 u = *(const f32x4 *)&U[rep * UL + loc];
+                const int64_t base = (int64_t)col * I.ld + ib;
+                const f32x4 x = ex[v];
+                const f32x4 p = epm[v];
+                float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    if (ib + e < I.N) {
+                        leapfrog(cf, xs[e], u[e], hg[ib + e], ps[e], xn[e]);
+                        bad |= !isfinite(xn[e]) || !isfinite(ps[e]);
+                    } else {
+                        xn[e] = 0.0f;
+                        ps[e] = 0.0f;
+                    }
+                }
+                *gst<f32x4>(phi_out + base) = (f32x4){xn[0], xn[1], xn[2], xn[3]};
+                *gst<f32x4>(I.p + base) = (f32x4){ps[0], ps[1], ps[2], ps[3]};
+                if (xb_out) {   // an operand copy exists only when a BF16 plan may read it
+                    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+                    bf16x4 b = {(bf16)xn[0], (bf16)xn[1], (bf16)xn[2], (bf16)xn[3]};
+                    *gst<bf16x4>(xb_out + base) = b;
+                }
+                if (win) {
+                    f32x4 s = *gld<f32x4>(I.S + base);
+                    s[0] = s[0] + xn[0]; s[1] = s[1] + xn[1]; s[2] = s[2] + xn[2]; s[3] = s[3] + xn[3];
+                    *gst<f32x4>(I.S + base) = s;
+                }
+            }
+        }
+        if (bad) atomicOr(a.err, ERR_NONFINITE);
+    }
+}
+
 // One launch per MD step for every BF16 and FP8 instance of the batch: the storage
 // type is uniform per tile.  A tile with instance index -1 is a placeholder of the
 // XCD placement and does nothing.
@@ -411,6 +445,15 @@ __global__ __launch_bounds__(512, 2) void k_step_batch_lds(BatchArgs a, int64_t 
     const BatchInst I = a.inst[tl.inst];
     if (I.jt == JT_FP8) batch_lds_tile<JT_FP8>(a, q, tl, I, Bs);
     else batch_lds_tile<JT_BF16>(a, q, tl, I, Bs);
+}
+
+// The same for the FP32 instances of the batch (their own tile table and launch).
+__global__ __launch_bounds__(512, 2) void k_step_batch_f32(BatchArgs a, int64_t q) {
+    __shared__ __align__(16) bf16 Bs[2][BL_REPS][BL_LDB];
+    const BatchTile tl = a.tiles[blockIdx.x];
+    if (tl.inst < 0) return;
+    const BatchInst I = a.inst[tl.inst];
+    batch_f32_tile(a, q, tl, I, Bs);
 }
 
 // Device tables of a batch, built once per handle: instance descriptors and the
@@ -473,42 +516,39 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
         return md->inst[x].Np > md->inst[y].Np;
     });
     std::vector<BatchTile> ht[3];
-    // FP32 storage: 32-row tiles, longest first
-    for (int k : dense) {
-        const Instance &I = md->inst[k];
-        if (I.jt != JT_F32) continue;
-        for (int i0 = 0; i0 < I.N; i0 += 32)
-            for (int r0 = 0; r0 < md->R; r0 += 64) ht[JT_F32].push_back({k, i0, r0, 0});
-    }
-    // BF16 / FP8 storage: every tile of an instance on one XCD (workgroup b of a
-    // launch runs on XCD b mod 8), so the instance's flux operand is fetched into one
-    // L2; instances go to the least-loaded XCD, largest first (LPT on the tile count,
-    // i.e. on N^2 R work); the per-XCD lists are interleaved into the launch order
-    // and padded with placeholder tiles.  An instance with at least an eighth of all
-    // the work is split instead: its row blocks are cut into eight contiguous ranges,
-    // one per XCD, each with all replica tiles, so every XCD reads an eighth of J and
-    // the 64-replica tiles of a row block share its J lines in one L2.
-    {
+    // Every tile of an instance on one XCD (workgroup b of a launch runs on XCD b mod 8),
+    // so the instance's flux operand is fetched into one L2; instances go to the
+    // least-loaded XCD, largest first (LPT on the tile count, i.e. on N^2 R work); the
+    // per-XCD lists are interleaved into the launch order and padded with placeholder
+    // tiles.  An instance with at
+    // least an eighth of all the work is split instead: its row blocks are cut into
+    // eight contiguous ranges, one per XCD, each with all replica tiles, so every XCD
+    // reads an eighth of J and the 64-replica tiles of a row block share its J lines in
+    // one L2.
+    // one launch for the FP32 instances, one for the BF16 and FP8 ones
+    for (int fam = 0; fam < 2; fam++) {
+        auto member = [&](const Instance &I) { return (I.jt == JT_F32) == (fam == 0); };
         constexpr int NX = 8;
         std::vector<BatchTile> xl[NX];
         int64_t load[NX] = {0};
         int64_t total = 0;
         for (int k : dense) {
             const Instance &I = md->inst[k];
-            if (I.jt == JT_F32) continue;
+            if (!member(I)) continue;
             total += (int64_t)((I.N + BL_ROWS - 1) / BL_ROWS) * ((md->R + 63) / 64) * I.Np;
         }
         for (int k : dense) {
             const Instance &I = md->inst[k];
-            if (I.jt == JT_F32) continue;
+            if (!member(I)) continue;
             const int nrb = (I.N + BL_ROWS - 1) / BL_ROWS;
-            const int64_t work = (int64_t)nrb * ((md->R + 63) / 64) * I.Np;
+            const int64_t tw = (int64_t)I.Np;      // work of a tile ~ its row length
+            const int64_t work = (int64_t)nrb * ((md->R + 63) / 64) * tw;
             if (nrb >= NX && NX * work >= total) {
                 for (int x = 0; x < NX; x++) {
                     for (int rb = x * nrb / NX; rb < (x + 1) * nrb / NX; rb++)
                         for (int r0 = 0; r0 < md->R; r0 += 64) {
                             xl[x].push_back({k, rb * BL_ROWS, r0, 0});
-                            load[x] += (int64_t)I.Np;
+                            load[x] += tw;
                         }
                 }
                 continue;
@@ -519,14 +559,15 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
             for (int i0 = 0; i0 < I.N; i0 += BL_ROWS)
                 for (int r0 = 0; r0 < md->R; r0 += 64) {
                     xl[x].push_back({k, i0, r0, 0});
-                    load[x] += (int64_t)I.Np;   // work of a tile ~ its row length
+                    load[x] += tw;
                 }
         }
         size_t longest = 0;
         for (int x = 0; x < NX; x++) longest = std::max(longest, xl[x].size());
+        std::vector<BatchTile> &dst = ht[fam == 0 ? JT_F32 : JT_BF16];
         for (size_t j = 0; j < longest; j++)
             for (int x = 0; x < NX; x++)
-                ht[JT_BF16].push_back(j < xl[x].size() ? xl[x][j] : BatchTile{-1, 0, 0, 0});
+                dst.push_back(j < xl[x].size() ? xl[x][j] : BatchTile{-1, 0, 0, 0});
     }
     hipError_t e = dev_malloc((void **)&bp->dinst, sizeof(BatchInst) * hi.size());
     if (e == hipSuccess)
@@ -561,7 +602,7 @@ static void enqueue_steps(hqa_md *md, const BatchPlan *bp, int64_t q0, int64_t q
             if (!bp->ntiles[t]) continue;
             a.tiles = bp->dtiles[t];
             a.ntiles = bp->ntiles[t];
-            if (t == JT_F32) k_step_batch<JT_F32><<<a.ntiles, 256, 0, st>>>(a, q);
+            if (t == JT_F32) k_step_batch_f32<<<a.ntiles, 512, 0, st>>>(a, q);
             else k_step_batch_lds<<<a.ntiles, 512, 0, st>>>(a, q);   // BF16 and FP8
         }
         cur ^= 1;

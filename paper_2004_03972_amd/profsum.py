@@ -11,8 +11,9 @@ copy of B bytes) and the factor B / (1024 * value) that turns the counter into b
 ``srchash`` prints the SHA-256 of the dense step kernel's sources, stored beside PMC
 figures so that a later reader can tell whether the kernel changed since.  ``isahash``
 prints the SHA-256 of one kernel's gfx950 machine code as built into libhqa.so (its
-instruction text without addresses, plus its kernel descriptor): a host-only edit of a
-shared header leaves it unchanged, any change of the kernel's code does not.
+instruction text without addresses up to its last s_endpgm, plus its kernel
+descriptor): a host-only edit of a shared header, or a change of another kernel, leaves
+it unchanged; any change of the kernel's code does not.
 
   python -m paper_2004_03972_amd.profsum isahash --kernel k_step_batch_lds [--lib PATH]
 """
@@ -112,6 +113,10 @@ def isa_hash(kernel: str, lib: str | None = None) -> str | None:
             return None
         body = [ln.split("//")[0].rstrip() for ln in lines[start:]]
         body = [ln for ln in body if ln.strip()]
+        # the padding after the last s_endpgm depends on what the linker placed next
+        ends = [k for k, ln in enumerate(body) if ln.split() and ln.split()[0] == "s_endpgm"]
+        if ends:
+            body = body[:ends[-1] + 1]
         if len(body) < 2:
             return None
         # the kernel descriptor (register counts, LDS size, launch properties)

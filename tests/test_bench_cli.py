@@ -35,7 +35,7 @@ def test_kernel_code_hash_identifies_one_kernel():
     a = profsum.isa_hash("k_step_batch_lds")
     assert a is not None and len(a) == 64
     assert profsum.isa_hash("k_step_batch_lds") == a
-    b = profsum.isa_hash("k_step_batch<0>")
+    b = profsum.isa_hash("k_energy_mv<64, 1>")
     assert b is not None and b != a
-    assert profsum.isa_hash("k_step_batch") is None          # two kernels match
+    assert profsum.isa_hash("k_energy_mv<") is None          # four instances match
     assert profsum.isa_hash("no_such_kernel_name") is None

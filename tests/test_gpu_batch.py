@@ -69,6 +69,31 @@ def test_batch_equals_individual_runs(H, R):
         a.close()
 
 
+@pytest.mark.parametrize("R", [64, 24])
+def test_f32_batch_equals_individual_runs(H, R):
+    """FP32 storage in the batch kernel (128-row tiles, FP32 flux block in LDS, 16x16x4
+    FP32 MFMAs): every instance of an uneven FP32 batch evolves bit-identically to the
+    same instance run alone on the per-step plan, with ragged row blocks and replica
+    tiles."""
+    sizes = [100, 333, 517, 130]
+    probs = []
+    for k, N in enumerate(sizes):
+        J, h = inst.uniform_glass(N, 600 + k)
+        probs.append(H.Problem(J * 0.1, h=h))
+    T = 150
+    b = H.MD(probs, H.make_schedule(T, 30), R, "f32", seed=6)
+    b.run()
+    b.sync()
+    assert b.last_plan == "batch"
+    for k, p in enumerate(probs):
+        a = H.MD(p, H.make_schedule(T, 30), R, "f32", seed=6, plan="step")
+        a.run()
+        for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM):
+            assert np.array_equal(a.state(w), b.state(w, k)), (k, w)
+        a.close()
+    b.close()
+
+
 def test_batch_fields_all_instances(H):
     import torch
     rng = np.random.default_rng(77)

@@ -60,18 +60,14 @@ struct BatchArgs {
 // flux operand block (64 replicas x 128 columns, BF16) is staged once into LDS by
 // the whole workgroup with full-line loads and shared by the eight row tiles, so it
 // is read from L2 once per 128 rows instead of once per 32; the J fragments come
-// from the MFMA-tiled copy, two groups ahead in registers; the LDS block is double-
+// from the MFMA-tiled copy, one group ahead in registers; the LDS block is double-
 // buffered with one barrier per group.  Chains, operands and epilogue are those of
 // the other dense kernels (bit-identical results).  Wavefronts whose rows are all
 // padding compute on a real row tile, store nothing, and take part in the staging and
-// the barriers.  Registers hold three groups in turn (the loop is unrolled by three,
-// so no set is copied into another): the J fragments of group g + 2 and the flux
-// block of group g + 3 are requested at the start of group g, and the flux block of
-// group g + 1 is stored into the other LDS buffer at its end.  The epilogue's fluxes
-// and momenta are requested before the first group.  The deeper prefetch
-// costs registers (188 VGPRs) but not occupancy: at 146 VGPRs a compute unit already
-// held only one 512-thread workgroup, and the two-deep version took 2.3% longer per
-// step on the 512-instance batch.
+// the barriers.  The kernel is held to 128 VGPRs so that two workgroups share a
+// compute unit: each covers the other's memory waits, tile prologue and epilogue.  On
+// the 512-instance batch that beat one workgroup per CU with a three-deep register
+// prefetch and the epilogue's loads issued early (220 VGPRs) by 4%.
 //
 // Every global access goes through global-address-space pointers.  The buffers come
 // from a table in memory, so plain pointers would be generic (flat) ones, and a flat
@@ -111,7 +107,6 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
     const int tid = threadIdx.x, lane = tid & 63, kg = lane >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i0 = tl.i0 + 16 * w;
-    const bool active = i0 < I.N;
     const int r0 = tl.r0;
     // buffers of the current parity, chosen without run-time indexing of the table
     const bool odd = a.cur != 0;
@@ -123,28 +118,17 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
     constexpr int NA = JT == JT_BF16 ? 4 : 2;          // 16-byte words of J per lane and group
     // the tiled copy holds ceil(N / 16) row tiles: a wavefront whose rows are all
     // padding reads the last real row tile instead (its results are never stored)
+    // (wavefront-uniform bases and 32-bit per-lane offsets: the offsets take one register
+    // each where a per-lane pointer takes two)
     const int jtile = min(i0, I.N - 1) / 16;
-    const auto *Jt = gld<u32x4_b>((const uint8_t *)I.Jt +
-                                  ((int64_t)jtile * I.nrounds * 64 + lane) * (16 * NA));
+    const auto *Jt = gld<u32x4_b>((const uint8_t *)I.Jt + (int64_t)jtile * I.nrounds * 64 * (16 * NA));
+    const int jl = lane * NA;
     // staging: thread -> (replica row, 16-column segment) of the 64 x 128 block
     const int srow = tid >> 3, sseg = tid & 7;
-    const auto *Bsrc = gld<u32x4_b>(xb_in + (int64_t)min(r0 + srow, a.R - 1) * I.ld + 16 * sseg);
+    const auto *Bsrc = gld<u32x4_b>(xb_in + (int64_t)r0 * I.ld);
+    const int sl = ((min(r0 + srow, a.R - 1) - r0) * I.ld + 16 * sseg) / 8;
     u32x4_b *Bdst0 = (u32x4_b *)&Bs[0][srow][16 * sseg];
     u32x4_b *Bdst1 = (u32x4_b *)&Bs[1][srow][16 * sseg];
-
-    // The epilogue's fluxes and momenta are requested now, so their latency is hidden
-    // behind the groups: thread (replica t / 8, j = t % 8) takes rows 32 v + 4 j .. + 3
-    // of replica r0 + t / 8 (clamped to a real replica; rows up to i0 + 127 < Np exist).
-    const int rep = tid >> 3, j8 = tid & 7;
-    f32x4 ex[4], epm[4];
-    {
-        const int64_t cbase = (int64_t)min(r0 + rep, a.R - 1) * I.ld + tl.i0 + 4 * j8;
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-            ex[v] = *gld<f32x4>(phi_in + cbase + 32 * v);
-            epm[v] = *gld<f32x4>(I.p + cbase + 32 * v);
-        }
-    }
 
     f32x4 acc[4][4];
 #pragma unroll
@@ -152,60 +136,55 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[rt][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    // Three register sets used in turn (the loop is unrolled by three): the couplings
-    // of group g + 2 and the fluxes of group g + 3 are requested when group g begins, so
-    // a group's couplings have two groups of time to arrive and its fluxes three.
-    u32x4_b A0[NA], A1[NA], A2[NA];
-    u32x4_b S0a, S0b, S1a, S1b, S2a, S2b;
+    // Two register sets for the couplings, one for the fluxes: the couplings and the
+    // fluxes of group g + 1 are requested when group g begins (the loop is unrolled by
+    // two, so no set is copied into the other).  At 128 VGPRs two workgroups share a CU,
+    // and each covers the other's waits, prologue and epilogue.
+    u32x4_b A0[NA], A1[NA];
+    u32x4_b S0a, S0b;
 #define HQA_LOAD_J(g, A)                                                              \
     do {                                                                              \
-        _Pragma("unroll") for (int j = 0; j < NA; j++) A[j] = Jt[(int64_t)(g) * 64 * NA + j]; \
+        _Pragma("unroll") for (int j = 0; j < NA; j++) A[j] = Jt[(g) * 64 * NA + jl + j]; \
     } while (0)
 #define HQA_LOAD_S(g, Sa, Sb)                                                         \
     do {                                                                              \
-        Sa = Bsrc[16 * (g)];                                                          \
-        Sb = Bsrc[16 * (g) + 1];                                                      \
+        Sa = Bsrc[sl + 16 * (g)];                                                     \
+        Sb = Bsrc[sl + 16 * (g) + 1];                                                 \
     } while (0)
 #define HQA_MFMA_GROUP(buf, A)                                                        \
     do {                                                                              \
         _Pragma("unroll") for (int j = 0; j < 4; j++) {                              \
             const bf16x8 av = a_chunk<JT>(A, j);                                      \
-            bf16x8 bv[4];                                                             \
-            _Pragma("unroll") for (int rt = 0; rt < 4; rt++)                         \
-                bv[rt] = *(const bf16x8 *)&Bs[buf][16 * rt + (lane & 15)][32 * j + 8 * kg]; \
-            _Pragma("unroll") for (int rt = 0; rt < 4; rt++)                         \
-                acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[rt], acc[rt][j], 0, 0, 0); \
+            _Pragma("unroll") for (int rt = 0; rt < 4; rt++) {                       \
+                const bf16x8 bv = *(const bf16x8 *)&Bs[buf][16 * rt + (lane & 15)][32 * j + 8 * kg]; \
+                acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[rt][j], 0, 0, 0); \
+            }                                                                         \
         }                                                                             \
     } while (0)
     const int gl = ngroups - 1;
-    HQA_LOAD_J(0, A0);
     HQA_LOAD_S(0, S0a, S0b);
-    HQA_LOAD_J(min(1, gl), A1);
-    HQA_LOAD_S(min(1, gl), S1a, S1b);
-    HQA_LOAD_S(min(2, gl), S2a, S2b);
+    HQA_LOAD_J(0, A0);
     Bdst0[0] = S0a;
     Bdst0[1] = S0b;
     __syncthreads();
-    // group g: couplings in set g % 3, fluxes in LDS buffer g % 2
-#define HQA_BODY(g, Ag, An2, Sn3a, Sn3b, Sn1a, Sn1b)                                  \
-    do {                                                                              \
-        HQA_LOAD_J(min((g) + 2, gl), An2);                                            \
-        HQA_LOAD_S(min((g) + 3, gl), Sn3a, Sn3b);                                     \
-        __builtin_amdgcn_sched_barrier(0);                                            \
-        HQA_MFMA_GROUP((g) & 1, Ag);                                                  \
-        u32x4_b *dst = ((g) & 1) ? Bdst0 : Bdst1;                                     \
-        dst[0] = Sn1a;                                                                \
-        dst[1] = Sn1b;                                                                \
-        __syncthreads();                                                              \
-    } while (0)
-    for (int gi = 0; gi < ngroups; gi += 3) {
-        HQA_BODY(gi, A0, A2, S0a, S0b, S1a, S1b);
+    // even groups compute from A0 and LDS buffer 0, odd ones from A1 and buffer 1
+    for (int gi = 0; gi < ngroups; gi += 2) {
+        HQA_LOAD_J(min(gi + 1, gl), A1);
+        HQA_LOAD_S(min(gi + 1, gl), S0a, S0b);
+        __builtin_amdgcn_sched_barrier(0);
+        HQA_MFMA_GROUP(0, A0);
+        Bdst1[0] = S0a;
+        Bdst1[1] = S0b;
+        __syncthreads();
         if (gi + 1 >= ngroups) break;
-        HQA_BODY(gi + 1, A1, A0, S1a, S1b, S2a, S2b);
-        if (gi + 2 >= ngroups) break;
-        HQA_BODY(gi + 2, A2, A1, S2a, S2b, S0a, S0b);
+        HQA_LOAD_J(min(gi + 2, gl), A0);
+        HQA_LOAD_S(min(gi + 2, gl), S0a, S0b);
+        __builtin_amdgcn_sched_barrier(0);
+        HQA_MFMA_GROUP(1, A1);
+        Bdst0[0] = S0a;
+        Bdst0[1] = S0b;
+        __syncthreads();
     }
-#undef HQA_BODY
 #undef HQA_LOAD_J
 #undef HQA_LOAD_S
 #undef HQA_MFMA_GROUP
@@ -228,6 +207,7 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
         const bool win = q + 1 >= a.T - a.W + 1;
         bool bad = false;
         const auto *hg = gld<float>(I.h);
+        const int rep = tid >> 3, j8 = tid & 7;
         const int col = r0 + rep;
         if (col < a.R) {
 #pragma unroll
@@ -237,8 +217,8 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
                 if (ib >= I.N) continue;
                 const f32x4 u = *(const f32x4 *)&U[rep * UL + loc];
                 const int64_t base = (int64_t)col * I.ld + ib;
-                const f32x4 x = ex[v];
-                const f32x4 p = epm[v];
+                const f32x4 x = *gld<f32x4>(phi_in + base);
+                const f32x4 p = *gld<f32x4>(I.p + base);
                 float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
@@ -280,7 +260,6 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
     const int tid = threadIdx.x, lane = tid & 63, kg = lane >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i0 = tl.i0 + 16 * w;
-    const bool active = i0 < I.N;
     const int r0 = tl.r0;
     // buffers of the current parity, chosen without run-time indexing of the table
     const bool odd = a.cur != 0;
@@ -298,31 +277,15 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
     u32x4_b *Bdst0 = (u32x4_b *)&Bs0[srow][8 * sseg];
     u32x4_b *Bdst1 = (u32x4_b *)&Bs1[srow][8 * sseg];
 
-    // The epilogue's fluxes and momenta are requested now, so their latency is hidden
-    // behind the groups: thread (replica t / 8, j = t % 8) takes rows 32 v + 4 j .. + 3
-    // of replica r0 + t / 8 (clamped to a real replica; rows up to i0 + 127 < Np exist).
-    const int rep = tid >> 3, j8 = tid & 7;
-    f32x4 ex[4], epm[4];
-    {
-        const int64_t cbase = (int64_t)min(r0 + rep, a.R - 1) * I.ld + tl.i0 + 4 * j8;
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-            ex[v] = *gld<f32x4>(phi_in + cbase + 32 * v);
-            epm[v] = *gld<f32x4>(I.p + cbase + 32 * v);
-        }
-    }
-
     f32x4 acc[4][4];
 #pragma unroll
     for (int rt = 0; rt < 4; rt++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[rt][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    // Three register sets used in turn (the loop is unrolled by three): the couplings
-    // of group g + 2 and the fluxes of group g + 3 are requested when group g begins, so
-    // a group's couplings have two groups of time to arrive and its fluxes three.
-    u32x4_b A0[NA], A1[NA], A2[NA];
-    u32x4_b S0a, S0b, S1a, S1b, S2a, S2b;
+    // Two register sets for the couplings, one for the fluxes, as in batch_lds_tile.
+    u32x4_b A0[NA], A1[NA];
+    u32x4_b S0a, S0b;
 #define HQA_LOAD_J(g, A)                                                              \
     do {                                                                              \
         _Pragma("unroll") for (int j = 0; j < NA; j++) A[j] = Jt[(int64_t)(g) * 16 + 4 * j]; \
@@ -336,43 +299,36 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
     do {                                                                              \
         _Pragma("unroll") for (int j = 0; j < 4; j++) {                              \
             const f32x4 av = __builtin_bit_cast(f32x4, A[j]);                         \
-            f32x4 bv[4];                                                              \
-            _Pragma("unroll") for (int rt = 0; rt < 4; rt++)                         \
-                bv[rt] = *(const f32x4 *)&((buf) ? Bs1 : Bs0)[16 * rt + (lane & 15)][16 * j + 4 * kg]; \
-            _Pragma("unroll") for (int rt = 0; rt < 4; rt++)                         \
+            _Pragma("unroll") for (int rt = 0; rt < 4; rt++) {                       \
+                const f32x4 bv = *(const f32x4 *)&((buf) ? Bs1 : Bs0)[16 * rt + (lane & 15)][16 * j + 4 * kg]; \
                 _Pragma("unroll") for (int e = 0; e < 4; e++)                        \
-                    acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[rt][e], acc[rt][j], 0, 0, 0); \
+                    acc[rt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[e], bv[e], acc[rt][j], 0, 0, 0); \
+            }                                                                         \
         }                                                                             \
     } while (0)
     const int gl = ngroups - 1;
-    HQA_LOAD_J(0, A0);
     HQA_LOAD_S(0, S0a, S0b);
-    HQA_LOAD_J(min(1, gl), A1);
-    HQA_LOAD_S(min(1, gl), S1a, S1b);
-    HQA_LOAD_S(min(2, gl), S2a, S2b);
+    HQA_LOAD_J(0, A0);
     Bdst0[0] = S0a;
     Bdst0[1] = S0b;
     __syncthreads();
-    // group g: couplings in set g % 3, fluxes in LDS buffer g % 2
-#define HQA_BODY(g, Ag, An2, Sn3a, Sn3b, Sn1a, Sn1b)                                  \
-    do {                                                                              \
-        HQA_LOAD_J(min((g) + 2, gl), An2);                                            \
-        HQA_LOAD_S(min((g) + 3, gl), Sn3a, Sn3b);                                     \
-        __builtin_amdgcn_sched_barrier(0);                                            \
-        HQA_MFMA_GROUP((g) & 1, Ag);                                                  \
-        u32x4_b *dst = ((g) & 1) ? Bdst0 : Bdst1;                                     \
-        dst[0] = Sn1a;                                                                \
-        dst[1] = Sn1b;                                                                \
-        __syncthreads();                                                              \
-    } while (0)
-    for (int gi = 0; gi < ngroups; gi += 3) {
-        HQA_BODY(gi, A0, A2, S0a, S0b, S1a, S1b);
+    for (int gi = 0; gi < ngroups; gi += 2) {
+        HQA_LOAD_J(min(gi + 1, gl), A1);
+        HQA_LOAD_S(min(gi + 1, gl), S0a, S0b);
+        __builtin_amdgcn_sched_barrier(0);
+        HQA_MFMA_GROUP(0, A0);
+        Bdst1[0] = S0a;
+        Bdst1[1] = S0b;
+        __syncthreads();
         if (gi + 1 >= ngroups) break;
-        HQA_BODY(gi + 1, A1, A0, S1a, S1b, S2a, S2b);
-        if (gi + 2 >= ngroups) break;
-        HQA_BODY(gi + 2, A2, A1, S2a, S2b, S0a, S0b);
+        HQA_LOAD_J(min(gi + 2, gl), A0);
+        HQA_LOAD_S(min(gi + 2, gl), S0a, S0b);
+        __builtin_amdgcn_sched_barrier(0);
+        HQA_MFMA_GROUP(1, A1);
+        Bdst0[0] = S0a;
+        Bdst0[1] = S0b;
+        __syncthreads();
     }
-#undef HQA_BODY
 #undef HQA_LOAD_J
 #undef HQA_LOAD_S
 #undef HQA_MFMA_GROUP
@@ -395,6 +351,7 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
         const bool win = q + 1 >= a.T - a.W + 1;
         bool bad = false;
         const auto *hg = gld<float>(I.h);
+        const int rep = tid >> 3, j8 = tid & 7;
         const int col = r0 + rep;
         if (col < a.R) {
 #pragma unroll
@@ -404,8 +361,8 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
                 if (ib >= I.N) continue;
                 const f32x4 u = *(const f32x4 *)&U[rep * UL + loc];
                 const int64_t base = (int64_t)col * I.ld + ib;
-                const f32x4 x = ex[v];
-                const f32x4 p = epm[v];
+                const f32x4 x = *gld<f32x4>(phi_in + base);
+                const f32x4 p = *gld<f32x4>(I.p + base);
                 float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
@@ -438,7 +395,7 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
 // One launch per MD step for every BF16 and FP8 instance of the batch: the storage
 // type is uniform per tile.  A tile with instance index -1 is a placeholder of the
 // XCD placement and does nothing.
-__global__ __launch_bounds__(512, 2) void k_step_batch_lds(BatchArgs a, int64_t q) {
+__global__ __launch_bounds__(512, 4) void k_step_batch_lds(BatchArgs a, int64_t q) {
     __shared__ __align__(16) bf16 Bs[2][BL_REPS][BL_LDB];
     const BatchTile tl = a.tiles[blockIdx.x];
     if (tl.inst < 0) return;
@@ -448,7 +405,7 @@ __global__ __launch_bounds__(512, 2) void k_step_batch_lds(BatchArgs a, int64_t 
 }
 
 // The same for the FP32 instances of the batch (their own tile table and launch).
-__global__ __launch_bounds__(512, 2) void k_step_batch_f32(BatchArgs a, int64_t q) {
+__global__ __launch_bounds__(512, 4) void k_step_batch_f32(BatchArgs a, int64_t q) {
     __shared__ __align__(16) bf16 Bs[2][BL_REPS][BL_LDB];
     const BatchTile tl = a.tiles[blockIdx.x];
     if (tl.inst < 0) return;

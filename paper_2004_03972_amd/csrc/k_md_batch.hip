@@ -138,8 +138,10 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
 
     // Two register sets for the couplings, one for the fluxes: the couplings and the
     // fluxes of group g + 1 are requested when group g begins (the loop is unrolled by
-    // two, so no set is copied into the other).  At 128 VGPRs two workgroups share a CU,
-    // and each covers the other's waits, prologue and epilogue.
+    // two, so no set is copied into the other).  The fluxes are requested first: loads
+    // complete in order, so the wait that lets them go to LDS at the end of group g
+    // leaves the couplings in flight across the barrier.  At 128 VGPRs two workgroups
+    // share a CU, and each covers the other's waits, prologue and epilogue.
     u32x4_b A0[NA], A1[NA];
     u32x4_b S0a, S0b;
 #define HQA_LOAD_J(g, A)                                                              \
@@ -169,16 +171,16 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
     __syncthreads();
     // even groups compute from A0 and LDS buffer 0, odd ones from A1 and buffer 1
     for (int gi = 0; gi < ngroups; gi += 2) {
-        HQA_LOAD_J(min(gi + 1, gl), A1);
         HQA_LOAD_S(min(gi + 1, gl), S0a, S0b);
+        HQA_LOAD_J(min(gi + 1, gl), A1);
         __builtin_amdgcn_sched_barrier(0);
         HQA_MFMA_GROUP(0, A0);
         Bdst1[0] = S0a;
         Bdst1[1] = S0b;
         __syncthreads();
         if (gi + 1 >= ngroups) break;
-        HQA_LOAD_J(min(gi + 2, gl), A0);
         HQA_LOAD_S(min(gi + 2, gl), S0a, S0b);
+        HQA_LOAD_J(min(gi + 2, gl), A0);
         __builtin_amdgcn_sched_barrier(0);
         HQA_MFMA_GROUP(1, A1);
         Bdst0[0] = S0a;
@@ -202,13 +204,26 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
             const f32x4 u = combine4(parts);
             *(f32x4 *)&U[(16 * rt + (lane & 15)) * UL + 16 * w + 4 * kg] = u;
         }
+        // the fluxes and momenta are requested before the barrier (the couplings'
+        // registers are free by now), so their latency overlaps the exchange
+        const int rep = tid >> 3, j8 = tid & 7;
+        const int col = r0 + rep;
+        f32x4 xv[4], pv[4];
+        if (col < a.R) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int ib = tl.i0 + 32 * v + 4 * j8;
+                if (ib >= I.N) continue;
+                const int64_t base = (int64_t)col * I.ld + ib;
+                xv[v] = *gld<f32x4>(phi_in + base);
+                pv[v] = *gld<f32x4>(I.p + base);
+            }
+        }
         __syncthreads();
         const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
         const bool win = q + 1 >= a.T - a.W + 1;
         bool bad = false;
         const auto *hg = gld<float>(I.h);
-        const int rep = tid >> 3, j8 = tid & 7;
-        const int col = r0 + rep;
         if (col < a.R) {
 #pragma unroll
             for (int v = 0; v < 4; v++) {
@@ -217,8 +232,8 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
                 if (ib >= I.N) continue;
                 const f32x4 u = *(const f32x4 *)&U[rep * UL + loc];
                 const int64_t base = (int64_t)col * I.ld + ib;
-                const f32x4 x = *gld<f32x4>(phi_in + base);
-                const f32x4 p = *gld<f32x4>(I.p + base);
+                const f32x4 x = xv[v];
+                const f32x4 p = pv[v];
                 float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
@@ -313,16 +328,16 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
     Bdst0[1] = S0b;
     __syncthreads();
     for (int gi = 0; gi < ngroups; gi += 2) {
-        HQA_LOAD_J(min(gi + 1, gl), A1);
         HQA_LOAD_S(min(gi + 1, gl), S0a, S0b);
+        HQA_LOAD_J(min(gi + 1, gl), A1);
         __builtin_amdgcn_sched_barrier(0);
         HQA_MFMA_GROUP(0, A0);
         Bdst1[0] = S0a;
         Bdst1[1] = S0b;
         __syncthreads();
         if (gi + 1 >= ngroups) break;
-        HQA_LOAD_J(min(gi + 2, gl), A0);
         HQA_LOAD_S(min(gi + 2, gl), S0a, S0b);
+        HQA_LOAD_J(min(gi + 2, gl), A0);
         __builtin_amdgcn_sched_barrier(0);
         HQA_MFMA_GROUP(1, A1);
         Bdst0[0] = S0a;
@@ -346,13 +361,26 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
             const f32x4 u = combine4(parts);
             *(f32x4 *)&U[(16 * rt + (lane & 15)) * UL + 16 * w + 4 * kg] = u;
         }
+        // the fluxes and momenta are requested before the barrier (the couplings'
+        // registers are free by now), so their latency overlaps the exchange
+        const int rep = tid >> 3, j8 = tid & 7;
+        const int col = r0 + rep;
+        f32x4 xv[4], pv[4];
+        if (col < a.R) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int ib = tl.i0 + 32 * v + 4 * j8;
+                if (ib >= I.N) continue;
+                const int64_t base = (int64_t)col * I.ld + ib;
+                xv[v] = *gld<f32x4>(phi_in + base);
+                pv[v] = *gld<f32x4>(I.p + base);
+            }
+        }
         __syncthreads();
         const StepCoef cf = step_coef(a.a32, a.b32, q, a.rg, a.M);
         const bool win = q + 1 >= a.T - a.W + 1;
         bool bad = false;
         const auto *hg = gld<float>(I.h);
-        const int rep = tid >> 3, j8 = tid & 7;
-        const int col = r0 + rep;
         if (col < a.R) {
 #pragma unroll
             for (int v = 0; v < 4; v++) {
@@ -361,8 +389,8 @@ __device__ __forceinline__ void batch_f32_tile(const BatchArgs &a, int64_t q, co
                 if (ib >= I.N) continue;
                 const f32x4 u = *(const f32x4 *)&U[rep * UL + loc];
                 const int64_t base = (int64_t)col * I.ld + ib;
-                const f32x4 x = *gld<f32x4>(phi_in + base);
-                const f32x4 p = *gld<f32x4>(I.p + base);
+                const f32x4 x = xv[v];
+                const f32x4 p = pv[v];
                 float xs[4] = {x[0], x[1], x[2], x[3]}, ps[4] = {p[0], p[1], p[2], p[3]}, xn[4];
 #pragma unroll
                 for (int e = 0; e < 4; e++) {

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 8
+#define HQA_ABI_VERSION 9
 
 typedef enum {
     HQA_OK = 0,
@@ -227,7 +227,8 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step);
 
 /* Restart every instance from tau = 0 without re-uploading J: phi(0) = 0, p(0) = +-1
  * from the counter hash with the given seed (as at init), window sums cleared, the
- * step index set to 0 and the non-finite flag cleared.  Asynchronous. */
+ * step index set to 0 and the non-finite flag cleared.  Asynchronous; kernels only (no
+ * memset), so the call may be recorded into a HIP graph. */
 hqa_status hqa_md_reset(hqa_md *md, uint64_t seed);
 
 /* Wait for queued work; HQA_ENONFINITE if any flux or momentum became non-finite. */
@@ -346,6 +347,29 @@ hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t sol
 hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count,
                              int32_t n_amb, int32_t solve, double *energy, double *cut,
                              int32_t out_mem);
+
+/* One whole pass of the method over every instance of the handle (Methods, molecular
+ * dynamics from tau = 0 to 1, then the read-out of the HQA section): hqa_md_reset(seed),
+ * the steps from 0 to T as hqa_md_run, then for every instance c the read-out of
+ * hqa_classify_many (n_amb, solve 0 or 1) with its R exact energies and cuts written to
+ * the DEVICE arrays energy[c R .. c R + R) and cut[c R .. c R + R) (either may be NULL,
+ * not both).  Results equal those of that sequence of calls bit for bit.  All of it is
+ * enqueued on the handle's stream (the read-outs on up to four side streams of the
+ * handle's own that rejoin it): nothing is synchronised, and after the first call with a
+ * given read-out size nothing is allocated (the scratch, streams and events stay with
+ * the handle until hqa_md_destroy; a larger read-out later waits for the handle's stream
+ * and reallocates).  The caller synchronises (hqa_md_sync reports a non-finite state)
+ * before reading the outputs.  With flags = HQA_MD_GRAPH the pass is captured into one
+ * HIP graph on its first call with these arguments (seed, n_amb, solve, energy, cut and
+ * the flux-buffer parity, which an odd T flips) and replayed by later calls: a replay
+ * reruns every kernel of the pass.  Up to 4 such graphs per handle, least recently used
+ * dropped first.  Graph mode needs every instance dense and on the batch plan (several
+ * dense instances, plan AUTO untuned or tuned to BATCH, no statistics window), else
+ * HQA_EUNSUPPORTED; flags = 0 runs any handle.  Errors as hqa_classify_many, checked for
+ * every instance before any device work; HQA_EINVAL for solve outside {0, 1}, unknown
+ * flags or both outputs NULL. */
+hqa_status hqa_md_pass(hqa_md *md, uint64_t seed, int32_t n_amb, int32_t solve, double *energy,
+                       double *cut, int32_t flags);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): hqa_classify with the same

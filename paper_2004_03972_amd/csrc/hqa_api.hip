@@ -293,6 +293,8 @@ void hqa_md_opts_default(hqa_md_opts *o) {
     o->plan = HQA_PLAN_AUTO;
 }
 
+static void free_pass(void *p);
+
 void hqa_md_destroy(hqa_md *md) {
     if (!md) return;
     if (md->stream || true) (void)hipStreamSynchronize(md->stream);
@@ -300,6 +302,7 @@ void hqa_md_destroy(hqa_md *md) {
     dfree(md->a64); dfree(md->b64); dfree(md->a32); dfree(md->b32);
     dfree(md->err); dfree(md->scratch_i); dfree(md->bar);
     free_batch_plan(md->batch);
+    free_pass(md->pass);
     delete md;
 }
 
@@ -574,16 +577,8 @@ static hipError_t run_csr(hqa_md *md, Instance &I, int64_t q0, int64_t q1, bool 
     return launch_md_steps_csr(md, I, q0, q1);
 }
 
-hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
-    if (!md) return fail(HQA_EINVAL, "null handle");
-    int64_t q1 = until_step < 0 ? md->sch.T : until_step;
-    if (q1 > md->sch.T) return fail(HQA_EINVAL, "until_step beyond T");
-    if (q1 < md->q) return fail(HQA_ESTATE, "until_step %lld is before the current step %lld",
-                                (long long)q1, (long long)md->q);
-    if (q1 == md->q) return HQA_OK;
-    CallTimer tm(md->stream);
-    const int64_t q0 = md->q;
-    md->last_plan = 0;
+// Which way several dense instances advance (the batch plan, or clusters).
+static void multi_ways(const hqa_md *md, int64_t q1, bool *batched, bool *clustered) {
     int ndense = 0;
     for (auto &I : md->inst) ndense += I.layout == HQA_DENSE;
     // steps inside an early-stop statistics window run on the per-step kernels,
@@ -593,10 +588,19 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     const bool multi = md->prec != HQA_PREC_F64_REF && ndense > 1 && !stats_live;
     const int mp = md->plan == HQA_PLAN_AUTO ? (md->multi_plan ? md->multi_plan : HQA_PLAN_BATCH)
                                              : md->plan;
-    const bool batched = multi && md->plan == HQA_PLAN_AUTO && mp == HQA_PLAN_BATCH;
-    const bool clustered = multi && mp == HQA_PLAN_CLUSTER;
+    *batched = multi && md->plan == HQA_PLAN_AUTO && mp == HQA_PLAN_BATCH;
+    *clustered = multi && mp == HQA_PLAN_CLUSTER;
+}
+
+// The steps md->q -> q1 on md->stream; `graph` lets the batch plan replay its cached
+// step graphs.
+static hqa_status run_core(hqa_md *md, int64_t q1, bool graph) {
+    md->last_plan = 0;
+    const bool stats_live = md->stats_k1 > md->q && md->stats_k0 < q1;
+    bool batched = false, clustered = false;
+    multi_ways(md, q1, &batched, &clustered);
     if (batched) {
-        hipError_t e = launch_md_steps_batch(md, md->q, q1, md->flags & HQA_MD_GRAPH);
+        hipError_t e = launch_md_steps_batch(md, md->q, q1, graph);
         if (e != hipSuccess) return fail(dev_status(e), "batch step launch: %s", hipGetErrorString(e));
         md->last_plan = HQA_PLAN_BATCH;
     }
@@ -613,6 +617,20 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
         if (e != hipSuccess) return fail(dev_status(e), "step launch: %s", hipGetErrorString(e));
     }
     md->q = q1;
+    return HQA_OK;
+}
+
+hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    int64_t q1 = until_step < 0 ? md->sch.T : until_step;
+    if (q1 > md->sch.T) return fail(HQA_EINVAL, "until_step beyond T");
+    if (q1 < md->q) return fail(HQA_ESTATE, "until_step %lld is before the current step %lld",
+                                (long long)q1, (long long)md->q);
+    if (q1 == md->q) return HQA_OK;
+    CallTimer tm(md->stream);
+    const int64_t q0 = md->q;
+    const hqa_status rs = run_core(md, q1, md->flags & HQA_MD_GRAPH);
+    if (rs != HQA_OK) return rs;
     const double ms = tm.stop();
     if (ms >= 0.0) {
         static const char *names[] = {"none", "step", "cluster", "resident", "batch"};
@@ -624,18 +642,38 @@ hqa_status hqa_md_run(hqa_md *md, int64_t until_step) {
     return HQA_OK;
 }
 
-hqa_status hqa_md_reset(hqa_md *md, uint64_t seed) {
-    if (!md) return fail(HQA_EINVAL, "null handle");
-    HIPCHK(hipMemsetAsync(md->err, 0, sizeof(int32_t), md->stream));
+// Zeroes n 32-bit words with a kernel rather than a memset, so that a reset can be
+// recorded into a HIP graph.
+__global__ void k_zero_u32(uint32_t *p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+static hipError_t zero_u32(void *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    k_zero_u32<<<(unsigned)blocks, 256, 0, st>>>((uint32_t *)p, n);
+    return hipGetLastError();
+}
+
+// The reset's device work on md->stream: no memset, no synchronisation.
+static hipError_t reset_core(hqa_md *md, uint64_t seed) {
+    hipError_t e = zero_u32(md->err, 1, md->stream);
     for (auto &I : md->inst) {
-        if (md->prec != HQA_PREC_F64_REF) {
+        if (e == hipSuccess && md->prec != HQA_PREC_F64_REF) {
             // padded rows / replicas of both flux buffers must stay zero
             size_t n = I.smaj ? (size_t)I.N * I.ld : (size_t)I.Rp * I.ld;
-            HIPCHK(hipMemsetAsync(I.phi32[I.cur ^ 1], 0, n * 4, md->stream));
+            e = zero_u32(I.phi32[I.cur ^ 1], (int64_t)n, md->stream);
         }
-        HIPCHK(launch_init_state(I, md->R, md->prec, seed, nullptr, nullptr, md->stream));
+        if (e == hipSuccess) e = launch_init_state(I, md->R, md->prec, seed, nullptr, nullptr, md->stream);
     }
     md->q = 0;
+    return e;
+}
+
+hqa_status hqa_md_reset(hqa_md *md, uint64_t seed) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    HIPCHK(reset_core(md, seed));
     return HQA_OK;
 }
 
@@ -1175,7 +1213,7 @@ hqa_status hqa_md_hamiltonian(hqa_md *md, int32_t instance, double *H, int32_t d
 // (solve = 1) or by the tabu search (solve = 2), merge, energies.
 static hqa_status classify_checks(hqa_md *md, int32_t instance, int32_t n_amb, int32_t solve,
                                   const hqa_classify_out *out, const float *prob,
-                                  bool need_spins = true) {
+                                  bool need_spins = true, bool need_T = true) {
     hqa_status s = check_instance(md, instance);
     if (s != HQA_OK) return s;
     if (!out || (need_spins && !out->spins)) return fail(HQA_EINVAL, "out->spins is required");
@@ -1184,7 +1222,7 @@ static hqa_status classify_checks(hqa_md *md, int32_t instance, int32_t n_amb, i
     if (n_amb < 0 || n_amb > N) return fail(HQA_EINVAL, "n_amb must lie in [0, N]");
     if (solve == 1 && n_amb > 24)
         return fail(HQA_EUNSUPPORTED, "exact enumeration limited to n <= 24");
-    if (!prob && md->q != md->sch.T)
+    if (!prob && need_T && md->q != md->sch.T)
         return fail(HQA_ESTATE, "classify needs the run to reach step T");
     if ((solve || out->energy || out->cut || out->h_eff) && !exact_ok(I))
         return fail(HQA_EUNSUPPORTED, "coupling exponents span too many binades for exact sums");
@@ -1768,6 +1806,184 @@ hqa_status hqa_ising_energy(const hqa_problem *prob, const int8_t *spins, int32_
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     free_instance(I);
     if (e != hipSuccess) return fail(dev_status(e), "energy: %s", hipGetErrorString(e));
+    return HQA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One whole pass (reset, every step, the read-out of every instance) as one unit of
+// stream work, optionally captured into a HIP graph and replayed.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int PASS_SIDE = 4;          // side streams of the read-out
+constexpr size_t PASS_MAX_GRAPHS = 4;
+
+struct PassGraph {
+    uint64_t seed;
+    int32_t n_amb, solve;
+    double *E, *C;
+    std::vector<int> cur0, cur1;      // flux-buffer parities before and after the pass
+    hipGraphExec_t exec;
+};
+
+struct PassRes {
+    uint8_t *scratch = nullptr;
+    size_t cap = 0;                   // bytes per side stream
+    hipStream_t side[PASS_SIDE] = {};
+    hipEvent_t ev[PASS_SIDE + 1] = {};
+    hipStream_t cap_stream = nullptr; // capture stream (the handle's stream may be the null stream)
+    std::vector<PassGraph> graphs;    // least recently used first
+};
+}  // namespace
+
+static void drop_pass_graphs(PassRes *pr) {
+    for (auto &g : pr->graphs) (void)hipGraphExecDestroy(g.exec);
+    pr->graphs.clear();
+}
+
+static void free_pass(void *p) {
+    PassRes *pr = (PassRes *)p;
+    if (!pr) return;
+    drop_pass_graphs(pr);
+    for (int k = 0; k < PASS_SIDE; k++) {
+        if (pr->side[k]) (void)hipStreamSynchronize(pr->side[k]);
+        if (pr->side[k]) (void)hipStreamDestroy(pr->side[k]);
+    }
+    for (int k = 0; k <= PASS_SIDE; k++)
+        if (pr->ev[k]) (void)hipEventDestroy(pr->ev[k]);
+    if (pr->cap_stream) (void)hipStreamDestroy(pr->cap_stream);
+    dfree(pr->scratch);
+    delete pr;
+}
+
+// The pass's device work on md->stream: no allocation, no memset, no synchronisation.
+static hqa_status enqueue_pass(hqa_md *md, PassRes *pr, uint64_t seed, int32_t n_amb,
+                               int32_t solve, double *E, double *C) {
+    HIPCHK(reset_core(md, seed));
+    hqa_status s = run_core(md, md->sch.T, false);
+    if (s != HQA_OK) return s;
+    const int32_t count = (int32_t)md->inst.size();
+    const int NS = std::min<int32_t>(count, PASS_SIDE);
+    const int R = md->R;
+    HIPCHK(hipEventRecord(pr->ev[PASS_SIDE], md->stream));
+    for (int k = 0; k < NS; k++) HIPCHK(hipStreamWaitEvent(pr->side[k], pr->ev[PASS_SIDE], 0));
+    for (int32_t c = 0; c < count && s == HQA_OK; c++) {
+        const int k = c % NS;
+        ScratchArena A;
+        A.base = pr->scratch + (size_t)k * pr->cap;
+        A.cap = pr->cap;
+        hqa_classify_out oc{};
+        oc.energy = E ? E + (size_t)c * R : nullptr;
+        oc.cut = C ? C + (size_t)c * R : nullptr;
+        s = classify_core(md, c, n_amb, solve, &oc, HQA_DEVICE, nullptr, HQA_HOST, 0, 0, A, false,
+                          pr->side[k]);
+    }
+    // the side streams rejoin the handle's stream whatever happened above
+    for (int k = 0; k < NS; k++) {
+        HIPCHK(hipEventRecord(pr->ev[k], pr->side[k]));
+        HIPCHK(hipStreamWaitEvent(md->stream, pr->ev[k], 0));
+    }
+    return s;
+}
+
+hqa_status hqa_md_pass(hqa_md *md, uint64_t seed, int32_t n_amb, int32_t solve, double *energy,
+                       double *cut, int32_t flags) {
+    if (!md) return fail(HQA_EINVAL, "null handle");
+    if (!energy && !cut) return fail(HQA_EINVAL, "energy and cut are both NULL");
+    if (solve != 0 && solve != 1) return fail(HQA_EINVAL, "solve must be 0 or 1");
+    if (flags & ~HQA_MD_GRAPH) return fail(HQA_EINVAL, "unknown flags 0x%x", flags);
+    const bool graph = flags & HQA_MD_GRAPH;
+    const int32_t count = (int32_t)md->inst.size();
+    hqa_classify_out o{};
+    o.energy = energy;
+    o.cut = cut;
+    size_t need = 0;
+    for (int32_t c = 0; c < count; c++) {
+        hqa_status s = classify_checks(md, c, n_amb, solve, &o, nullptr, false, false);
+        if (s != HQA_OK) return s;
+        need = std::max(need, classify_scratch_bytes(md->R, md->inst[c].N, n_amb, solve, &o));
+    }
+    if (graph) {
+        bool batched = false, clustered = false;
+        const int64_t q_saved = md->q;
+        md->q = 0;
+        multi_ways(md, md->sch.T, &batched, &clustered);
+        md->q = q_saved;
+        for (auto &I : md->inst) batched = batched && I.layout == HQA_DENSE;
+        if (!batched)
+            return fail(HQA_EUNSUPPORTED, "a captured pass needs every instance on the batch plan");
+    }
+    PassRes *pr = (PassRes *)md->pass;
+    if (!pr) {
+        pr = new PassRes();
+        md->pass = pr;
+        hipError_t e = hipSuccess;
+        for (int k = 0; k <= PASS_SIDE && e == hipSuccess; k++)
+            e = hipEventCreateWithFlags(&pr->ev[k], hipEventDisableTiming);
+        for (int k = 0; k < PASS_SIDE && e == hipSuccess; k++)
+            e = hipStreamCreateWithFlags(&pr->side[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&pr->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(dev_status(e), "pass streams: %s", hipGetErrorString(e));
+    }
+    if (need > pr->cap) {
+        // earlier passes may still use the old scratch, and captured graphs name it
+        HIPCHK(hipStreamSynchronize(md->stream));
+        drop_pass_graphs(pr);
+        dfree(pr->scratch);
+        pr->scratch = nullptr;
+        pr->cap = 0;
+        const int NS = std::min<int32_t>(count, PASS_SIDE);
+        HIPCHK(dev_malloc((void **)&pr->scratch, (size_t)NS * need));
+        pr->cap = need;
+    }
+    if (!graph) return enqueue_pass(md, pr, seed, n_amb, solve, energy, cut);
+
+    // the batch plan's tables are built (allocated and uploaded) before any capture
+    hipError_t pe = launch_md_steps_batch(md, md->q, md->q, false);
+    if (pe != hipSuccess) return fail(dev_status(pe), "batch plan: %s", hipGetErrorString(pe));
+    std::vector<int> cur0;
+    for (auto &I : md->inst) cur0.push_back(I.cur);
+    for (size_t k = 0; k < pr->graphs.size(); k++) {
+        PassGraph g = pr->graphs[k];
+        if (g.seed == seed && g.n_amb == n_amb && g.solve == solve && g.E == energy &&
+            g.C == cut && g.cur0 == cur0) {
+            pr->graphs.erase(pr->graphs.begin() + k);
+            pr->graphs.push_back(g);
+            HIPCHK(hipGraphLaunch(g.exec, md->stream));
+            for (size_t i = 0; i < md->inst.size(); i++) md->inst[i].cur = g.cur1[i];
+            md->q = md->sch.T;
+            return HQA_OK;
+        }
+    }
+    // capture on the pass's own stream, with the handle pointed at it meanwhile; the
+    // capture records the work without running it
+    hipStream_t own = md->stream;
+    hipError_t e = hipStreamBeginCapture(pr->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(dev_status(e), "begin capture: %s", hipGetErrorString(e));
+    md->stream = pr->cap_stream;
+    hqa_status s = enqueue_pass(md, pr, seed, n_amb, solve, energy, cut);
+    md->stream = own;
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(pr->cap_stream, &gr);
+    hipGraphExec_t exec = nullptr;
+    if (s == HQA_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+    if (gr) (void)hipGraphDestroy(gr);
+    std::vector<int> cur1;
+    for (auto &I : md->inst) cur1.push_back(I.cur);
+    // the capture ran nothing: the handle's host state goes back to before the pass
+    for (size_t i = 0; i < md->inst.size(); i++) md->inst[i].cur = cur0[i];
+    if (s != HQA_OK) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        return s;
+    }
+    if (e != hipSuccess) return fail(dev_status(e), "pass capture: %s", hipGetErrorString(e));
+    if (pr->graphs.size() >= PASS_MAX_GRAPHS) {
+        (void)hipGraphExecDestroy(pr->graphs.front().exec);
+        pr->graphs.erase(pr->graphs.begin());
+    }
+    pr->graphs.push_back(PassGraph{seed, n_amb, solve, energy, cut, cur0, cur1, exec});
+    HIPCHK(hipGraphLaunch(exec, md->stream));
+    for (size_t i = 0; i < md->inst.size(); i++) md->inst[i].cur = cur1[i];
+    md->q = md->sch.T;
     return HQA_OK;
 }
 

@@ -119,6 +119,8 @@ struct hqa_md {
     void *batch = nullptr;                   // device tile tables of a multi-instance batch
                                              // and its captured step graphs
     int32_t flags = 0;                       // HQA_MD_* run flags
+    void *pass = nullptr;                    // read-out scratch, side streams and captured
+                                             // graphs of hqa_md_pass
     int64_t stats_k0 = 0, stats_k1 = 0;      // early-stop statistics window [k0, k1)
     int64_t stats_every = 1;                 // ... sampling steps k0, k0 + every, ...
 };

@@ -31,10 +31,10 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
             "hqa_es_confidence", "hqa_es_destroy", "hqa_classify_tabu", "hqa_md_run_es",
-            "hqa_classify_noalloc", "hqa_classify_many")
+            "hqa_classify_noalloc", "hqa_classify_many", "hqa_md_pass")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
 HQA_NOALLOC_SCRATCH_BYTES = 16 << 20
-ABI_VERSION = 8
+ABI_VERSION = 9
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 HQA_MD_GRAPH = 1
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
@@ -111,6 +111,7 @@ def lib():
         L.hqa_classify.argtypes = [P, i32, i32, i32, P, i32]
         L.hqa_classify_noalloc.argtypes = [P, i32, i32, i32, P, i32]
         L.hqa_classify_many.argtypes = [P, P, i32, i32, i32, P, P, i32]
+        L.hqa_md_pass.argtypes = [P, C.c_uint64, i32, i32, P, P, i32]
         L.hqa_ising_energy.argtypes = [P, P, i32, P, P, i32, P]
         L.hqa_md_destroy.argtypes = [P]
         L.hqa_md_stats_window.argtypes = [P, i64, i64, i64]
@@ -269,6 +270,12 @@ def hqa_classify_many(md, instances, count: int, n_amb: int, solve: int, energy,
     e, _e = _addr(energy)
     c, _c = _addr(cut)
     _check(lib().hqa_classify_many(md, ks, count, n_amb, solve, e, c, out_mem))
+
+
+def hqa_md_pass(md, seed: int, n_amb: int, solve: int, energy, cut, flags: int):
+    e, _e = _addr(energy)
+    c, _c = _addr(cut)
+    _check(lib().hqa_md_pass(md, seed, n_amb, solve, e, c, flags))
 
 
 def hqa_classify_tabu(md, instance: int, n_amb: int, iters: int, tenure: int,
@@ -589,6 +596,21 @@ class MD:
         res["h_eff"] = res["h_eff"][:, :n_amb]
         return res
 
+
+    def run_pass(self, seed: int, n_amb: int, solve: bool = True, graph: bool = True,
+                 energy=None, cut=None):
+        """One whole pass (reset with `seed`, every MD step, the read-out of every instance)
+        enqueued on the handle's stream (hqa_md_pass), replayed from a captured HIP graph
+        when `graph`.  Returns the device tensors (energy, cut) [count][R] float64, filled
+        once the stream has reached them (call sync() before reading)."""
+        import torch
+        shape = (len(self.problems), self.R)
+        if energy is None:
+            energy = torch.empty(shape, dtype=torch.float64, device="cuda")
+        if cut is None:
+            cut = torch.empty(shape, dtype=torch.float64, device="cuda")
+        hqa_md_pass(self.h, seed, n_amb, int(solve), energy, cut, HQA_MD_GRAPH if graph else 0)
+        return energy, cut
 
     def classify_many(self, n_amb: int, solve: bool = True, instances=None):
         """Exact energies and cuts [count][R] of the read-out of several instances

@@ -45,7 +45,7 @@ def test_binding_covers_every_declared_symbol():
 
 def test_abi_version_and_defaults(libhqa):
     from paper_2004_03972_amd import hqa
-    assert hqa.hqa_abi_version() == hqa.ABI_VERSION == 8
+    assert hqa.hqa_abi_version() == hqa.ABI_VERSION == 9
     s = hqa.hqa_schedule_default()
     # Methods, "Scheduling functions for MD": (0.008, 4, 3), (0.12, 0.05, 1); M = 6 (Results)
     assert (s.alpha_f, s.rho1, s.rho2, s.beta_f, s.kappa1, s.kappa2) == (0.008, 4, 3, 0.12, 0.05, 1)
@@ -98,4 +98,13 @@ def test_classify_many_refuses_bad_arguments_on_the_host(libhqa):
     E = np.empty(4)
     with pytest.raises(hqa.HQAError) as e:
         hqa.hqa_classify_many(None, np.zeros(1, np.int32), 1, 2, 1, E, None, hqa.HQA_HOST)
+    assert e.value.status == hqa.HQA_EINVAL and "handle" in str(e.value)
+
+
+def test_pass_refuses_bad_arguments_on_the_host(libhqa):
+    from paper_2004_03972_amd import hqa
+    import numpy as np
+    E = np.empty(4)
+    with pytest.raises(hqa.HQAError) as e:
+        hqa.hqa_md_pass(None, 1, 2, 1, E, None, hqa.HQA_MD_GRAPH)
     assert e.value.status == hqa.HQA_EINVAL and "handle" in str(e.value)

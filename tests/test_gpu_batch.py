@@ -241,6 +241,57 @@ def test_graph_replay_equals_eager(H):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("T", [160, 161])
+def test_pass_equals_separate_calls(H, T):
+    """hqa_md_pass: a whole pass (reset, every step, the read-out of every instance)
+    equals hqa_md_reset + hqa_md_run + hqa_classify_many bit for bit, in energies, cuts
+    and the final state; replayed from its captured HIP graph several times with other
+    eager work and synchronisations between the replays (an odd T flips the flux-buffer
+    parity, so two graphs alternate), and run eagerly.  A handle that is not on the
+    batch plan refuses graph mode but runs the pass eagerly."""
+    import torch
+    probs, Js = _mixed_batch(H, [100, 333], [517, 700], 90)
+    R, n = 64, 12
+    ws = (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM)
+    md = H.MD(probs, H.make_schedule(T, 30), R, "bf16", seed=3)
+    md.reset(21)
+    md.run()
+    E0, C0 = md.classify_many(n, True)
+    S0 = [[md.state(w, k) for w in ws] for k in range(len(probs))]
+    E = torch.full((len(probs), R), float("nan"), dtype=torch.float64, device="cuda")
+    C = torch.full((len(probs), R), float("nan"), dtype=torch.float64, device="cuda")
+    for rnd in range(4):
+        print("pass replay round", rnd, flush=True)
+        E.fill_(float("nan"))
+        C.fill_(float("nan"))
+        md.run_pass(21, n, True, graph=rnd < 3, energy=E, cut=C)
+        md.sync()
+        assert md.step == T
+        assert np.array_equal(E.cpu().numpy(), E0) and np.array_equal(C.cpu().numpy(), C0), rnd
+        for k in range(len(probs)):
+            for w, ref in zip(ws, S0[k]):
+                assert np.array_equal(md.state(w, k), ref), (rnd, k, w)
+        # other eager work between the replays: another seed through the separate calls
+        md.reset(40 + rnd)
+        md.run()
+        md.classify_many(n, False)
+        torch.cuda.synchronize()
+    md.close()
+    # one dense instance under AUTO runs on the per-step plan: graph mode is refused
+    one = H.MD(probs[2], H.make_schedule(T, 30), R, "fp8", seed=5)
+    e1 = torch.empty((1, R), dtype=torch.float64, device="cuda")
+    with pytest.raises(H.HQAError) as ex:
+        one.run_pass(8, n, True, graph=True, energy=e1, cut=None)
+    assert ex.value.status == H.HQA_EUNSUPPORTED
+    one.run_pass(8, n, True, graph=False, energy=e1, cut=None)
+    one.sync()
+    one.reset(8)
+    one.run()
+    Er, _ = one.classify_many(n, True)
+    assert np.array_equal(e1.cpu().numpy(), Er)
+    one.close()
+
+
 def test_classify_many_equals_per_instance(H):
     """hqa_classify_many: the energies and cuts of every listed instance equal
     hqa_classify's bit for bit (exact enumeration at n = 12 and the MD-alone read-out),

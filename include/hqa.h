@@ -37,6 +37,11 @@
  *    when the case comes again.  Every plan gives bit-identical trajectories, so
  *    the file affects speed only; entries that do not fit the instance are
  *    ignored.
+ *  - HQA_SPIN_LIMIT=k (k >= 0): every bounded wait of the CLUSTER plan's
+ *    persistent kernels gives up after k polls instead of 2^22, read at each
+ *    launch (tests of the abort path).  A wait that gives up raises the launch's
+ *    abort flag, every workgroup leaves, the launch ends normally and
+ *    hqa_md_sync reports HQA_EDEVICE; hqa_md_reset makes the handle usable again.
  */
 #ifndef HQA_H
 #define HQA_H

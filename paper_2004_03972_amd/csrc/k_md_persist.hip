@@ -133,6 +133,18 @@ __device__ __forceinline__ bool check_placement(int32_t *abort_flag, int32_t *er
     return true;
 }
 
+// Polls a wait may make before it gives up: 2^22 (seconds of waiting), or
+// HQA_SPIN_LIMIT=k (k >= 0) read at each launch, for tests of the abort path.
+static int64_t spin_limit() {
+    const char *v = getenv("HQA_SPIN_LIMIT");
+    if (v && *v) {
+        char *end = nullptr;
+        const long long k = strtoll(v, &end, 10);
+        if (end && *end == 0 && k >= 0) return (int64_t)k;
+    }
+    return (int64_t)1 << 22;
+}
+
 struct Waiter {
     int64_t spins;
     bool dead;
@@ -852,7 +864,7 @@ hipError_t launch_md_persist_set(hqa_md *md, Instance *const *set, int K, int64_
     a.jstride = pl.jstride;
     a.jbytes = pl.jbytes;
     a.pstride = pl.pstride;
-    a.spin_limit = (int64_t)1 << 22;
+    a.spin_limit = spin_limit();
     switch (I0.jt) {
         case JT_F32: e = launch_jt<JT_F32>(a, pl, md->stream); break;
         case JT_BF16: e = launch_jt<JT_BF16>(a, pl, md->stream); break;

@@ -1,7 +1,8 @@
 """The library's environment switches on the GPU: allocation-failure injection
 (HQA_FAULT_ALLOC) through every device allocation that init, a batched run and a
-read-out make, the per-call timing lines (HQA_TIMING) and the persisted tuner choices
-(HQA_TUNE_CACHE)."""
+read-out make, the per-call timing lines (HQA_TIMING), the persisted tuner choices
+(HQA_TUNE_CACHE) and the abort path of the persistent kernels' bounded waits
+(HQA_SPIN_LIMIT)."""
 import os
 
 import numpy as np
@@ -132,3 +133,41 @@ def test_tune_cache(H, monkeypatch, tmp_path):
     md.close()
     keys = [ln.split("|")[0] for ln in path.read_text().splitlines()]
     assert sum(" one " in k for k in keys) == 2 and sum(" several " in k for k in keys) == 1
+
+
+def test_spin_limit_aborts_cleanly(H, monkeypatch):
+    """HQA_SPIN_LIMIT=0: every wait of the CLUSTER plan's persistent kernel gives up at its
+    first poll that finds a flux not yet published.  The launch still ends (the abort flag
+    sends every workgroup home), hqa_md_sync reports HQA_EDEVICE naming the barrier bound,
+    and after hqa_md_reset without the limit the handle's trajectory equals a fresh
+    handle's bit for bit."""
+    prob = H.Problem(inst.er_maxcut(400, 0.05, 9), storage="fp8")
+    T, R = 60, 64
+    ws = (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM)
+    ref = H.MD(prob, H.make_schedule(T, 10), R, "fp8", seed=4, plan="cluster")
+    ref.run()
+    ref.sync()
+    assert ref.last_plan == "cluster"
+    want = [ref.state(w) for w in ws]
+    ref.close()
+    md = H.MD(prob, H.make_schedule(T, 10), R, "fp8", seed=4, plan="cluster")
+    aborted = 0
+    for rnd in range(3):
+        print("spin-limit round", rnd, flush=True)
+        monkeypatch.setenv("HQA_SPIN_LIMIT", "0")
+        md.reset(4)
+        md.run()
+        try:
+            md.sync()
+        except H.HQAError as e:
+            assert e.status == H.HQA_EDEVICE and "barrier" in str(e), str(e)
+            aborted += 1
+        monkeypatch.delenv("HQA_SPIN_LIMIT")
+        md.reset(4)
+        md.run()
+        md.sync()
+        assert md.last_plan == "cluster"
+        for w, x in zip(ws, want):
+            assert np.array_equal(md.state(w), x), (rnd, w)
+    md.close()
+    assert aborted >= 1

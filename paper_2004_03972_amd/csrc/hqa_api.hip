@@ -1957,6 +1957,7 @@ hqa_status hqa_md_pass(hqa_md *md, uint64_t seed, int32_t n_amb, int32_t solve, 
     // capture on the pass's own stream, with the handle pointed at it meanwhile; the
     // capture records the work without running it
     hipStream_t own = md->stream;
+    const int64_t q_before = md->q;
     hipError_t e = hipStreamBeginCapture(pr->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail(dev_status(e), "begin capture: %s", hipGetErrorString(e));
     md->stream = pr->cap_stream;
@@ -1971,6 +1972,7 @@ hqa_status hqa_md_pass(hqa_md *md, uint64_t seed, int32_t n_amb, int32_t solve, 
     for (auto &I : md->inst) cur1.push_back(I.cur);
     // the capture ran nothing: the handle's host state goes back to before the pass
     for (size_t i = 0; i < md->inst.size(); i++) md->inst[i].cur = cur0[i];
+    md->q = q_before;
     if (s != HQA_OK) {
         if (exec) (void)hipGraphExecDestroy(exec);
         return s;

@@ -274,15 +274,22 @@ def bench_ea3d(args, hqa, torch):
 BATCH_R, BATCH_T, BATCH_N_AMB, BATCH_SEED = 64, 5000, 20, 4
 BATCH_WORKLOAD = ("512 uneven dense instances: 256 SK N~U{100..2000} J~N(0,1/N) stored BF16, "
                   "256 ER MAX-CUT N~U{500..5000} p~U[0.01,0.1] unit weights J=+w stored FP8 "
-                  "e4m3 (exact); R=64 replicas each, T=5000 MD steps, W=100, n=20 exact")
+                  "e4m3 (exact) and streamed one bit per coupling; R=64 replicas each, T=5000 "
+                  "MD steps, W=100, n=20 exact")
 
 
-def batch_bytes_per_step(specs, R, W, T):
-    """Algorithmic HBM bytes of one MD step of the batch: every coupling once in its storage
-    type (BF16 2 B, FP8 1 B), and per spin-update 20 B of state (flux in 4, momentum in 4
-    and out 4, new flux out 4, its BF16 operand copy out 2 and in 2 as the MFMA operand),
-    plus the window sum (in 4, out 4) on W of the T steps."""
-    j = sum(N * N * (2 if fam == "sk" else 1) for fam, N, _, _ in specs)
+FORM_BYTES = {"f32": 4.0, "bf16": 2.0, "fp8": 1.0, "bit": 0.125}
+
+
+def batch_bytes_per_step(specs, R, W, T, forms=None):
+    """Algorithmic HBM bytes of one MD step of the batch: every coupling once in the form the
+    batch plan streams it (`forms`, from the library: BF16 2 B, FP8 1 B, one bit for 0/1
+    couplings; without it BF16 for SK and FP8 for ER), and per spin-update 20 B of state
+    (flux in 4, momentum in 4 and out 4, new flux out 4, its BF16 operand copy out 2 and in
+    2 as the MFMA operand), plus the window sum (in 4, out 4) on W of the T steps."""
+    if forms is None:
+        forms = ["bf16" if fam == "sk" else "fp8" for fam, _, _, _ in specs]
+    j = sum(N * N * FORM_BYTES[f] for (_, N, _, _), f in zip(specs, forms))
     upd = sum(N for _, N, _, _ in specs) * R
     return j + upd * (20.0 + 8.0 * W / T), j, upd
 
@@ -421,7 +428,8 @@ def bench_batch(args, hqa, torch):
     torch.cuda.synchronize()
     total_ms = t0e.elapsed_time(t1e)
     _log(f"  chosen: {total_ms:.1f} ms for {args.steps} steps (MD {np.mean(md_ms):.1f} ms per run)")
-    bytes_step, jbytes, upd_step = batch_bytes_per_step(specs, Rr, W, Tt)
+    forms = [md.batch_form(k) for k in range(Kn)]
+    bytes_step, jbytes, upd_step = batch_bytes_per_step(specs, Rr, W, Tt, forms)
     flop_step = sum(2.0 * N * N * Rr for _, N, _, _ in specs)
     upd_run = upd_step * Tt
     value = upd_run * args.steps / (total_ms / 1e3)
@@ -458,6 +466,7 @@ def bench_batch(args, hqa, torch):
         "config": {"workload": BATCH_WORKLOAD if Kn == 512 and Tt == BATCH_T else
                    f"{Kn} uneven instances, R={Rr}, T={Tt}", "instances": Kn, "replicas": Rr,
                    "md_steps": Tt, "n_amb": BATCH_N_AMB, "j_storage": "bf16 (SK) / fp8 (ER)",
+                   "j_streamed": {f: forms.count(f) for f in sorted(set(forms))},
                    "spin_updates_per_run": upd_run, "parallelism": "none (1 GPU)",
                    "launch": "eager" if args.eager else "one HIP graph per run"},
         "md_only_spin_updates_per_s": upd_run / (np.mean(md_ms) / 1e3),

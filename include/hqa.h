@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define HQA_ABI_VERSION 9
+#define HQA_ABI_VERSION 10
 
 typedef enum {
     HQA_OK = 0,
@@ -238,6 +238,14 @@ hqa_status hqa_md_reset(hqa_md *md, uint64_t seed);
 
 /* Wait for queued work; HQA_ENONFINITE if any flux or momentum became non-finite. */
 hqa_status hqa_md_sync(hqa_md *md);
+
+/* Storage form the BATCH plan streams for a dense instance once the plan is built (by
+ * the first batched hqa_md_run or hqa_md_pass): 0 FP32, 1 BF16, 2 FP8 e4m3, 3 one bit
+ * per coupling (an FP8 instance whose couplings are all 0 or 1, such as unit-weight
+ * MAX-CUT: the bits expand in registers to the FP8 path's BF16 operands, so the
+ * results are the same bit for bit, from 1/8 of the coupling bytes); -1 before the plan
+ * is built, for a CSR instance, a bad index or a NULL handle. */
+int32_t hqa_md_batch_form(const hqa_md *md, int32_t instance);
 
 /* The plan the last hqa_md_run used for the binary32 instances (HQA_PLAN_STEP,
  * _CLUSTER, _RESIDENT or _BATCH; the last instance's when they differ), 0 if it

@@ -120,6 +120,7 @@ static void free_instance(Instance &I) {
     dfree(I.J64); dfree(I.rp); dfree(I.ci); dfree(I.h64); dfree(I.h32); dfree(I.Js); dfree(I.v32);
     for (int k = 0; k < 2; k++) { dfree(I.phi64[k]); dfree(I.phi32[k]); dfree(I.phib[k]); }
     dfree(I.p64); dfree(I.S64); dfree(I.p32); dfree(I.S32); dfree(I.xch); dfree(I.Jt);
+    dfree(I.Jbits);
     dfree(I.st); dfree(I.n1); dfree(I.inv_n2);
     I = Instance();
 }
@@ -480,6 +481,11 @@ hqa_status hqa_md_init(const hqa_problem *probs, int32_t count, const hqa_schedu
 }
 
 int64_t hqa_md_step_index(const hqa_md *md) { return md ? md->q : -1; }
+
+int32_t hqa_md_batch_form(const hqa_md *md, int32_t instance) {
+    if (!md || instance < 0 || instance >= (int32_t)md->inst.size()) return -1;
+    return batch_form(md, instance);
+}
 
 int32_t hqa_md_last_plan(const hqa_md *md) { return md ? md->last_plan : 0; }
 

@@ -17,7 +17,9 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 // Storage type of J for the fast paths.
-enum JType { JT_F32 = 0, JT_BF16 = 1, JT_FP8 = 2 };
+// JT_BIT: couplings that are all 0 or 1, streamed by the batch plan as one bit each
+// (its MFMA operands are the FP8 path's, so results are identical)
+enum JType { JT_F32 = 0, JT_BF16 = 1, JT_FP8 = 2, JT_BIT = 3 };
 
 // Error bits raised by kernels into a device word.
 enum {
@@ -59,6 +61,8 @@ struct Instance {
     JType jt = JT_F32;        // storage type of Js
     void *Js = nullptr;       // dense storage for the fast paths, Np*Np of JType
     void *Jt = nullptr;       // MFMA-tiled copy of Js for the resident plan (built on first use)
+    void *Jbits = nullptr;    // 1-bit tiled copy when every coupling is 0 or 1 (batch plan)
+    int jbits = 0;            // 0 not checked, 1 Jbits built, -1 some coupling is not 0 or 1
     float *v32 = nullptr;     // CSR FP32 values
 
     // state
@@ -151,6 +155,8 @@ size_t resident_lds_bytes(int N);
 bool resident_fits(const Instance &I, int max_lds);
 hipError_t launch_md_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t ensure_tiled_j(Instance &I, hipStream_t st);
+hipError_t ensure_tiled_bits(Instance &I, hipStream_t st);
+int batch_form(const hqa_md *md, int instance);
 bool csr_resident_fits(hqa_md *md, Instance &I);
 hipError_t launch_md_csr_resident(hqa_md *md, Instance &I, int64_t q0, int64_t q1);
 hipError_t launch_field(hqa_md *md, Instance &I, double *u, hipStream_t st);

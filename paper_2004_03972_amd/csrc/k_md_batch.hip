@@ -3,7 +3,9 @@
 // A batch of uneven instances (sizes N_k, one shared schedule and replica count)
 // advances step by step; each step is one launch over a tile table of (instance, 128
 // rows, 64 replicas) tiles, whatever the storage type (FP32, BF16, FP8), so with 64
-// replicas each J row block is read once per step.  The tiles of an instance share
+// replicas each J row block is read once per step.  An FP8 instance whose couplings are
+// all 0 or 1 (unit-weight MAX-CUT) is streamed from a copy with one bit per coupling,
+// expanded in registers to the same BF16 operands.  The tiles of an instance share
 // one XCD, and instances are placed longest-first (LPT by padded size), so the largest
 // instances start first and the short tiles fill the tail of the step.  The field
 // uses the chunk-to-chain decomposition of the other dense kernels, and the update
@@ -33,7 +35,7 @@ __device__ __forceinline__ bf16x8 cvt_fp8x8_b(uint2 raw) {
 struct BatchInst {
     int N, Np, ld, jt;
     const void *J;
-    const void *Jt;       // MFMA-tiled copy of J (BF16 / FP8 storage)
+    const void *Jt;       // MFMA-tiled copy of J (BF16 / FP8 storage, or bits for JT_BIT)
     int nrounds;          // 128-column groups per row (Np / 128)
     const float *h;
     float *phi[2];
@@ -90,9 +92,24 @@ typedef __attribute__((__vector_size__(4 * sizeof(unsigned)))) unsigned u32x4_b;
 
 // The four K chunks of one 128-column group as BF16 operands: from four 16-byte words
 // (BF16 storage) or from the eight FP8 bytes of each chunk in two words (FP8 storage).
-template <int JT>
-__device__ __forceinline__ bf16x8 a_chunk(const u32x4_b *g, int j) {
-    if constexpr (JT == JT_BF16) {
+// Eight couplings of value 0 or 1 (bit e = element e) as eight BF16 operands: each pair
+// of bits t becomes the word t0 * 0x3F80 + t1 * 0x3F800000 (BF16 1.0 = 0x3F80).
+__device__ __forceinline__ bf16x8 bits_to_bf16x8(uint32_t byte) {
+    u32x4_b o;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t t = (byte >> (2 * i)) & 3u;
+        const uint32_t m = (t * 0x8001u) & 0x10001u;   // bit 0 -> bit 0, bit 1 -> bit 16
+        o[i] = m * 0x3F80u;
+    }
+    return __builtin_bit_cast(bf16x8, o);
+}
+
+template <int JT, typename W>
+__device__ __forceinline__ bf16x8 a_chunk(const W *g, int j) {
+    if constexpr (JT == JT_BIT) {
+        return bits_to_bf16x8((g[0] >> (8 * j)) & 0xFFu);
+    } else if constexpr (JT == JT_BF16) {
         return __builtin_bit_cast(bf16x8, g[j]);
     } else {
         const u32x4_b w = g[j >> 1];
@@ -115,13 +132,16 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
     float *phi_out = odd ? I.phi[0] : I.phi[1];
     bf16 *xb_out = odd ? I.xb[0] : I.xb[1];
     const int ngroups = I.Np / 128;
-    constexpr int NA = JT == JT_BF16 ? 4 : 2;          // 16-byte words of J per lane and group
+    // words of J per lane and group: 16-byte words of BF16 or FP8, or one 32-bit word of
+    // bits (four chunks of eight couplings)
+    using JW = typename std::conditional<JT == JT_BIT, uint32_t, u32x4_b>::type;
+    constexpr int NA = JT == JT_BF16 ? 4 : JT == JT_FP8 ? 2 : 1;
     // the tiled copy holds ceil(N / 16) row tiles: a wavefront whose rows are all
     // padding reads the last real row tile instead (its results are never stored)
     // (wavefront-uniform bases and 32-bit per-lane offsets: the offsets take one register
     // each where a per-lane pointer takes two)
     const int jtile = min(i0, I.N - 1) / 16;
-    const auto *Jt = gld<u32x4_b>((const uint8_t *)I.Jt + (int64_t)jtile * I.nrounds * 64 * (16 * NA));
+    const auto *Jt = gld<JW>((const uint8_t *)I.Jt + (int64_t)jtile * I.nrounds * 64 * (int)sizeof(JW) * NA);
     const int jl = lane * NA;
     // staging: thread -> (replica row, 16-column segment) of the 64 x 128 block
     const int srow = tid >> 3, sseg = tid & 7;
@@ -142,7 +162,7 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
     // complete in order, so the wait that lets them go to LDS at the end of group g
     // leaves the couplings in flight across the barrier.  At 128 VGPRs two workgroups
     // share a CU, and each covers the other's waits, prologue and epilogue.
-    u32x4_b A0[NA], A1[NA];
+    JW A0[NA], A1[NA];
     u32x4_b S0a, S0b;
 #define HQA_LOAD_J(g, A)                                                              \
     do {                                                                              \
@@ -429,6 +449,7 @@ __global__ __launch_bounds__(512, 4) void k_step_batch_lds(BatchArgs a, int64_t 
     if (tl.inst < 0) return;
     const BatchInst I = a.inst[tl.inst];
     if (I.jt == JT_FP8) batch_lds_tile<JT_FP8>(a, q, tl, I, Bs);
+    else if (I.jt == JT_BIT) batch_lds_tile<JT_BIT>(a, q, tl, I, Bs);
     else batch_lds_tile<JT_BF16>(a, q, tl, I, Bs);
 }
 
@@ -483,12 +504,24 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
         b.Jt = nullptr;
         b.nrounds = I.Np / 128;
         if (I.layout == HQA_DENSE && (I.jt == JT_BF16 || I.jt == JT_FP8)) {
-            hipError_t e = ensure_tiled_j(I, md->stream);
+            // FP8 with every coupling 0 or 1: the 1-bit copy; otherwise (BF16, other FP8)
+            // the MFMA-tiled copy of the storage
+            hipError_t e = I.jt == JT_FP8 ? ensure_tiled_bits(I, md->stream) : hipSuccess;
+            if (e == hipSuccess && I.jbits <= 0) e = ensure_tiled_j(I, md->stream);
             if (e != hipSuccess) {
                 delete bp;
                 return e;
             }
-            b.Jt = I.Jt;
+            if (I.jbits > 0) {
+                b.jt = JT_BIT;
+                b.Jt = I.Jbits;
+            } else {
+                b.Jt = I.Jt;
+            }
+            if (!b.Jt) {   // every streamed form needs its copy
+                delete bp;
+                return hipErrorInvalidValue;
+            }
         }
         b.phi[0] = I.phi32[0]; b.phi[1] = I.phi32[1];
         b.xb[0] = I.phib[0]; b.xb[1] = I.phib[1];
@@ -497,6 +530,8 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
         if (I.layout == HQA_DENSE) dense.push_back((int)k);
     }
     // longest processing time first: larger padded size first, then instance index
+    // (every tile of an instance costs the same, so the order by size is the order by
+    // tile work within a storage form)
     std::stable_sort(dense.begin(), dense.end(), [&](int x, int y) {
         return md->inst[x].Np > md->inst[y].Np;
     });
@@ -517,16 +552,23 @@ static hipError_t build_plan(hqa_md *md, BatchPlan *&out) {
         std::vector<BatchTile> xl[NX];
         int64_t load[NX] = {0};
         int64_t total = 0;
+        // work of a tile: the bytes it streams (its couplings and the staged flux
+        // block) plus a fixed cost of its first loads and epilogue (about the time of
+        // 256 KB)
+        auto tile_work = [&](const Instance &I) -> int64_t {
+            const int64_t jb = I.jt == JT_F32 ? 512 : I.jt == JT_BF16 ? 256 : I.jbits > 0 ? 16 : 128;
+            return (jb + 128) * (int64_t)I.Np + 262144;
+        };
         for (int k : dense) {
             const Instance &I = md->inst[k];
             if (!member(I)) continue;
-            total += (int64_t)((I.N + BL_ROWS - 1) / BL_ROWS) * ((md->R + 63) / 64) * I.Np;
+            total += (int64_t)((I.N + BL_ROWS - 1) / BL_ROWS) * ((md->R + 63) / 64) * tile_work(I);
         }
         for (int k : dense) {
             const Instance &I = md->inst[k];
             if (!member(I)) continue;
             const int nrb = (I.N + BL_ROWS - 1) / BL_ROWS;
-            const int64_t tw = (int64_t)I.Np;      // work of a tile ~ its row length
+            const int64_t tw = tile_work(I);
             const int64_t work = (int64_t)nrb * ((md->R + 63) / 64) * tw;
             if (nrb >= NX && NX * work >= total) {
                 for (int x = 0; x < NX; x++) {
@@ -630,6 +672,74 @@ static hipError_t batch_graph(hqa_md *md, BatchPlan *bp, int64_t q0, int64_t q1,
     }
     bp->graphs.push_back({q0, q1, cur, exec});
     *out = exec;
+    return hipSuccess;
+}
+
+// The storage form the batch plan streams for an instance (JT_F32, JT_BF16, JT_FP8 or
+// JT_BIT), or -1 when the plan is not built or the instance is not dense.
+int batch_form(const hqa_md *md, int instance) {
+    const Instance &I = md->inst[instance];
+    if (!md->batch || I.layout != HQA_DENSE) return -1;
+    if (I.jt == JT_FP8 && I.jbits > 0) return JT_BIT;
+    return I.jt;
+}
+
+// 1-bit MFMA-tiled copy of an FP8 storage whose every byte is 0 or 0x38 (1.0): word
+// (t, m, lane) holds, at bit 8 k + e, J[16 t + (lane & 15)][128 m + 32 k + 8 (lane >> 4)
+// + e] for k = 0..3, e = 0..7 (the A-operand fragments of chunks 4m..4m+3 of row tile t,
+// in the order of the FP8 tiled copy).  Any other byte sets *bad.
+__global__ void k_tile_bits(const uint8_t *__restrict__ J, int Np, int ntile, int nrounds,
+                            uint32_t *__restrict__ out, int32_t *bad) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (t, m, lane)
+    const int64_t n = (int64_t)ntile * nrounds * 64;
+    if (g >= n) return;
+    const int lane = (int)(g & 63);
+    const int64_t tm = g >> 6;
+    const int m = (int)(tm % nrounds), t = (int)(tm / nrounds);
+    const int row = 16 * t + (lane & 15);
+    uint32_t w = 0;
+    bool odd = false;
+    for (int k = 0; k < 4; k++) {
+        const uint8_t *src = J + (int64_t)row * Np + 128 * m + 32 * k + 8 * (lane >> 4);
+        for (int e = 0; e < 8; e++) {
+            const uint8_t v = src[e];
+            odd |= v != 0 && v != 0x38;
+            w |= (uint32_t)(v == 0x38) << (8 * k + e);
+        }
+    }
+    out[g] = w;
+    if (odd) atomicOr(bad, 1);
+}
+
+// Builds the 1-bit copy of an FP8 instance once, or marks the instance as not {0, 1}.
+// Synchronises the stream (once per instance, when the batch plan is built).
+hipError_t ensure_tiled_bits(Instance &I, hipStream_t st) {
+    if (I.jbits != 0) return hipSuccess;
+    if (I.jt != JT_FP8 || !I.Js) {
+        I.jbits = -1;
+        return hipSuccess;
+    }
+    const int ntile = (I.N + 15) / 16, nrounds = I.Np / 128;
+    const int64_t n = (int64_t)ntile * nrounds * 64;
+    int32_t *dbad = nullptr;
+    hipError_t e = dev_malloc((void **)&dbad, sizeof(int32_t));
+    if (e == hipSuccess) e = dev_malloc(&I.Jbits, n * 4);
+    if (e == hipSuccess) e = hipMemsetAsync(dbad, 0, sizeof(int32_t), st);
+    if (e == hipSuccess) {
+        k_tile_bits<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((const uint8_t *)I.Js, I.Np, ntile,
+                                                               nrounds, (uint32_t *)I.Jbits, dbad);
+        e = hipGetLastError();
+    }
+    int32_t bad = 1;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, dbad, sizeof bad, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (dbad) (void)hipFree(dbad);
+    if (e != hipSuccess || bad) {
+        if (I.Jbits) (void)hipFree(I.Jbits);
+        I.Jbits = nullptr;
+    }
+    if (e != hipSuccess) return e;
+    I.jbits = bad ? -1 : 1;
     return hipSuccess;
 }
 

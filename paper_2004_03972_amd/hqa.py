@@ -31,10 +31,10 @@ EXPORTED = ("hqa_abi_version", "hqa_last_error", "hqa_schedule_default", "hqa_md
             "hqa_md_stats_window", "hqa_md_features", "hqa_classify_probs", "hqa_es_create",
             "hqa_es_params", "hqa_es_grad", "hqa_es_train_step", "hqa_es_predict",
             "hqa_es_confidence", "hqa_es_destroy", "hqa_classify_tabu", "hqa_md_run_es",
-            "hqa_classify_noalloc", "hqa_classify_many", "hqa_md_pass")
+            "hqa_classify_noalloc", "hqa_classify_many", "hqa_md_pass", "hqa_md_batch_form")
 HQA_ES_NFEAT, HQA_ES_NPARAM = 12, 5187
 HQA_NOALLOC_SCRATCH_BYTES = 16 << 20
-ABI_VERSION = 9
+ABI_VERSION = 10
 HQA_PLAN_AUTO, HQA_PLAN_STEP, HQA_PLAN_CLUSTER, HQA_PLAN_RESIDENT, HQA_PLAN_BATCH = 0, 1, 2, 3, 4
 HQA_MD_GRAPH = 1
 PLANS = {"auto": HQA_PLAN_AUTO, "step": HQA_PLAN_STEP, "cluster": HQA_PLAN_CLUSTER,
@@ -95,6 +95,8 @@ def lib():
         L.hqa_md_reset.argtypes = [P, C.c_uint64]
         L.hqa_md_step_index.argtypes = [P]
         L.hqa_md_step_index.restype = i64
+        L.hqa_md_batch_form.argtypes = [P, i32]
+        L.hqa_md_batch_form.restype = i32
         L.hqa_md_last_plan.argtypes = [P]
         L.hqa_md_last_plan.restype = i32
         L.hqa_md_tune.argtypes = [P, i32]
@@ -194,6 +196,13 @@ def hqa_md_reset(md, seed: int):
 
 def hqa_md_step_index(md) -> int:
     return lib().hqa_md_step_index(md)
+
+
+BATCH_FORMS = {0: "f32", 1: "bf16", 2: "fp8", 3: "bit"}
+
+
+def hqa_md_batch_form(md, instance: int) -> int:
+    return lib().hqa_md_batch_form(md, instance)
 
 
 def hqa_md_last_plan(md) -> int:
@@ -498,6 +507,11 @@ class MD:
     @property
     def step(self) -> int:
         return hqa_md_step_index(self.h)
+
+    def batch_form(self, k: int = 0):
+        """Storage form the batch plan streams for instance k ("f32", "bf16", "fp8" or
+        "bit"), or None before the plan is built."""
+        return BATCH_FORMS.get(hqa_md_batch_form(self.h, k))
 
     @property
     def last_plan(self):

@@ -45,7 +45,7 @@ def test_binding_covers_every_declared_symbol():
 
 def test_abi_version_and_defaults(libhqa):
     from paper_2004_03972_amd import hqa
-    assert hqa.hqa_abi_version() == hqa.ABI_VERSION == 9
+    assert hqa.hqa_abi_version() == hqa.ABI_VERSION == 10
     s = hqa.hqa_schedule_default()
     # Methods, "Scheduling functions for MD": (0.008, 4, 3), (0.12, 0.05, 1); M = 6 (Results)
     assert (s.alpha_f, s.rho1, s.rho2, s.beta_f, s.kappa1, s.kappa2) == (0.008, 4, 3, 0.12, 0.05, 1)

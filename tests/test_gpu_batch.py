@@ -56,17 +56,45 @@ def _mixed_batch(H, sizes_sk, sizes_er, seed0):
 
 @pytest.mark.parametrize("R", [64, 40])
 def test_batch_equals_individual_runs(H, R):
+    """Every instance of an uneven batch (SK in BF16; unit-weight ER MAX-CUT, which the
+    batch plan streams one bit per coupling) evolves bit-identically to the same instance
+    run alone on its own plan (FP8 storage for ER)."""
     probs, Js = _mixed_batch(H, [100, 333, 517], [700, 1200], 10)
     T = 160
     b = H.MD(probs, H.make_schedule(T, 30), R, "bf16", seed=3)
     b.run()
     b.sync()
+    assert [b.batch_form(k) for k in range(len(probs))] == ["bf16"] * 3 + ["bit"] * 2
     for k, p in enumerate(probs):
         a = H.MD(p, H.make_schedule(T, 30), R, "bf16", seed=3)
         a.run()
         for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM):
             assert np.array_equal(a.state(w), b.state(w, k)), (k, w)
         a.close()
+
+
+def test_bit_form_only_for_zero_one_couplings(H):
+    """The one-bit form is taken only when every coupling is 0 or 1: FP8 instances with
+    +-1 couplings or small integers stay FP8 in the batch, unit weights go to bits (also
+    with ragged sizes N = 130, 129 + 128 k), and every instance still equals its lone run
+    bit for bit; the per-step plan ignores the form."""
+    Js = [inst.pm_complete(200, 3), inst.small_int(257, 4, 0, 2, density=0.3),
+          inst.er_maxcut(130, 0.2, 5), inst.er_maxcut(385, 0.1, 6)]
+    probs = [H.Problem(J, storage="fp8") for J in Js]
+    T, R = 120, 64
+    b = H.MD(probs, H.make_schedule(T, 30), R, "bf16", seed=8)
+    assert b.batch_form(0) is None
+    b.run()
+    b.sync()
+    assert b.last_plan == "batch"
+    assert [b.batch_form(k) for k in range(len(probs))] == ["fp8", "fp8", "bit", "bit"]
+    for k, p in enumerate(probs):
+        a = H.MD(p, H.make_schedule(T, 30), R, "bf16", seed=8, plan="step")
+        a.run()
+        for w in (H.HQA_STATE_PHI, H.HQA_STATE_P, H.HQA_STATE_WSUM):
+            assert np.array_equal(a.state(w), b.state(w, k)), (k, w)
+        a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("R", [64, 24])

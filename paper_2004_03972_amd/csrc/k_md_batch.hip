@@ -184,28 +184,57 @@ __device__ __forceinline__ void batch_lds_tile(const BatchArgs &a, int64_t q, co
         }                                                                             \
     } while (0)
     const int gl = ngroups - 1;
-    HQA_LOAD_S(0, S0a, S0b);
-    HQA_LOAD_J(0, A0);
-    Bdst0[0] = S0a;
-    Bdst0[1] = S0b;
-    __syncthreads();
-    // even groups compute from A0 and LDS buffer 0, odd ones from A1 and buffer 1
-    for (int gi = 0; gi < ngroups; gi += 2) {
-        HQA_LOAD_S(min(gi + 1, gl), S0a, S0b);
-        HQA_LOAD_J(min(gi + 1, gl), A1);
-        __builtin_amdgcn_sched_barrier(0);
-        HQA_MFMA_GROUP(0, A0);
-        Bdst1[0] = S0a;
-        Bdst1[1] = S0b;
-        __syncthreads();
-        if (gi + 1 >= ngroups) break;
-        HQA_LOAD_S(min(gi + 2, gl), S0a, S0b);
-        HQA_LOAD_J(min(gi + 2, gl), A0);
-        __builtin_amdgcn_sched_barrier(0);
-        HQA_MFMA_GROUP(1, A1);
+    if constexpr (JT == JT_BIT) {
+        // bit tiles hold two flux register sets (their couplings take one register per
+        // set): the fluxes of group g + 2 are requested when group g begins
+        u32x4_b S1a, S1b;
+        HQA_LOAD_S(0, S0a, S0b);
+        HQA_LOAD_J(0, A0);
         Bdst0[0] = S0a;
         Bdst0[1] = S0b;
         __syncthreads();
+        HQA_LOAD_S(min(1, gl), S0a, S0b);
+        for (int gi = 0; gi < ngroups; gi += 2) {
+            HQA_LOAD_S(min(gi + 2, gl), S1a, S1b);
+            HQA_LOAD_J(min(gi + 1, gl), A1);
+            __builtin_amdgcn_sched_barrier(0);
+            HQA_MFMA_GROUP(0, A0);
+            Bdst1[0] = S0a;
+            Bdst1[1] = S0b;
+            __syncthreads();
+            if (gi + 1 >= ngroups) break;
+            HQA_LOAD_S(min(gi + 3, gl), S0a, S0b);
+            HQA_LOAD_J(min(gi + 2, gl), A0);
+            __builtin_amdgcn_sched_barrier(0);
+            HQA_MFMA_GROUP(1, A1);
+            Bdst0[0] = S1a;
+            Bdst0[1] = S1b;
+            __syncthreads();
+        }
+    } else {
+        HQA_LOAD_S(0, S0a, S0b);
+        HQA_LOAD_J(0, A0);
+        Bdst0[0] = S0a;
+        Bdst0[1] = S0b;
+        __syncthreads();
+        // even groups compute from A0 and LDS buffer 0, odd ones from A1 and buffer 1
+        for (int gi = 0; gi < ngroups; gi += 2) {
+            HQA_LOAD_S(min(gi + 1, gl), S0a, S0b);
+            HQA_LOAD_J(min(gi + 1, gl), A1);
+            __builtin_amdgcn_sched_barrier(0);
+            HQA_MFMA_GROUP(0, A0);
+            Bdst1[0] = S0a;
+            Bdst1[1] = S0b;
+            __syncthreads();
+            if (gi + 1 >= ngroups) break;
+            HQA_LOAD_S(min(gi + 2, gl), S0a, S0b);
+            HQA_LOAD_J(min(gi + 2, gl), A0);
+            __builtin_amdgcn_sched_barrier(0);
+            HQA_MFMA_GROUP(1, A1);
+            Bdst0[0] = S0a;
+            Bdst0[1] = S0b;
+            __syncthreads();
+        }
     }
 #undef HQA_LOAD_J
 #undef HQA_LOAD_S

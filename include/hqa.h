@@ -350,11 +350,12 @@ hqa_status hqa_classify(hqa_md *md, int32_t instance, int32_t n_amb, int32_t sol
  * hqa_classify with the same n_amb and solve, and its R exact energies and cuts go to
  * energy[c R .. c R + R) and cut[c R .. c R + R) (either may be NULL, not both; host or
  * device memory per out_mem).  Spins and the other outputs are not returned (hqa_classify
- * gives them per instance).  Results equal those of hqa_classify bit for bit.  The
- * instances go round-robin to up to four streams of the call's own (ordered after the
- * handle's stream, which waits for them at the end), each with one scratch region sized
- * for the largest listed instance, so the small kernels of several instances overlap;
- * the call synchronises once, at its end, instead of per instance.  Errors as
+ * gives them per instance).  Results equal those of hqa_classify bit for bit.  Each
+ * stage of the read-out (selection, reduction, enumeration, merge, energy) is one
+ * launch for all listed instances, each with a scratch region sized for the largest
+ * listed instance, so the small grids of single instances no longer leave the device
+ * idle; the call synchronises on the handle's stream, once after uploading the stage
+ * arguments and once at its end.  Errors as
  * hqa_classify, checked for every listed instance before any device work; HQA_EINVAL for
  * count < 1, a NULL list or both outputs NULL. */
 hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count,

@@ -1455,66 +1455,71 @@ hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count
     hqa_status s = hqa_md_sync(md);
     if (s != HQA_OK) return s;
     CallTimer tm(md->stream);
-    // The instances are independent: they go round-robin to NS side streams, each with
-    // its own scratch region, so that the small kernels of several instances overlap.
-    // The side streams start after the handle's stream (an event) and the handle's stream
-    // waits for all of them before the results are copied.
-    const int NS = (int)std::min<int32_t>(count, 4);
-    const size_t res = out_mem == HQA_HOST ? ScratchArena::round((size_t)count * R * 8) : 0;
+    // One launch per stage for all listed instances (select, reduce, enumerate, merge,
+    // energy), each instance with a scratch region sized for the largest; the energies
+    // and cuts go straight to the device outputs (or to staging for host outputs).
+    const size_t res = ScratchArena::round((size_t)count * R * 8);
+    const size_t argb = ScratchArena::round(readout_batch_arg_bytes(count));
     uint8_t *base = nullptr;
-    HIPCHK(dev_malloc((void **)&base, NS * need + 2 * res));
+    HIPCHK(dev_malloc((void **)&base, (size_t)count * need + 2 * res + argb));
     double *dE = energy, *dC = cut;
     if (out_mem == HQA_HOST) {
-        dE = energy ? (double *)(base + NS * need) : nullptr;
-        dC = cut ? (double *)(base + NS * need + res) : nullptr;
+        dE = energy ? (double *)(base + (size_t)count * need) : nullptr;
+        dC = cut ? (double *)(base + (size_t)count * need + res) : nullptr;
     }
-    hipStream_t side[4] = {};
-    hipEvent_t ev[5] = {};
+    uint8_t *argbuf = base + (size_t)count * need + 2 * res;
+    std::vector<ReadoutJob> jobs(count);
     hipError_t e = hipSuccess;
-    for (int k = 0; k <= NS && e == hipSuccess; k++)
-        e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
-    for (int k = 0; k < NS && e == hipSuccess; k++)
-        e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventRecord(ev[NS], md->stream);
-    for (int k = 0; k < NS && e == hipSuccess; k++) e = hipStreamWaitEvent(side[k], ev[NS], 0);
-    hipStream_t own = md->stream;
-    for (int32_t c = 0; c < count && s == HQA_OK && e == hipSuccess; c++) {
-        const int k = c % NS;
+    for (int32_t c = 0; c < count && e == hipSuccess; c++) {
+        Instance &I = md->inst[instances[c]];
         ScratchArena A;
-        A.base = base + (size_t)k * need;
+        A.base = base + (size_t)c * need;
         A.cap = need;
-        hqa_classify_out oc{};
-        oc.energy = dE ? dE + (size_t)c * R : nullptr;
-        oc.cut = dC ? dC + (size_t)c * R : nullptr;
-        s = classify_core(md, instances[c], n_amb, solve, &oc, HQA_DEVICE, nullptr, HQA_HOST, 0,
-                          0, A, false, side[k]);
+        ReadoutJob &jb = jobs[c];
+        jb.I = &I;
+        jb.prec = md->prec;
+        jb.W = md->sch.W;
+        jb.h_eff = jb.J_eff = jb.e_red = nullptr;
+        jb.code = nullptr;
+        jb.escr = nullptr;
+        // the same carving as the one-instance read-out
+        e = A.get(&jb.amb, (size_t)R * (n_amb ? n_amb : 1));
+        if (e == hipSuccess) e = A.get(&jb.spins, (size_t)R * I.N);
+        if (e == hipSuccess && solve && n_amb > 0) {
+            e = A.get(&jb.h_eff, (size_t)R * n_amb);
+            if (e == hipSuccess) e = A.get(&jb.J_eff, (size_t)R * n_amb * n_amb);
+            if (e == hipSuccess) e = A.get(&jb.code, (size_t)R);
+            if (e == hipSuccess) e = A.get(&jb.e_red, (size_t)R);
+            uint8_t *escr = nullptr;
+            if (e == hipSuccess) e = A.get(&escr, enum_scratch_bytes(n_amb, R));
+            jb.escr = escr;
+        }
+        double *E = nullptr, *C = nullptr;
+        uint8_t *part = nullptr;
+        if (e == hipSuccess) e = A.get(&E, (size_t)R);
+        if (e == hipSuccess) e = A.get(&C, (size_t)R);
+        if (e == hipSuccess) e = A.get(&part, energy_part_bytes(I.N, R));
+        jb.E = dE ? dE + (size_t)c * R : E;
+        jb.C = dC ? dC + (size_t)c * R : C;
+        jb.part = part;
     }
-    for (int k = 0; k < NS && e == hipSuccess; k++) {
-        e = hipEventRecord(ev[k], side[k]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(own, ev[k], 0);
-    }
-    if (s == HQA_OK && e == hipSuccess && out_mem == HQA_HOST) {
+    if (e == hipSuccess)
+        e = launch_readout_batch(jobs, R, n_amb, solve, argbuf, argb, md->stream);
+    if (e == hipSuccess && out_mem == HQA_HOST) {
         if (energy) e = hipMemcpyAsync(energy, dE, (size_t)count * R * 8, hipMemcpyDeviceToHost,
-                                       own);
+                                       md->stream);
         if (e == hipSuccess && cut)
-            e = hipMemcpyAsync(cut, dC, (size_t)count * R * 8, hipMemcpyDeviceToHost, own);
+            e = hipMemcpyAsync(cut, dC, (size_t)count * R * 8, hipMemcpyDeviceToHost, md->stream);
     }
-    // whatever happened above, every stream is drained before its memory is released
-    for (int k = 0; k < NS; k++)
-        if (side[k]) (void)hipStreamSynchronize(side[k]);
-    hipError_t e2 = hipStreamSynchronize(own);
-    for (int k = 0; k < NS; k++)
-        if (side[k]) (void)hipStreamDestroy(side[k]);
-    for (int k = 0; k <= NS; k++)
-        if (ev[k]) (void)hipEventDestroy(ev[k]);
+    // whatever happened above, the stream is drained before its memory is released
+    hipError_t e2 = hipStreamSynchronize(md->stream);
     (void)hipFree(base);
-    if (s != HQA_OK) return s;
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return fail(dev_status(e), "read-out: %s", hipGetErrorString(e));
     const double ms = tm.stop();
     if (ms >= 0.0)
-        fprintf(stderr, "hqa timing: read-out of %d instances (R = %d, n = %d, solve %d, %d "
-                "streams): %.3f ms\n", count, R, n_amb, solve, NS, ms);
+        fprintf(stderr, "hqa timing: read-out of %d instances (R = %d, n = %d, solve %d, one "
+                "launch per stage): %.3f ms\n", count, R, n_amb, solve, ms);
     return HQA_OK;
 }
 

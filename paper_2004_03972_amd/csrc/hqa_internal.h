@@ -186,6 +186,22 @@ void fault_alloc_arm();
 // bytes of device scratch for the per-slice partial sums.
 int energy_slices(int N, int V);
 size_t energy_part_bytes(int N, int V);
+// One instance's part of a batched read-out: its buffers in device scratch.
+struct ReadoutJob {
+    const Instance *I;
+    int prec, W;
+    int32_t *amb;
+    int8_t *spins;
+    double *h_eff, *J_eff;
+    int64_t *code;
+    double *e_red;
+    void *escr;
+    double *E, *C;
+    void *part;
+};
+size_t readout_batch_arg_bytes(int count);
+hipError_t launch_readout_batch(const std::vector<ReadoutJob> &jobs, int R, int n, int solve,
+                                void *argbuf, size_t argcap, hipStream_t st);
 hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
                          void *part, hipStream_t st);
 hipError_t launch_select_keys(int N, int R, const float *keys, int n, int32_t *amb,

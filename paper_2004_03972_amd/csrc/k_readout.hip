@@ -3,6 +3,9 @@
 #include <math.h>
 
 #include "exact_acc.h"
+#include <cstring>
+#include <vector>
+
 #include "hqa_internal.h"
 
 namespace hqa {
@@ -42,12 +45,12 @@ __device__ __forceinline__ uint64_t sel_key(const SelArgs &a, int r, int i, int8
     return (uint64_t)__float_as_uint(fabsf(pb));
 }
 
-__global__ __launch_bounds__(256) void k_select(SelArgs a) {
+__device__ __forceinline__ void select_body(const SelArgs &a, const int bx_) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t s_prefix;
     __shared__ int s_k;
     __shared__ int wsum[2][4];
-    const int r = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r = bx_, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     // spins
     for (int i = tid; i < a.N && !a.keys; i += 256) {
         int8_t s;
@@ -102,6 +105,16 @@ __global__ __launch_bounds__(256) void k_select(SelArgs a) {
         for (int v = 0; v < 4; v++) { eq_run += wsum[0][v]; out_run += wsum[1][v]; }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_select(SelArgs a) { select_body(a, blockIdx.x); }
+
+// Many instances in one launch: instance blockIdx.y, its own block count nb[y].
+__global__ __launch_bounds__(256) void k_select_many(const SelArgs *as, const int *nb) {
+    const int k = blockIdx.y;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const SelArgs a = as[k];
+    select_body(a, blockIdx.x);
 }
 
 hipError_t launch_select(const Instance &I, int R, int prec, int W, int n, int32_t *amb,
@@ -160,9 +173,9 @@ __device__ __forceinline__ double jlookup(const RedArgs &a, int i, int j) {
     return (lo < a.rp[i + 1] && a.ci[lo] == j) ? a.J[lo] : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
+__device__ __forceinline__ void reduce_body(const RedArgs &a, const int bx_) {
     const int lane = threadIdx.x & 63;
-    const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wid = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
     if (wid >= (int64_t)a.R * a.n) return;
     const int r = (int)(wid / a.n), ai = (int)(wid % a.n);
     const int32_t *A = a.amb + (int64_t)r * a.n;
@@ -187,6 +200,15 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
     if (a.J_eff)   // optional: the tabu search reads J[A, A] from the instance itself
         for (int b = lane; b < a.n; b += 64)
             a.J_eff[((int64_t)r * a.n + ai) * a.n + b] = jlookup(a, row, A[b]);
+}
+
+__global__ __launch_bounds__(256) void k_reduce(RedArgs a) { reduce_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void k_reduce_many(const RedArgs *as, const int *nb) {
+    const int k = blockIdx.y;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const RedArgs a = as[k];
+    reduce_body(a, blockIdx.x);
 }
 
 hipError_t launch_reduce(const Instance &I, int R, int n, const int32_t *amb,
@@ -324,11 +346,11 @@ struct EnumRealArgs {
 };
 
 template <int NL>
-__global__ __launch_bounds__(256) void k_enum_real(EnumRealArgs a, int pass) {
+__device__ __forceinline__ void enum_real_body(const EnumRealArgs &a, int pass, const int bx_) {
     __shared__ double Jd[ENUM_MAXN * ENUM_MAXN], J2[ENUM_MAXN * ENUM_MAXN], hd[ENUM_MAXN];
     __shared__ double sE[256];
     __shared__ int64_t sC[256];
-    const int r = blockIdx.x / a.P, p = blockIdx.x % a.P, tid = threadIdx.x, n = a.n;
+    const int r = bx_ / a.P, p = bx_ % a.P, tid = threadIdx.x, n = a.n;
     for (int k = tid; k < n * n; k += 256) {
         const double v = a.J_eff[(int64_t)r * n * n + k];
         Jd[k] = v;
@@ -414,10 +436,24 @@ __global__ __launch_bounds__(256) void k_enum_real(EnumRealArgs a, int pass) {
     }
 }
 
+template <int NL>
+__global__ __launch_bounds__(256) void k_enum_real(EnumRealArgs a, int pass) {
+    enum_real_body<NL>(a, pass, blockIdx.x);
+}
+
+template <int NL>
+__global__ __launch_bounds__(256) void k_enum_real_many(const EnumRealArgs *as, const int *nb,
+                                                        int pass) {
+    const int k = blockIdx.y;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const EnumRealArgs a = as[k];
+    enum_real_body<NL>(a, pass, blockIdx.x);
+}
+
 // One wavefront per replica: minimum over the P workgroup results; after pass 1 the
 // rescoring threshold, after pass 2 the result.
-__global__ __launch_bounds__(64) void k_enum_real_mid(EnumRealArgs a, int pass) {
-    const int r = blockIdx.x, lane = threadIdx.x, n = a.n;
+__device__ __forceinline__ void enum_real_mid_body(const EnumRealArgs &a, int pass, const int bx_) {
+    const int r = bx_, lane = threadIdx.x, n = a.n;
     double E = INFINITY;
     int64_t C = INT64_MAX;
     for (int p = lane; p < a.P; p += 64) {
@@ -456,6 +492,18 @@ __global__ __launch_bounds__(64) void k_enum_real_mid(EnumRealArgs a, int pass) 
         const double delta = u * S * (mterms + K * (2.0 * n + 1.0) + K * K);
         a.thresh[r] = E + 2.0 * delta + 4.0 * u * S;
     }
+}
+
+__global__ __launch_bounds__(64) void k_enum_real_mid(EnumRealArgs a, int pass) {
+    enum_real_mid_body(a, pass, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void k_enum_real_mid_many(const EnumRealArgs *as, const int *nb,
+                                                          int pass) {
+    const int k = blockIdx.y;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const EnumRealArgs a = as[k];
+    enum_real_mid_body(a, pass, blockIdx.x);
 }
 
 template <int NL>
@@ -554,12 +602,12 @@ __device__ __forceinline__ void walk_i32(const int32_t *Jv, const int32_t *J2, c
 }
 
 template <int NL>
-__global__ __launch_bounds__(1024) void k_enumerate_int(EnumArgs a) {
+__device__ __forceinline__ void enumerate_int_body(const EnumArgs &a, const int bx_) {
     __shared__ int32_t Jv[ENUM_MAXN * ENUM_MAXN], J2[ENUM_MAXN * ENUM_MAXN], hv[ENUM_MAXN];
     __shared__ int64_t Jl[ENUM_MAXN * ENUM_MAXN], hl[ENUM_MAXN];
     __shared__ int64_t sEi[1024], sC[1024];
     __shared__ unsigned long long sS;
-    const int r = blockIdx.x, tid = threadIdx.x, n = a.n;
+    const int r = bx_, tid = threadIdx.x, n = a.n;
     if (tid == 0) sS = 0;
     __syncthreads();
     for (int k = tid; k < n * n; k += 1024) {
@@ -610,6 +658,19 @@ __global__ __launch_bounds__(1024) void k_enumerate_int(EnumArgs a) {
         a.code[r] = sC[0];
         a.e_red[r] = (double)sEi[0];
     }
+}
+
+template <int NL>
+__global__ __launch_bounds__(1024) void k_enumerate_int(EnumArgs a) {
+    enumerate_int_body<NL>(a, blockIdx.x);
+}
+
+template <int NL>
+__global__ __launch_bounds__(1024) void k_enumerate_int_many(const EnumArgs *as, const int *nb) {
+    const int k = blockIdx.y;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const EnumArgs a = as[k];
+    enumerate_int_body<NL>(a, blockIdx.x);
 }
 
 template <int NL>
@@ -669,14 +730,33 @@ hipError_t launch_enumerate(int n, int R, const double *J_eff, const double *h_e
     return hipGetLastError();
 }
 
-__global__ void k_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
-                        int8_t *spins) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+struct MergeArgs {
+    int N, R, n;
+    const int32_t *amb;
+    const int64_t *code;
+    int8_t *spins;
+};
+
+__device__ __forceinline__ void merge_body(int N, int R, int n, const int32_t *amb,
+                                           const int64_t *code, int8_t *spins, const int bx_) {
+    int64_t t = (int64_t)bx_ * blockDim.x + threadIdx.x;
     if (t >= (int64_t)R * n) return;
     int r = (int)(t / n), ai = (int)(t % n);
     int i = amb[t];
     if (i < 0 || i >= N) return;
     spins[(int64_t)r * N + i] = ((code[r] >> ai) & 1) ? -1 : 1;
+}
+
+__global__ void k_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
+                        int8_t *spins) {
+    merge_body(N, R, n, amb, code, spins, blockIdx.x);
+}
+
+__global__ void k_merge_many(const MergeArgs *as, const int *nb) {
+    const int k = blockIdx.y;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const MergeArgs a = as[k];
+    merge_body(a.N, a.R, a.n, a.amb, a.code, a.spins, blockIdx.x);
 }
 
 hipError_t launch_merge(int N, int R, int n, const int32_t *amb, const int64_t *code,
@@ -899,9 +979,15 @@ static __host__ __device__ EnMvLayout energy_mv_layout(int P, int V, int L) {
 // thread per (word, spin): its 64 loads (rows clamped to the last vector, bits past it
 // cleared) are independent, so they are all in flight at once, and consecutive threads
 // read consecutive bytes of a row.
-__global__ __launch_bounds__(256) void k_pack_masks(int N, int V, const int8_t *spins,
-                                                    uint64_t *masks) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+struct PackArgs {
+    int N, V;
+    const int8_t *spins;
+    uint64_t *masks;
+};
+
+__device__ __forceinline__ void pack_masks_body(int N, int V, const int8_t *spins,
+                                                uint64_t *masks, const int bx_) {
+    const int64_t t = (int64_t)bx_ * blockDim.x + threadIdx.x;
     const int nw = (V + 63) / 64;
     if (t >= (int64_t)nw * N) return;
     const int b = (int)(t / N), j = (int)(t % N);
@@ -914,6 +1000,18 @@ __global__ __launch_bounds__(256) void k_pack_masks(int N, int V, const int8_t *
     const int have = V - 64 * b;                     // vectors in this word
     if (have < 64) m &= (1ull << have) - 1ull;
     masks[t] = m;
+}
+
+__global__ __launch_bounds__(256) void k_pack_masks(int N, int V, const int8_t *spins,
+                                                    uint64_t *masks) {
+    pack_masks_body(N, V, spins, masks, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_pack_masks_many(const PackArgs *as, const int *nb) {
+    const int k = blockIdx.y;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const PackArgs a = as[k];
+    pack_masks_body(a.N, a.V, a.spins, a.masks, blockIdx.x);
 }
 
 __device__ __forceinline__ double mv_coupling(const EnMvArgs &a, int i, int j) {
@@ -952,9 +1050,9 @@ __device__ __forceinline__ void mv_split(const EnMvArgs &a, double r, double (&t
 // the column sums of C for every vector of the group and, for vector g G + x, the sum
 // Hn; group 0 also sums S and Ht.
 template <int G, int L>
-__global__ __launch_bounds__(256) void k_energy_mv(EnMvArgs a) {
+__device__ __forceinline__ void energy_mv_body(const EnMvArgs &a, const int bx_, const int by_) {
     __shared__ double red[4][G + 2][L];
-    const int p = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+    const int p = bx_, g = by_, tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int v0 = g * G, word = v0 >> 6, sh = v0 & 63;
     const bool first = g == 0;
@@ -1045,12 +1143,26 @@ __global__ __launch_bounds__(256) void k_energy_mv(EnMvArgs a) {
     }
 }
 
+template <int G, int L>
+__global__ __launch_bounds__(256) void k_energy_mv(EnMvArgs a) {
+    energy_mv_body<G, L>(a, blockIdx.x, blockIdx.y);
+}
+
+// Many instances: instance blockIdx.z, its own slice count nb[z] (= its a.P).
+template <int G, int L>
+__global__ __launch_bounds__(256) void k_energy_mv_many(const EnMvArgs *as, const int *nb) {
+    const int k = blockIdx.z;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const EnMvArgs a = as[k];
+    energy_mv_body<G, L>(a, blockIdx.x, blockIdx.y);
+}
+
 // Per vector (one wavefront, lanes over the slices): level totals over the slices (exact
 // binary64 in any grouping), then E = S - 2 C + Ht - 2 Hn and C in the fixed-point
 // accumulator, each rounded once.
 template <int L>
-__global__ __launch_bounds__(256) void k_energy_mv_merge(EnMvArgs a) {
-    const int v = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+__device__ __forceinline__ void energy_mv_merge_body(const EnMvArgs &a, const int bx_) {
+    const int v = bx_ * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (v >= a.V) return;
     const EnMvLayout lay = energy_mv_layout(a.P, a.V, L);
     double C[L], Hn[L], S[L], Ht[L];
@@ -1089,6 +1201,19 @@ __global__ __launch_bounds__(256) void k_energy_mv_merge(EnMvArgs a) {
     }
     if (a.E) a.E[v] = acc_round(ae, a.b0);
     if (a.cut) a.cut[v] = acc_round(ac, a.b0);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_energy_mv_merge(EnMvArgs a) {
+    energy_mv_merge_body<L>(a, blockIdx.x);
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_energy_mv_merge_many(const EnMvArgs *as, const int *nb) {
+    const int k = blockIdx.y;
+    if ((int)blockIdx.x >= nb[k]) return;
+    const EnMvArgs a = as[k];
+    energy_mv_merge_body<L>(a, blockIdx.x);
 }
 
 int energy_slices(int N, int V) {
@@ -1186,6 +1311,200 @@ hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *
     a.E = E; a.cut = cut;
     k_energy<<<V * a.P, 256, 0, st>>>(a);
     k_energy_merge<<<(V + 63) / 64, 64, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The read-out of many instances (same R, n and solve) in one launch per stage: every
+// stage's kernel runs for all instances at once (instance = the last grid dimension,
+// each with its own block count), in the order select, reduce, enumerate, merge,
+// energy, so the many small grids of one instance no longer leave the device idle.
+// Each stage computes exactly what the per-instance launches compute.
+// ---------------------------------------------------------------------------
+namespace {
+struct Blob {
+    std::vector<uint8_t> h;
+    size_t put(const void *p, size_t n) {
+        const size_t off = (h.size() + 255) & ~(size_t)255;
+        h.resize(off + n);
+        memcpy(h.data() + off, p, n);
+        return off;
+    }
+};
+template <class T>
+size_t put_vec(Blob &b, const std::vector<T> &v) { return b.put(v.data(), v.size() * sizeof(T)); }
+}  // namespace
+
+size_t readout_batch_arg_bytes(int count) {
+    // the argument arrays and their block counts, each rounded to 256 bytes
+    const size_t per = sizeof(EnMvArgs) + sizeof(EnumRealArgs) + sizeof(EnumArgs) + sizeof(SelArgs) +
+                       sizeof(RedArgs) + sizeof(MergeArgs) + sizeof(PackArgs) + 24 * sizeof(int);
+    return (size_t)count * per + 40 * 256;
+}
+
+hipError_t launch_readout_batch(const std::vector<ReadoutJob> &jobs, int R, int n, int solve,
+                                void *argbuf, size_t argcap, hipStream_t st) {
+    const int count = (int)jobs.size();
+    if (count == 0) return hipSuccess;
+    Blob b;
+    // select
+    std::vector<SelArgs> sel(count);
+    std::vector<int> nsel(count, R);
+    for (int c = 0; c < count; c++) {
+        const ReadoutJob &j = jobs[c];
+        SelArgs &a = sel[c];
+        a.N = j.I->N; a.R = R; a.ld = j.I->ld; a.smaj = j.I->smaj; a.f64 = j.prec == HQA_PREC_F64_REF;
+        a.W = j.W; a.n = n; a.S64 = j.I->S64; a.S32 = j.I->S32; a.amb = j.amb; a.spins = j.spins;
+        a.keys = nullptr;
+    }
+    const size_t o_sel = put_vec(b, sel), o_nsel = put_vec(b, nsel);
+    // reduce, enumerate, merge (exact solution of the reduced problems)
+    const bool solving = solve && n > 0;
+    std::vector<RedArgs> red;
+    std::vector<EnumRealArgs> er;
+    std::vector<EnumArgs> ei;
+    std::vector<MergeArgs> mg;
+    std::vector<int> nred, ner, nmid, nei, nmg;
+    const int pt = n < ENUM_PT_REAL ? n : ENUM_PT_REAL;
+    const int Pe = ((1 << pt) + 255) / 256;
+    if (solving) {
+        for (int c = 0; c < count; c++) {
+            const ReadoutJob &j = jobs[c];
+            const Instance &I = *j.I;
+            RedArgs a;
+            a.N = I.N; a.R = R; a.n = n; a.csr = I.layout == HQA_CSR; a.b0 = I.es.lsb;
+            a.J = I.J64; a.rp = I.rp; a.ci = I.ci; a.h = I.h64;
+            a.amb = j.amb; a.spins = j.spins; a.h_eff = j.h_eff; a.J_eff = j.J_eff;
+            red.push_back(a);
+            nred.push_back((R * n + 3) / 4);
+            if (!I.j_integral) {
+                EnumRealArgs e;
+                e.n = n; e.R = R; e.P = Pe; e.b0 = I.es.lsb;
+                e.J_eff = j.J_eff; e.h_eff = j.h_eff; e.code = j.code; e.e_red = j.e_red;
+                e.partE = (double *)j.escr;
+                e.partC = (int64_t *)((char *)j.escr + (size_t)R * e.P * 8);
+                e.thresh = (double *)((char *)j.escr + (size_t)R * e.P * 16);
+                er.push_back(e);
+                ner.push_back(R * Pe);
+                nmid.push_back(R);
+            } else {
+                EnumArgs e;
+                e.n = n; e.R = R; e.b0 = I.es.lsb; e.integral = 1;
+                e.J_eff = j.J_eff; e.h_eff = j.h_eff; e.code = j.code; e.e_red = j.e_red;
+                ei.push_back(e);
+                nei.push_back(R);
+            }
+            MergeArgs m;
+            m.N = I.N; m.R = R; m.n = n; m.amb = j.amb; m.code = j.code; m.spins = j.spins;
+            mg.push_back(m);
+            nmg.push_back((R * n + 255) / 256);
+        }
+    }
+    const size_t o_red = put_vec(b, red), o_nred = put_vec(b, nred);
+    const size_t o_er = put_vec(b, er), o_ner = put_vec(b, ner), o_nmid = put_vec(b, nmid);
+    const size_t o_ei = put_vec(b, ei), o_nei = put_vec(b, nei);
+    const size_t o_mg = put_vec(b, mg), o_nmg = put_vec(b, nmg);
+    // energy: the many-vector kernel by level count; others one instance at a time
+    std::vector<PackArgs> pk;
+    std::vector<int> npk;
+    std::vector<EnMvArgs> mv[5];
+    std::vector<int> nmv[5], nmm[5];   // slices of the sums, blocks of the merge
+    std::vector<int> fallback;
+    for (int c = 0; c < count; c++) {
+        const ReadoutJob &j = jobs[c];
+        const Instance &I = *j.I;
+        EnMvArgs m;
+        const int L = energy_levels(I, m.K);
+        if (!L) {
+            fallback.push_back(c);
+            continue;
+        }
+        m.N = I.N; m.V = R; m.b0 = I.es.lsb;
+        m.J = I.J64; m.h = I.h64; m.spins = j.spins; m.E = j.E; m.cut = j.C;
+        m.jt = -1; m.ldj = 0; m.Js = nullptr;
+        if (I.js_exact && I.Js) {
+            m.jt = (int)I.jt; m.ldj = I.Np; m.Js = I.Js;
+        }
+        m.masks = (uint64_t *)j.part;
+        const size_t mw = (size_t)((R + 63) / 64) * I.N;
+        m.part = (double *)((uint8_t *)j.part + ((mw * 8 + 255) & ~(size_t)255));
+        const int G = energy_mv_group(L);
+        m.P = energy_mv_slices(I.N, (R + G - 1) / G);
+        PackArgs q;
+        q.N = I.N; q.V = R; q.spins = j.spins; q.masks = m.masks;
+        pk.push_back(q);
+        npk.push_back((int)((mw + 255) / 256));
+        mv[L].push_back(m);
+        nmv[L].push_back(m.P);
+        nmm[L].push_back((R + 3) / 4);
+    }
+    const size_t o_pk = put_vec(b, pk), o_npk = put_vec(b, npk);
+    size_t o_mv[5] = {}, o_nmv[5] = {}, o_nmm[5] = {};
+    for (int L = 1; L <= 4; L++) {
+        o_mv[L] = put_vec(b, mv[L]);
+        o_nmv[L] = put_vec(b, nmv[L]);
+        o_nmm[L] = put_vec(b, nmm[L]);
+    }
+    if (b.h.size() > argcap) return hipErrorInvalidValue;
+    // the host copy of the arguments lives only in this call: wait for the upload
+    hipError_t e = hipMemcpyAsync(argbuf, b.h.data(), b.h.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    uint8_t *d = (uint8_t *)argbuf;
+    auto mx = [](const std::vector<int> &v) { int m = 0; for (int x : v) m = std::max(m, x); return m; };
+    k_select_many<<<dim3(R, count), 256, 0, st>>>((const SelArgs *)(d + o_sel), (const int *)(d + o_nsel));
+    if (solving) {
+        k_reduce_many<<<dim3(mx(nred), count), 256, 0, st>>>((const RedArgs *)(d + o_red),
+                                                            (const int *)(d + o_nred));
+        if (!er.empty()) {
+            const EnumRealArgs *as = (const EnumRealArgs *)(d + o_er);
+            const int *nr = (const int *)(d + o_ner), *nm = (const int *)(d + o_nmid);
+            const int ce = (int)er.size();
+            for (int pass = 1; pass <= 2; pass++) {
+                switch (n - pt) {
+#define HQA_ER(NL) case NL: k_enum_real_many<NL><<<dim3(R * Pe, ce), 256, 0, st>>>(as, nr, pass); break;
+                    HQA_ER(0) HQA_ER(1) HQA_ER(2) HQA_ER(3) HQA_ER(4) HQA_ER(5) HQA_ER(6)
+                    HQA_ER(7) HQA_ER(8) HQA_ER(9) HQA_ER(10) HQA_ER(11)
+                    default: k_enum_real_many<12><<<dim3(R * Pe, ce), 256, 0, st>>>(as, nr, pass); break;
+#undef HQA_ER
+                }
+                k_enum_real_mid_many<<<dim3(R, ce), 64, 0, st>>>(as, nm, pass);
+            }
+        }
+        if (!ei.empty()) {
+            const EnumArgs *as = (const EnumArgs *)(d + o_ei);
+            const int *ni = (const int *)(d + o_nei);
+            const int ci = (int)ei.size();
+            switch (n > ENUM_PT ? n - ENUM_PT : 0) {
+#define HQA_EI(NL) case NL: k_enumerate_int_many<NL><<<dim3(R, ci), 1024, 0, st>>>(as, ni); break;
+                HQA_EI(0) HQA_EI(1) HQA_EI(2) HQA_EI(3) HQA_EI(4) HQA_EI(5) HQA_EI(6) HQA_EI(7)
+                HQA_EI(8) HQA_EI(9) HQA_EI(10) HQA_EI(11) HQA_EI(12) HQA_EI(13)
+                default: k_enumerate_int_many<14><<<dim3(R, ci), 1024, 0, st>>>(as, ni); break;
+#undef HQA_EI
+            }
+        }
+        k_merge_many<<<dim3(mx(nmg), count), 256, 0, st>>>((const MergeArgs *)(d + o_mg),
+                                                          (const int *)(d + o_nmg));
+    }
+    if (!pk.empty())
+        k_pack_masks_many<<<dim3(mx(npk), (int)pk.size()), 256, 0, st>>>(
+            (const PackArgs *)(d + o_pk), (const int *)(d + o_npk));
+    for (int L = 1; L <= 4; L++) {
+        if (mv[L].empty()) continue;
+        const int G = energy_mv_group(L), groups = (R + G - 1) / G, cl = (int)mv[L].size();
+        const EnMvArgs *as = (const EnMvArgs *)(d + o_mv[L]);
+        const int *np = (const int *)(d + o_nmv[L]), *nq = (const int *)(d + o_nmm[L]);
+        const dim3 g1(mx(nmv[L]), groups, cl), g2((R + 3) / 4, cl);
+        if (L == 1) { k_energy_mv_many<64, 1><<<g1, 256, 0, st>>>(as, np); k_energy_mv_merge_many<1><<<g2, 256, 0, st>>>(as, nq); }
+        if (L == 2) { k_energy_mv_many<32, 2><<<g1, 256, 0, st>>>(as, np); k_energy_mv_merge_many<2><<<g2, 256, 0, st>>>(as, nq); }
+        if (L == 3) { k_energy_mv_many<16, 3><<<g1, 256, 0, st>>>(as, np); k_energy_mv_merge_many<3><<<g2, 256, 0, st>>>(as, nq); }
+        if (L == 4) { k_energy_mv_many<16, 4><<<g1, 256, 0, st>>>(as, np); k_energy_mv_merge_many<4><<<g2, 256, 0, st>>>(as, nq); }
+    }
+    for (int c : fallback) {
+        const ReadoutJob &j = jobs[c];
+        e = launch_energy(*j.I, R, j.spins, j.E, j.C, j.part, st);
+        if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
 }
 

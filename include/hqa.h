@@ -368,11 +368,12 @@ hqa_status hqa_classify_many(hqa_md *md, const int32_t *instances, int32_t count
  * hqa_classify_many (n_amb, solve 0 or 1) with its R exact energies and cuts written to
  * the DEVICE arrays energy[c R .. c R + R) and cut[c R .. c R + R) (either may be NULL,
  * not both).  Results equal those of that sequence of calls bit for bit.  All of it is
- * enqueued on the handle's stream (the read-outs on up to four side streams of the
- * handle's own that rejoin it): nothing is synchronised, and after the first call with a
- * given read-out size nothing is allocated (the scratch, streams and events stay with
- * the handle until hqa_md_destroy; a larger read-out later waits for the handle's stream
- * and reallocates).  The caller synchronises (hqa_md_sync reports a non-finite state)
+ * enqueued on the handle's stream (the read-out as one launch per stage for all
+ * instances): nothing is synchronised and nothing is allocated, except that the first
+ * call, and a call whose n_amb, solve or output arrays differ from the previous call's,
+ * waits once for the handle's stream while it uploads the read-out's stage arguments
+ * (the scratch, argument table and capture stream stay with the handle until
+ * hqa_md_destroy; a larger read-out reallocates them).  The caller synchronises (hqa_md_sync reports a non-finite state)
  * before reading the outputs.  With flags = HQA_MD_GRAPH the pass is captured into one
  * HIP graph on its first call with these arguments (seed, n_amb, solve, energy, cut and
  * the flux-buffer parity, which an odd T flips) and replayed by later calls: a replay

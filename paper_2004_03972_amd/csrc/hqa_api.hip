@@ -1825,7 +1825,6 @@ hqa_status hqa_ising_energy(const hqa_problem *prob, const int8_t *spins, int32_
 // stream work, optionally captured into a HIP graph and replayed.
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int PASS_SIDE = 4;          // side streams of the read-out
 constexpr size_t PASS_MAX_GRAPHS = 4;
 
 struct PassGraph {
@@ -1838,9 +1837,12 @@ struct PassGraph {
 
 struct PassRes {
     uint8_t *scratch = nullptr;
-    size_t cap = 0;                   // bytes per side stream
-    hipStream_t side[PASS_SIDE] = {};
-    hipEvent_t ev[PASS_SIDE + 1] = {};
+    size_t cap = 0;                   // bytes per instance
+    uint8_t *args = nullptr;          // the read-out's stage arguments (uploaded once per key)
+    size_t argcap = 0;
+    bool table = false;               // args hold the table of (tn, tsolve, tE, tC)
+    int32_t tn = 0, tsolve = 0;
+    double *tE = nullptr, *tC = nullptr;
     hipStream_t cap_stream = nullptr; // capture stream (the handle's stream may be the null stream)
     std::vector<PassGraph> graphs;    // least recently used first
 };
@@ -1855,45 +1857,64 @@ static void free_pass(void *p) {
     PassRes *pr = (PassRes *)p;
     if (!pr) return;
     drop_pass_graphs(pr);
-    for (int k = 0; k < PASS_SIDE; k++) {
-        if (pr->side[k]) (void)hipStreamSynchronize(pr->side[k]);
-        if (pr->side[k]) (void)hipStreamDestroy(pr->side[k]);
-    }
-    for (int k = 0; k <= PASS_SIDE; k++)
-        if (pr->ev[k]) (void)hipEventDestroy(pr->ev[k]);
     if (pr->cap_stream) (void)hipStreamDestroy(pr->cap_stream);
     dfree(pr->scratch);
+    dfree(pr->args);
     delete pr;
 }
 
-// The pass's device work on md->stream: no allocation, no memset, no synchronisation.
+// The read-out jobs of a pass: instance c's buffers carved from its scratch region in
+// the order of the one-instance read-out; energies and cuts go to E, C (device).
+static hipError_t pass_jobs(hqa_md *md, PassRes *pr, int32_t n_amb, int32_t solve, double *E,
+                            double *C, std::vector<ReadoutJob> &jobs) {
+    const int32_t count = (int32_t)md->inst.size();
+    const int R = md->R;
+    jobs.assign(count, ReadoutJob{});
+    hipError_t e = hipSuccess;
+    for (int32_t c = 0; c < count && e == hipSuccess; c++) {
+        Instance &I = md->inst[c];
+        ScratchArena A;
+        A.base = pr->scratch + (size_t)c * pr->cap;
+        A.cap = pr->cap;
+        ReadoutJob &jb = jobs[c];
+        jb.I = &I;
+        jb.prec = md->prec;
+        jb.W = md->sch.W;
+        e = A.get(&jb.amb, (size_t)R * (n_amb ? n_amb : 1));
+        if (e == hipSuccess) e = A.get(&jb.spins, (size_t)R * I.N);
+        if (e == hipSuccess && solve && n_amb > 0) {
+            e = A.get(&jb.h_eff, (size_t)R * n_amb);
+            if (e == hipSuccess) e = A.get(&jb.J_eff, (size_t)R * n_amb * n_amb);
+            if (e == hipSuccess) e = A.get(&jb.code, (size_t)R);
+            if (e == hipSuccess) e = A.get(&jb.e_red, (size_t)R);
+            uint8_t *escr = nullptr;
+            if (e == hipSuccess) e = A.get(&escr, enum_scratch_bytes(n_amb, R));
+            jb.escr = escr;
+        }
+        double *Es = nullptr, *Cs = nullptr;
+        uint8_t *part = nullptr;
+        if (e == hipSuccess) e = A.get(&Es, (size_t)R);
+        if (e == hipSuccess) e = A.get(&Cs, (size_t)R);
+        if (e == hipSuccess) e = A.get(&part, energy_part_bytes(I.N, R));
+        jb.E = E ? E + (size_t)c * R : Es;
+        jb.C = C ? C + (size_t)c * R : Cs;
+        jb.part = part;
+    }
+    return e;
+}
+
+// The pass's device work on md->stream: no allocation, no memset, no synchronisation
+// (the read-out's stage arguments were uploaded before).
 static hqa_status enqueue_pass(hqa_md *md, PassRes *pr, uint64_t seed, int32_t n_amb,
                                int32_t solve, double *E, double *C) {
     HIPCHK(reset_core(md, seed));
     hqa_status s = run_core(md, md->sch.T, false);
     if (s != HQA_OK) return s;
-    const int32_t count = (int32_t)md->inst.size();
-    const int NS = std::min<int32_t>(count, PASS_SIDE);
-    const int R = md->R;
-    HIPCHK(hipEventRecord(pr->ev[PASS_SIDE], md->stream));
-    for (int k = 0; k < NS; k++) HIPCHK(hipStreamWaitEvent(pr->side[k], pr->ev[PASS_SIDE], 0));
-    for (int32_t c = 0; c < count && s == HQA_OK; c++) {
-        const int k = c % NS;
-        ScratchArena A;
-        A.base = pr->scratch + (size_t)k * pr->cap;
-        A.cap = pr->cap;
-        hqa_classify_out oc{};
-        oc.energy = E ? E + (size_t)c * R : nullptr;
-        oc.cut = C ? C + (size_t)c * R : nullptr;
-        s = classify_core(md, c, n_amb, solve, &oc, HQA_DEVICE, nullptr, HQA_HOST, 0, 0, A, false,
-                          pr->side[k]);
-    }
-    // the side streams rejoin the handle's stream whatever happened above
-    for (int k = 0; k < NS; k++) {
-        HIPCHK(hipEventRecord(pr->ev[k], pr->side[k]));
-        HIPCHK(hipStreamWaitEvent(md->stream, pr->ev[k], 0));
-    }
-    return s;
+    std::vector<ReadoutJob> jobs;
+    HIPCHK(pass_jobs(md, pr, n_amb, solve, E, C, jobs));
+    HIPCHK(launch_readout_batch(jobs, md->R, n_amb, solve, pr->args, pr->argcap, md->stream,
+                                READOUT_LAUNCH));
+    return HQA_OK;
 }
 
 hqa_status hqa_md_pass(hqa_md *md, uint64_t seed, int32_t n_amb, int32_t solve, double *energy,
@@ -1927,24 +1948,35 @@ hqa_status hqa_md_pass(hqa_md *md, uint64_t seed, int32_t n_amb, int32_t solve, 
     if (!pr) {
         pr = new PassRes();
         md->pass = pr;
-        hipError_t e = hipSuccess;
-        for (int k = 0; k <= PASS_SIDE && e == hipSuccess; k++)
-            e = hipEventCreateWithFlags(&pr->ev[k], hipEventDisableTiming);
-        for (int k = 0; k < PASS_SIDE && e == hipSuccess; k++)
-            e = hipStreamCreateWithFlags(&pr->side[k], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&pr->cap_stream, hipStreamNonBlocking);
-        if (e != hipSuccess) return fail(dev_status(e), "pass streams: %s", hipGetErrorString(e));
+        hipError_t e = hipStreamCreateWithFlags(&pr->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(dev_status(e), "pass stream: %s", hipGetErrorString(e));
     }
-    if (need > pr->cap) {
-        // earlier passes may still use the old scratch, and captured graphs name it
+    if (need > pr->cap || !pr->args) {
+        // earlier passes may still use the old buffers, and captured graphs name them
         HIPCHK(hipStreamSynchronize(md->stream));
         drop_pass_graphs(pr);
+        pr->table = false;
         dfree(pr->scratch);
         pr->scratch = nullptr;
         pr->cap = 0;
-        const int NS = std::min<int32_t>(count, PASS_SIDE);
-        HIPCHK(dev_malloc((void **)&pr->scratch, (size_t)NS * need));
+        HIPCHK(dev_malloc((void **)&pr->scratch, (size_t)count * need));
         pr->cap = need;
+        if (!pr->args) {
+            pr->argcap = readout_batch_arg_bytes(count);
+            HIPCHK(dev_malloc((void **)&pr->args, pr->argcap));
+        }
+    }
+    if (!pr->table || pr->tn != n_amb || pr->tsolve != solve || pr->tE != energy ||
+        pr->tC != cut) {
+        // a new argument table: graphs captured with the old one would read it
+        HIPCHK(hipStreamSynchronize(md->stream));
+        drop_pass_graphs(pr);
+        std::vector<ReadoutJob> jobs;
+        HIPCHK(pass_jobs(md, pr, n_amb, solve, energy, cut, jobs));
+        HIPCHK(launch_readout_batch(jobs, md->R, n_amb, solve, pr->args, pr->argcap, md->stream,
+                                    READOUT_UPLOAD));
+        pr->table = true;
+        pr->tn = n_amb; pr->tsolve = solve; pr->tE = energy; pr->tC = cut;
     }
     if (!graph) return enqueue_pass(md, pr, seed, n_amb, solve, energy, cut);
 

@@ -200,8 +200,12 @@ struct ReadoutJob {
     void *part;
 };
 size_t readout_batch_arg_bytes(int count);
+// mode: READOUT_ALL uploads the stage arguments (and waits for the upload) and launches;
+// READOUT_UPLOAD only uploads; READOUT_LAUNCH only launches, from a table an earlier call
+// with the same jobs uploaded (no copy, no wait: such a launch may be recorded in a graph)
+enum { READOUT_ALL = 0, READOUT_UPLOAD = 1, READOUT_LAUNCH = 2 };
 hipError_t launch_readout_batch(const std::vector<ReadoutJob> &jobs, int R, int n, int solve,
-                                void *argbuf, size_t argcap, hipStream_t st);
+                                void *argbuf, size_t argcap, hipStream_t st, int mode = READOUT_ALL);
 hipError_t launch_energy(const Instance &I, int V, const int8_t *spins, double *E, double *cut,
                          void *part, hipStream_t st);
 hipError_t launch_select_keys(int N, int R, const float *keys, int n, int32_t *amb,

@@ -1343,7 +1343,7 @@ size_t readout_batch_arg_bytes(int count) {
 }
 
 hipError_t launch_readout_batch(const std::vector<ReadoutJob> &jobs, int R, int n, int solve,
-                                void *argbuf, size_t argcap, hipStream_t st) {
+                                void *argbuf, size_t argcap, hipStream_t st, int mode) {
     const int count = (int)jobs.size();
     if (count == 0) return hipSuccess;
     Blob b;
@@ -1447,9 +1447,12 @@ hipError_t launch_readout_batch(const std::vector<ReadoutJob> &jobs, int R, int 
     }
     if (b.h.size() > argcap) return hipErrorInvalidValue;
     // the host copy of the arguments lives only in this call: wait for the upload
-    hipError_t e = hipMemcpyAsync(argbuf, b.h.data(), b.h.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (mode != READOUT_LAUNCH) {
+        e = hipMemcpyAsync(argbuf, b.h.data(), b.h.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess || mode == READOUT_UPLOAD) return e;
+    }
     uint8_t *d = (uint8_t *)argbuf;
     auto mx = [](const std::vector<int> &v) { int m = 0; for (int x : v) m = std::max(m, x); return m; };
     k_select_many<<<dim3(R, count), 256, 0, st>>>((const SelArgs *)(d + o_sel), (const int *)(d + o_nsel));
